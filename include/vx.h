@@ -1,0 +1,325 @@
+/*
+ * vx.h — C ABI of an MI355X (gfx950) streamed equi-join / aggregate library.
+ *
+ * The operations follow "Vortex: Overcoming Memory Capacity Limitations in
+ * GPU-Accelerated Large-Scale Data Analytics" (VLDB 2025):
+ *   - an equi-join reduced to aggregates, SUM(A.val + B.val) over
+ *     A.key == B.key (Sec. 7.1, hash join query), where the probe side lives in
+ *     host memory and is larger than the device (Sec. 1, 3: data starts in CPU
+ *     memory, nothing is cached on the GPU);
+ *   - the probe side streamed in chunks through two device buffers while the
+ *     kernel works on the previous chunk (Sec. 5.3, Pipelined Executor), with
+ *     copies submitted only when they can run at once (Sec. 4.3, first design
+ *     principle);
+ *   - columns of low estimated selectivity read by zero-copy access instead of
+ *     being copied, with the threshold TH = E / (C_l2 * N_exchange) (Sec. 6.3);
+ *   - a star join of small filtered dimension tables kept on the GPU against a
+ *     streamed fact table, with GROUP BY (Sec. 7.1, Star Schema Benchmark plan);
+ *   - radix partitioning into groups with a boundary array (Sec. 6.2.1) for the
+ *     case where the build side exceeds device memory (Sec. 6.2).
+ * Learned (CDF-model) range partitioning and the batched persistent-kernel join
+ * are additions of this library; the paper leaves skew-aware partitioning out of
+ * its scope (Sec. 6.2.1).
+ *
+ * Conventions for every entry point:
+ *   - Every call returns a vx_status; nothing throws across the ABI.  On a
+ *     status other than VX_OK, vx_last_error() returns a thread-local message.
+ *   - Calls are synchronous: they return after their results are on the host
+ *     (or written to the caller's output arrays).
+ *   - Column pointers (vx_col.data) may point to device memory of the context's
+ *     device, or to pinned, device-mapped host memory (hipHostMalloc or
+ *     vx_host_alloc).  Pageable host memory is rejected with VX_ENOTPINNED.
+ *     Inputs are borrowed for the duration of the call and never written.
+ *   - All device memory the library uses comes from the caller's arena given
+ *     to vx_ctx_create; if a call's working set does not fit, it returns
+ *     VX_EBUDGET and leaves the context usable.  The library calls no device
+ *     allocator of its own.
+ *   - Integer SUMs are two's-complement modulo 2^64; int32 values are
+ *     sign-extended first.  Key equality is bitwise; every key value is legal.
+ *   - A context is bound to one device and is not thread-safe.
+ */
+#ifndef VX_H
+#define VX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VX_OK = 0,
+  VX_EINVAL = 1,        /* bad argument (null pointer, type mismatch, size) */
+  VX_EBUDGET = 2,       /* the arena cannot hold the call's working set */
+  VX_ENOMEM = 3,        /* host allocation failed */
+  VX_EHIP = 4,          /* a HIP runtime call failed */
+  VX_ENOTPINNED = 5,    /* a host column is not pinned / device-mapped */
+  VX_ECAPACITY = 6,     /* an output array is too small (its required size is reported) */
+  VX_EUNSUPPORTED = 7,  /* a valid request this build does not handle */
+  VX_EDUPKEY = 8        /* duplicate key in a build declared unique */
+} vx_status;
+
+typedef enum { VX_I32 = 1, VX_I64 = 2 } vx_type;
+
+/* A borrowed column: data points to n elements of type `type`. */
+typedef struct {
+  const void* data;
+  int32_t type;     /* vx_type */
+  int32_t reserved; /* must be 0 */
+} vx_col;
+
+/* ------------------------------------------------------------------------ context */
+
+typedef struct vx_ctx vx_ctx;
+
+/*
+ * Create a context on `device` over the caller's device buffer `arena` of
+ * `arena_bytes` (the device-memory budget; 256-byte aligned).  `stream` is a
+ * hipStream_t for compute work, or NULL for a library-owned stream; a second,
+ * library-owned stream carries the host-to-device copies.  The arena stays
+ * owned by the caller and must outlive the context.
+ */
+vx_status vx_ctx_create(int device, void* arena, uint64_t arena_bytes, void* stream, vx_ctx** out);
+vx_status vx_ctx_destroy(vx_ctx* ctx);
+
+/* Thread-local text describing the last non-OK status (never NULL). */
+const char* vx_last_error(void);
+
+/* Bytes of the arena currently held by live tables. */
+uint64_t vx_ctx_arena_used(const vx_ctx* ctx);
+
+/* Pinned, device-mapped host memory for columns (page-locked; freed with vx_host_free). */
+vx_status vx_host_alloc(uint64_t bytes, void** out);
+vx_status vx_host_free(void* p);
+
+/* ------------------------------------------------------------------------ statistics */
+
+typedef struct {
+  uint64_t rows;            /* probe (or fact) rows processed */
+  uint64_t chunks;          /* chunks streamed (0: device-resident input) */
+  uint64_t chunk_rows;      /* rows per chunk used */
+  uint64_t sdma_bytes;      /* bytes copied host-to-device by the copy stream */
+  uint64_t zc_bytes_est;    /* zero-copy bytes read, estimated as touched 128-byte lines */
+  uint32_t zc_mask;         /* bit c set: probe payload / fact column c read by zero-copy */
+  uint32_t n_buffers;       /* chunk buffers used by the pipeline */
+  double build_ms;          /* wall time of the build phase */
+  double probe_ms;          /* wall time of the probe / stream phase */
+  double total_ms;
+  double kernel_ms;         /* summed device time of the main kernels (HIP events) */
+  uint64_t kernel_launches; /* main-kernel launches timed in kernel_ms */
+  uint64_t table_bytes;     /* device bytes of the hash table(s) */
+  uint64_t n_parts;         /* partitions used (partitioned join) */
+  double imbalance;         /* max/mean rows per partition (partitioned join) */
+  double part_ms;           /* partition pass wall time */
+  double train_ms;          /* CDF model training wall time */
+  uint64_t singleton_rows;  /* rows resolved through singleton partitions */
+} vx_stats;
+
+/* ------------------------------------------------------------------------ build / probe */
+
+enum {
+  VX_UNIQUE = 1,  /* keys are unique; a duplicate fails the build with VX_EDUPKEY */
+  VX_PREAGG = 2   /* duplicates allowed: the table stores per key its count and payload sums */
+};
+
+typedef struct {
+  vx_col key;
+  const vx_col* pay;   /* n_pay payload columns (NULL if n_pay == 0) */
+  uint32_t n_pay;      /* <= 4 */
+  uint32_t flags;      /* VX_UNIQUE or VX_PREAGG */
+  uint64_t n;          /* rows */
+  float load_factor;   /* 0 = default (0.5); table capacity is a power of two */
+  uint32_t reserved;
+} vx_build_desc;
+
+typedef struct vx_table vx_table;
+
+/*
+ * Build a device hash table over the build side (the table the paper keeps in
+ * GPU memory while the other side streams, Sec. 5.1, 7.1).  Host-resident
+ * build columns are streamed through the context's chunk buffers.  The table
+ * is carved from the arena and owned by the library until vx_table_destroy.
+ */
+vx_status vx_build(vx_ctx* ctx, const vx_build_desc* desc, vx_table** out);
+vx_status vx_table_destroy(vx_table* table);
+
+/* Aggregates of one join: count, then per build payload, then per probe payload. */
+typedef struct {
+  uint64_t match_count;
+  uint64_t sum[8]; /* sum[c] for build payload c (c < n_build_pay), then probe payloads */
+} vx_agg;
+
+enum {
+  VX_LATE_AUTO = -1,   /* per column: zero-copy if the wire-byte model says it moves fewer bytes
+                          than streaming, with the selectivity measured on the first chunk */
+  VX_LATE_SDMA = 0,    /* stream every payload column with the keys */
+  VX_LATE_ZC = 1,      /* read payload columns of matching rows by zero-copy */
+  VX_LATE_PAPER = 2    /* the paper's rule: zero-copy iff selectivity < E / (C_l2 * 1) */
+};
+
+typedef struct {
+  vx_col key;
+  const vx_col* pay;   /* probe payload columns, read only for matching rows */
+  uint32_t n_pay;      /* <= 4; n_build_pay + n_pay <= 8 */
+  int32_t late_mat;    /* VX_LATE_* */
+  uint64_t n;
+  uint64_t chunk_rows; /* 0 = auto */
+  uint32_t n_buffers;  /* chunk buffers in the pipeline, 2..4; 0 = 2 (the paper's mem A / mem B) */
+  uint32_t reserved;
+  vx_agg* chunk_aggs;  /* optional host array: per-chunk aggregates (cap chunk_aggs_cap) */
+  uint64_t chunk_aggs_cap;
+} vx_probe_desc;
+
+/*
+ * Probe `table` with every probe row and aggregate the matches.  Device-
+ * resident keys are probed in place; host-resident keys are streamed through
+ * n_buffers chunk buffers carved from the arena (VX_EBUDGET if two chunks of
+ * one row do not fit).  `stats` may be NULL.
+ */
+vx_status vx_probe_stream(vx_ctx* ctx, const vx_table* table, const vx_probe_desc* desc,
+                          vx_agg* out, vx_stats* stats);
+
+/* ------------------------------------------------------------------------ one-shot joins */
+
+typedef enum {
+  VX_JOIN_PLAIN = 1,        /* build + probe of two tables */
+  VX_JOIN_STAR = 2,         /* star join with GROUP BY */
+  VX_JOIN_BATCH = 3,        /* many independent device-resident joins in one launch */
+  VX_JOIN_PARTITIONED = 4   /* build side too large for the budget: partition, then join */
+} vx_join_kind;
+
+typedef struct {
+  vx_col key;
+  uint64_t n;
+  vx_col filter;       /* filter attribute; a row passes iff lo <= filter <= hi */
+  int64_t lo, hi;
+  vx_col group;        /* group attribute, or data == NULL for none */
+} vx_star_dim;
+
+typedef struct {
+  int32_t g0, g1;      /* group attributes of the first two dimensions that have one (0 if absent) */
+  uint64_t count;
+  uint64_t sum[4];     /* per measure */
+} vx_group_row;
+
+typedef struct {
+  uint32_t n_dims;             /* 1..4 */
+  uint32_t n_measures;         /* 0..4 */
+  vx_star_dim dims[4];         /* device or host; keys unique (VX_EDUPKEY otherwise) */
+  vx_col fact_fk[4];           /* fact foreign key per dimension */
+  vx_col measure[4];
+  uint64_t n_fact;
+  uint64_t chunk_rows;         /* 0 = auto */
+  int32_t late_mat;            /* VX_LATE_*: fact columns after the first probed one */
+  uint32_t reserved;
+  vx_group_row* groups;        /* host output, ascending (g0, g1), count > 0 only */
+  uint64_t groups_cap;
+} vx_star_join;
+
+typedef struct {
+  uint32_t n_jobs;
+  int32_t mode;                /* 0: one persistent launch in a HIP graph; 1: two launches per job */
+  const vx_col* build_key;     /* per job, device-resident, unique keys */
+  const vx_col* build_pay;     /* per job one payload column (data may be NULL) */
+  const uint64_t* n_build;
+  const vx_col* probe_key;     /* per job, device-resident */
+  const uint64_t* n_probe;
+  vx_agg* out;                 /* per job: match_count and sum[0] = SUM(build payload) */
+  uint32_t tile_rows;          /* 0 = autotuned */
+  uint32_t block;              /* workgroup size, 0 = autotuned */
+  float load_factor;           /* 0 = autotuned */
+  uint32_t reserved;
+} vx_batch_join;
+
+typedef enum {
+  VX_PART_AUTO = 0,            /* learned if its estimated imbalance beats radix-hash, else radix-hash */
+  VX_PART_RADIX_HASH = 1,      /* top bits of a 64-bit mix of the key */
+  VX_PART_RADIX_BITS = 2,      /* raw key bits [shift, shift + log2 P) as in the paper */
+  VX_PART_LEARNED = 3,         /* CDF-model range splitters, trained on the GPU */
+  VX_PART_QUANTILE = 4,        /* range splitters from sample quantiles (no model) */
+  VX_PART_UNTRAINED = 5,       /* CDF model at its initial weights (control) */
+  VX_PART_RANGE = 6            /* caller-given splitters */
+} vx_part_method;
+
+typedef struct {
+  uint32_t method;             /* vx_part_method */
+  uint32_t n_parts;            /* 0 = planned from the budget; radix methods round up to 2^k */
+  uint32_t shift;              /* VX_PART_RADIX_BITS */
+  uint32_t train_steps;        /* 0 = 300 */
+  float sample_frac;           /* 0 = 0.01 */
+  float lr;                    /* 0 = 1e-2 */
+  uint64_t seed;               /* sampling seed */
+  const int64_t* splitters;    /* VX_PART_RANGE: n_splitters ascending keys */
+  uint32_t n_splitters;
+  uint32_t reserved;
+} vx_part_opts;
+
+typedef struct {
+  vx_build_desc build;         /* host-resident; VX_PREAGG implied */
+  vx_probe_desc probe;         /* host-resident keys; no probe payloads */
+  vx_part_opts part;
+} vx_partitioned_join;
+
+typedef struct {
+  int32_t kind;                /* vx_join_kind */
+  int32_t reserved;
+  union {
+    struct { vx_build_desc build; vx_probe_desc probe; } plain;
+    vx_star_join star;
+    vx_batch_join batch;
+    vx_partitioned_join part;
+  } u;
+} vx_join_desc;
+
+typedef struct {
+  vx_agg agg;                  /* PLAIN, PARTITIONED */
+  uint64_t n_groups;           /* STAR: groups with count > 0 (required capacity on VX_ECAPACITY) */
+  uint32_t part_method_used;   /* PARTITIONED */
+  uint32_t reserved;
+  vx_stats stats;
+} vx_join_out;
+
+/* One-shot join of any kind; `out` must not be NULL. */
+vx_status vx_join_agg(vx_ctx* ctx, const vx_join_desc* desc, vx_join_out* out);
+
+/* ------------------------------------------------------------------------ partitioning */
+
+typedef struct {
+  vx_col key;                  /* device or pinned host */
+  const vx_col* pay;           /* payload columns carried by the scatter */
+  uint32_t n_pay;              /* <= 4 */
+  uint32_t reserved;
+  uint64_t n;
+  vx_part_opts opts;
+  void* out_key;               /* optional: clustered keys (host or device, n elements) */
+  void* const* out_pay;        /* optional: clustered payloads, one per column */
+} vx_partition_desc;
+
+typedef struct {
+  uint32_t method_used;
+  uint32_t n_parts;
+  uint64_t* hist;              /* caller array [n_parts_cap] */
+  uint64_t* boundary;          /* caller array [n_parts_cap + 1]: exclusive prefix, boundary[P] = n */
+  int64_t* splitters;          /* caller array [n_parts_cap] for range methods (count in n_splitters) */
+  uint32_t n_parts_cap;
+  uint32_t n_splitters;
+  double imbalance;            /* max/mean of hist */
+  double est_imbalance_radix;  /* on the sample */
+  double est_imbalance_range;  /* on the sample */
+  double final_loss;           /* learned: training loss after the last step */
+  float* model;                /* optional caller array [193]: w1[64], b1[64], w2[64], b2 */
+} vx_partition_out;
+
+/*
+ * Assign every row to a partition, histogram the assignment, and write the
+ * boundary array (Sec. 6.2.1: boundary[h] is the first clustered position of
+ * group h, empty groups take the next boundary, boundary[P] = n).  If out_key
+ * is given, rows are scattered stably (input order kept within a partition).
+ */
+vx_status vx_partition(vx_ctx* ctx, const vx_partition_desc* desc, vx_partition_out* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VX_H */

@@ -1,0 +1,337 @@
+"""Python binding of the vx C ABI (include/vx.h): argument marshalling only.
+
+Every step of the join / aggregate / partition path runs in the HIP library
+``libvx.so`` built from ``csrc/`` by :func:`paper_2502_09541_amd.build.build`.
+PyTorch provides the device arena (a uint8 CUDA tensor) and the compute
+stream; pinned host columns come from :class:`HostBuffer` (vx_host_alloc) or
+any page-locked numpy/torch buffer.
+
+Importing this module does not load the library; the first call does, and it
+raises if the library was not built (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvx.so")
+_lib = None
+
+VX_OK, VX_EINVAL, VX_EBUDGET, VX_ENOMEM, VX_EHIP, VX_ENOTPINNED, VX_ECAPACITY, VX_EUNSUPPORTED, \
+    VX_EDUPKEY = range(9)
+STATUS_NAMES = ["VX_OK", "VX_EINVAL", "VX_EBUDGET", "VX_ENOMEM", "VX_EHIP", "VX_ENOTPINNED",
+                "VX_ECAPACITY", "VX_EUNSUPPORTED", "VX_EDUPKEY"]
+VX_I32, VX_I64 = 1, 2
+VX_UNIQUE, VX_PREAGG = 1, 2
+VX_LATE_AUTO, VX_LATE_SDMA, VX_LATE_ZC, VX_LATE_PAPER = -1, 0, 1, 2
+VX_JOIN_PLAIN, VX_JOIN_STAR, VX_JOIN_BATCH, VX_JOIN_PARTITIONED = 1, 2, 3, 4
+(VX_PART_AUTO, VX_PART_RADIX_HASH, VX_PART_RADIX_BITS, VX_PART_LEARNED, VX_PART_QUANTILE,
+ VX_PART_UNTRAINED, VX_PART_RANGE) = range(7)
+PART_METHODS = {"auto": 0, "radix_hash": 1, "radix_bits": 2, "learned": 3, "quantile": 4,
+                "untrained": 5, "range": 6}
+
+
+class VxError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else status}: {msg}")
+        self.status = status
+
+
+# ----------------------------------------------------------------------------- ABI structs
+
+class Col(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("type", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("rows", C.c_uint64), ("chunks", C.c_uint64), ("chunk_rows", C.c_uint64),
+                ("sdma_bytes", C.c_uint64), ("zc_bytes_est", C.c_uint64), ("zc_mask", C.c_uint32),
+                ("n_buffers", C.c_uint32), ("build_ms", C.c_double), ("probe_ms", C.c_double),
+                ("total_ms", C.c_double), ("kernel_ms", C.c_double), ("kernel_launches", C.c_uint64),
+                ("table_bytes", C.c_uint64), ("n_parts", C.c_uint64), ("imbalance", C.c_double),
+                ("part_ms", C.c_double), ("train_ms", C.c_double), ("singleton_rows", C.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class BuildDesc(C.Structure):
+    _fields_ = [("key", Col), ("pay", C.POINTER(Col)), ("n_pay", C.c_uint32), ("flags", C.c_uint32),
+                ("n", C.c_uint64), ("load_factor", C.c_float), ("reserved", C.c_uint32)]
+
+
+class Agg(C.Structure):
+    _fields_ = [("match_count", C.c_uint64), ("sum", C.c_uint64 * 8)]
+
+    def to_list(self, nsums):
+        return [int(self.match_count)] + [int(self.sum[i]) for i in range(nsums)]
+
+
+class ProbeDesc(C.Structure):
+    _fields_ = [("key", Col), ("pay", C.POINTER(Col)), ("n_pay", C.c_uint32), ("late_mat", C.c_int32),
+                ("n", C.c_uint64), ("chunk_rows", C.c_uint64), ("n_buffers", C.c_uint32),
+                ("reserved", C.c_uint32), ("chunk_aggs", C.POINTER(Agg)), ("chunk_aggs_cap", C.c_uint64)]
+
+
+class StarDim(C.Structure):
+    _fields_ = [("key", Col), ("n", C.c_uint64), ("filter", Col), ("lo", C.c_int64), ("hi", C.c_int64),
+                ("group", Col)]
+
+
+class GroupRow(C.Structure):
+    _fields_ = [("g0", C.c_int32), ("g1", C.c_int32), ("count", C.c_uint64), ("sum", C.c_uint64 * 4)]
+
+
+class StarJoin(C.Structure):
+    _fields_ = [("n_dims", C.c_uint32), ("n_measures", C.c_uint32), ("dims", StarDim * 4),
+                ("fact_fk", Col * 4), ("measure", Col * 4), ("n_fact", C.c_uint64),
+                ("chunk_rows", C.c_uint64), ("late_mat", C.c_int32), ("reserved", C.c_uint32),
+                ("groups", C.POINTER(GroupRow)), ("groups_cap", C.c_uint64)]
+
+
+class BatchJoin(C.Structure):
+    _fields_ = [("n_jobs", C.c_uint32), ("mode", C.c_int32), ("build_key", C.POINTER(Col)),
+                ("build_pay", C.POINTER(Col)), ("n_build", C.POINTER(C.c_uint64)),
+                ("probe_key", C.POINTER(Col)), ("n_probe", C.POINTER(C.c_uint64)),
+                ("out", C.POINTER(Agg)), ("tile_rows", C.c_uint32), ("block", C.c_uint32),
+                ("load_factor", C.c_float), ("reserved", C.c_uint32)]
+
+
+class PartOpts(C.Structure):
+    _fields_ = [("method", C.c_uint32), ("n_parts", C.c_uint32), ("shift", C.c_uint32),
+                ("train_steps", C.c_uint32), ("sample_frac", C.c_float), ("lr", C.c_float),
+                ("seed", C.c_uint64), ("splitters", C.POINTER(C.c_int64)), ("n_splitters", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
+class PartitionedJoin(C.Structure):
+    _fields_ = [("build", BuildDesc), ("probe", ProbeDesc), ("part", PartOpts)]
+
+
+class _PlainJoin(C.Structure):
+    _fields_ = [("build", BuildDesc), ("probe", ProbeDesc)]
+
+
+class _JoinUnion(C.Union):
+    _fields_ = [("plain", _PlainJoin), ("star", StarJoin), ("batch", BatchJoin),
+                ("part", PartitionedJoin)]
+
+
+class JoinDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("u", _JoinUnion)]
+
+
+class JoinOut(C.Structure):
+    _fields_ = [("agg", Agg), ("n_groups", C.c_uint64), ("part_method_used", C.c_uint32),
+                ("reserved", C.c_uint32), ("stats", Stats)]
+
+
+class PartitionDesc(C.Structure):
+    _fields_ = [("key", Col), ("pay", C.POINTER(Col)), ("n_pay", C.c_uint32), ("reserved", C.c_uint32),
+                ("n", C.c_uint64), ("opts", PartOpts), ("out_key", C.c_void_p),
+                ("out_pay", C.POINTER(C.c_void_p))]
+
+
+class PartitionOut(C.Structure):
+    _fields_ = [("method_used", C.c_uint32), ("n_parts", C.c_uint32), ("hist", C.POINTER(C.c_uint64)),
+                ("boundary", C.POINTER(C.c_uint64)), ("splitters", C.POINTER(C.c_int64)),
+                ("n_parts_cap", C.c_uint32), ("n_splitters", C.c_uint32), ("imbalance", C.c_double),
+                ("est_imbalance_radix", C.c_double), ("est_imbalance_range", C.c_double),
+                ("final_loss", C.c_double), ("model", C.POINTER(C.c_float))]
+
+
+EXPORTS = ["vx_ctx_create", "vx_ctx_destroy", "vx_last_error", "vx_ctx_arena_used", "vx_host_alloc",
+           "vx_host_free", "vx_build", "vx_table_destroy", "vx_probe_stream", "vx_join_agg",
+           "vx_partition"]
+
+
+def lib():
+    """Load libvx.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    vp, st = C.c_void_p, C.c_int
+    L.vx_ctx_create.argtypes = [C.c_int, vp, C.c_uint64, vp, C.POINTER(vp)]
+    L.vx_ctx_destroy.argtypes = [vp]
+    L.vx_last_error.restype = C.c_char_p
+    L.vx_ctx_arena_used.argtypes = [vp]
+    L.vx_ctx_arena_used.restype = C.c_uint64
+    L.vx_host_alloc.argtypes = [C.c_uint64, C.POINTER(vp)]
+    L.vx_host_free.argtypes = [vp]
+    L.vx_build.argtypes = [vp, C.POINTER(BuildDesc), C.POINTER(vp)]
+    L.vx_table_destroy.argtypes = [vp]
+    L.vx_probe_stream.argtypes = [vp, vp, C.POINTER(ProbeDesc), C.POINTER(Agg), C.POINTER(Stats)]
+    L.vx_join_agg.argtypes = [vp, C.POINTER(JoinDesc), C.POINTER(JoinOut)]
+    L.vx_partition.argtypes = [vp, C.POINTER(PartitionDesc), C.POINTER(PartitionOut)]
+    for name in ("vx_ctx_create", "vx_ctx_destroy", "vx_host_alloc", "vx_host_free", "vx_build",
+                 "vx_table_destroy", "vx_probe_stream", "vx_join_agg", "vx_partition"):
+        getattr(L, name).restype = st
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != VX_OK:
+        raise VxError(status, lib().vx_last_error().decode())
+
+
+# ----------------------------------------------------------------------------- memory
+
+class HostBuffer:
+    """Pinned, device-mapped host memory from vx_host_alloc, viewed as a numpy array."""
+
+    def __init__(self, n, dtype):
+        self.dtype = np.dtype(dtype)
+        self.n = int(n)
+        p = C.c_void_p()
+        _check(lib().vx_host_alloc(max(1, self.n * self.dtype.itemsize), C.byref(p)))
+        self.ptr = p.value
+        buf = (C.c_byte * max(1, self.n * self.dtype.itemsize)).from_address(self.ptr)
+        self.array = np.frombuffer(buf, dtype=self.dtype, count=self.n)
+
+    def free(self):
+        if self.ptr:
+            self.array = None
+            lib().vx_host_free(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def col(x):
+    """A vx_col for a CUDA tensor, a numpy array (pinned host memory) or a HostBuffer."""
+    if isinstance(x, HostBuffer):
+        x = x.array
+    if isinstance(x, np.ndarray):
+        if not x.flags.c_contiguous:
+            raise ValueError("columns must be contiguous")
+        t = {np.dtype(np.int32): VX_I32, np.dtype(np.int64): VX_I64}.get(x.dtype)
+        if t is None:
+            raise TypeError(f"column dtype {x.dtype} is not int32/int64")
+        return Col(x.ctypes.data if x.size else None, t, 0)
+    import torch
+    if isinstance(x, torch.Tensor):
+        if not x.is_contiguous():
+            raise ValueError("columns must be contiguous")
+        t = {torch.int32: VX_I32, torch.int64: VX_I64}.get(x.dtype)
+        if t is None:
+            raise TypeError(f"column dtype {x.dtype} is not int32/int64")
+        return Col(x.data_ptr() if x.numel() else None, t, 0)
+    raise TypeError(f"unsupported column object {type(x)}")
+
+
+def _cols(xs):
+    xs = list(xs or [])
+    arr = (Col * max(1, len(xs)))(*[col(x) for x in xs])
+    return arr, len(xs)
+
+
+# ----------------------------------------------------------------------------- context
+
+class Context:
+    """A vx_ctx over a torch-allocated device arena of `budget_bytes`."""
+
+    def __init__(self, budget_bytes, device=0, stream=None):
+        import torch
+        self.device = device
+        self.arena = torch.empty(int(budget_bytes), dtype=torch.uint8, device=f"cuda:{device}")
+        s = stream if stream is not None else torch.cuda.current_stream(device)
+        self.stream = s
+        h = C.c_void_p()
+        _check(lib().vx_ctx_create(device, self.arena.data_ptr(), int(budget_bytes),
+                                   C.c_void_p(s.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().vx_ctx_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def arena_used(self):
+        return int(lib().vx_ctx_arena_used(self.h))
+
+    # ------------------------------------------------------------------ build / probe
+    def build(self, key, pays=(), unique=True, load_factor=0.0):
+        pa, npay = _cols(pays)
+        d = BuildDesc(col(key), pa, npay, VX_UNIQUE if unique else VX_PREAGG, _len(key),
+                      float(load_factor), 0)
+        h = C.c_void_p()
+        _check(lib().vx_build(self.h, C.byref(d), C.byref(h)))
+        return Table(self, h, npay, (pa, key, pays))
+
+    def join_plain(self, bkey, bpays, pkey, ppays=(), unique=True, late_mat=VX_LATE_AUTO,
+                   chunk_rows=0, n_buffers=0, load_factor=0.0):
+        """One-shot build + probe. Returns ([count, sums...], stats dict)."""
+        bp, nbp = _cols(bpays)
+        pp, npp = _cols(ppays)
+        d = JoinDesc()
+        d.kind = VX_JOIN_PLAIN
+        d.u.plain.build = BuildDesc(col(bkey), bp, nbp, VX_UNIQUE if unique else VX_PREAGG,
+                                    _len(bkey), float(load_factor), 0)
+        d.u.plain.probe = ProbeDesc(col(pkey), pp, npp, late_mat, _len(pkey), int(chunk_rows),
+                                    int(n_buffers), 0, None, 0)
+        out = JoinOut()
+        _check(lib().vx_join_agg(self.h, C.byref(d), C.byref(out)))
+        return out.agg.to_list(nbp + npp), out.stats.as_dict()
+
+
+def _len(x):
+    if isinstance(x, HostBuffer):
+        return x.n
+    return int(x.shape[0]) if hasattr(x, "shape") else len(x)
+
+
+class Table:
+    def __init__(self, ctx, h, n_pay, keep):
+        self.ctx, self.h, self.n_pay, self._keep = ctx, h, n_pay, keep
+
+    def probe(self, key, pays=(), late_mat=VX_LATE_AUTO, chunk_rows=0, n_buffers=0, chunk_aggs=False):
+        """Probe and aggregate. Returns ([count, sums...], stats dict[, per-chunk lists])."""
+        pa, npay = _cols(pays)
+        n = _len(key)
+        ca, cap = None, 0
+        if chunk_aggs:
+            cr = chunk_rows or n or 1
+            cap = max(1, (n + cr - 1) // cr)
+            ca = (Agg * cap)()
+        d = ProbeDesc(col(key), pa, npay, late_mat, n, int(chunk_rows), int(n_buffers), 0,
+                      ca, cap)
+        out, st = Agg(), Stats()
+        _check(lib().vx_probe_stream(self.ctx.h, self.h, C.byref(d), C.byref(out), C.byref(st)))
+        res = out.to_list(self.n_pay + npay)
+        if chunk_aggs:
+            return res, st.as_dict(), [ca[i].to_list(self.n_pay + npay) for i in range(cap)]
+        return res, st.as_dict()
+
+    def destroy(self):
+        if self.h:
+            lib().vx_table_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
