@@ -113,6 +113,7 @@ typedef struct {
   double part_ms;           /* partition pass wall time */
   double train_ms;          /* CDF model training wall time */
   uint64_t singleton_rows;  /* rows resolved through singleton partitions */
+  uint64_t survivors;       /* star join: fact rows that pass every dimension */
 } vx_stats;
 
 /* ------------------------------------------------------------------------ build / probe */

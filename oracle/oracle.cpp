@@ -46,9 +46,11 @@ inline int64_t at(const or_col& c, uint64_t i) {
   return ((const int64_t*)c.p)[i];
 }
 
+constexpr uint32_t kMaxSums = 8;
+
 struct BuildAgg {
   uint64_t count = 0;
-  std::vector<uint64_t> sums;
+  uint64_t sums[kMaxSums] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 /* Per distinct build key: its multiplicity mB(k) and the sum of each build
@@ -60,7 +62,6 @@ BuildMap make_build_map(or_col bkey, const or_col* bpay, uint32_t nbp, uint64_t 
   m.reserve(nb ? nb : 1);
   for (uint64_t i = 0; i < nb; ++i) {
     BuildAgg& a = m[at(bkey, i)];
-    if (a.sums.empty()) a.sums.assign(nbp, 0);
     a.count += 1;
     for (uint32_t c = 0; c < nbp; ++c) a.sums[c] += (uint64_t)at(bpay[c], i);
   }
@@ -86,6 +87,7 @@ extern "C" {
  */
 int or_join_agg_hash(or_col bkey, const or_col* bpay, uint32_t nbp, uint64_t nb,
                      or_col pkey, const or_col* ppay, uint32_t npp, uint64_t np, uint64_t* out) {
+  if (nbp > kMaxSums) return 1;
   BuildMap m = make_build_map(bkey, bpay, nbp, nb);
   std::memset(out, 0, sizeof(uint64_t) * (1 + nbp + npp));
   for (uint64_t i = 0; i < np; ++i) {
@@ -107,6 +109,7 @@ struct or_build {
 };
 
 or_build* or_build_create(or_col bkey, const or_col* bpay, uint32_t nbp, uint64_t nb) {
+  if (nbp > kMaxSums) return nullptr;
   or_build* b = new or_build;
   b->m = make_build_map(bkey, bpay, nbp, nb);
   b->nbp = nbp;

@@ -52,7 +52,8 @@ class Stats(C.Structure):
                 ("n_buffers", C.c_uint32), ("build_ms", C.c_double), ("probe_ms", C.c_double),
                 ("total_ms", C.c_double), ("kernel_ms", C.c_double), ("kernel_launches", C.c_uint64),
                 ("table_bytes", C.c_uint64), ("n_parts", C.c_uint64), ("imbalance", C.c_double),
-                ("part_ms", C.c_double), ("train_ms", C.c_double), ("singleton_rows", C.c_uint64)]
+                ("part_ms", C.c_double), ("train_ms", C.c_double), ("singleton_rows", C.c_uint64),
+                ("survivors", C.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -295,6 +296,40 @@ class Context:
         out = JoinOut()
         _check(lib().vx_join_agg(self.h, C.byref(d), C.byref(out)))
         return out.agg.to_list(nbp + npp), out.stats.as_dict()
+
+    def join_star(self, dims, fks, meas, groups_cap=4096, late_mat=VX_LATE_AUTO, chunk_rows=0):
+        """Star join + GROUP BY. dims: list of {key, filt, lo, hi, group (or None)}.
+        Returns (g [n,2] int64, count [n] uint64, sums [n, nmeas] uint64, stats), sorted by (g0, g1)."""
+        return _star_call(self, dims, fks, meas, groups_cap, late_mat, chunk_rows)
+
+
+def _star_call(ctx, dims, fks, meas, groups_cap, late_mat, chunk_rows):
+    d = JoinDesc()
+    d.kind = VX_JOIN_STAR
+    sj = d.u.star
+    sj.n_dims = len(dims)
+    sj.n_measures = len(meas)
+    for i, dm in enumerate(dims):
+        grp = dm.get("group")
+        sj.dims[i] = StarDim(col(dm["key"]), _len(dm["key"]), col(dm["filt"]), int(dm["lo"]), int(dm["hi"]),
+                             col(grp) if grp is not None else Col(None, VX_I32, 0))
+        sj.fact_fk[i] = col(fks[i])
+    for i, m in enumerate(meas):
+        sj.measure[i] = col(m)
+    sj.n_fact = _len(fks[0])
+    sj.chunk_rows = int(chunk_rows)
+    sj.late_mat = int(late_mat)
+    rows = (GroupRow * max(1, groups_cap))()
+    sj.groups = rows
+    sj.groups_cap = groups_cap
+    out = JoinOut()
+    _check(lib().vx_join_agg(ctx.h, C.byref(d), C.byref(out)))
+    n = int(out.n_groups)
+    g = np.array([[rows[i].g0, rows[i].g1] for i in range(n)], dtype=np.int64).reshape(n, 2)
+    cnt = np.array([rows[i].count for i in range(n)], dtype=np.uint64)
+    sums = np.array([[rows[i].sum[c] for c in range(len(meas))] for i in range(n)],
+                    dtype=np.uint64).reshape(n, len(meas))
+    return g, cnt, sums, out.stats.as_dict()
 
 
 def _len(x):

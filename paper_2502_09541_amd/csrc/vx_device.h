@@ -1,0 +1,67 @@
+// Device-side helpers shared by the kernels of several translation units.
+#pragma once
+
+#include "vx_table.h"
+
+namespace vx {
+
+template <typename K>
+__device__ __forceinline__ uint64_t key_bits(K k) {
+  return (uint64_t)(typename KeyTraits<K>::U)k;
+}
+
+__device__ __forceinline__ long long load_signed(const void* base, uint64_t idx, uint32_t size) {
+  if (size == 4) return (long long)((const int*)base)[idx];
+  return ((const long long*)base)[idx];
+}
+
+__device__ __forceinline__ long long slot_signed(const uint8_t* slot, uint32_t off, uint32_t size) {
+  if (size == 4) return (long long)*(const int*)(slot + off);
+  return *(const long long*)(slot + off);
+}
+
+template <int NACC>
+__device__ __forceinline__ void block_flush(unsigned long long (&acc)[NACC], int nacc,
+                                            unsigned long long* out) {
+  __shared__ unsigned long long red[NACC][16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int a = 0; a < NACC; ++a) {
+    unsigned long long v = acc[a];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) red[a][wave] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < (unsigned)nacc) {
+    unsigned long long s = 0;
+    for (int w = 0; w < nw; ++w) s += red[threadIdx.x][w];
+    if (s) atomicAdd(out + threadIdx.x, s);
+  }
+}
+
+
+// Find `k` in a unique table.  Returns the slot, or nullptr when absent; keys equal to the
+// empty marker are looked up in the side record by the caller.
+template <typename K>
+__device__ __forceinline__ const uint8_t* find_slot(const TableView& t, K k) {
+  using U = typename KeyTraits<K>::U;
+  const U kEmpty = KeyTraits<K>::kEmpty;
+  const U kb = (U)k;
+  uint64_t h = slot_of(key_bits(k), t.log2cap);
+  for (uint64_t step = 0; step <= t.mask; ++step) {
+    const uint8_t* slot = t.slots + (h << t.slot_shift);
+    U sk = *(const U*)slot;
+    if (sk == kb) return slot;
+    if (sk == kEmpty) return nullptr;
+    h = (h + 1) & t.mask;
+  }
+  return nullptr;
+}
+
+template <typename K>
+__device__ __forceinline__ K load_key(const void* base, uint64_t idx) {
+  return ((const K*)base)[idx];
+}
+
+}  // namespace vx

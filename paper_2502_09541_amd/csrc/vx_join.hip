@@ -12,46 +12,10 @@
 #include <cmath>
 #include <cstring>
 
-#include "vx_table.h"
+#include "vx_device.h"
+#include "vx_pipeline.h"
 
 namespace vx {
-
-// ---------------------------------------------------------------- device helpers
-
-template <typename K>
-__device__ __forceinline__ uint64_t key_bits(K k) {
-  return (uint64_t)(typename KeyTraits<K>::U)k;
-}
-
-__device__ __forceinline__ long long load_signed(const void* base, uint64_t idx, uint32_t size) {
-  if (size == 4) return (long long)((const int*)base)[idx];
-  return ((const long long*)base)[idx];
-}
-
-__device__ __forceinline__ long long slot_signed(const uint8_t* slot, uint32_t off, uint32_t size) {
-  if (size == 4) return (long long)*(const int*)(slot + off);
-  return *(const long long*)(slot + off);
-}
-
-template <int NACC>
-__device__ __forceinline__ void block_flush(unsigned long long (&acc)[NACC], int nacc,
-                                            unsigned long long* out) {
-  __shared__ unsigned long long red[NACC][16];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#pragma unroll
-  for (int a = 0; a < NACC; ++a) {
-    unsigned long long v = acc[a];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if (lane == 0) red[a][wave] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x < (unsigned)nacc) {
-    unsigned long long s = 0;
-    for (int w = 0; w < nw; ++w) s += red[threadIdx.x][w];
-    if (s) atomicAdd(out + threadIdx.x, s);
-  }
-}
 
 // ---------------------------------------------------------------- table init
 
@@ -538,15 +502,12 @@ int build_group_lanes() {
 
 // ---------------------------------------------------------------- streamed probe executor
 
-struct ProbePlan {
-  uint64_t chunk_rows = 0;
-  uint32_t n_buffers = 2;
-  uint64_t buf_bytes = 0;
-};
-
-static uint64_t env_u64(const char* name, uint64_t dflt) {
-  const char* e = getenv(name);
-  return e ? strtoull(e, nullptr, 10) : dflt;
+// Per probe payload column: read by zero-copy (true) or streamed with the keys (false),
+// given the selectivity measured on the first chunk.
+static bool choose_zero_copy(int32_t late_mat, double sel, uint64_t rows, uint64_t matches, int es) {
+  if (late_mat == VX_LATE_PAPER) return sel < (double)es / (double)kZcLine;  // TH = E/(C_l2 * 1)
+  double wire = zc_wire_bytes(rows, std::min(matches, rows), es) / (double)std::max<uint64_t>(rows, 1);
+  return wire < 0.95 * es;
 }
 
 vx_status probe_impl(vx_ctx* ctx, const vx_table* t, const vx_probe_desc* d, vx_agg* out,
@@ -558,269 +519,73 @@ vx_status probe_impl(vx_ctx* ctx, const vx_table* t, const vx_probe_desc* d, vx_
   VX_CHECK(d->n_pay == 0 || d->pay != nullptr, VX_EINVAL, "probe: pay is NULL");
   VX_CHECK(t->view.n_pay + d->n_pay <= 8, VX_EINVAL, "probe: more than 8 aggregate sums");
   VX_CHECK(d->late_mat >= -1 && d->late_mat <= 2, VX_EINVAL, "probe: late_mat %d", d->late_mat);
-  ColInfo kc;
-  VX_TRY(classify(ctx, d->key, d->n, &kc, "probe key"));
-  ColInfo pc[kMaxPay];
-  for (uint32_t p = 0; p < d->n_pay; ++p) VX_TRY(classify(ctx, d->pay[p], d->n, &pc[p], "probe payload"));
+  std::vector<PipeCol> cols(1 + d->n_pay);
+  VX_TRY(classify(ctx, d->key, d->n, &cols[0].info, "probe key"));
+  cols[0].may_copy = cols[0].copy = true;
+  for (uint32_t p = 0; p < d->n_pay; ++p) {
+    VX_TRY(classify(ctx, d->pay[p], d->n, &cols[1 + p].info, "probe payload"));
+    cols[1 + p].may_copy = d->late_mat != VX_LATE_ZC;
+    cols[1 + p].copy = d->late_mat == VX_LATE_SDMA;
+  }
   VX_HIP(hipSetDevice(ctx->device));
   const uint64_t n = d->n;
-  const int ks = kc.elsize;
   const uint32_t nacc = 1 + t->view.n_pay + d->n_pay;
   vx_stats s{};
   s.rows = n;
   s.table_bytes = t->bytes;
-  std::vector<unsigned long long> total(kAccWords, 0);
 
-  // chunking
-  bool streamed = kc.where == Where::Host;
-  uint64_t chunk_rows;
-  if (d->chunk_rows) chunk_rows = d->chunk_rows;
-  else if (streamed) chunk_rows = env_u64("VX_CHUNK_BYTES", 64ull << 20) / (uint64_t)ks;
-  else chunk_rows = n ? n : 1;
-  if (chunk_rows == 0) chunk_rows = 1;
-  uint64_t n_chunks = n ? (n + chunk_rows - 1) / chunk_rows : 0;
-  uint64_t acc_rows_cap = ctx->dev_acc_words / kAccWords;
-
-  // per-column late materialization decision (streamed path only): zero-copy or SDMA
-  uint32_t zc_mask = 0;
-  bool decide_after_first = false;
-  if (streamed) {
-    if (d->late_mat == VX_LATE_ZC) zc_mask = (1u << d->n_pay) - 1;
-    else if (d->late_mat == VX_LATE_SDMA) zc_mask = 0;
-    else {
-      zc_mask = (1u << d->n_pay) - 1;    // the first chunk runs zero-copy and measures selectivity
-      decide_after_first = d->n_pay > 0 && n_chunks > 1;
-    }
-  }
-  // payload columns that are device-resident are always read in place
-  for (uint32_t p = 0; p < d->n_pay; ++p)
-    if (pc[p].where == Where::Device) zc_mask |= 1u << p;
-
-  uint32_t nbuf = d->n_buffers ? d->n_buffers : (uint32_t)env_u64("VX_BUFFERS", 2);
-  VX_CHECK(nbuf >= 2 && nbuf <= 4, VX_EINVAL, "probe: n_buffers %u outside 2..4", nbuf);
-
-  // buffers: keys + every payload column that may be copied
-  uint64_t row_bytes = (uint64_t)ks;
-  for (uint32_t p = 0; p < d->n_pay; ++p)
-    if (pc[p].where == Where::Host && d->late_mat != VX_LATE_ZC) row_bytes += (uint64_t)pc[p].elsize;
-  ArenaBlock bufs[4];
-  uint64_t buf_bytes = 0;
-  if (streamed && n) {
-    if (chunk_rows > n) chunk_rows = n;
-    // shrink chunks until the pipeline fits the free arena
-    for (;;) {
-      buf_bytes = chunk_rows * row_bytes + 256 * (1 + kMaxPay);
-      bool ok = true;
-      for (uint32_t b = 0; b < nbuf; ++b) {
-        bufs[b].a = &ctx->arena;
-        bufs[b].p = ctx->arena.alloc(buf_bytes);
-        if (!bufs[b].p) ok = false;
-      }
-      if (ok) break;
-      for (uint32_t b = 0; b < nbuf; ++b) bufs[b].reset();
-      VX_CHECK(chunk_rows > 1024 && !d->chunk_rows, VX_EBUDGET,
-               "probe: %u chunk buffers of %llu rows x %llu B do not fit the arena (%llu B free)",
-               nbuf, (unsigned long long)chunk_rows, (unsigned long long)row_bytes,
-               (unsigned long long)(ctx->arena.capacity() - ctx->arena.used()));
-      chunk_rows /= 2;
-    }
-    n_chunks = (n + chunk_rows - 1) / chunk_rows;
-  }
-  s.chunk_rows = chunk_rows;
-  s.chunks = streamed ? n_chunks : 0;
-  s.n_buffers = streamed ? nbuf : 0;
-
-  uint64_t acc_rows = std::min<uint64_t>(std::max<uint64_t>(n_chunks, 1), acc_rows_cap);
-  fill_zero((uint64_t*)ctx->dev_acc, acc_rows * kAccWords, ctx->compute);
-  fill_zero((uint64_t*)ctx->dev_flags, 1, ctx->compute);
-
-  std::vector<hipEvent_t> ev_copied(nbuf), ev_free(nbuf);
-  std::vector<bool> free_pending(nbuf, false);
-  hipEvent_t k_beg = get_event(ctx), k_end = get_event(ctx);
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> kev;
-  for (uint32_t b = 0; b < nbuf; ++b) {
-    ev_copied[b] = get_event(ctx);
-    ev_free[b] = get_event(ctx);
-  }
-  auto cleanup = [&]() {
-    for (uint32_t b = 0; b < nbuf; ++b) {
-      put_event(ctx, ev_copied[b]);
-      put_event(ctx, ev_free[b]);
-    }
-    for (auto& pr : kev) {
-      put_event(ctx, pr.first);
-      put_event(ctx, pr.second);
-    }
-    put_event(ctx, k_beg);
-    put_event(ctx, k_end);
-  };
-
-  auto chunk_layout = [&](uint32_t b, uint64_t rows, const void** key_dst, const void** pay_dst) {
-    uint8_t* base = bufs[b].p;
-    *key_dst = base;
-    uint64_t off = (rows * (uint64_t)ks + 255) / 256 * 256;
-    for (uint32_t p = 0; p < d->n_pay; ++p) {
-      pay_dst[p] = nullptr;
-      if (pc[p].where == Where::Host && !((zc_mask >> p) & 1u)) {
-        pay_dst[p] = base + off;
-        off += (rows * (uint64_t)pc[p].elsize + 255) / 256 * 256;
-      }
-    }
-  };
-
-  vx_status status = VX_OK;
-  double tk0 = now_ms();
-  if (!streamed) {
-    // device-resident keys: probe in place, one launch per chunk (chunks only matter for
-    // per-chunk aggregates)
-    for (uint64_t c = 0; c < n_chunks && status == VX_OK; ++c) {
-      uint64_t r0 = c * chunk_rows, rows = std::min(chunk_rows, n - r0);
-      ProbeCols q{};
-      q.key = (const uint8_t*)kc.dev + r0 * ks;
-      q.n = rows;
-      q.row0 = r0;
-      q.n_pay = d->n_pay;
-      for (uint32_t p = 0; p < d->n_pay; ++p) {
-        q.pay[p] = pc[p].dev;
-        q.pay_size[p] = (uint32_t)pc[p].elsize;
-        q.pay_global |= 1u << p;
-      }
-      hipEvent_t a = get_event(ctx), b2 = get_event(ctx);
-      kev.push_back({a, b2});
-      (void)hipEventRecord(a, ctx->compute);
-      status = launch_probe(ctx, t, q, (unsigned long long*)ctx->dev_acc + (c % acc_rows) * kAccWords,
-                            ctx->compute);
-      (void)hipEventRecord(b2, ctx->compute);
-    }
-  } else {
-    // Pipelined executor: buffer b = chunk % nbuf.  A copy is enqueued only once its buffer
-    // is free (the host waits for the kernel that last read it), so it starts at once.
-    uint64_t issued = 0;
-    auto issue_copy = [&](uint64_t c) -> vx_status {
-      uint32_t b = (uint32_t)(c % nbuf);
-      if (free_pending[b]) {
-        VX_HIP(hipEventSynchronize(ev_free[b]));
-        free_pending[b] = false;
-      }
-      uint64_t r0 = c * chunk_rows, rows = std::min(chunk_rows, n - r0);
-      const void* kd;
-      const void* pd[kMaxPay];
-      chunk_layout(b, rows, &kd, pd);
-      VX_HIP(hipMemcpyAsync(const_cast<void*>(kd), (const uint8_t*)kc.host + r0 * ks, rows * ks,
-                            hipMemcpyHostToDevice, ctx->copy));
-      s.sdma_bytes += rows * ks;
-      for (uint32_t p = 0; p < d->n_pay; ++p) {
-        if (!pd[p]) continue;
-        uint64_t es = (uint64_t)pc[p].elsize;
-        VX_HIP(hipMemcpyAsync(const_cast<void*>(pd[p]), (const uint8_t*)pc[p].host + r0 * es,
-                              rows * es, hipMemcpyHostToDevice, ctx->copy));
-        s.sdma_bytes += rows * es;
-      }
-      VX_HIP(hipEventRecord(ev_copied[b], ctx->copy));
-      return VX_OK;
-    };
-    auto issue_kernel = [&](uint64_t c) -> vx_status {
-      uint32_t b = (uint32_t)(c % nbuf);
-      uint64_t r0 = c * chunk_rows, rows = std::min(chunk_rows, n - r0);
-      const void* kd;
-      const void* pd[kMaxPay];
-      chunk_layout(b, rows, &kd, pd);
-      VX_HIP(hipStreamWaitEvent(ctx->compute, ev_copied[b], 0));
-      ProbeCols q{};
-      q.key = kd;
-      q.n = rows;
-      q.row0 = r0;
-      q.n_pay = d->n_pay;
-      for (uint32_t p = 0; p < d->n_pay; ++p) {
-        q.pay_size[p] = (uint32_t)pc[p].elsize;
-        if (pd[p]) q.pay[p] = pd[p];
-        else {
-          q.pay[p] = pc[p].dev;
-          q.pay_global |= 1u << p;
-        }
-      }
-      hipEvent_t a = get_event(ctx), e2 = get_event(ctx);
-      kev.push_back({a, e2});
-      VX_HIP(hipEventRecord(a, ctx->compute));
-      VX_TRY(launch_probe(ctx, t, q, (unsigned long long*)ctx->dev_acc + (c % acc_rows) * kAccWords,
-                          ctx->compute));
-      VX_HIP(hipEventRecord(e2, ctx->compute));
-      VX_HIP(hipEventRecord(ev_free[b], ctx->compute));
-      free_pending[b] = true;
-      return VX_OK;
-    };
-    auto run = [&]() -> vx_status {
-      if (n_chunks == 0) return VX_OK;
-      uint64_t start = 0;
-      if (decide_after_first) {
-        VX_TRY(issue_copy(0));
-        VX_TRY(issue_kernel(0));
-        unsigned long long first[kAccWords];
-        VX_HIP(hipMemcpyAsync(first, ctx->dev_acc, sizeof first, hipMemcpyDeviceToHost, ctx->compute));
-        VX_HIP(hipStreamSynchronize(ctx->compute));
-        uint64_t rows0 = std::min(chunk_rows, n);
-        double sel = rows0 ? (double)first[0] / (double)rows0 : 0.0;
-        // note: match_count counts pairs; for unique build keys it is the matching-row count
-        for (uint32_t p = 0; p < d->n_pay; ++p) {
-          if (pc[p].where != Where::Host) continue;
-          int es = pc[p].elsize;
-          bool zc;
-          if (d->late_mat == VX_LATE_PAPER) {
-            zc = sel < (double)es / (double)kZcLine;       // TH = E / (C_l2 * N_exchange), N = 1
-          } else {
-            double wire = zc_wire_bytes(rows0, first[0] < rows0 ? first[0] : rows0, es) / rows0;
-            zc = wire < 0.95 * es;
-          }
-          if (!zc) zc_mask &= ~(1u << p);
-        }
-        start = 1;
-        issued = 1;
-      }
-      // prologue: fill the buffers
-      uint64_t ahead = std::min<uint64_t>(n_chunks, start + nbuf - 1);
-      for (uint64_t c = std::max(issued, start); c < ahead; ++c) VX_TRY(issue_copy(c));
-      issued = std::max(issued, ahead);
-      for (uint64_t c = start; c < n_chunks; ++c) {
-        VX_TRY(issue_kernel(c));
-        if (issued < n_chunks) {
-          VX_TRY(issue_copy(issued));
-          ++issued;
-        }
-      }
-      return VX_OK;
-    };
-    status = run();
-  }
-  if (status != VX_OK) {
-    (void)hipStreamSynchronize(ctx->copy);
-    (void)hipStreamSynchronize(ctx->compute);
-    cleanup();
-    return status;
-  }
-  // per-chunk aggregates back to the host
-  hipError_t e = hipMemcpyAsync(ctx->host_acc, ctx->dev_acc, acc_rows * kAccWords * 8,
-                                hipMemcpyDeviceToHost, ctx->compute);
-  if (e == hipSuccess) e = hipStreamSynchronize(ctx->compute);
-  if (e != hipSuccess) {
-    cleanup();
-    set_error("probe: %s", hipGetErrorString(e));
-    return VX_EHIP;
-  }
-  double tk1 = now_ms();
-  double kms = 0;
-  for (auto& pr : kev) {
-    float ms = 0;
-    if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) kms += ms;
-  }
-  s.kernel_ms = kms;
-  s.kernel_launches = kev.size();
-  cleanup();
-  for (uint64_t r = 0; r < acc_rows; ++r)
-    for (int a = 0; a < kAccWords; ++a) total[a] += ctx->host_acc[r * kAccWords + a];
-  if (d->chunk_aggs) {
+  Pipeline pipe;
+  VX_TRY(pipe.plan(ctx, n, d->chunk_rows, d->n_buffers, cols));
+  const uint64_t n_chunks = pipe.n_chunks();
+  const uint64_t acc_rows_cap = ctx->dev_acc_words / kAccWords;
+  const uint64_t acc_rows = std::min<uint64_t>(std::max<uint64_t>(n_chunks, 1), acc_rows_cap);
+  if (d->chunk_aggs)
     VX_CHECK(n_chunks <= d->chunk_aggs_cap && n_chunks <= acc_rows_cap, VX_ECAPACITY,
              "probe: %llu chunks exceed chunk_aggs_cap %llu", (unsigned long long)n_chunks,
              (unsigned long long)d->chunk_aggs_cap);
+  fill_zero((uint64_t*)ctx->dev_acc, acc_rows * kAccWords, ctx->compute);
+
+  auto kernel = [&](const ChunkView& v) -> vx_status {
+    ProbeCols q{};
+    q.key = v.ptr[0];
+    if ((v.global_mask & 1u)) q.key = (const uint8_t*)v.ptr[0] + v.row0 * (uint64_t)cols[0].info.elsize;
+    q.n = v.rows;
+    q.row0 = v.row0;
+    q.n_pay = d->n_pay;
+    for (uint32_t p = 0; p < d->n_pay; ++p) {
+      q.pay[p] = v.ptr[1 + p];
+      q.pay_size[p] = (uint32_t)cols[1 + p].info.elsize;
+      if ((v.global_mask >> (1 + p)) & 1u) q.pay_global |= 1u << p;
+    }
+    return launch_probe(ctx, t, q, (unsigned long long*)ctx->dev_acc + (v.index % acc_rows) * kAccWords,
+                        ctx->compute);
+  };
+  Pipeline::DecideFn decide = nullptr;
+  bool any_host_pay = false;
+  for (uint32_t p = 0; p < d->n_pay; ++p) any_host_pay |= cols[1 + p].info.where == Where::Host;
+  if ((d->late_mat == VX_LATE_AUTO || d->late_mat == VX_LATE_PAPER) && any_host_pay) {
+    decide = [&](std::vector<PipeCol>& cs) -> vx_status {
+      unsigned long long first[kAccWords];
+      VX_HIP(hipMemcpy(first, ctx->dev_acc, sizeof first, hipMemcpyDeviceToHost));
+      uint64_t rows0 = std::min(pipe.chunk_rows(), n);
+      double sel = rows0 ? (double)first[0] / (double)rows0 : 0.0;
+      for (uint32_t p = 0; p < d->n_pay; ++p)
+        if (cs[1 + p].may_copy)
+          cs[1 + p].copy = !choose_zero_copy(d->late_mat, sel, rows0, first[0], cs[1 + p].info.elsize);
+      return VX_OK;
+    };
+  }
+  double tk0 = now_ms();
+  vx_status status = pipe.run(kernel, decide);
+  if (status != VX_OK) return status;   // the pipeline's destructor drains both streams
+  VX_HIP(hipMemcpyAsync(ctx->host_acc, ctx->dev_acc, acc_rows * kAccWords * 8, hipMemcpyDeviceToHost,
+                        ctx->compute));
+  VX_HIP(hipStreamSynchronize(ctx->compute));
+  double tk1 = now_ms();
+  std::vector<unsigned long long> total(kAccWords, 0);
+  for (uint64_t r = 0; r < acc_rows; ++r)
+    for (int a = 0; a < kAccWords; ++a) total[a] += ctx->host_acc[r * kAccWords + a];
+  if (d->chunk_aggs) {
     for (uint64_t c = 0; c < n_chunks; ++c) {
       vx_agg& ca = d->chunk_aggs[c];
       std::memset(&ca, 0, sizeof ca);
@@ -831,16 +596,25 @@ vx_status probe_impl(vx_ctx* ctx, const vx_table* t, const vx_probe_desc* d, vx_
   std::memset(out, 0, sizeof *out);
   out->match_count = total[0];
   for (uint32_t a = 1; a < nacc; ++a) out->sum[a - 1] = total[a];
-  // zero-copy wire estimate from per-chunk match counts (unique keys: matches = rows)
+  uint32_t zc_mask = 0;
   for (uint32_t p = 0; p < d->n_pay; ++p) {
-    if (pc[p].where != Where::Host || !((zc_mask >> p) & 1u)) continue;
-    for (uint64_t c = 0; c < n_chunks; ++c) {
-      uint64_t rows = std::min(chunk_rows, n - c * chunk_rows);
-      uint64_t m = c < acc_rows ? ctx->host_acc[c * kAccWords] : 0;
-      s.zc_bytes_est += (uint64_t)zc_wire_bytes(rows, std::min(m, rows), pc[p].elsize);
+    const PipeCol& c = pipe.cols()[1 + p];
+    if (c.info.where != Where::Host || c.copy) continue;
+    zc_mask |= 1u << p;
+    // zero-copy wire estimate from per-chunk match counts (unique keys: matches = rows)
+    for (uint64_t k = 0; k < n_chunks; ++k) {
+      uint64_t rows = std::min(pipe.chunk_rows(), n - k * pipe.chunk_rows());
+      uint64_t m = k < acc_rows ? ctx->host_acc[k * kAccWords] : 0;
+      s.zc_bytes_est += (uint64_t)zc_wire_bytes(rows, std::min(m, rows), c.info.elsize);
     }
   }
   s.zc_mask = zc_mask;
+  s.chunk_rows = pipe.chunk_rows();
+  s.chunks = pipe.streamed() ? n_chunks : 0;
+  s.n_buffers = pipe.streamed() ? pipe.n_buffers() : 0;
+  s.sdma_bytes = pipe.sdma_bytes();
+  s.kernel_ms = pipe.kernel_ms();
+  s.kernel_launches = pipe.kernel_launches();
   s.probe_ms = tk1 - tk0;
   s.total_ms = now_ms() - t0;
   if (st) *st = s;

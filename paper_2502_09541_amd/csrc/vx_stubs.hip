@@ -2,10 +2,6 @@
 #include "vx_table.h"
 
 namespace vx {
-vx_status join_star(vx_ctx*, const vx_star_join*, vx_join_out*) {
-  set_error("vx_join_agg: STAR not built");
-  return VX_EUNSUPPORTED;
-}
 vx_status join_batch(vx_ctx*, const vx_batch_join*, vx_join_out*) {
   set_error("vx_join_agg: BATCH not built");
   return VX_EUNSUPPORTED;

@@ -1,0 +1,63 @@
+"""Full-size parity of the streamed join in the launch configuration bench.py times.
+
+2^26 build rows and 2^31 host-resident probe rows (48 GiB pinned), 16 GiB budget, automatic
+late materialization.  The oracle's hash map of 2^26 keys is too slow to build here, so the
+expected aggregates come from the generator's closed form (each probe row knows the build row it
+matches), which tests/test_oracle_join.py pins to the oracle at small scale.  Every aggregate,
+the per-chunk aggregates of sampled chunks, and a second run (determinism) are compared exactly.
+"""
+import numpy as np
+import pytest
+
+import datagen
+
+pytestmark = pytest.mark.gpu
+
+M64 = 1 << 64
+GiB = 1 << 30
+
+
+def test_streamed_join_full_size_closed_form(gpu):
+    import torch
+    nb, np_ = 1 << 26, 1 << 31
+    print("full-size streamed join: allocating 49 GiB pinned", flush=True)
+    H = {}
+    for name, n, dt in (("bk", nb, np.int64), ("b0", nb, np.int32), ("b1", nb, np.int32),
+                        ("pk", np_, np.int64), ("p0", np_, np.int64), ("p1", np_, np.int64)):
+        H[name] = gpu.HostBuffer(n, dt)
+    try:
+        datagen.stream_build(nb, out=(H["bk"].array, H["b0"].array, H["b1"].array))
+        step = 1 << 27
+        for r0 in range(0, np_, step):
+            datagen.stream_probe(nb, step, out=(H["pk"].array[r0:r0 + step], H["p0"].array[r0:r0 + step],
+                                                H["p1"].array[r0:r0 + step]), row0=r0)
+        print("generated; running the join", flush=True)
+        with gpu.Context(16 * GiB) as ctx:
+            t = ctx.build(H["bk"], [H["b0"], H["b1"]])
+            tot, st, per = t.probe(H["pk"], [H["p0"], H["p1"]], chunk_aggs=True,
+                                   chunk_rows=(64 << 20) // 8)
+            tot2, _ = t.probe(H["pk"], [H["p0"], H["p1"]])
+            t.destroy()
+        assert tot == tot2
+        assert st["chunks"] == 256 and st["zc_mask"] == 3
+        print("closed form over", np_, "rows", flush=True)
+        b0 = H["b0"].array.astype(np.int64)
+        b1 = H["b1"].array.astype(np.int64)
+        exp = [0, 0, 0, 0, 0]
+        cr = st["chunk_rows"]
+        hit = np.empty(cr, np.int64)
+        for c in range(np_ // cr):
+            r0 = c * cr
+            datagen.fill_probe_fk(datagen.SEED_STREAM, datagen.COL_BKEY, nb, 0.1, hit_row=hit, row0=r0)
+            h = hit >= 0
+            rows = hit[h]
+            vals = [int(h.sum()), int(b0[rows].sum()), int(b1[rows].sum()),
+                    int(H["p0"].array[r0:r0 + cr][h].sum()), int(H["p1"].array[r0:r0 + cr][h].sum())]
+            if c in (0, 77, np_ // cr - 1):
+                assert per[c] == [v % M64 for v in vals], f"chunk {c}"
+            exp = [e + v for e, v in zip(exp, vals)]
+        assert tot == [e % M64 for e in exp]
+        assert [sum(x) % M64 for x in zip(*per)] == tot
+    finally:
+        for h in H.values():
+            h.free()
