@@ -319,6 +319,27 @@ typedef struct {
  */
 vx_status vx_partition(vx_ctx* ctx, const vx_partition_desc* desc, vx_partition_out* out);
 
+/* ------------------------------------------------------------------------ CDF model kernels */
+
+/*
+ * The kernels behind VX_PART_LEARNED, exported so their numerics can be checked on their
+ * own.  The model is y(x) = b2 + sum_{j<64} w2_j * relu(w1_j * x + b1_j) in FP32, with
+ * parameters laid out as float[193] = {w1[64], b1[64], w2[64], b2} in host memory; x, t are
+ * n floats in device or pinned host memory; outputs are host arrays.
+ *
+ * vx_cdf_loss_grad: the mean squared error (1/n) sum (y_i - t_i)^2 and its gradient, from
+ *   one forward/backward pass (relu'(0) = 0); gradient accumulated in FP64 in a fixed order
+ *   and rounded to FP32.  Deterministic.
+ * vx_cdf_forward: y_i for every x_i (the evaluation used to place splitters).
+ * vx_cdf_train: `steps` full-batch Adam steps (beta 0.9 / 0.999, eps 1e-8, learning rate lr,
+ *   0 = 1e-2) from the given parameters, updated in place; *final_loss = loss after training.
+ */
+vx_status vx_cdf_loss_grad(vx_ctx* ctx, const float* x, const float* t, uint64_t n,
+                           const float* params, float* grad, double* loss);
+vx_status vx_cdf_forward(vx_ctx* ctx, const float* x, uint64_t n, const float* params, float* y);
+vx_status vx_cdf_train(vx_ctx* ctx, const float* x, const float* t, uint64_t n, float* params,
+                       uint32_t steps, float lr, double* final_loss);
+
 #ifdef __cplusplus
 }
 #endif

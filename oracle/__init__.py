@@ -80,6 +80,8 @@ def _load():
     lib.or_splitters_from_cdf.argtypes = [C.POINTER(C.c_int64), f64p, C.c_uint64, C.c_uint32,
                                           C.POINTER(C.c_int64)]
     lib.or_splitters_from_cdf.restype = C.c_uint32
+    lib.or_sample_bernoulli.argtypes = [_Col, C.c_uint64, C.c_uint64, C.c_double, C.POINTER(C.c_int64)]
+    lib.or_sample_bernoulli.restype = C.c_uint64
     _lib = lib
     return lib
 
@@ -264,3 +266,17 @@ def splitters_from_cdf(sorted_keys, y, nparts):
     n = _load().or_splitters_from_cdf(_ptr(s, C.c_int64), _ptr(y, C.c_double), len(s), nparts,
                                       _ptr(out, C.c_int64))
     return out[:n].copy()
+
+
+def sample_bernoulli(keys, seed, frac):
+    """Keys of the rows kept by the SplitMix64 Bernoulli draw, in row order."""
+    out = np.zeros(max(1, len(keys)), dtype=np.int64)
+    m = _load().or_sample_bernoulli(_col(keys), len(keys), int(seed), float(frac), _ptr(out, C.c_int64))
+    return out[:m].copy()
+
+
+def feature_scale(kmin, kmax):
+    """FP32 scale 1 / (L * 2^23) with L = floor(log2(min(kmax - kmin, 2^63 - 1) + 1)) + 1."""
+    r = min((int(kmax) - int(kmin)), (1 << 63) - 1)
+    L = (r + 1).bit_length()
+    return np.float32(1.0 / (L * 8388608.0))

@@ -320,20 +320,41 @@ double or_late_mat_threshold(double elem_bytes, double line_bytes, double n_exch
 }
 
 /*
+ * Bernoulli row sample: row i is kept iff the (i+1)-th output of the SplitMix64 generator
+ * (Steele, Lea and Flood, "Fast splittable pseudorandom number generators", OOPSLA 2014)
+ * started from state `seed` is below frac * 2^64.  Keys of kept rows are written in row
+ * order; returns their count.
+ */
+uint64_t or_sample_bernoulli(or_col keys, uint64_t n, uint64_t seed, double frac, int64_t* out) {
+  uint64_t thr = frac >= 1.0 ? ~0ULL : (uint64_t)(frac * 18446744073709551616.0);
+  uint64_t state = seed, m = 0;
+  for (uint64_t i = 0; i < n; ++i) {
+    state += 0x9E3779B97F4A7C15ULL;
+    uint64_t z = state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z ^= z >> 31;
+    if (z < thr) out[m++] = at(keys, i);
+  }
+  return m;
+}
+
+/*
  * Learned range-partition splitters: a cumulative-distribution model of the
  * key sample (not in the paper, which leaves skew handling out of scope).
  *
  * Feature of a key: a piecewise-linear base-2 logarithm of its offset above
  * the sample minimum (Mitchell's approximation: the exponent plus the next 23
  * mantissa bits, read as a fixed-point number), as an FP32 value in [0, 1):
- *   u = key - kmin (0 if key < kmin), l = floor(log2(u + 1)),
+ *   u = key - kmin (0 if key < kmin, at most 2^63 - 1), l = floor(log2(u + 1)),
  *   m = the 23 bits of (u + 1) below its leading one,
  *   x = float(l * 2^23 + m) * scale, scale = 1 / (L * 2^23) as FP32.
  * Exact in FP32 up to the single int->float rounding (round to nearest even).
  */
 float or_cdf_feature(int64_t key, int64_t kmin, float scale) {
   uint64_t u = key < kmin ? 0ULL : (uint64_t)key - (uint64_t)kmin;
-  uint64_t v = u + 1;  /* u < 2^63 for keys in the sample's range */
+  if (u > 0x7FFFFFFFFFFFFFFFULL) u = 0x7FFFFFFFFFFFFFFFULL;   /* saturate: v <= 2^63 */
+  uint64_t v = u + 1;
   uint32_t l = 63;
   while (!((v >> l) & 1ULL)) --l;
   uint64_t m = l >= 23 ? (v >> (l - 23)) & 0x7FFFFFULL : (v << (23 - l)) & 0x7FFFFFULL;

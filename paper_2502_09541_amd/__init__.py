@@ -146,7 +146,8 @@ class PartitionOut(C.Structure):
 
 EXPORTS = ["vx_ctx_create", "vx_ctx_destroy", "vx_last_error", "vx_ctx_arena_used", "vx_host_alloc",
            "vx_host_free", "vx_build", "vx_table_destroy", "vx_probe_stream", "vx_join_agg",
-           "vx_partition"]
+           "vx_partition", "vx_cdf_loss_grad", "vx_cdf_forward", "vx_cdf_train"]
+N_MODEL_PARAMS = 193
 
 
 def lib():
@@ -170,8 +171,13 @@ def lib():
     L.vx_probe_stream.argtypes = [vp, vp, C.POINTER(ProbeDesc), C.POINTER(Agg), C.POINTER(Stats)]
     L.vx_join_agg.argtypes = [vp, C.POINTER(JoinDesc), C.POINTER(JoinOut)]
     L.vx_partition.argtypes = [vp, C.POINTER(PartitionDesc), C.POINTER(PartitionOut)]
+    fp = C.POINTER(C.c_float)
+    L.vx_cdf_loss_grad.argtypes = [vp, vp, vp, C.c_uint64, fp, fp, C.POINTER(C.c_double)]
+    L.vx_cdf_forward.argtypes = [vp, vp, C.c_uint64, fp, fp]
+    L.vx_cdf_train.argtypes = [vp, vp, vp, C.c_uint64, fp, C.c_uint32, C.c_float, C.POINTER(C.c_double)]
     for name in ("vx_ctx_create", "vx_ctx_destroy", "vx_host_alloc", "vx_host_free", "vx_build",
-                 "vx_table_destroy", "vx_probe_stream", "vx_join_agg", "vx_partition"):
+                 "vx_table_destroy", "vx_probe_stream", "vx_join_agg", "vx_partition",
+                 "vx_cdf_loss_grad", "vx_cdf_forward", "vx_cdf_train"):
         getattr(L, name).restype = st
     _lib = L
     return L
@@ -297,6 +303,92 @@ class Context:
         _check(lib().vx_join_agg(self.h, C.byref(d), C.byref(out)))
         return out.agg.to_list(nbp + npp), out.stats.as_dict()
 
+    # ------------------------------------------------------------------ partitioning
+    def partition(self, key, pays=(), method="radix_hash", n_parts=0, shift=0, splitters=None,
+                  sample_frac=0.0, seed=0, train_steps=0, lr=0.0, out_key=None, out_pays=None,
+                  n_parts_cap=4096):
+        """vx_partition. Returns a dict: method_used, n_parts, hist, boundary, splitters,
+        imbalance, est_imbalance_radix, est_imbalance_range, final_loss, model."""
+        pa, npay = _cols(pays)
+        spl = None
+        if splitters is not None:
+            spl = np.ascontiguousarray(splitters, dtype=np.int64)
+        opts = PartOpts(PART_METHODS[method] if isinstance(method, str) else int(method), int(n_parts),
+                        int(shift), int(train_steps), float(sample_frac), float(lr), int(seed),
+                        spl.ctypes.data_as(C.POINTER(C.c_int64)) if spl is not None and len(spl) else None,
+                        0 if spl is None else len(spl), 0)
+        outp = None
+        okey = None
+        if out_key is not None:
+            okey = col(out_key).data
+            if out_pays:
+                outp = (C.c_void_p * len(out_pays))(*[col(o).data for o in out_pays])
+        d = PartitionDesc(col(key), pa, npay, 0, _len(key), opts, okey, outp)
+        hist = np.zeros(n_parts_cap, np.uint64)
+        bnd = np.zeros(n_parts_cap + 1, np.uint64)
+        sp = np.zeros(n_parts_cap, np.int64)
+        model = np.zeros(N_MODEL_PARAMS, np.float32)
+        o = PartitionOut()
+        o.hist = hist.ctypes.data_as(C.POINTER(C.c_uint64))
+        o.boundary = bnd.ctypes.data_as(C.POINTER(C.c_uint64))
+        o.splitters = sp.ctypes.data_as(C.POINTER(C.c_int64))
+        o.n_parts_cap = n_parts_cap
+        o.model = model.ctypes.data_as(C.POINTER(C.c_float))
+        _check(lib().vx_partition(self.h, C.byref(d), C.byref(o)))
+        P = int(o.n_parts)
+        return dict(method_used=int(o.method_used), n_parts=P, hist=hist[:P].copy(),
+                    boundary=bnd[:P + 1].copy(), splitters=sp[:int(o.n_splitters)].copy(),
+                    imbalance=o.imbalance, est_imbalance_radix=o.est_imbalance_radix,
+                    est_imbalance_range=o.est_imbalance_range, final_loss=o.final_loss, model=model)
+
+    # ------------------------------------------------------------------ CDF model kernels
+    def cdf_loss_grad(self, x, t, params):
+        p = np.ascontiguousarray(params, np.float32)
+        g = np.zeros(N_MODEL_PARAMS, np.float32)
+        loss = C.c_double()
+        _check(lib().vx_cdf_loss_grad(self.h, _fptr(x), _fptr(t), _len(x), p.ctypes.data_as(C.POINTER(C.c_float)),
+                                      g.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss)))
+        return loss.value, g
+
+    def cdf_forward(self, x, params):
+        p = np.ascontiguousarray(params, np.float32)
+        y = np.zeros(_len(x), np.float32)
+        _check(lib().vx_cdf_forward(self.h, _fptr(x), _len(x), p.ctypes.data_as(C.POINTER(C.c_float)),
+                                    y.ctypes.data_as(C.POINTER(C.c_float))))
+        return y
+
+    def cdf_train(self, x, t, params, steps, lr=0.0):
+        p = np.array(params, np.float32)
+        loss = C.c_double()
+        _check(lib().vx_cdf_train(self.h, _fptr(x), _fptr(t), _len(x), p.ctypes.data_as(C.POINTER(C.c_float)),
+                                  int(steps), float(lr), C.byref(loss)))
+        return p, loss.value
+
+    def join_partitioned(self, bkey, bpays, pkey, method="auto", n_parts=0, seed=0, sample_frac=0.0,
+                         train_steps=0, lr=0.0, splitters=None, per_partition=False):
+        """Partitioned join (pre-aggregated build). Returns ([count, sums...], stats, method_used
+        [, per-partition aggregate lists])."""
+        bp, nbp = _cols(bpays)
+        d = JoinDesc()
+        d.kind = VX_JOIN_PARTITIONED
+        pj = d.u.part
+        pj.build = BuildDesc(col(bkey), bp, nbp, VX_PREAGG, _len(bkey), 0.0, 0)
+        cap = 4096 if per_partition else 0
+        pa = (Agg * cap)() if cap else None
+        pj.probe = ProbeDesc(col(pkey), None, 0, VX_LATE_AUTO, _len(pkey), 0, 0, 0, pa, cap)
+        spl = None if splitters is None else np.ascontiguousarray(splitters, np.int64)
+        pj.part = PartOpts(PART_METHODS[method] if isinstance(method, str) else int(method), int(n_parts), 0,
+                           int(train_steps), float(sample_frac), float(lr), int(seed),
+                           spl.ctypes.data_as(C.POINTER(C.c_int64)) if spl is not None and len(spl) else None,
+                           0 if spl is None else len(spl), 0)
+        out = JoinOut()
+        _check(lib().vx_join_agg(self.h, C.byref(d), C.byref(out)))
+        res = (out.agg.to_list(nbp), out.stats.as_dict(), int(out.part_method_used))
+        if per_partition:
+            P = int(out.stats.n_parts)
+            return res + ([pa[i].to_list(nbp) for i in range(P)],)
+        return res
+
     def join_star(self, dims, fks, meas, groups_cap=4096, late_mat=VX_LATE_AUTO, chunk_rows=0):
         """Star join + GROUP BY. dims: list of {key, filt, lo, hi, group (or None)}.
         Returns (g [n,2] int64, count [n] uint64, sums [n, nmeas] uint64, stats), sorted by (g0, g1)."""
@@ -330,6 +422,16 @@ def _star_call(ctx, dims, fks, meas, groups_cap, late_mat, chunk_rows):
     sums = np.array([[rows[i].sum[c] for c in range(len(meas))] for i in range(n)],
                     dtype=np.uint64).reshape(n, len(meas))
     return g, cnt, sums, out.stats.as_dict()
+
+
+def _fptr(x):
+    """Device address of a float32 CUDA tensor, or of a pinned float32 HostBuffer."""
+    if isinstance(x, HostBuffer):
+        return x.ptr
+    import torch
+    if isinstance(x, torch.Tensor) and x.dtype == torch.float32 and x.is_contiguous():
+        return x.data_ptr()
+    raise TypeError("float inputs must be contiguous float32 CUDA tensors or HostBuffers")
 
 
 def _len(x):

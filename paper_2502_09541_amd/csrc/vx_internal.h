@@ -106,10 +106,18 @@ struct vx_ctx {
   uint64_t l2_bytes = 4u << 20;
   // pinned host mirror of results
   uint64_t* host_acc = nullptr;
+  // device-to-host copies of intermediate results (partition pass write-back)
+  hipStream_t d2h = nullptr;
+  // pinned host memory for intermediates that live in CPU memory (grow-only, kept until destroy)
+  uint8_t* host_scratch = nullptr;
+  uint64_t host_scratch_bytes = 0;
   std::vector<hipEvent_t> ev_pool;
 };
 
 namespace vx {
+
+// Pinned host scratch of at least `bytes` (grows by reallocation; contents not kept).
+vx_status host_scratch(vx_ctx* ctx, uint64_t bytes, uint8_t** out);
 
 vx_status classify(const vx_ctx* ctx, const vx_col& c, uint64_t n, ColInfo* out, const char* what);
 int elsize_of(int32_t type);

@@ -171,33 +171,6 @@ constexpr int kPreaggTile = 4096;
 constexpr int kPreaggProbe = 32;
 
 template <typename K>
-__device__ __forceinline__ void global_preagg_add(const TableView& t, K k, unsigned long long cnt,
-                                                  const unsigned long long* sums,
-                                                  unsigned int* flags) {
-  using U = typename KeyTraits<K>::U;
-  const U kEmpty = KeyTraits<K>::kEmpty;
-  U kb = (U)k;
-  if (kb == kEmpty) {
-    atomicAdd(t.side, cnt);
-    for (uint32_t p = 0; p < t.n_pay; ++p) atomicAdd(t.side + 1 + p, sums[p]);
-    return;
-  }
-  uint64_t h = slot_of(key_bits(k), t.log2cap);
-  for (uint64_t step = 0; step <= t.mask; ++step) {
-    uint8_t* slot = t.slots + (h << t.slot_shift);
-    U prev = atomicCAS((U*)slot, kEmpty, kb);
-    if (prev == kEmpty || prev == kb) {
-      unsigned long long* w = (unsigned long long*)(slot + 8);
-      atomicAdd(w, cnt);
-      for (uint32_t p = 0; p < t.n_pay; ++p) atomicAdd(w + 1 + p, sums[p]);
-      return;
-    }
-    h = (h + 1) & t.mask;
-  }
-  atomicOr(flags, kFlagFull);
-}
-
-template <typename K>
 __global__ void __launch_bounds__(256) k_build_preagg(TableView t, BuildCols c, uint64_t n,
                                                       unsigned int* flags) {
   __shared__ unsigned long long lkey[kPreaggLds];

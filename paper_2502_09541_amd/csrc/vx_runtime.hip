@@ -140,6 +140,28 @@ vx_status classify(const vx_ctx* ctx, const vx_col& c, uint64_t n, ColInfo* out,
   return VX_ENOTPINNED;
 }
 
+vx_status host_scratch(vx_ctx* ctx, uint64_t bytes, uint8_t** out) {
+  if (ctx->host_scratch_bytes < bytes) {
+    if (ctx->host_scratch) {
+      VX_HIP(hipStreamSynchronize(ctx->d2h));
+      VX_HIP(hipHostFree(ctx->host_scratch));
+      ctx->host_scratch = nullptr;
+      ctx->host_scratch_bytes = 0;
+    }
+    void* p = nullptr;
+    hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocMapped | hipHostMallocPortable);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("host scratch of %llu bytes: %s", (unsigned long long)bytes, hipGetErrorString(e));
+      return VX_ENOMEM;
+    }
+    ctx->host_scratch = (uint8_t*)p;
+    ctx->host_scratch_bytes = bytes;
+  }
+  *out = ctx->host_scratch;
+  return VX_OK;
+}
+
 hipEvent_t get_event(vx_ctx* ctx) {
   if (!ctx->ev_pool.empty()) {
     hipEvent_t e = ctx->ev_pool.back();
@@ -233,9 +255,11 @@ vx_status vx_ctx_create(int device, void* arena, uint64_t arena_bytes, void* str
     c->own_compute = true;
   }
   if (hipStreamCreateWithFlags(&c->copy, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->d2h, hipStreamNonBlocking) != hipSuccess ||
       hipHostMalloc((void**)&c->host_acc, c->dev_acc_words * 8, hipHostMallocDefault) != hipSuccess) {
     if (c->own_compute) (void)hipStreamDestroy(c->compute);
     if (c->copy) (void)hipStreamDestroy(c->copy);
+    if (c->d2h) (void)hipStreamDestroy(c->d2h);
     delete c;
     set_error("vx_ctx_create: stream or pinned scratch creation failed");
     return VX_EHIP;
@@ -251,8 +275,11 @@ vx_status vx_ctx_destroy(vx_ctx* c) {
   (void)hipStreamSynchronize(c->copy);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->own_compute) (void)hipStreamDestroy(c->compute);
+  (void)hipStreamSynchronize(c->d2h);
   (void)hipStreamDestroy(c->copy);
+  (void)hipStreamDestroy(c->d2h);
   (void)hipHostFree(c->host_acc);
+  if (c->host_scratch) (void)hipHostFree(c->host_scratch);
   delete c;
   return VX_OK;
 }

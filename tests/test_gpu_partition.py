@@ -1,0 +1,284 @@
+"""GPU parity of partitioning and of the CDF-model kernels against the oracle, via the C ABI.
+
+Partition ids, histograms, boundary arrays and the stable scatter are integer results and
+must match exactly.  Splitters are integers chosen from FP32 model values: the test feeds
+the GPU's own FP32 model outputs to the oracle's splitter rule, so both sides take the same
+decision in the same precision, and the result must match exactly.
+"""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+GiB = 1 << 30
+F01 = float(np.float32(0.01))   # the sampling fraction as the library stores it (FP32)
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu):
+    c = gpu.Context(4 * GiB)
+    yield c
+    c.close()
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def pinned(vx, a):
+    hb = vx.HostBuffer(len(a), a.dtype)
+    hb.array[:] = a
+    return hb
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _keys(n, seed=0):
+    rng = np.random.default_rng(seed)
+    k = np.concatenate([rng.zipf(1.3, n // 2), rng.integers(-2**62, 2**62, n - n // 2)]).astype(np.int64)
+    rng.shuffle(k)
+    return k
+
+
+def _expect(ids, P, key, pays):
+    order, b = oracle.cluster_boundary(ids, P)
+    return oracle.histogram(ids, P), b, key[order.astype(np.int64)], [p[order.astype(np.int64)] for p in pays]
+
+
+def _torch_empty_like(a):
+    import torch
+    return torch.empty(len(a), dtype=torch.int64 if a.dtype == np.int64 else torch.int32, device="cuda")
+
+
+@pytest.mark.parametrize("P", [1, 2, 16, 1024])
+def test_radix_hash_device_scatter(gpu, ctx, P):
+    key = _keys(300_007, 1)
+    pay = [np.arange(len(key), dtype=np.int64) * 7, (np.arange(len(key)) % 1000).astype(np.int32)]
+    ok, op = _torch_empty_like(key), [_torch_empty_like(p) for p in pay]
+    _say("radix hash device", P)
+    r = ctx.partition(dev(key), [dev(p) for p in pay], method="radix_hash", n_parts=P, out_key=ok, out_pays=op)
+    log2p = (P - 1).bit_length()
+    h, b, ck, cp = _expect(oracle.part_ids_hash(key, log2p), P, key, pay)
+    assert r["n_parts"] == P and np.array_equal(r["hist"], h) and np.array_equal(r["boundary"], b)
+    assert np.array_equal(ok.cpu().numpy(), ck)
+    for o, e in zip(op, cp):
+        assert np.array_equal(o.cpu().numpy(), e)
+
+
+def test_radix_bits_host_streamed_scatter(gpu, ctx, monkeypatch):
+    """Host-resident input in many chunks, written to host memory by zero-copy stores."""
+    monkeypatch.setenv("VX_CHUNK_BYTES", str(8 * 40_000))
+    key = _keys(1_000_003, 2)
+    pay = [np.arange(len(key), dtype=np.int64)]
+    hk, hp = pinned(gpu, key), [pinned(gpu, p) for p in pay]
+    ok, op = gpu.HostBuffer(len(key), np.int64), [gpu.HostBuffer(len(key), np.int64)]
+    _say("radix bits host streamed")
+    r = ctx.partition(hk, hp, method="radix_bits", n_parts=64, shift=3, out_key=ok, out_pays=op)
+    h, b, ck, cp = _expect(oracle.part_ids_bits(key, 3, 6), 64, key, pay)
+    assert np.array_equal(r["hist"], h) and np.array_equal(r["boundary"], b)
+    assert np.array_equal(ok.array, ck) and np.array_equal(op[0].array, cp[0])
+
+
+def test_range_given_splitters_and_hist_only(gpu, ctx):
+    key = _keys(200_000, 3)
+    spl = np.array([-2**61, -5, 0, 1, 2, 3, 10, 1000, 2**40], np.int64)
+    _say("range given")
+    r = ctx.partition(dev(key), method="range", splitters=spl)
+    ids = oracle.part_ids_range(key, spl)
+    assert r["n_parts"] == len(spl) + 1
+    assert np.array_equal(r["hist"], oracle.histogram(ids, len(spl) + 1))
+    assert np.array_equal(r["boundary"], oracle.cluster_boundary(ids, len(spl) + 1)[1])
+    with pytest.raises(gpu.VxError):
+        ctx.partition(dev(key), method="range", splitters=spl[::-1].copy())
+
+
+def test_partition_edges(gpu, ctx):
+    _say("partition edges")
+    e = np.zeros(0, np.int64)
+    r = ctx.partition(dev(np.zeros(1, np.int64))[:0], method="radix_hash", n_parts=8)
+    assert r["hist"].sum() == 0 and r["boundary"].tolist() == [0] * 9
+    same = np.full(5000, 42, np.int64)
+    r = ctx.partition(dev(same), method="radix_hash", n_parts=8)
+    assert sorted(r["hist"].tolist()) == [0] * 7 + [5000]
+    assert r["imbalance"] == 8.0
+    del e
+
+
+def test_quantile_splitters_exact(gpu, ctx):
+    """Sample (SplitMix64 Bernoulli), GPU radix sort, mid-CDF targets, splitter rule:
+    identical to the oracle's sample, sort, targets and rule."""
+    rng = np.random.default_rng(4)
+    key = np.concatenate([rng.zipf(1.1, 1_500_000), rng.integers(1, 2**40, 500_000)]).astype(np.int64)
+    rng.shuffle(key)
+    seed, P = 12345, 64
+    _say("quantile splitters")
+    r = ctx.partition(pinned(gpu, key), method="quantile", n_parts=P, seed=seed, sample_frac=0.01)
+    s = np.sort(oracle.sample_bernoulli(key, seed, F01))
+    t = oracle.cdf_targets(s).astype(np.float64)
+    exp = oracle.splitters_from_cdf(s, t, P)
+    assert np.array_equal(r["splitters"], exp)
+    ids = oracle.part_ids_range(key, exp)
+    assert np.array_equal(r["hist"], oracle.histogram(ids, len(exp) + 1))
+    # the heavy key 1 (about 30% of rows) carries several quantiles: a singleton partition
+    assert 1 in exp.tolist() and 2 in exp.tolist()
+
+
+def test_learned_splitters_exact(gpu, ctx):
+    """The trained model's FP32 outputs, fed to the oracle's splitter rule over the oracle's own
+    sample and features, give the GPU's splitters exactly."""
+    import torch
+    rng = np.random.default_rng(5)
+    key = np.concatenate([rng.zipf(1.1, 800_000), rng.integers(1, 2**40, 200_000)]).astype(np.int64)
+    seed, P = 777, 32
+    _say("learned splitters")
+    r = ctx.partition(dev(key), method="learned", n_parts=P, seed=seed, sample_frac=0.01, train_steps=60)
+    s = np.sort(oracle.sample_bernoulli(key, seed, F01))
+    x = oracle.cdf_feature(s, s[0], oracle.feature_scale(s[0], s[-1]))
+    y = ctx.cdf_forward(torch.from_numpy(x).cuda(), r["model"]).astype(np.float64)
+    exp = oracle.splitters_from_cdf(s, y, P)
+    assert np.array_equal(r["splitters"], exp)
+    assert r["final_loss"] > 0 and np.isfinite(r["final_loss"])
+    assert np.array_equal(r["hist"], oracle.histogram(oracle.part_ids_range(key, exp), len(exp) + 1))
+
+
+def _grad_bound(params, x, t):
+    """Rounding bound for the GPU gradient, per component.
+
+    The GPU evaluates z = fma(w1, x, b1) (one rounding), h = relu(z), p = w2 * h (one rounding)
+    and y = b2 + (butterfly sum of 64 p's: 6 roundings) in FP32, so
+    |dy_i| <= g6 * (|b2| + sum_j |w2_j h_ij|) + 2u * sum_j |w2_j h_ij|, u = 2^-24, g6 = 7u.
+    Every gradient term is (2/n) e_i * a_ic with a_ic in {h_ij, w2_j [z>0], w2_j x_i [z>0], 1};
+    the FP64 accumulation adds nothing visible, and the result is rounded to FP32 (u |g|).
+    Hence |dg_c| <= (2/n) sum_i (|dy_i| |a_ic| + |e_i| |da_ic|) + u |g_c|, with
+    |da_ic| <= 2u |a_ic| covering the rounded h and z."""
+    H = 64
+    u = 2.0**-24
+    w1, b1, w2, b2 = (params[:H].astype(np.float64), params[H:2 * H].astype(np.float64),
+                      params[2 * H:3 * H].astype(np.float64), float(params[3 * H]))
+    xd = x.astype(np.float64)[:, None]
+    z = xd * w1 + b1
+    h = np.maximum(z, 0)
+    S = np.abs(b2) + np.abs(w2 * h).sum(1)
+    y = b2 + (w2 * h).sum(1)
+    e = np.abs(y - t.astype(np.float64))
+    dy = 7 * u * S + 2 * u * np.abs(w2 * h).sum(1)
+    n = len(x)
+    act = (z > 0).astype(np.float64)
+    a_w1 = np.abs(w2) * np.abs(xd) * act
+    a_b1 = np.abs(w2) * act
+    a_w2 = h
+    term = lambda a: (2 / n) * ((dy[:, None] * a).sum(0) + (e[:, None] * 2 * u * a).sum(0))
+    return np.concatenate([term(a_w1), term(a_b1), term(a_w2), [(2 / n) * dy.sum()]]), np.abs(z).min()
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_cdf_gradient_parity(gpu, ctx, seed):
+    import torch
+    rng = np.random.default_rng(seed)
+    n = 50_000
+    x = np.sort(rng.random(n)).astype(np.float32)
+    t = ((np.arange(n) + 0.5) / n).astype(np.float32)
+    p = np.concatenate([rng.normal(1, 0.3, 64), -rng.random(64), rng.normal(0, 0.05, 64), [0.01]]).astype(np.float32)
+    _say("cdf gradient parity", seed)
+    loss_g, g_g = ctx.cdf_loss_grad(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda(), p)
+    loss_o, g_o = oracle.mlp_loss_grad(p, x, t)
+    bound, zmin = _grad_bound(p, x, t)
+    assert zmin > 1e-6    # no activation flips within rounding
+    u = 2.0**-24
+    err = np.abs(g_g.astype(np.float64) - g_o)
+    assert np.all(err <= bound + u * np.abs(g_o) + 1e-30), (err / (bound + 1e-30)).max()
+    assert abs(loss_g - loss_o) <= 1e-6 * loss_o
+
+
+def test_cdf_train_deterministic_and_descends(gpu, ctx):
+    import torch
+    rng = np.random.default_rng(3)
+    s = np.sort(rng.zipf(1.2, 100_000)).astype(np.int64)
+    x = oracle.cdf_feature(s, s[0], oracle.feature_scale(s[0], s[-1]))
+    t = oracle.cdf_targets(s)
+    H = 64
+    p0 = np.concatenate([np.ones(H), -np.arange(H) / H, np.full(H, 1 / H), [0]]).astype(np.float32)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    _say("cdf train")
+    p1, l1 = ctx.cdf_train(xd, td, p0, 100)
+    p2, l2 = ctx.cdf_train(xd, td, p0, 100)
+    assert np.array_equal(p1, p2) and l1 == l2
+    l0, _ = oracle.mlp_loss_grad(p0, x, t)
+    assert l1 < 0.5 * l0
+    # one step against the oracle's Adam step from the oracle's gradient
+    q, _ = ctx.cdf_train(xd, td, p0, 1)
+    _, g = oracle.mlp_loss_grad(p0, x, t)
+    qo, m, v = p0.copy(), np.zeros_like(p0), np.zeros_like(p0)
+    oracle.adam_step(qo, m, v, g.astype(np.float32), 1)
+    big = np.abs(g) > 1e-3 * np.abs(g).max()     # sign of tiny components is rounding-dependent
+    assert np.allclose(q[big], qo[big], rtol=0, atol=1e-6)
+
+
+def test_auto_method_reports_estimates(gpu, ctx):
+    rng = np.random.default_rng(8)
+    key = rng.zipf(1.1, 2_000_000).astype(np.int64)
+    _say("auto method")
+    r = ctx.partition(dev(key), method="auto", n_parts=64, seed=5, train_steps=40)
+    assert r["est_imbalance_radix"] > 1.0 and r["est_imbalance_range"] > 0
+    assert r["method_used"] in (1, 3)
+    assert r["hist"].sum() == len(key)
+
+
+# ----------------------------------------------------------------------------- partitioned join
+
+def _zipf_join(n_b, n_p, seed):
+    rng = np.random.default_rng(seed)
+    bk = rng.zipf(1.1, n_b).astype(np.int64)
+    bp = rng.integers(0, 1 << 32, n_b).astype(np.int64)
+    pk = rng.zipf(1.1, n_p).astype(np.int64)
+    return bk, bp, pk
+
+
+@pytest.mark.parametrize("method", ["radix_hash", "radix_bits", "learned", "quantile", "untrained", "auto"])
+def test_partitioned_join_methods_exact(gpu, ctx, method, monkeypatch):
+    """Every partitioner gives the oracle's exact aggregates (many chunks per side)."""
+    monkeypatch.setenv("VX_CHUNK_BYTES", str(8 * 50_000))
+    bk, bp, pk = _zipf_join(300_000, 1_000_001, 6)
+    _say("partitioned join", method)
+    got, st, used = ctx.join_partitioned(pinned(gpu, bk), [pinned(gpu, bp)], pinned(gpu, pk), method=method,
+                                         n_parts=64, seed=9, train_steps=80)
+    assert got == oracle.join_agg(bk, [bp], pk, [])
+    if method in ("learned", "quantile"):
+        assert st["singleton_rows"] > 0.1 * (len(bk) + len(pk))
+    if method == "radix_hash":
+        assert st["singleton_rows"] == 0 and st["n_parts"] == 64
+
+
+def test_partitioned_join_per_partition_radix(gpu, ctx):
+    bk, bp, pk = _zipf_join(100_000, 300_000, 7)
+    _say("partitioned per-partition")
+    got, st, used, per = ctx.join_partitioned(dev(bk), [dev(bp)], dev(pk), method="radix_hash", n_parts=16,
+                                              per_partition=True)
+    ib, ip = oracle.part_ids_hash(bk, 4), oracle.part_ids_hash(pk, 4)
+    for p in range(16):
+        assert per[p] == oracle.join_agg(bk[ib == p], [bp[ib == p]], pk[ip == p], [])
+    assert [sum(x) % (1 << 64) for x in zip(*per)] == got
+
+
+def test_partitioned_join_edges(gpu, ctx):
+    i64 = np.iinfo(np.int64)
+    _say("partitioned edges")
+    bk = np.array([i64.min, i64.min, 5, 5, 5, i64.max], np.int64)
+    bp = np.array([1, 2, 3, 4, 5, 6], np.int64)
+    pk = np.array([i64.min, 5, 5, i64.max, 7], np.int64)
+    for m in ("radix_hash", "quantile"):
+        got = ctx.join_partitioned(dev(bk), [dev(bp)], dev(pk), method=m, n_parts=4, sample_frac=1.0)[0]
+        assert got == oracle.join_agg(bk, [bp], pk, [])
+    e = np.zeros(0, np.int64)
+    assert ctx.join_partitioned(dev(bk), [dev(bp)], dev(np.zeros(1, np.int64))[:0], method="radix_hash",
+                                n_parts=4)[0] == [0, 0]
+    same = np.full(10_000, 3, np.int64)
+    got = ctx.join_partitioned(dev(same), [dev(same)], dev(same[:77]), method="learned", n_parts=8,
+                               sample_frac=0.5, train_steps=10)[0]
+    assert got == oracle.join_agg(same, [same], same[:77], [])
+    del e
