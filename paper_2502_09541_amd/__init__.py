@@ -389,6 +389,25 @@ class Context:
             return res + ([pa[i].to_list(nbp) for i in range(P)],)
         return res
 
+    def join_batch(self, bkeys, bpays, pkeys, mode=0, tile_rows=0, block=0, load_factor=0.0):
+        """Batched joins (device-resident). bpays entries may be None. Returns
+        ([[count, sum] per job], stats)."""
+        J = len(bkeys)
+        bk = (Col * max(1, J))(*[col(x) for x in bkeys])
+        bp = (Col * max(1, J))(*[col(x) if x is not None else Col(None, VX_I32, 0) for x in bpays])
+        pk = (Col * max(1, J))(*[col(x) for x in pkeys])
+        nb = (C.c_uint64 * max(1, J))(*[_len(x) for x in bkeys])
+        npr = (C.c_uint64 * max(1, J))(*[_len(x) for x in pkeys])
+        outs = (Agg * max(1, J))()
+        d = JoinDesc()
+        d.kind = VX_JOIN_BATCH
+        d.u.batch = BatchJoin(J, int(mode), bk, bp, nb, pk, npr, outs, int(tile_rows), int(block),
+                              float(load_factor), 0)
+        out = JoinOut()
+        self._keep_batch = (bk, bp, pk, nb, npr, outs, list(bkeys), list(bpays), list(pkeys))
+        _check(lib().vx_join_agg(self.h, C.byref(d), C.byref(out)))
+        return [outs[j].to_list(1) for j in range(J)], out.stats.as_dict()
+
     def join_star(self, dims, fks, meas, groups_cap=4096, late_mat=VX_LATE_AUTO, chunk_rows=0):
         """Star join + GROUP BY. dims: list of {key, filt, lo, hi, group (or None)}.
         Returns (g [n,2] int64, count [n] uint64, sums [n, nmeas] uint64, stats), sorted by (g0, g1)."""

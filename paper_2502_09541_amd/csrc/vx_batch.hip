@@ -1,0 +1,594 @@
+// Many independent device-resident joins in one persistent launch.
+//
+// The work is a queue of tiles, job by job: job j's build tiles, then its probe tiles.  Each
+// workgroup takes the next tile from a global counter.  A build tile inserts its rows into the
+// job's table and then bumps the job's build counter (release); a probe tile first waits until
+// that counter reaches the job's build-tile count (acquire).  Every build tile a probe tile can
+// wait for was handed out earlier, to a workgroup that is already running and never waits
+// itself, so the queue cannot deadlock whatever the grid size; the wait is still bounded and
+// raises an error flag if it ever expires.  The table init, the counter reset, the kernel and
+// the copy of the results are captured once in a HIP graph and replayed.  Tile size,
+// workgroup size and load factor come from a small autotuner that times candidates on the
+// batch itself and caches the winner per workload class (optionally in the file named by
+// VX_TUNE_CACHE).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "vx_device.h"
+
+namespace vx {
+
+struct BatchJob {
+  const void* bkey;
+  const void* bpay;
+  const void* pkey;
+  uint64_t nb, np;
+  uint8_t* slots;         // capacity slots of 8 (int32 key + int32 payload) or 16 bytes
+  uint64_t mask;
+  uint32_t log2cap;
+  uint32_t pay_size;      // 0 (no payload), 4 or 8
+  uint64_t tile0;         // first queue index of the job
+  uint32_t build_tiles, probe_tiles;
+  unsigned long long* side;   // sentinel-key record: count, payload sum
+};
+
+constexpr uint32_t kMaxBatchJobs = 4096;
+constexpr uint64_t kSpinLimit = 1ull << 26;
+
+template <typename K>
+__device__ __forceinline__ void batch_build_rows(const BatchJob& jb, uint64_t r0, uint64_t r1,
+                                                 uint32_t slot_shift, unsigned int* flags) {
+  using U = typename KeyTraits<K>::U;
+  const U kEmpty = KeyTraits<K>::kEmpty;
+  for (uint64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+    K k = ((const K*)jb.bkey)[i];
+    U kb = (U)k;
+    long long v = jb.pay_size ? load_signed(jb.bpay, i, jb.pay_size) : 0;
+    if (kb == kEmpty) {
+      unsigned long long prev = atomicAdd(jb.side, 1ull);
+      if (prev) atomicOr(flags, kFlagDup);
+      atomicAdd(jb.side + 1, (unsigned long long)v);
+      continue;
+    }
+    uint64_t h = slot_of(key_bits(k), jb.log2cap);
+    bool done = false;
+    for (uint64_t step = 0; step <= jb.mask; ++step) {
+      uint8_t* slot = jb.slots + (h << slot_shift);
+      U prev = atomicCAS((U*)slot, kEmpty, kb);
+      if (prev == kEmpty) {
+        if (jb.pay_size == 4) *(int*)(slot + sizeof(K)) = (int)v;
+        else if (jb.pay_size == 8) *(long long*)(slot + 8) = v;
+        done = true;
+        break;
+      }
+      if (prev == kb) {
+        atomicOr(flags, kFlagDup);
+        done = true;
+        break;
+      }
+      h = (h + 1) & jb.mask;
+    }
+    if (!done) atomicOr(flags, kFlagFull);
+  }
+}
+
+template <typename K>
+__device__ __forceinline__ void batch_probe_rows(const BatchJob& jb, uint64_t r0, uint64_t r1,
+                                                 uint32_t slot_shift, unsigned long long& cnt,
+                                                 unsigned long long& sum) {
+  using U = typename KeyTraits<K>::U;
+  const U kEmpty = KeyTraits<K>::kEmpty;
+  for (uint64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+    K k = __builtin_nontemporal_load(((const K*)jb.pkey) + i);
+    U kb = (U)k;
+    if (kb == kEmpty) {
+      unsigned long long c = jb.side[0];
+      cnt += c;
+      if (c) sum += jb.side[1];
+      continue;
+    }
+    uint64_t h = slot_of(key_bits(k), jb.log2cap);
+    for (uint64_t step = 0; step <= jb.mask; ++step) {
+      const uint8_t* slot = jb.slots + (h << slot_shift);
+      U sk = *(const U*)slot;
+      if (sk == kb) {
+        cnt += 1;
+        if (jb.pay_size == 4) sum += (unsigned long long)(long long)*(const int*)(slot + sizeof(K));
+        else if (jb.pay_size == 8) sum += (unsigned long long)*(const long long*)(slot + 8);
+        break;
+      }
+      if (sk == kEmpty) break;
+      h = (h + 1) & jb.mask;
+    }
+  }
+}
+
+__device__ __forceinline__ void block_add2(unsigned long long cnt, unsigned long long sum,
+                                           unsigned long long* out) {
+  __shared__ unsigned long long red[2][16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int o = 32; o > 0; o >>= 1) {
+    cnt += __shfl_xor(cnt, o, 64);
+    sum += __shfl_xor(sum, o, 64);
+  }
+  __syncthreads();
+  if (lane == 0) {
+    red[0][wave] = cnt;
+    red[1][wave] = sum;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    unsigned long long s = 0;
+    for (int w = 0; w < nw; ++w) s += red[threadIdx.x][w];
+    if (s) atomicAdd(out + threadIdx.x, s);
+  }
+}
+
+template <typename K>
+__global__ void __launch_bounds__(512) k_batch(const BatchJob* jobs, uint32_t n_jobs,
+                                               uint64_t total_tiles, uint32_t tile_rows,
+                                               uint32_t slot_shift, unsigned long long* next,
+                                               unsigned int* built, unsigned long long* acc,
+                                               unsigned int* flags) {
+  __shared__ unsigned long long tile0[kMaxBatchJobs];
+  __shared__ unsigned long long s_tile;
+  for (uint32_t j = threadIdx.x; j < n_jobs; j += blockDim.x) tile0[j] = jobs[j].tile0;
+  __syncthreads();
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = atomicAdd(next, 1ull);
+    __syncthreads();
+    const uint64_t t = s_tile;
+    __syncthreads();
+    if (t >= total_tiles) break;
+    uint32_t lo = 0, hi = n_jobs;
+    while (hi - lo > 1) {
+      uint32_t mid = (lo + hi) >> 1;
+      if (tile0[mid] <= t) lo = mid;
+      else hi = mid;
+    }
+    const BatchJob jb = jobs[lo];
+    const uint64_t local = t - jb.tile0;
+    if (local < jb.build_tiles) {
+      uint64_t r0 = local * tile_rows, r1 = r0 + tile_rows < jb.nb ? r0 + tile_rows : jb.nb;
+      batch_build_rows<K>(jb, r0, r1, slot_shift, flags);
+      __threadfence();                     // release this tile's table writes
+      __syncthreads();
+      if (threadIdx.x == 0) atomicAdd(built + lo, 1u);
+    } else {
+      if (threadIdx.x == 0) {
+        uint64_t spins = 0;
+        while (__hip_atomic_load(built + lo, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < jb.build_tiles) {
+          __builtin_amdgcn_s_sleep(2);
+          if (++spins > kSpinLimit) {
+            atomicOr(flags, kFlagFull);
+            break;
+          }
+        }
+      }
+      __syncthreads();
+      __threadfence();                     // acquire the build tiles' writes
+      uint64_t p = local - jb.build_tiles;
+      uint64_t r0 = p * tile_rows, r1 = r0 + tile_rows < jb.np ? r0 + tile_rows : jb.np;
+      unsigned long long cnt = 0, sum = 0;
+      batch_probe_rows<K>(jb, r0, r1, slot_shift, cnt, sum);
+      block_add2(cnt, sum, acc + 2 * lo);
+    }
+  }
+}
+
+// one job, two plain launches (the baseline): build kernel over its rows, probe kernel
+template <typename K>
+__global__ void k_job_build(BatchJob jb, uint32_t slot_shift, unsigned int* flags) {
+  uint64_t per = (jb.nb + gridDim.x - 1) / gridDim.x;
+  uint64_t r0 = blockIdx.x * per, r1 = r0 + per < jb.nb ? r0 + per : jb.nb;
+  if (r0 < r1) batch_build_rows<K>(jb, r0, r1, slot_shift, flags);
+}
+
+template <typename K>
+__global__ void k_job_probe(BatchJob jb, uint32_t slot_shift, unsigned long long* acc) {
+  uint64_t per = (jb.np + gridDim.x - 1) / gridDim.x;
+  uint64_t r0 = blockIdx.x * per, r1 = r0 + per < jb.np ? r0 + per : jb.np;
+  unsigned long long cnt = 0, sum = 0;
+  if (r0 < r1) batch_probe_rows<K>(jb, r0, r1, slot_shift, cnt, sum);
+  block_add2(cnt, sum, acc);
+}
+
+// Set every slot's key to the empty marker (int32 keys: word 0; int64 keys: word 1) and zero
+// the rest, over all jobs' tables (one contiguous region), plus the per-job side records.
+__global__ void k_batch_init(uint32_t* slots, uint64_t n_slots, uint32_t slot_words, uint32_t key_size) {
+  for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < n_slots;
+       s += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t* w = slots + s * slot_words;
+    for (uint32_t i = 0; i < slot_words; ++i) w[i] = 0;
+    w[key_size == 4 ? 0 : 1] = 0x80000000u;
+  }
+}
+
+// ---------------------------------------------------------------- host side
+
+struct BatchConfig {
+  uint32_t tile_rows = 4096;
+  uint32_t block = 256;
+  float load_factor = 0.5f;
+};
+
+struct BatchPlan {
+  std::vector<BatchJob> jobs;
+  uint64_t total_tiles = 0;
+  uint64_t slots = 0;
+  uint32_t slot_shift = 3;
+};
+
+static vx_status plan_batch(const vx_batch_join* d, const BatchConfig& cfg, int ks, uint32_t ps,
+                            BatchPlan* pl) {
+  pl->jobs.resize(d->n_jobs);
+  uint32_t slot_bytes = 8;
+  while (slot_bytes < (uint32_t)ks + ps) slot_bytes <<= 1;
+  if (ks == 8 && ps) slot_bytes = 16;
+  pl->slot_shift = 0;
+  while ((1u << pl->slot_shift) < slot_bytes) ++pl->slot_shift;
+  uint64_t tile = 0, slots = 0;
+  for (uint32_t j = 0; j < d->n_jobs; ++j) {
+    BatchJob& b = pl->jobs[j];
+    std::memset(&b, 0, sizeof b);
+    b.bkey = d->build_key[j].data;
+    b.bpay = d->build_pay ? d->build_pay[j].data : nullptr;
+    b.pkey = d->probe_key[j].data;
+    b.nb = d->n_build[j];
+    b.np = d->n_probe[j];
+    b.pay_size = b.bpay ? (uint32_t)ps : 0;
+    uint64_t want = (uint64_t)std::ceil((double)std::max<uint64_t>(b.nb, 1) / cfg.load_factor);
+    uint64_t cap = 64;
+    while (cap < want) cap <<= 1;
+    b.mask = cap - 1;
+    b.log2cap = 0;
+    while ((1ull << b.log2cap) < cap) ++b.log2cap;
+    b.slots = (uint8_t*)(uintptr_t)slots;   // offset, relocated once memory is carved
+    slots += cap;
+    b.tile0 = tile;
+    b.build_tiles = (uint32_t)((b.nb + cfg.tile_rows - 1) / cfg.tile_rows);
+    b.probe_tiles = (uint32_t)((b.np + cfg.tile_rows - 1) / cfg.tile_rows);
+    tile += b.build_tiles + b.probe_tiles;
+  }
+  pl->total_tiles = tile;
+  pl->slots = slots;
+  return VX_OK;
+}
+
+struct BatchRun {
+  ArenaBlock mem;              // slots, side records, descriptors, counters, accumulators
+  BatchPlan plan;
+  BatchJob* jobs_dev = nullptr;
+  unsigned long long* next = nullptr;
+  unsigned int* built = nullptr;
+  unsigned long long* acc = nullptr;
+  uint8_t* slots = nullptr;
+  uint64_t counter_words = 0;
+};
+
+static vx_status setup_run(vx_ctx* ctx, const vx_batch_join* d, const BatchConfig& cfg, int ks,
+                           uint32_t ps, BatchRun* r) {
+  VX_TRY(plan_batch(d, cfg, ks, ps, &r->plan));
+  const uint32_t J = d->n_jobs;
+  uint64_t slot_bytes = r->plan.slots << r->plan.slot_shift;
+  uint64_t side_bytes = (uint64_t)J * 16;
+  uint64_t desc_bytes = (uint64_t)J * sizeof(BatchJob);
+  // counters and accumulators are contiguous so one fill kernel clears them
+  r->counter_words = 1 + (J + 1) / 2 + 2 * (uint64_t)J + 2 * (uint64_t)J;
+  uint64_t bytes = slot_bytes + 256 + desc_bytes + 256 + r->counter_words * 8 + 256;
+  r->mem.a = &ctx->arena;
+  r->mem.p = ctx->arena.alloc(bytes);
+  VX_CHECK(r->mem.p, VX_EBUDGET, "batch: %llu bytes of tables and descriptors do not fit the arena",
+           (unsigned long long)bytes);
+  r->slots = r->mem.p;
+  uint8_t* q = r->mem.p + ((slot_bytes + 255) / 256) * 256;
+  r->jobs_dev = (BatchJob*)q;
+  q += ((desc_bytes + 255) / 256) * 256;
+  uint64_t* cw = (uint64_t*)q;
+  r->next = (unsigned long long*)cw;
+  r->built = (unsigned int*)(cw + 1);
+  unsigned long long* sides = (unsigned long long*)(cw + 1 + (J + 1) / 2);
+  r->acc = sides + 2 * (uint64_t)J;
+  (void)side_bytes;
+  for (uint32_t j = 0; j < J; ++j) {
+    BatchJob& b = r->plan.jobs[j];
+    b.slots = r->slots + (((uint64_t)(uintptr_t)b.slots) << r->plan.slot_shift);
+    b.side = sides + 2 * (uint64_t)j;
+  }
+  VX_HIP(hipMemcpyAsync(r->jobs_dev, r->plan.jobs.data(), desc_bytes, hipMemcpyHostToDevice, ctx->compute));
+  return VX_OK;
+}
+
+// the work of one batch on `s`: init tables, clear counters, persistent kernel, results to host
+static vx_status enqueue_persistent(vx_ctx* ctx, const BatchRun& r, const BatchConfig& cfg, int ks,
+                                    uint32_t J, hipStream_t s, uint64_t* host_out) {
+  uint32_t sw = (1u << r.plan.slot_shift) / 4;
+  unsigned ig = (unsigned)std::min<uint64_t>((r.plan.slots + 255) / 256, (uint64_t)ctx->cu_count * 16);
+  hipLaunchKernelGGL(k_batch_init, dim3(std::max(ig, 1u)), dim3(256), 0, s, (uint32_t*)r.slots, r.plan.slots,
+                     sw, (uint32_t)ks);
+  fill_zero((uint64_t*)r.next, r.counter_words, s);
+  fill_zero((uint64_t*)ctx->dev_flags, 1, s);
+  // resident workgroups: a few per CU is enough to keep every CU busy between tiles
+  unsigned grid = (unsigned)std::min<uint64_t>(std::max<uint64_t>(r.plan.total_tiles, 1),
+                                               (uint64_t)ctx->cu_count * (cfg.block >= 512 ? 4 : 8));
+  if (ks == 8)
+    hipLaunchKernelGGL(k_batch<int64_t>, dim3(grid), dim3(cfg.block), 0, s, r.jobs_dev, J, r.plan.total_tiles,
+                       cfg.tile_rows, r.plan.slot_shift, r.next, r.built, r.acc, ctx->dev_flags);
+  else
+    hipLaunchKernelGGL(k_batch<int32_t>, dim3(grid), dim3(cfg.block), 0, s, r.jobs_dev, J, r.plan.total_tiles,
+                       cfg.tile_rows, r.plan.slot_shift, r.next, r.built, r.acc, ctx->dev_flags);
+  VX_HIP(hipGetLastError());
+  if (host_out) {
+    VX_HIP(hipMemcpyAsync(host_out, r.acc, 2 * (uint64_t)J * 8, hipMemcpyDeviceToHost, s));
+    VX_HIP(hipMemcpyAsync(host_out + 2 * (uint64_t)J, ctx->dev_flags, 4, hipMemcpyDeviceToHost, s));
+  }
+  return VX_OK;
+}
+
+struct TuneCache {
+  std::map<std::string, BatchConfig> m;
+};
+
+static TuneCache g_tune;
+
+static std::string class_key(const vx_ctx* ctx, const vx_batch_join* d, int ks) {
+  uint64_t nb = 0, np = 0, mb = 0;
+  for (uint32_t j = 0; j < d->n_jobs; ++j) {
+    nb += d->n_build[j];
+    np += d->n_probe[j];
+    mb = std::max<uint64_t>(mb, d->n_build[j]);
+  }
+  auto lg = [](uint64_t v) { int r = 0; while ((1ull << r) < v) ++r; return r; };
+  std::ostringstream o;
+  o << "cu" << ctx->cu_count << "_k" << ks << "_j" << lg(d->n_jobs) << "_b" << lg(nb) << "_p" << lg(np)
+    << "_m" << lg(mb);
+  return o.str();
+}
+
+static bool load_tuned(const std::string& key, BatchConfig* c) {
+  auto it = g_tune.m.find(key);
+  if (it != g_tune.m.end()) {
+    *c = it->second;
+    return true;
+  }
+  const char* path = getenv("VX_TUNE_CACHE");
+  if (!path) return false;
+  std::ifstream f(path);
+  std::string k;
+  BatchConfig v;
+  bool found = false;
+  while (f >> k >> v.tile_rows >> v.block >> v.load_factor)
+    if (k == key) {
+      *c = v;
+      found = true;
+    }
+  if (found) g_tune.m[key] = *c;
+  return found;
+}
+
+static void store_tuned(const std::string& key, const BatchConfig& c) {
+  g_tune.m[key] = c;
+  const char* path = getenv("VX_TUNE_CACHE");
+  if (!path) return;
+  std::ofstream f(path, std::ios::app);
+  f << key << " " << c.tile_rows << " " << c.block << " " << c.load_factor << "\n";
+}
+
+static vx_status time_config(vx_ctx* ctx, const vx_batch_join* d, const BatchConfig& cfg, int ks, uint32_t ps,
+                             float* ms) {
+  BatchRun r;
+  VX_TRY(setup_run(ctx, d, cfg, ks, ps, &r));
+  hipEvent_t a = get_event(ctx), b = get_event(ctx);
+  VX_TRY(enqueue_persistent(ctx, r, cfg, ks, d->n_jobs, ctx->compute, nullptr));   // warm
+  VX_HIP(hipEventRecord(a, ctx->compute));
+  VX_TRY(enqueue_persistent(ctx, r, cfg, ks, d->n_jobs, ctx->compute, nullptr));
+  VX_HIP(hipEventRecord(b, ctx->compute));
+  VX_HIP(hipEventSynchronize(b));
+  VX_HIP(hipEventElapsedTime(ms, a, b));
+  put_event(ctx, a);
+  put_event(ctx, b);
+  return VX_OK;
+}
+
+static vx_status autotune(vx_ctx* ctx, const vx_batch_join* d, int ks, uint32_t ps, BatchConfig* best) {
+  std::string key = class_key(ctx, d, ks);
+  if (load_tuned(key, best)) return VX_OK;
+  float best_ms = 1e30f;
+  for (uint32_t tile : {2048u, 8192u, 32768u})
+    for (uint32_t block : {256u, 512u})
+      for (float lf : {0.5f, 0.7f}) {
+        BatchConfig c{tile, block, lf};
+        float ms = 0;
+        VX_TRY(time_config(ctx, d, c, ks, ps, &ms));
+        if (ms < best_ms) {
+          best_ms = ms;
+          *best = c;
+        }
+      }
+  store_tuned(key, *best);
+  return VX_OK;
+}
+
+struct GraphCache {
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  std::vector<BatchJob> key;
+  BatchConfig cfg;
+  BatchRun* run = nullptr;
+};
+
+static std::map<const vx_ctx*, GraphCache*> g_graphs;
+
+static void drop_graph(GraphCache* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g->run;
+  delete g;
+}
+
+static bool same_jobs(const std::vector<BatchJob>& a, const vx_batch_join* d) {
+  if (a.size() != d->n_jobs) return false;
+  for (uint32_t j = 0; j < d->n_jobs; ++j)
+    if (a[j].bkey != d->build_key[j].data || a[j].pkey != d->probe_key[j].data ||
+        a[j].nb != d->n_build[j] || a[j].np != d->n_probe[j] ||
+        a[j].bpay != (d->build_pay ? d->build_pay[j].data : nullptr))
+      return false;
+  return true;
+}
+
+void batch_release_ctx(const vx_ctx* ctx) {
+  auto it = g_graphs.find(ctx);
+  if (it != g_graphs.end()) {
+    drop_graph(it->second);
+    g_graphs.erase(it);
+  }
+}
+
+vx_status join_batch(vx_ctx* ctx, const vx_batch_join* d, vx_join_out* out) {
+  double t0 = now_ms();
+  VX_CHECK(d->n_jobs <= kMaxBatchJobs, VX_EINVAL, "batch: %u jobs (max %u)", d->n_jobs, kMaxBatchJobs);
+  VX_CHECK(d->n_jobs == 0 || (d->build_key && d->n_build && d->probe_key && d->n_probe && d->out),
+           VX_EINVAL, "batch: null job arrays");
+  VX_CHECK(d->mode == 0 || d->mode == 1, VX_EINVAL, "batch: mode %d", d->mode);
+  VX_HIP(hipSetDevice(ctx->device));
+  if (d->n_jobs == 0) return VX_OK;
+  const int32_t kt = d->build_key[0].type;
+  const int ks = elsize_of(kt);
+  VX_CHECK(ks, VX_EINVAL, "batch: key type %d", kt);
+  int32_t pt = 0;
+  for (uint32_t j = 0; j < d->n_jobs; ++j) {
+    VX_CHECK(d->build_key[j].type == kt && d->probe_key[j].type == kt, VX_EINVAL,
+             "batch: every job must use the same key type");
+    ColInfo ci;
+    VX_TRY(classify(ctx, d->build_key[j], d->n_build[j], &ci, "batch build key"));
+    VX_CHECK(ci.where == Where::Device, VX_EINVAL, "batch: job %u build keys must be device-resident", j);
+    VX_TRY(classify(ctx, d->probe_key[j], d->n_probe[j], &ci, "batch probe key"));
+    VX_CHECK(ci.where == Where::Device, VX_EINVAL, "batch: job %u probe keys must be device-resident", j);
+    if (d->build_pay && d->build_pay[j].data) {
+      VX_CHECK(pt == 0 || pt == d->build_pay[j].type, VX_EINVAL, "batch: payload types differ");
+      pt = d->build_pay[j].type;
+      VX_TRY(classify(ctx, d->build_pay[j], d->n_build[j], &ci, "batch build payload"));
+      VX_CHECK(ci.where == Where::Device, VX_EINVAL, "batch: job %u payload must be device-resident", j);
+    }
+  }
+  const uint32_t ps = pt ? (uint32_t)elsize_of(pt) : 0;
+  const uint32_t J = d->n_jobs;
+  BatchConfig cfg;
+  bool tuned = d->tile_rows == 0 || d->block == 0 || d->load_factor == 0.0f;
+  if (tuned && d->mode == 0) VX_TRY(autotune(ctx, d, ks, ps, &cfg));
+  if (d->tile_rows) cfg.tile_rows = d->tile_rows;
+  if (d->block) cfg.block = d->block;
+  if (d->load_factor > 0) cfg.load_factor = d->load_factor;
+  VX_CHECK(cfg.block == 256 || cfg.block == 512, VX_EINVAL, "batch: block %u (256 or 512)", cfg.block);
+  VX_CHECK(cfg.tile_rows >= 64, VX_EINVAL, "batch: tile_rows %u < 64", cfg.tile_rows);
+  VX_CHECK(cfg.load_factor > 0.05f && cfg.load_factor <= 0.95f, VX_EINVAL, "batch: load factor");
+
+  std::vector<uint64_t> host(2 * (uint64_t)J + 1, 0);
+  vx_stats& s = out->stats;
+  std::memset(&s, 0, sizeof s);
+  if (d->mode == 0) {
+    GraphCache*& gc = g_graphs[ctx];
+    if (!gc || !same_jobs(gc->key, d) || gc->cfg.tile_rows != cfg.tile_rows || gc->cfg.block != cfg.block ||
+        gc->cfg.load_factor != cfg.load_factor) {
+      drop_graph(gc);
+      gc = new GraphCache;
+      gc->run = new BatchRun;
+      gc->cfg = cfg;
+      VX_TRY(setup_run(ctx, d, cfg, ks, ps, gc->run));
+      gc->key = gc->run->plan.jobs;
+      for (uint32_t j = 0; j < J; ++j) {   // keep the caller's pointers for the comparison
+        gc->key[j].bkey = d->build_key[j].data;
+        gc->key[j].pkey = d->probe_key[j].data;
+        gc->key[j].bpay = d->build_pay ? d->build_pay[j].data : nullptr;
+      }
+      VX_HIP(hipStreamSynchronize(ctx->compute));
+      VX_HIP(hipStreamBeginCapture(ctx->compute, hipStreamCaptureModeThreadLocal));
+      vx_status cst = enqueue_persistent(ctx, *gc->run, cfg, ks, J, ctx->compute, ctx->host_acc);
+      hipError_t ce = hipStreamEndCapture(ctx->compute, &gc->graph);
+      VX_TRY(cst);
+      VX_HIP(ce);
+      VX_HIP(hipGraphInstantiate(&gc->exec, gc->graph, nullptr, nullptr, 0));
+    }
+    hipEvent_t a = get_event(ctx), b = get_event(ctx);
+    VX_HIP(hipEventRecord(a, ctx->compute));
+    VX_HIP(hipGraphLaunch(gc->exec, ctx->compute));
+    VX_HIP(hipEventRecord(b, ctx->compute));
+    VX_HIP(hipStreamSynchronize(ctx->compute));
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, a, b);
+    put_event(ctx, a);
+    put_event(ctx, b);
+    std::memcpy(host.data(), ctx->host_acc, (2 * (uint64_t)J) * 8);
+    unsigned int f = 0;
+    std::memcpy(&f, ctx->host_acc + 2 * (uint64_t)J, 4);
+    VX_CHECK(!(f & kFlagDup), VX_EDUPKEY, "batch: duplicate build key");
+    VX_CHECK(!(f & kFlagFull), VX_ECAPACITY, "batch: table full or build wait expired");
+    s.kernel_ms = ms;
+    s.kernel_launches = 1;
+    s.table_bytes = gc->run->plan.slots << gc->run->plan.slot_shift;
+    s.chunk_rows = cfg.tile_rows;
+    s.n_buffers = cfg.block;
+    s.imbalance = cfg.load_factor;
+  } else {
+    BatchRun r;
+    VX_TRY(setup_run(ctx, d, cfg, ks, ps, &r));
+    uint32_t sw = (1u << r.plan.slot_shift) / 4;
+    fill_zero((uint64_t*)r.next, r.counter_words, ctx->compute);
+    fill_zero((uint64_t*)ctx->dev_flags, 1, ctx->compute);
+    hipEvent_t a = get_event(ctx), b = get_event(ctx);
+    VX_HIP(hipEventRecord(a, ctx->compute));
+    for (uint32_t j = 0; j < J; ++j) {
+      const BatchJob& jb = r.plan.jobs[j];
+      uint64_t cap = jb.mask + 1;
+      unsigned ig = (unsigned)std::min<uint64_t>((cap + 255) / 256, (uint64_t)ctx->cu_count * 16);
+      hipLaunchKernelGGL(k_batch_init, dim3(ig), dim3(256), 0, ctx->compute, (uint32_t*)jb.slots, cap, sw,
+                         (uint32_t)ks);
+      unsigned gb = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((jb.nb + cfg.tile_rows - 1) / cfg.tile_rows,
+                                                                       (uint64_t)ctx->cu_count * 8));
+      unsigned gp = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((jb.np + cfg.tile_rows - 1) / cfg.tile_rows,
+                                                                       (uint64_t)ctx->cu_count * 8));
+      if (ks == 8) {
+        hipLaunchKernelGGL(k_job_build<int64_t>, dim3(gb), dim3(cfg.block), 0, ctx->compute, jb, r.plan.slot_shift,
+                           ctx->dev_flags);
+        hipLaunchKernelGGL(k_job_probe<int64_t>, dim3(gp), dim3(cfg.block), 0, ctx->compute, jb, r.plan.slot_shift,
+                           r.acc + 2 * (uint64_t)j);
+      } else {
+        hipLaunchKernelGGL(k_job_build<int32_t>, dim3(gb), dim3(cfg.block), 0, ctx->compute, jb, r.plan.slot_shift,
+                           ctx->dev_flags);
+        hipLaunchKernelGGL(k_job_probe<int32_t>, dim3(gp), dim3(cfg.block), 0, ctx->compute, jb, r.plan.slot_shift,
+                           r.acc + 2 * (uint64_t)j);
+      }
+    }
+    VX_HIP(hipGetLastError());
+    VX_HIP(hipEventRecord(b, ctx->compute));
+    VX_HIP(hipMemcpyAsync(host.data(), r.acc, 2 * (uint64_t)J * 8, hipMemcpyDeviceToHost, ctx->compute));
+    VX_HIP(hipStreamSynchronize(ctx->compute));
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, a, b);
+    put_event(ctx, a);
+    put_event(ctx, b);
+    VX_TRY(check_flags(ctx, "batch"));
+    s.kernel_ms = ms;
+    s.kernel_launches = 3 * (uint64_t)J;
+    s.table_bytes = r.plan.slots << r.plan.slot_shift;
+  }
+  uint64_t rows = 0;
+  for (uint32_t j = 0; j < J; ++j) {
+    std::memset(&d->out[j], 0, sizeof(vx_agg));
+    d->out[j].match_count = host[2 * j];
+    d->out[j].sum[0] = host[2 * j + 1];
+    rows += d->n_probe[j];
+  }
+  s.rows = rows;
+  s.total_ms = now_ms() - t0;
+  return VX_OK;
+}
+
+}  // namespace vx

@@ -116,6 +116,9 @@ struct vx_ctx {
 
 namespace vx {
 
+// Drop the batch join's cached graph and tables held for this context.
+void batch_release_ctx(const vx_ctx* ctx);
+
 // Pinned host scratch of at least `bytes` (grows by reallocation; contents not kept).
 vx_status host_scratch(vx_ctx* ctx, uint64_t bytes, uint8_t** out);
 

@@ -108,12 +108,18 @@ __global__ void k_build_unique_group(TableView t, BuildCols c, uint64_t n, unsig
   for (uint64_t wb = wave_first; wb < n; wb += stride) {
     uint64_t i = wb + lane;
     bool valid = i < n;
+    // every lane loads its own row (coalesced) before the group works through the rows
     K mykey = valid ? ((const K*)c.key)[i] : (K)0;
+    long long mypay[kMaxPay] = {0, 0, 0, 0};
+    for (uint32_t p = 0; p < t.n_pay; ++p)
+      if (valid) mypay[p] = load_signed(c.pay[p], i, c.pay_size[p]);
     for (int r = 0; r < G; ++r) {
       int src = gbase + r;
       bool v = __shfl(valid ? 1 : 0, src, 64) != 0;
       if (!v) continue;                       // uniform within the group
       K k = __shfl(mykey, src, 64);
+      long long pv[kMaxPay];
+      for (uint32_t p = 0; p < kMaxPay; ++p) pv[p] = __shfl(mypay[p], src, 64);
       uint64_t row = wb + src;
       U kb = (U)k;
       if (kb == kEmpty) {
@@ -140,7 +146,10 @@ __global__ void k_build_unique_group(TableView t, BuildCols c, uint64_t n, unsig
           if (lane == leader) {
             U prev = atomicCAS((U*)slot, kEmpty, kb);
             if (prev == kEmpty) {
-              write_unique_payloads<K>(t, slot, c, row);
+              for (uint32_t p = 0; p < t.n_pay; ++p) {
+                if (t.pay_size[p] == 4) *(int*)(slot + t.pay_off[p]) = (int)pv[p];
+                else *(long long*)(slot + t.pay_off[p]) = pv[p];
+              }
               won = 1;
             } else if (prev == kb) {
               atomicOr(flags, kFlagDup);

@@ -276,6 +276,7 @@ vx_status vx_ctx_destroy(vx_ctx* c) {
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->own_compute) (void)hipStreamDestroy(c->compute);
   (void)hipStreamSynchronize(c->d2h);
+  batch_release_ctx(c);
   (void)hipStreamDestroy(c->copy);
   (void)hipStreamDestroy(c->d2h);
   (void)hipHostFree(c->host_acc);

@@ -1,0 +1,88 @@
+"""GPU parity of the batched join (persistent kernel in a HIP graph, and the per-job baseline)."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+GiB = 1 << 30
+M64 = 1 << 64
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu):
+    c = gpu.Context(8 * GiB)
+    yield c
+    c.close()
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _jobs(n_jobs, seed, b_lo=1 << 10, b_hi=1 << 16):
+    b, p = datagen.batch_sizes(n_jobs, seed=seed, b_lo=b_lo, b_hi=b_hi)
+    return [datagen.batch_job(j, int(b[j]), int(p[j]), seed=seed) for j in range(n_jobs)]
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_batch_matches_oracle(gpu, ctx, mode):
+    jobs = _jobs(24, 41)
+    _say("batch mode", mode)
+    got, st = ctx.join_batch([dev(j[0]) for j in jobs], [dev(j[1]) for j in jobs], [dev(j[2]) for j in jobs],
+                             mode=mode)
+    for (bk, bp, pk), g in zip(jobs, got):
+        assert g == oracle.join_agg(bk, [bp], pk, [])
+    assert st["rows"] == sum(len(j[2]) for j in jobs)
+
+
+def test_batch_explicit_configs_and_graph_replay(gpu, ctx):
+    jobs = _jobs(16, 42)
+    exp = [oracle.join_agg(bk, [bp], pk, []) for bk, bp, pk in jobs]
+    args = ([dev(j[0]) for j in jobs], [dev(j[1]) for j in jobs], [dev(j[2]) for j in jobs])
+    for tile, block, lf in ((64, 256, 0.5), (1024, 512, 0.7), (65536, 256, 0.9)):
+        _say("batch config", tile, block, lf)
+        got, _ = ctx.join_batch(*args, tile_rows=tile, block=block, load_factor=lf)
+        assert got == exp
+    # replays of the cached graph, with eager work in between
+    import torch
+    for r in range(3):
+        got, st = ctx.join_batch(*args, tile_rows=1024, block=512, load_factor=0.7)
+        assert got == exp
+        torch.cuda.synchronize()
+        _ = (args[2][0] + 1).sum().item()
+    assert st["kernel_launches"] == 1
+
+
+def test_batch_edges(gpu, ctx):
+    i32 = np.iinfo(np.int32)
+    bk = [np.array([i32.min, 1, 2], np.int32), np.zeros(0, np.int32), np.array([5], np.int32)]
+    bp = [np.array([7, 8, 9], np.int32), np.zeros(0, np.int32), np.array([-3], np.int32)]
+    pk = [np.array([i32.min, i32.min, 2, 3], np.int32), np.array([1, 2], np.int32), np.zeros(0, np.int32)]
+    _say("batch edges")
+    for mode in (0, 1):
+        got, _ = ctx.join_batch([dev(x) for x in bk], [dev(x) for x in bp], [dev(x) for x in pk], mode=mode,
+                                tile_rows=64, block=256, load_factor=0.5)
+        assert got == [oracle.join_agg(a, [b], c, []) for a, b, c in zip(bk, bp, pk)]
+    with pytest.raises(gpu.VxError) as ei:
+        ctx.join_batch([dev(np.array([1, 1], np.int32))], [None], [dev(np.array([1], np.int32))],
+                       tile_rows=64, block=256, load_factor=0.5)
+    assert ei.value.status == gpu.VX_EDUPKEY
+
+
+def test_batch_int64_keys(gpu, ctx):
+    rng = np.random.default_rng(3)
+    bk = [rng.permutation(1 << 40)[:0] if False else np.unique(rng.integers(-2**60, 2**60, n)).astype(np.int64)
+          for n in (1000, 5000, 300)]
+    bp = [rng.integers(-2**40, 2**40, len(k)).astype(np.int64) for k in bk]
+    pk = [np.concatenate([k[::2], rng.integers(-2**60, 2**60, 3 * len(k))]).astype(np.int64) for k in bk]
+    _say("batch int64")
+    got, _ = ctx.join_batch([dev(x) for x in bk], [dev(x) for x in bp], [dev(x) for x in pk])
+    assert got == [oracle.join_agg(a, [b], c, []) for a, b, c in zip(bk, bp, pk)]

@@ -149,13 +149,14 @@ def test_learned_splitters_exact(gpu, ctx):
 def _grad_bound(params, x, t):
     """Rounding bound for the GPU gradient, per component.
 
-    The GPU evaluates z = fma(w1, x, b1) (one rounding), h = relu(z), p = w2 * h (one rounding)
-    and y = b2 + (butterfly sum of 64 p's: 6 roundings) in FP32, so
-    |dy_i| <= g6 * (|b2| + sum_j |w2_j h_ij|) + 2u * sum_j |w2_j h_ij|, u = 2^-24, g6 = 7u.
-    Every gradient term is (2/n) e_i * a_ic with a_ic in {h_ij, w2_j [z>0], w2_j x_i [z>0], 1};
-    the FP64 accumulation adds nothing visible, and the result is rounded to FP32 (u |g|).
-    Hence |dg_c| <= (2/n) sum_i (|dy_i| |a_ic| + |e_i| |da_ic|) + u |g_c|, with
-    |da_ic| <= 2u |a_ic| covering the rounded h and z."""
+    The GPU evaluates z = fma(w1, x, b1) (one rounding: |dz| <= u |z|), h = relu(z),
+    p = w2 * h (one rounding) and y = b2 + (butterfly sum of 64 p's: 6 roundings) in FP32,
+    u = 2^-24, so |dy_i| <= 7u (|b2| + sum_j |w2_j h_ij|) + 2u sum_j |w2_j h_ij|.  Where
+    |z_ij| <= u (|w1_j x_i| + |b1_j|) the activation may differ from the oracle's; that unit then
+    moves y by at most |w2_j z_ij| and its own gradient terms by their full size.
+    Every gradient term is (2/n) e_i a_ic with a_ic in {w2_j x_i [z>0], w2_j [z>0], h_ij, 1};
+    the FP64 accumulation adds nothing visible and the result is rounded to FP32 (u |g|).
+    Hence |dg_c| <= (2/n) sum_i (|dy_i| |a_ic| + |e_i| 2u |a_ic| + |e_i| |flip_ic|) + u |g_c|."""
     H = 64
     u = 2.0**-24
     w1, b1, w2, b2 = (params[:H].astype(np.float64), params[H:2 * H].astype(np.float64),
@@ -163,17 +164,24 @@ def _grad_bound(params, x, t):
     xd = x.astype(np.float64)[:, None]
     z = xd * w1 + b1
     h = np.maximum(z, 0)
+    flip = np.abs(z) <= u * (np.abs(w1 * xd) + np.abs(b1))
     S = np.abs(b2) + np.abs(w2 * h).sum(1)
     y = b2 + (w2 * h).sum(1)
     e = np.abs(y - t.astype(np.float64))
-    dy = 7 * u * S + 2 * u * np.abs(w2 * h).sum(1)
+    dy = 7 * u * S + 2 * u * np.abs(w2 * h).sum(1) + (flip * np.abs(w2 * z)).sum(1)
     n = len(x)
     act = (z > 0).astype(np.float64)
     a_w1 = np.abs(w2) * np.abs(xd) * act
     a_b1 = np.abs(w2) * act
     a_w2 = h
-    term = lambda a: (2 / n) * ((dy[:, None] * a).sum(0) + (e[:, None] * 2 * u * a).sum(0))
-    return np.concatenate([term(a_w1), term(a_b1), term(a_w2), [(2 / n) * dy.sum()]]), np.abs(z).min()
+    f_w1 = flip * np.abs(w2) * np.abs(xd)
+    f_b1 = flip * np.abs(w2)
+    f_w2 = flip * np.abs(z)
+
+    def term(a, f):
+        return (2 / n) * ((dy[:, None] * a).sum(0) + (e[:, None] * (2 * u * a + f)).sum(0))
+
+    return np.concatenate([term(a_w1, f_w1), term(a_b1, f_b1), term(a_w2, f_w2), [(2 / n) * dy.sum()]])
 
 
 @pytest.mark.parametrize("seed", [0, 1])
@@ -187,8 +195,7 @@ def test_cdf_gradient_parity(gpu, ctx, seed):
     _say("cdf gradient parity", seed)
     loss_g, g_g = ctx.cdf_loss_grad(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda(), p)
     loss_o, g_o = oracle.mlp_loss_grad(p, x, t)
-    bound, zmin = _grad_bound(p, x, t)
-    assert zmin > 1e-6    # no activation flips within rounding
+    bound = _grad_bound(p, x, t)
     u = 2.0**-24
     err = np.abs(g_g.astype(np.float64) - g_o)
     assert np.all(err <= bound + u * np.abs(g_o) + 1e-30), (err / (bound + 1e-30)).max()
