@@ -219,7 +219,8 @@ typedef struct {
 
 typedef struct {
   uint32_t n_jobs;
-  int32_t mode;                /* 0: one persistent launch in a HIP graph; 1: two launches per job */
+  int32_t mode;                /* 0: one HIP graph launch: a build-phase and a probe-phase kernel that
+                                  each drain the tiles of every job; 1: two launches per job */
   const vx_col* build_key;     /* per job, device-resident, unique keys */
   const vx_col* build_pay;     /* per job one payload column (data may be NULL) */
   const uint64_t* n_build;

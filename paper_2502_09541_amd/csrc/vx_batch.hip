@@ -1,16 +1,14 @@
-// Many independent device-resident joins in one persistent launch.
+// Many independent device-resident joins, batched into one HIP graph launch.
 //
-// The work is a queue of tiles, job by job: job j's build tiles, then its probe tiles.  Each
-// workgroup takes the next tile from a global counter.  A build tile inserts its rows into the
-// job's table and then bumps the job's build counter (release); a probe tile first waits until
-// that counter reaches the job's build-tile count (acquire).  Every build tile a probe tile can
-// wait for was handed out earlier, to a workgroup that is already running and never waits
-// itself, so the queue cannot deadlock whatever the grid size; the wait is still bounded and
-// raises an error flag if it ever expires.  The table init, the counter reset, the kernel and
-// the copy of the results are captured once in a HIP graph and replayed.  Tile size,
-// workgroup size and load factor come from a small autotuner that times candidates on the
-// batch itself and caches the winner per workload class (optionally in the file named by
-// VX_TUNE_CACHE).
+// The work is a list of equal-size tiles: every job's build tiles, then every job's probe
+// tiles, largest jobs first.  Two queue-draining kernels cover it: the build kernel walks the
+// build tiles grid-stride and inserts each tile's rows into its job's table; the probe kernel
+// walks the probe tiles and aggregates each tile into its job's result.  The kernel boundary
+// between them is the only dependency, so no workgroup ever waits for another.  Table init,
+// result reset, both kernels and the copy of the results are captured once in a HIP graph and
+// replayed while the batch is unchanged.  Tile size, workgroup size and load factor come from
+// a small autotuner that times candidates on the batch itself and caches the winner per
+// workload class (optionally in the file named by VX_TUNE_CACHE).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -33,13 +31,13 @@ struct BatchJob {
   uint64_t mask;
   uint32_t log2cap;
   uint32_t pay_size;      // 0 (no payload), 4 or 8
-  uint64_t tile0;         // first queue index of the job
+  uint64_t tile0;         // first build-phase tile of the job
+  uint64_t ptile0;        // first probe-phase tile of the job
   uint32_t build_tiles, probe_tiles;
   unsigned long long* side;   // sentinel-key record: count, payload sum
 };
 
 constexpr uint32_t kMaxBatchJobs = 4096;
-constexpr uint64_t kSpinLimit = 1ull << 26;
 
 template <typename K>
 __device__ __forceinline__ void batch_build_rows(const BatchJob& jb, uint64_t r0, uint64_t r1,
@@ -130,22 +128,18 @@ __device__ __forceinline__ void block_add2(unsigned long long cnt, unsigned long
   }
 }
 
-template <typename K>
-__global__ void __launch_bounds__(512) k_batch(const BatchJob* jobs, uint32_t n_jobs,
-                                               uint64_t total_tiles, uint32_t tile_rows,
-                                               uint32_t slot_shift, unsigned long long* next,
-                                               unsigned int* built, unsigned long long* acc,
-                                               unsigned int* flags) {
+// Tiles of one phase: tile t of the phase belongs to the job whose first tile index (tile0 of
+// the phase) is the largest one <= t.
+template <typename K, bool BUILD>
+__global__ void __launch_bounds__(512) k_batch_phase(const BatchJob* jobs, uint32_t n_jobs,
+                                                     uint64_t phase_tiles, uint32_t tile_rows,
+                                                     uint32_t slot_shift, unsigned long long* acc,
+                                                     unsigned int* flags) {
   __shared__ unsigned long long tile0[kMaxBatchJobs];
-  __shared__ unsigned long long s_tile;
-  for (uint32_t j = threadIdx.x; j < n_jobs; j += blockDim.x) tile0[j] = jobs[j].tile0;
+  for (uint32_t j = threadIdx.x; j < n_jobs; j += blockDim.x)
+    tile0[j] = BUILD ? jobs[j].tile0 : jobs[j].ptile0;
   __syncthreads();
-  for (;;) {
-    if (threadIdx.x == 0) s_tile = atomicAdd(next, 1ull);
-    __syncthreads();
-    const uint64_t t = s_tile;
-    __syncthreads();
-    if (t >= total_tiles) break;
+  for (uint64_t t = blockIdx.x; t < phase_tiles; t += gridDim.x) {
     uint32_t lo = 0, hi = n_jobs;
     while (hi - lo > 1) {
       uint32_t mid = (lo + hi) >> 1;
@@ -153,28 +147,12 @@ __global__ void __launch_bounds__(512) k_batch(const BatchJob* jobs, uint32_t n_
       else hi = mid;
     }
     const BatchJob jb = jobs[lo];
-    const uint64_t local = t - jb.tile0;
-    if (local < jb.build_tiles) {
-      uint64_t r0 = local * tile_rows, r1 = r0 + tile_rows < jb.nb ? r0 + tile_rows : jb.nb;
+    const uint64_t local = t - (BUILD ? jb.tile0 : jb.ptile0);
+    const uint64_t n = BUILD ? jb.nb : jb.np;
+    const uint64_t r0 = local * tile_rows, r1 = r0 + tile_rows < n ? r0 + tile_rows : n;
+    if (BUILD) {
       batch_build_rows<K>(jb, r0, r1, slot_shift, flags);
-      __threadfence();                     // release this tile's table writes
-      __syncthreads();
-      if (threadIdx.x == 0) atomicAdd(built + lo, 1u);
     } else {
-      if (threadIdx.x == 0) {
-        uint64_t spins = 0;
-        while (__hip_atomic_load(built + lo, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < jb.build_tiles) {
-          __builtin_amdgcn_s_sleep(2);
-          if (++spins > kSpinLimit) {
-            atomicOr(flags, kFlagFull);
-            break;
-          }
-        }
-      }
-      __syncthreads();
-      __threadfence();                     // acquire the build tiles' writes
-      uint64_t p = local - jb.build_tiles;
-      uint64_t r0 = p * tile_rows, r1 = r0 + tile_rows < jb.np ? r0 + tile_rows : jb.np;
       unsigned long long cnt = 0, sum = 0;
       batch_probe_rows<K>(jb, r0, r1, slot_shift, cnt, sum);
       block_add2(cnt, sum, acc + 2 * lo);
@@ -219,7 +197,9 @@ struct BatchConfig {
 };
 
 struct BatchPlan {
-  std::vector<BatchJob> jobs;
+  std::vector<BatchJob> jobs;      // in tile order (largest probe side first)
+  std::vector<uint32_t> job_of;    // caller's job index of jobs[i]
+  uint64_t build_tiles = 0, probe_tiles = 0;
   uint64_t total_tiles = 0;
   uint64_t slots = 0;
   uint32_t slot_shift = 3;
@@ -227,15 +207,21 @@ struct BatchPlan {
 
 static vx_status plan_batch(const vx_batch_join* d, const BatchConfig& cfg, int ks, uint32_t ps,
                             BatchPlan* pl) {
-  pl->jobs.resize(d->n_jobs);
+  const uint32_t J = d->n_jobs;
+  pl->jobs.resize(J);
+  pl->job_of.resize(J);
+  for (uint32_t j = 0; j < J; ++j) pl->job_of[j] = j;
+  std::stable_sort(pl->job_of.begin(), pl->job_of.end(),
+                   [&](uint32_t a, uint32_t b) { return d->n_probe[a] > d->n_probe[b]; });
   uint32_t slot_bytes = 8;
   while (slot_bytes < (uint32_t)ks + ps) slot_bytes <<= 1;
   if (ks == 8 && ps) slot_bytes = 16;
   pl->slot_shift = 0;
   while ((1u << pl->slot_shift) < slot_bytes) ++pl->slot_shift;
-  uint64_t tile = 0, slots = 0;
-  for (uint32_t j = 0; j < d->n_jobs; ++j) {
-    BatchJob& b = pl->jobs[j];
+  uint64_t bt = 0, pt = 0, slots = 0;
+  for (uint32_t i = 0; i < J; ++i) {
+    const uint32_t j = pl->job_of[i];
+    BatchJob& b = pl->jobs[i];
     std::memset(&b, 0, sizeof b);
     b.bkey = d->build_key[j].data;
     b.bpay = d->build_pay ? d->build_pay[j].data : nullptr;
@@ -251,12 +237,16 @@ static vx_status plan_batch(const vx_batch_join* d, const BatchConfig& cfg, int 
     while ((1ull << b.log2cap) < cap) ++b.log2cap;
     b.slots = (uint8_t*)(uintptr_t)slots;   // offset, relocated once memory is carved
     slots += cap;
-    b.tile0 = tile;
+    b.tile0 = bt;
+    b.ptile0 = pt;
     b.build_tiles = (uint32_t)((b.nb + cfg.tile_rows - 1) / cfg.tile_rows);
     b.probe_tiles = (uint32_t)((b.np + cfg.tile_rows - 1) / cfg.tile_rows);
-    tile += b.build_tiles + b.probe_tiles;
+    bt += b.build_tiles;
+    pt += b.probe_tiles;
   }
-  pl->total_tiles = tile;
+  pl->build_tiles = bt;
+  pl->probe_tiles = pt;
+  pl->total_tiles = bt + pt;
   pl->slots = slots;
   return VX_OK;
 }
@@ -265,8 +255,7 @@ struct BatchRun {
   ArenaBlock mem;              // slots, side records, descriptors, counters, accumulators
   BatchPlan plan;
   BatchJob* jobs_dev = nullptr;
-  unsigned long long* next = nullptr;
-  unsigned int* built = nullptr;
+  unsigned long long* counters = nullptr;   // sides then accumulators (cleared together)
   unsigned long long* acc = nullptr;
   uint8_t* slots = nullptr;
   uint64_t counter_words = 0;
@@ -279,8 +268,8 @@ static vx_status setup_run(vx_ctx* ctx, const vx_batch_join* d, const BatchConfi
   uint64_t slot_bytes = r->plan.slots << r->plan.slot_shift;
   uint64_t side_bytes = (uint64_t)J * 16;
   uint64_t desc_bytes = (uint64_t)J * sizeof(BatchJob);
-  // counters and accumulators are contiguous so one fill kernel clears them
-  r->counter_words = 1 + (J + 1) / 2 + 2 * (uint64_t)J + 2 * (uint64_t)J;
+  // side records and accumulators are contiguous so one fill kernel clears them
+  r->counter_words = 2 * (uint64_t)J + 2 * (uint64_t)J;
   uint64_t bytes = slot_bytes + 256 + desc_bytes + 256 + r->counter_words * 8 + 256;
   r->mem.a = &ctx->arena;
   r->mem.p = ctx->arena.alloc(bytes);
@@ -290,10 +279,8 @@ static vx_status setup_run(vx_ctx* ctx, const vx_batch_join* d, const BatchConfi
   uint8_t* q = r->mem.p + ((slot_bytes + 255) / 256) * 256;
   r->jobs_dev = (BatchJob*)q;
   q += ((desc_bytes + 255) / 256) * 256;
-  uint64_t* cw = (uint64_t*)q;
-  r->next = (unsigned long long*)cw;
-  r->built = (unsigned int*)(cw + 1);
-  unsigned long long* sides = (unsigned long long*)(cw + 1 + (J + 1) / 2);
+  r->counters = (unsigned long long*)q;
+  unsigned long long* sides = r->counters;
   r->acc = sides + 2 * (uint64_t)J;
   (void)side_bytes;
   for (uint32_t j = 0; j < J; ++j) {
@@ -301,28 +288,35 @@ static vx_status setup_run(vx_ctx* ctx, const vx_batch_join* d, const BatchConfi
     b.slots = r->slots + (((uint64_t)(uintptr_t)b.slots) << r->plan.slot_shift);
     b.side = sides + 2 * (uint64_t)j;
   }
+  (void)side_bytes;
   VX_HIP(hipMemcpyAsync(r->jobs_dev, r->plan.jobs.data(), desc_bytes, hipMemcpyHostToDevice, ctx->compute));
   return VX_OK;
 }
 
-// the work of one batch on `s`: init tables, clear counters, persistent kernel, results to host
-static vx_status enqueue_persistent(vx_ctx* ctx, const BatchRun& r, const BatchConfig& cfg, int ks,
-                                    uint32_t J, hipStream_t s, uint64_t* host_out) {
+// the work of one batch on `s`: init tables, clear results, build phase, probe phase, results
+// to the host (accumulators are in tile order; the caller maps them back through job_of)
+static vx_status enqueue_batch(vx_ctx* ctx, const BatchRun& r, const BatchConfig& cfg, int ks,
+                               uint32_t J, hipStream_t s, uint64_t* host_out) {
   uint32_t sw = (1u << r.plan.slot_shift) / 4;
   unsigned ig = (unsigned)std::min<uint64_t>((r.plan.slots + 255) / 256, (uint64_t)ctx->cu_count * 16);
   hipLaunchKernelGGL(k_batch_init, dim3(std::max(ig, 1u)), dim3(256), 0, s, (uint32_t*)r.slots, r.plan.slots,
                      sw, (uint32_t)ks);
-  fill_zero((uint64_t*)r.next, r.counter_words, s);
+  fill_zero((uint64_t*)r.counters, r.counter_words, s);
   fill_zero((uint64_t*)ctx->dev_flags, 1, s);
-  // resident workgroups: a few per CU is enough to keep every CU busy between tiles
-  unsigned grid = (unsigned)std::min<uint64_t>(std::max<uint64_t>(r.plan.total_tiles, 1),
-                                               (uint64_t)ctx->cu_count * (cfg.block >= 512 ? 4 : 8));
-  if (ks == 8)
-    hipLaunchKernelGGL(k_batch<int64_t>, dim3(grid), dim3(cfg.block), 0, s, r.jobs_dev, J, r.plan.total_tiles,
-                       cfg.tile_rows, r.plan.slot_shift, r.next, r.built, r.acc, ctx->dev_flags);
-  else
-    hipLaunchKernelGGL(k_batch<int32_t>, dim3(grid), dim3(cfg.block), 0, s, r.jobs_dev, J, r.plan.total_tiles,
-                       cfg.tile_rows, r.plan.slot_shift, r.next, r.built, r.acc, ctx->dev_flags);
+  const uint64_t per_cu = cfg.block >= 512 ? 4 : 8;
+  unsigned gb = (unsigned)std::min<uint64_t>(std::max<uint64_t>(r.plan.build_tiles, 1), ctx->cu_count * per_cu);
+  unsigned gp = (unsigned)std::min<uint64_t>(std::max<uint64_t>(r.plan.probe_tiles, 1), ctx->cu_count * per_cu);
+  if (ks == 8) {
+    hipLaunchKernelGGL((k_batch_phase<int64_t, true>), dim3(gb), dim3(cfg.block), 0, s, r.jobs_dev, J,
+                       r.plan.build_tiles, cfg.tile_rows, r.plan.slot_shift, r.acc, ctx->dev_flags);
+    hipLaunchKernelGGL((k_batch_phase<int64_t, false>), dim3(gp), dim3(cfg.block), 0, s, r.jobs_dev, J,
+                       r.plan.probe_tiles, cfg.tile_rows, r.plan.slot_shift, r.acc, ctx->dev_flags);
+  } else {
+    hipLaunchKernelGGL((k_batch_phase<int32_t, true>), dim3(gb), dim3(cfg.block), 0, s, r.jobs_dev, J,
+                       r.plan.build_tiles, cfg.tile_rows, r.plan.slot_shift, r.acc, ctx->dev_flags);
+    hipLaunchKernelGGL((k_batch_phase<int32_t, false>), dim3(gp), dim3(cfg.block), 0, s, r.jobs_dev, J,
+                       r.plan.probe_tiles, cfg.tile_rows, r.plan.slot_shift, r.acc, ctx->dev_flags);
+  }
   VX_HIP(hipGetLastError());
   if (host_out) {
     VX_HIP(hipMemcpyAsync(host_out, r.acc, 2 * (uint64_t)J * 8, hipMemcpyDeviceToHost, s));
@@ -385,15 +379,15 @@ static vx_status time_config(vx_ctx* ctx, const vx_batch_join* d, const BatchCon
   BatchRun r;
   VX_TRY(setup_run(ctx, d, cfg, ks, ps, &r));
   hipEvent_t a = get_event(ctx), b = get_event(ctx);
-  VX_TRY(enqueue_persistent(ctx, r, cfg, ks, d->n_jobs, ctx->compute, nullptr));   // warm
+  VX_TRY(enqueue_batch(ctx, r, cfg, ks, d->n_jobs, ctx->compute, nullptr));   // warm
   VX_HIP(hipEventRecord(a, ctx->compute));
-  VX_TRY(enqueue_persistent(ctx, r, cfg, ks, d->n_jobs, ctx->compute, nullptr));
+  VX_TRY(enqueue_batch(ctx, r, cfg, ks, d->n_jobs, ctx->compute, nullptr));
   VX_HIP(hipEventRecord(b, ctx->compute));
   VX_HIP(hipEventSynchronize(b));
   VX_HIP(hipEventElapsedTime(ms, a, b));
   put_event(ctx, a);
   put_event(ctx, b);
-  return VX_OK;
+  return check_flags(ctx, "batch autotune");
 }
 
 static vx_status autotune(vx_ctx* ctx, const vx_batch_join* d, int ks, uint32_t ps, BatchConfig* best) {
@@ -415,10 +409,26 @@ static vx_status autotune(vx_ctx* ctx, const vx_batch_join* d, int ks, uint32_t 
   return VX_OK;
 }
 
+struct JobKey {
+  const void *bkey, *bpay, *pkey;
+  uint64_t nb, np;
+  bool operator==(const JobKey& o) const {
+    return bkey == o.bkey && bpay == o.bpay && pkey == o.pkey && nb == o.nb && np == o.np;
+  }
+};
+
+static std::vector<JobKey> job_keys(const vx_batch_join* d) {
+  std::vector<JobKey> k(d->n_jobs);
+  for (uint32_t j = 0; j < d->n_jobs; ++j)
+    k[j] = {d->build_key[j].data, d->build_pay ? d->build_pay[j].data : nullptr, d->probe_key[j].data,
+            d->n_build[j], d->n_probe[j]};
+  return k;
+}
+
 struct GraphCache {
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
-  std::vector<BatchJob> key;
+  std::vector<JobKey> key;
   BatchConfig cfg;
   BatchRun* run = nullptr;
 };
@@ -433,15 +443,6 @@ static void drop_graph(GraphCache* g) {
   delete g;
 }
 
-static bool same_jobs(const std::vector<BatchJob>& a, const vx_batch_join* d) {
-  if (a.size() != d->n_jobs) return false;
-  for (uint32_t j = 0; j < d->n_jobs; ++j)
-    if (a[j].bkey != d->build_key[j].data || a[j].pkey != d->probe_key[j].data ||
-        a[j].nb != d->n_build[j] || a[j].np != d->n_probe[j] ||
-        a[j].bpay != (d->build_pay ? d->build_pay[j].data : nullptr))
-      return false;
-  return true;
-}
 
 void batch_release_ctx(const vx_ctx* ctx) {
   auto it = g_graphs.find(ctx);
@@ -491,26 +492,22 @@ vx_status join_batch(vx_ctx* ctx, const vx_batch_join* d, vx_join_out* out) {
   VX_CHECK(cfg.load_factor > 0.05f && cfg.load_factor <= 0.95f, VX_EINVAL, "batch: load factor");
 
   std::vector<uint64_t> host(2 * (uint64_t)J + 1, 0);
+  std::vector<uint32_t> order;   // baseline: tile order of its plan
   vx_stats& s = out->stats;
   std::memset(&s, 0, sizeof s);
   if (d->mode == 0) {
     GraphCache*& gc = g_graphs[ctx];
-    if (!gc || !same_jobs(gc->key, d) || gc->cfg.tile_rows != cfg.tile_rows || gc->cfg.block != cfg.block ||
+    if (!gc || !(gc->key == job_keys(d)) || gc->cfg.tile_rows != cfg.tile_rows || gc->cfg.block != cfg.block ||
         gc->cfg.load_factor != cfg.load_factor) {
       drop_graph(gc);
       gc = new GraphCache;
       gc->run = new BatchRun;
       gc->cfg = cfg;
       VX_TRY(setup_run(ctx, d, cfg, ks, ps, gc->run));
-      gc->key = gc->run->plan.jobs;
-      for (uint32_t j = 0; j < J; ++j) {   // keep the caller's pointers for the comparison
-        gc->key[j].bkey = d->build_key[j].data;
-        gc->key[j].pkey = d->probe_key[j].data;
-        gc->key[j].bpay = d->build_pay ? d->build_pay[j].data : nullptr;
-      }
+      gc->key = job_keys(d);
       VX_HIP(hipStreamSynchronize(ctx->compute));
       VX_HIP(hipStreamBeginCapture(ctx->compute, hipStreamCaptureModeThreadLocal));
-      vx_status cst = enqueue_persistent(ctx, *gc->run, cfg, ks, J, ctx->compute, ctx->host_acc);
+      vx_status cst = enqueue_batch(ctx, *gc->run, cfg, ks, J, ctx->compute, ctx->host_acc);
       hipError_t ce = hipStreamEndCapture(ctx->compute, &gc->graph);
       VX_TRY(cst);
       VX_HIP(ce);
@@ -529,9 +526,9 @@ vx_status join_batch(vx_ctx* ctx, const vx_batch_join* d, vx_join_out* out) {
     unsigned int f = 0;
     std::memcpy(&f, ctx->host_acc + 2 * (uint64_t)J, 4);
     VX_CHECK(!(f & kFlagDup), VX_EDUPKEY, "batch: duplicate build key");
-    VX_CHECK(!(f & kFlagFull), VX_ECAPACITY, "batch: table full or build wait expired");
+    VX_CHECK(!(f & kFlagFull), VX_ECAPACITY, "batch: table full (internal sizing error)");
     s.kernel_ms = ms;
-    s.kernel_launches = 1;
+    s.kernel_launches = 2;
     s.table_bytes = gc->run->plan.slots << gc->run->plan.slot_shift;
     s.chunk_rows = cfg.tile_rows;
     s.n_buffers = cfg.block;
@@ -540,7 +537,7 @@ vx_status join_batch(vx_ctx* ctx, const vx_batch_join* d, vx_join_out* out) {
     BatchRun r;
     VX_TRY(setup_run(ctx, d, cfg, ks, ps, &r));
     uint32_t sw = (1u << r.plan.slot_shift) / 4;
-    fill_zero((uint64_t*)r.next, r.counter_words, ctx->compute);
+    fill_zero((uint64_t*)r.counters, r.counter_words, ctx->compute);
     fill_zero((uint64_t*)ctx->dev_flags, 1, ctx->compute);
     hipEvent_t a = get_event(ctx), b = get_event(ctx);
     VX_HIP(hipEventRecord(a, ctx->compute));
@@ -575,15 +572,19 @@ vx_status join_batch(vx_ctx* ctx, const vx_batch_join* d, vx_join_out* out) {
     put_event(ctx, a);
     put_event(ctx, b);
     VX_TRY(check_flags(ctx, "batch"));
+    order = r.plan.job_of;
     s.kernel_ms = ms;
     s.kernel_launches = 3 * (uint64_t)J;
     s.table_bytes = r.plan.slots << r.plan.slot_shift;
   }
+  // accumulators are in tile order: entry i belongs to the caller's job job_of[i]
+  const std::vector<uint32_t>& job_of = d->mode == 0 ? g_graphs[ctx]->run->plan.job_of : order;
   uint64_t rows = 0;
-  for (uint32_t j = 0; j < J; ++j) {
+  for (uint32_t i = 0; i < J; ++i) {
+    const uint32_t j = job_of[i];
     std::memset(&d->out[j], 0, sizeof(vx_agg));
-    d->out[j].match_count = host[2 * j];
-    d->out[j].sum[0] = host[2 * j + 1];
+    d->out[j].match_count = host[2 * i];
+    d->out[j].sum[0] = host[2 * i + 1];
     rows += d->n_probe[j];
   }
   s.rows = rows;

@@ -32,7 +32,7 @@ def _jobs(n_jobs, seed, b_lo=1 << 10, b_hi=1 << 16):
     return [datagen.batch_job(j, int(b[j]), int(p[j]), seed=seed) for j in range(n_jobs)]
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [1, 0])
 def test_batch_matches_oracle(gpu, ctx, mode):
     jobs = _jobs(24, 41)
     _say("batch mode", mode)
@@ -58,7 +58,7 @@ def test_batch_explicit_configs_and_graph_replay(gpu, ctx):
         assert got == exp
         torch.cuda.synchronize()
         _ = (args[2][0] + 1).sum().item()
-    assert st["kernel_launches"] == 1
+    assert st["kernel_launches"] == 2     # one graph: build phase and probe phase
 
 
 def test_batch_edges(gpu, ctx):
