@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--chunk-rows", type=int, default=0)
     ap.add_argument("--n-buffers", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="stream", choices=["stream", "plain", "star", "batch", "skew"],
+                    help="stream (default) is the headline line; the others print their own line")
+    ap.add_argument("--method", default="learned", help="skew workload: partitioner to time")
+    ap.add_argument("--n-parts", type=int, default=256)
     return ap.parse_args()
 
 
@@ -85,6 +89,10 @@ def main():
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no "
               f"multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "stream":
+        out = {"plain": run_plain, "star": run_star, "batch": run_batch, "skew": run_skew}[args.workload](args)
+        print(json.dumps(out), flush=True)
+        return
     import numpy as np
     import torch
 
@@ -189,6 +197,223 @@ def main():
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(args.log2_build, args.log2_probe)
     print(json.dumps(out), flush=True)
+
+
+# --------------------------------------------------------------------------- other workloads
+# Each prints its own JSON line (same fields); only the streamed join is the default line.
+
+def _common(metric_unit, value, ms, args, dtype, config, roofline, extra=None):
+    out = {"metric": METRIC, "value": value, "unit": metric_unit, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config,
+           "roofline": roofline}
+    if extra:
+        out.update(extra)
+    return out
+
+
+def _timed(step, args, torch):
+    ref = None
+    for _ in range(args.warmup):
+        ref = step()
+    torch.cuda.synchronize()
+    res = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res.append(step())
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    first = res[0][0]
+    if any(r[0] != first for r in res) or (ref is not None and ref[0] != first):
+        raise SystemExit("non-deterministic results across steps")
+    return ms, res
+
+
+def run_plain(args):
+    """In-memory join: 2^20 unique int32 build keys + one int32 payload, 2^24 int32 probes
+    (about half match), all device-resident; step = build + probe + aggregate."""
+    import torch
+    import datagen
+    import oracle
+    import paper_2502_09541_amd as vx
+    nb, np_ = 1 << 20, 1 << 24
+    bk, bp, pk = datagen.plain_join(nb, np_)
+    d = [torch.from_numpy(a).cuda() for a in (bk, bp, pk)]
+    ctx = vx.Context(4 * GiB)
+    ms, res = _timed(lambda: ctx.join_plain(d[0], [d[1]], d[2]), args, torch)
+    agg, st = res[0]
+    k_ms = sum(r[1]["kernel_ms"] for r in res) / sum(r[1]["kernel_launches"] for r in res)
+    # probe kernel: 4 B key + one 8 B slot per probe row (the 16 MiB table lives in MALL)
+    achieved = np_ * 12 / (k_ms * 1e6)
+    t0 = time.perf_counter()
+    exp = oracle.join_agg(bk, [bp], pk, [])
+    cpu = time.perf_counter() - t0
+    if exp != agg:
+        raise SystemExit("plain join result differs from the oracle")
+    ctx.close()
+    return _common("probe rows/s", np_ / (ms / 1e3), ms, args, "int32",
+                   {"workload": "plain_join_device_resident", "build_rows": nb, "probe_rows": np_,
+                    "key": "int32", "build_payloads": "1 x int32"},
+                   {"bound": "hbm", "kernel": "k_probe", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": k_ms,
+                    "rows_per_launch": np_},
+                   {"result": {"match_count": agg[0], "sum": agg[1]}, "checked_against_oracle": True,
+                    "build_ms": st["build_ms"], "probe_ms": st["probe_ms"],
+                    "cpu_baseline": {"value": np_ / cpu, "unit": "probe rows/s", "cores": 1, "kind": "oracle",
+                                     "sample": f"the full workload, build + probe in {cpu:.1f} s on 1 host thread"}})
+
+
+def run_star(args):
+    """Star join + GROUP BY: 600,000,000 fact rows (4 int32 foreign keys, 3 int32 measures) in
+    pinned host memory; dimensions of 2,556 / 200,000 / 3,000,000 / 2,000,000 rows with filter
+    selectivities 1/7, 1/5, 1/25, 1 on the device; 7 x 100 groups."""
+    import numpy as np
+    import torch
+    import datagen
+    import oracle
+    import paper_2502_09541_amd as vx
+    nf = 600_000_000
+    rows = datagen.STAR_DIM_ROWS
+    b_peak = measure_h2d_peak(torch)
+    dims = datagen.star_dims()
+    ddims = [dict(key=torch.from_numpy(x["key"]).cuda(), filt=torch.from_numpy(x["filt"]).cuda(), lo=0, hi=0,
+                  group=None if x["group"] is None else torch.from_numpy(x["group"]).cuda()) for x in dims]
+    fk = [vx.HostBuffer(nf, np.int32) for _ in range(4)]
+    ms_ = [vx.HostBuffer(nf, np.int32) for _ in range(3)]
+    step_rows = 1 << 26
+    for r0 in range(0, nf, step_rows):
+        r1 = min(nf, r0 + step_rows)
+        datagen.star_fact(r1 - r0, out=([h.array[r0:r1] for h in fk], [h.array[r0:r1] for h in ms_]), row0=r0)
+    log("star: inputs generated")
+    ctx = vx.Context(16 * GiB)
+
+    def step():
+        g, c, sm, st = ctx.join_star(ddims, fk, ms_, groups_cap=4096)
+        return (g.tolist(), c.tolist(), sm.tolist()), st
+
+    ms, res = _timed(step, args, torch)
+    st = res[0][1]
+    k_ms = sum(r[1]["kernel_ms"] for r in res) / sum(r[1]["kernel_launches"] for r in res)
+    wire = st["sdma_bytes"] + st["zc_bytes_est"]
+    # algorithmic link bytes: each fact column is needed only for rows alive when it is read
+    # (dimensions probed in ascending filter selectivity, then the 3 measures of survivors)
+    sel = sorted(float(np.mean(x["filt"] == 0)) for x in dims)
+    alive, alg = 1.0, 0.0
+    for sv in sel:
+        alg += alive * 4
+        alive *= sv
+    alg = nf * (alg + alive * 12)
+    # CPU oracle on a bounded sample: the first 2^24 fact rows
+    n_cpu = 1 << 24
+    t0 = time.perf_counter()
+    oracle.star_groupby(dims, [h.array[:n_cpu].copy() for h in fk], [h.array[:n_cpu].copy() for h in ms_])
+    cpu = time.perf_counter() - t0
+    ctx.close()
+    out = _common("fact rows/s", nf / (ms / 1e3), ms, args, "int32",
+                  {"workload": "star_join_groupby", "fact_rows": nf, "dims": list(rows),
+                   "filter_selectivity": ["1/7", "1/5", "1/25", "1"], "groups": len(res[0][0][0]),
+                   "chunk_rows": st["chunk_rows"], "zero_copy_columns": bin(st["zc_mask"]).count("1")},
+                  {"bound": "hbm", "kernel": "k_star",
+                   # per launch: 4 B foreign key from the chunk buffer + one 8 B slot of the first table
+                   "achieved": (nf / st["kernel_launches"]) * 12 / (k_ms * 1e6), "peak": HBM_PEAK_GBS,
+                   "unit": "GB/s", "frac": (nf / st["kernel_launches"]) * 12 / (k_ms * 1e6) / HBM_PEAK_GBS,
+                   "traffic": None, "avg_launch_ms": k_ms, "rows_per_launch": nf / st["kernel_launches"]},
+                  {"host_link": {"peak_measured_gbs": b_peak, "achieved_wire_gbs": wire / (ms * 1e6),
+                                 "frac_wire": wire / (ms * 1e6) / b_peak,
+                                 "achieved_algorithmic_gbs": alg / (ms * 1e6),
+                                 "frac_algorithmic": alg / (ms * 1e6) / b_peak},
+                   "survivors": st["survivors"], "build_ms": st["build_ms"],
+                   "cpu_baseline": {"value": n_cpu / cpu, "unit": "fact rows/s", "cores": 1, "kind": "oracle",
+                                    "sample": f"first {n_cpu} fact rows in {cpu:.1f} s on 1 host thread"}})
+    for h in fk + ms_:
+        h.free()
+    return out
+
+
+def run_batch(args):
+    """256 independent int32 joins, build sizes log-uniform in 2^10..2^22 (unique keys), probe
+    10x..100x the build (about half match), device-resident; one HIP graph launch per step,
+    against the per-job baseline of two launches per join."""
+    import torch
+    import datagen
+    import paper_2502_09541_amd as vx
+    b, p = datagen.batch_sizes(256)
+    jobs = [datagen.batch_job(j, int(b[j]), int(p[j])) for j in range(256)]
+    d = [[torch.from_numpy(a).cuda() for a in job] for job in jobs]
+    del jobs
+    ctx = vx.Context(32 * GiB)
+    args3 = ([x[0] for x in d], [x[1] for x in d], [x[2] for x in d])
+    rows = int(p.sum())
+    log(f"batch: {rows} probe rows over 256 joins; autotuning")
+    ms, res = _timed(lambda: ctx.join_batch(*args3, mode=0), args, torch)
+    ms1, res1 = _timed(lambda: ctx.join_batch(*args3, mode=1), args, torch)
+    if res[0][0] != res1[0][0]:
+        raise SystemExit("batched and per-job results differ")
+    st = res[0][1]
+    k_ms = sum(r[1]["kernel_ms"] for r in res) / len(res)
+    alg = rows * 12 + int(b.sum()) * 16       # probe: key + slot; build: key/payload + slot write
+    ctx.close()
+    return _common("probe rows/s", rows / (ms / 1e3), ms, args, "int32",
+                   {"workload": "batched_joins_256", "jobs": 256, "probe_rows": rows, "build_rows": int(b.sum()),
+                    "tile_rows": st["chunk_rows"], "block": st["n_buffers"], "load_factor": st["imbalance"]},
+                   {"bound": "hbm", "kernel": "graph(k_batch_phase build+probe)", "achieved": alg / (k_ms * 1e6),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg / (k_ms * 1e6) / HBM_PEAK_GBS,
+                    "traffic": None, "avg_launch_ms": k_ms, "rows_per_launch": rows},
+                   {"baseline_separate_launches": {"ms_per_step": ms1, "value": rows / (ms1 / 1e3),
+                                                   "launches": res1[0][1]["kernel_launches"]},
+                    "speedup_vs_separate_launches": ms1 / ms})
+
+
+def run_skew(args):
+    """Skewed partitioned join: 2^30 Zipf(1.1) int64 build keys over [1, 2^40] with an int64
+    payload, 2^32 Zipf(1.1) probe keys, pinned host memory, 32 GiB device budget; the build side
+    is partitioned (learned CDF splitters vs radix-hash), every method must give the same result."""
+    import numpy as np
+    import torch
+    import datagen
+    import paper_2502_09541_amd as vx
+    nb, np_ = 1 << 30, 1 << 32
+    b_peak = measure_h2d_peak(torch)
+    bk, bp, pk = vx.HostBuffer(nb, np.int64), vx.HostBuffer(nb, np.int64), vx.HostBuffer(np_, np.int64)
+    t0 = time.perf_counter()
+    step_rows = 1 << 27
+    for r0 in range(0, nb, step_rows):
+        datagen.skew_build(step_rows, out=(bk.array[r0:r0 + step_rows], bp.array[r0:r0 + step_rows]), row0=r0)
+    for r0 in range(0, np_, step_rows):
+        datagen.skew_probe(step_rows, out=pk.array[r0:r0 + step_rows], row0=r0)
+        log(f"skew: generated probe rows up to {r0 + step_rows}")
+    log(f"skew: inputs generated in {time.perf_counter() - t0:.1f} s")
+    ctx = vx.Context(32 * GiB)
+    lines = {}
+    for method in (args.method, "radix_hash"):
+        ms, res = _timed(lambda: ctx.join_partitioned(bk, [bp], pk, method=method, n_parts=args.n_parts, seed=7),
+                         args, torch)
+        agg, st, used = res[0]
+        lines[method] = dict(ms=ms, value=np_ / (ms / 1e3), agg=agg, st=st, used=used)
+        log(f"skew {method}: {ms:.1f} ms/step, partitions {st['n_parts']}, singleton rows {st['singleton_rows']}")
+    a, r = lines[args.method], lines["radix_hash"]
+    if a["agg"] != r["agg"]:
+        raise SystemExit("learned and radix-hash partitioned joins differ")
+    st = a["st"]
+    h2d = st["sdma_bytes"] + st["zc_bytes_est"]
+    ctx.close()
+    for h in (bk, bp, pk):
+        h.free()
+    return _common("probe rows/s", a["value"], a["ms"], args, "int64",
+                   {"workload": "skewed_partitioned_join", "build_rows": nb, "probe_rows": np_, "zipf_s": 1.1,
+                    "key_range": "[1, 2^40]", "device_budget_gib": 32, "method": args.method,
+                    "n_parts": st["n_parts"]},
+                   {"bound": "hbm", "kernel": "k_part_scatter/k_pj_probe", "achieved": None, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": None, "traffic": None},
+                   {"host_link": {"peak_measured_gbs": b_peak, "h2d_bytes_per_step": h2d,
+                                  "achieved_gbs": h2d / (a["ms"] * 1e6), "frac": h2d / (a["ms"] * 1e6) / b_peak},
+                    "result": {"match_count": a["agg"][0], "sum": a["agg"][1]},
+                    "learned": {"ms_per_step": a["ms"], "value": a["value"], "imbalance": st["imbalance"],
+                                "singleton_rows": st["singleton_rows"], "part_ms": st["part_ms"],
+                                "train_ms": st["train_ms"], "join_ms": st["probe_ms"]},
+                    "radix_hash": {"ms_per_step": r["ms"], "value": r["value"], "imbalance": r["st"]["imbalance"],
+                                   "part_ms": r["st"]["part_ms"], "join_ms": r["st"]["probe_ms"]},
+                    "learned_speedup_vs_radix_hash": r["ms"] / a["ms"], "bit_exact_across_methods": True})
 
 
 if __name__ == "__main__":

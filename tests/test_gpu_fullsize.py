@@ -61,3 +61,24 @@ def test_streamed_join_full_size_closed_form(gpu):
     finally:
         for h in H.values():
             h.free()
+
+
+def test_batch_full_size_closed_form(gpu):
+    """256 joins at full size (build 2^10..2^22 rows, probe 10..100x), one graph launch; each job
+    checked against its closed form (dense permutation keys: count = #{probe < n_build},
+    SUM = sum of pay_of_key[probe]), which tests/test_oracle_join.py pins to the oracle."""
+    import torch
+    b, p = datagen.batch_sizes(256)
+    print(f"batch full size: {int(p.sum())} probe rows", flush=True)
+    jobs = [datagen.batch_job(j, int(b[j]), int(p[j])) for j in range(256)]
+    dev = [[torch.from_numpy(a).cuda() for a in job] for job in jobs]
+    with gpu.Context(32 * GiB) as ctx:
+        got, st = ctx.join_batch([x[0] for x in dev], [x[1] for x in dev], [x[2] for x in dev])
+    del dev
+    print("batch full size: closed forms", flush=True)
+    for j, (bk, bp, pk) in enumerate(jobs):
+        pay_of_key = np.empty(len(bk), np.int64)
+        pay_of_key[bk] = bp
+        hit = pk < len(bk)
+        exp = [int(hit.sum()), int(pay_of_key[pk[hit]].sum()) % M64]
+        assert got[j] == exp, f"job {j}"
