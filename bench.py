@@ -41,30 +41,11 @@ def parse():
     ap.add_argument("--chunk-rows", type=int, default=0)
     ap.add_argument("--n-buffers", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="stream", choices=["stream", "plain", "star", "batch", "skew"],
+    ap.add_argument("--workload", default="stream", choices=["stream", "plain", "star", "batch", "skew", "calib"],
                     help="stream (default) is the headline line; the others print their own line")
     ap.add_argument("--method", default="learned", help="skew workload: partitioner to time")
     ap.add_argument("--n-parts", type=int, default=256)
     return ap.parse_args()
-
-
-def measure_h2d_peak(torch, total=GiB, chunk=64 << 20):
-    """Pinned hipMemcpyAsync host-to-device rate over `total` bytes in `chunk` pieces."""
-    h = torch.empty(total, dtype=torch.uint8, pin_memory=True)
-    d = torch.empty(total, dtype=torch.uint8, device="cuda")
-    s = torch.cuda.Stream()
-    best = 0.0
-    for _ in range(3):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        with torch.cuda.stream(s):
-            e0.record(s)
-            for off in range(0, total, chunk):
-                d[off:off + chunk].copy_(h[off:off + chunk], non_blocking=True)
-            e1.record(s)
-        e1.synchronize()
-        best = max(best, total / (e0.elapsed_time(e1) * 1e6))
-    del h, d
-    return best
 
 
 def cpu_baseline(log2_build, log2_probe):
@@ -90,7 +71,8 @@ def main():
               f"multi-GPU path", file=sys.stderr)
         sys.exit(2)
     if args.workload != "stream":
-        out = {"plain": run_plain, "star": run_star, "batch": run_batch, "skew": run_skew}[args.workload](args)
+        out = {"plain": run_plain, "star": run_star, "batch": run_batch, "skew": run_skew,
+               "calib": run_calib}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
     import numpy as np
@@ -101,8 +83,10 @@ def main():
 
     nb, np_ = 1 << args.log2_build, 1 << args.log2_probe
     log(f"workload: build {nb} rows, probe {np_} rows, budget {args.budget_gib} GiB")
-    b_peak = measure_h2d_peak(torch)
-    log(f"measured H2D peak {b_peak:.2f} GB/s")
+    ctx = vx.Context(int(args.budget_gib * GiB))
+    calib = ctx.calibrate()
+    b_peak = calib["h2d_gbs"]
+    log(f"measured H2D peak {b_peak:.2f} GB/s, zero-copy granule {calib['zc_granule']} B")
 
     t0 = time.perf_counter()
     H = {}
@@ -119,8 +103,6 @@ def main():
         datagen.stream_probe(nb, r1 - r0, out=(H["pk"].array[r0:r1], H["p0"].array[r0:r1],
                                                H["p1"].array[r0:r1]), row0=r0)
     log(f"generated inputs in {time.perf_counter() - t0:.1f} s")
-
-    ctx = vx.Context(int(args.budget_gib * GiB))
 
     def step():
         return ctx.join_plain(H["bk"], [H["b0"], H["b1"]], H["pk"], [H["p0"], H["p1"]],
@@ -189,6 +171,7 @@ def main():
                       "frac_algorithmic": alg_bytes / (ms * 1e6) / b_peak,
                       "wire_bytes_per_step": wire_bytes, "algorithmic_bytes_per_step": alg_bytes},
         "result": {"match_count": count, "sums": results[0][1:]},
+        "calibration": calib,
     }
     ctx.close()
     for h in H.values():
@@ -227,6 +210,15 @@ def _timed(step, args, torch):
     if any(r[0] != first for r in res) or (ref is not None and ref[0] != first):
         raise SystemExit("non-deterministic results across steps")
     return ms, res
+
+
+def run_calib(args):
+    """The link and memory denominators (vx_calibrate over 4 GiB of pinned memory)."""
+    import paper_2502_09541_amd as vx
+    ctx = vx.Context(8 * GiB)
+    c = ctx.calibrate(4 * GiB)
+    ctx.close()
+    return {"metric": "host link / device memory calibration", "calibration": c, "n_gpus": 1}
 
 
 def run_plain(args):
@@ -274,7 +266,6 @@ def run_star(args):
     import paper_2502_09541_amd as vx
     nf = 600_000_000
     rows = datagen.STAR_DIM_ROWS
-    b_peak = measure_h2d_peak(torch)
     dims = datagen.star_dims()
     ddims = [dict(key=torch.from_numpy(x["key"]).cuda(), filt=torch.from_numpy(x["filt"]).cuda(), lo=0, hi=0,
                   group=None if x["group"] is None else torch.from_numpy(x["group"]).cuda()) for x in dims]
@@ -286,6 +277,7 @@ def run_star(args):
         datagen.star_fact(r1 - r0, out=([h.array[r0:r1] for h in fk], [h.array[r0:r1] for h in ms_]), row0=r0)
     log("star: inputs generated")
     ctx = vx.Context(16 * GiB)
+    b_peak = ctx.calibrate()["h2d_gbs"]
 
     def step():
         g, c, sm, st = ctx.join_star(ddims, fk, ms_, groups_cap=4096)
@@ -373,7 +365,6 @@ def run_skew(args):
     import datagen
     import paper_2502_09541_amd as vx
     nb, np_ = 1 << 30, 1 << 32
-    b_peak = measure_h2d_peak(torch)
     bk, bp, pk = vx.HostBuffer(nb, np.int64), vx.HostBuffer(nb, np.int64), vx.HostBuffer(np_, np.int64)
     t0 = time.perf_counter()
     step_rows = 1 << 27
@@ -384,16 +375,17 @@ def run_skew(args):
         log(f"skew: generated probe rows up to {r0 + step_rows}")
     log(f"skew: inputs generated in {time.perf_counter() - t0:.1f} s")
     ctx = vx.Context(32 * GiB)
+    b_peak = ctx.calibrate()["h2d_gbs"]
     lines = {}
-    for method in (args.method, "radix_hash"):
+    for method in (args.method, "quantile", "radix_hash"):
         ms, res = _timed(lambda: ctx.join_partitioned(bk, [bp], pk, method=method, n_parts=args.n_parts, seed=7),
                          args, torch)
         agg, st, used = res[0]
         lines[method] = dict(ms=ms, value=np_ / (ms / 1e3), agg=agg, st=st, used=used)
         log(f"skew {method}: {ms:.1f} ms/step, partitions {st['n_parts']}, singleton rows {st['singleton_rows']}")
     a, r = lines[args.method], lines["radix_hash"]
-    if a["agg"] != r["agg"]:
-        raise SystemExit("learned and radix-hash partitioned joins differ")
+    if a["agg"] != r["agg"] or lines["quantile"]["agg"] != r["agg"]:
+        raise SystemExit("partitioned join results differ across partitioners")
     st = a["st"]
     h2d = st["sdma_bytes"] + st["zc_bytes_est"]
     ctx.close()
@@ -413,6 +405,9 @@ def run_skew(args):
                                 "train_ms": st["train_ms"], "join_ms": st["probe_ms"]},
                     "radix_hash": {"ms_per_step": r["ms"], "value": r["value"], "imbalance": r["st"]["imbalance"],
                                    "part_ms": r["st"]["part_ms"], "join_ms": r["st"]["probe_ms"]},
+                    "sample_quantile": {"ms_per_step": lines["quantile"]["ms"], "value": lines["quantile"]["value"],
+                                        "imbalance": lines["quantile"]["st"]["imbalance"],
+                                        "singleton_rows": lines["quantile"]["st"]["singleton_rows"]},
                     "learned_speedup_vs_radix_hash": r["ms"] / a["ms"], "bit_exact_across_methods": True})
 
 

@@ -85,12 +85,31 @@ vx_status vx_ctx_destroy(vx_ctx* ctx);
 /* Thread-local text describing the last non-OK status (never NULL). */
 const char* vx_last_error(void);
 
-/* Bytes of the arena currently held by live tables. */
+/* Bytes of the arena currently held by the context and live tables. */
 uint64_t vx_ctx_arena_used(const vx_ctx* ctx);
 
 /* Pinned, device-mapped host memory for columns (page-locked; freed with vx_host_free). */
 vx_status vx_host_alloc(uint64_t bytes, void** out);
 vx_status vx_host_free(void* p);
+
+/*
+ * Measure the host link and device memory on this machine: host-to-device copy rate (64 MiB
+ * copies), zero-copy read rate (contiguous and strided) and the zero-copy transfer granule (the
+ * largest stride at which every touched line still crosses the link), and a device streaming
+ * read.  `pinned` is caller-owned pinned host memory of `bytes` (>= 64 MiB) whose contents are
+ * read only.  The granule becomes the line size of the context's late-materialization model
+ * (Sec. 6.3, C_l2); before a calibration it is 128 bytes.
+ */
+typedef struct {
+  double h2d_gbs;
+  double zc_read_gbs;
+  double hbm_read_gbs;
+  uint32_t zc_granule;
+  uint32_t zc_stride_bytes[8];
+  double zc_stride_gelems[8];   /* elements per ns at each stride */
+} vx_link_calib;
+
+vx_status vx_calibrate(vx_ctx* ctx, void* pinned, uint64_t bytes, vx_link_calib* out);
 
 /* ------------------------------------------------------------------------ statistics */
 
@@ -99,7 +118,7 @@ typedef struct {
   uint64_t chunks;          /* chunks streamed (0: device-resident input) */
   uint64_t chunk_rows;      /* rows per chunk used */
   uint64_t sdma_bytes;      /* bytes copied host-to-device by the copy stream */
-  uint64_t zc_bytes_est;    /* zero-copy bytes read, estimated as touched 128-byte lines */
+  uint64_t zc_bytes_est;    /* zero-copy bytes read, estimated as touched lines of the granule */
   uint32_t zc_mask;         /* bit c set: probe payload / fact column c read by zero-copy */
   uint32_t n_buffers;       /* chunk buffers used by the pipeline */
   double build_ms;          /* wall time of the build phase */
@@ -138,8 +157,8 @@ typedef struct vx_table vx_table;
 /*
  * Build a device hash table over the build side (the table the paper keeps in
  * GPU memory while the other side streams, Sec. 5.1, 7.1).  Host-resident
- * build columns are streamed through the context's chunk buffers.  The table
- * is carved from the arena and owned by the library until vx_table_destroy.
+ * build columns are read in place by zero-copy.  The table is carved from the
+ * arena and owned by the library until vx_table_destroy.
  */
 vx_status vx_build(vx_ctx* ctx, const vx_build_desc* desc, vx_table** out);
 vx_status vx_table_destroy(vx_table* table);
@@ -155,7 +174,8 @@ enum {
                           than streaming, with the selectivity measured on the first chunk */
   VX_LATE_SDMA = 0,    /* stream every payload column with the keys */
   VX_LATE_ZC = 1,      /* read payload columns of matching rows by zero-copy */
-  VX_LATE_PAPER = 2    /* the paper's rule: zero-copy iff selectivity < E / (C_l2 * 1) */
+  VX_LATE_PAPER = 2    /* the paper's rule: zero-copy iff selectivity < E / (C_l2 * 1), with C_l2 the
+                          context's zero-copy granule */
 };
 
 typedef struct {

@@ -59,6 +59,12 @@ class Stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class LinkCalib(C.Structure):
+    _fields_ = [("h2d_gbs", C.c_double), ("zc_read_gbs", C.c_double), ("hbm_read_gbs", C.c_double),
+                ("zc_granule", C.c_uint32), ("zc_stride_bytes", C.c_uint32 * 8),
+                ("zc_stride_gelems", C.c_double * 8)]
+
+
 class BuildDesc(C.Structure):
     _fields_ = [("key", Col), ("pay", C.POINTER(Col)), ("n_pay", C.c_uint32), ("flags", C.c_uint32),
                 ("n", C.c_uint64), ("load_factor", C.c_float), ("reserved", C.c_uint32)]
@@ -146,7 +152,7 @@ class PartitionOut(C.Structure):
 
 EXPORTS = ["vx_ctx_create", "vx_ctx_destroy", "vx_last_error", "vx_ctx_arena_used", "vx_host_alloc",
            "vx_host_free", "vx_build", "vx_table_destroy", "vx_probe_stream", "vx_join_agg",
-           "vx_partition", "vx_cdf_loss_grad", "vx_cdf_forward", "vx_cdf_train"]
+           "vx_partition", "vx_cdf_loss_grad", "vx_cdf_forward", "vx_cdf_train", "vx_calibrate"]
 N_MODEL_PARAMS = 193
 
 
@@ -175,9 +181,10 @@ def lib():
     L.vx_cdf_loss_grad.argtypes = [vp, vp, vp, C.c_uint64, fp, fp, C.POINTER(C.c_double)]
     L.vx_cdf_forward.argtypes = [vp, vp, C.c_uint64, fp, fp]
     L.vx_cdf_train.argtypes = [vp, vp, vp, C.c_uint64, fp, C.c_uint32, C.c_float, C.POINTER(C.c_double)]
+    L.vx_calibrate.argtypes = [vp, vp, C.c_uint64, C.POINTER(LinkCalib)]
     for name in ("vx_ctx_create", "vx_ctx_destroy", "vx_host_alloc", "vx_host_free", "vx_build",
                  "vx_table_destroy", "vx_probe_stream", "vx_join_agg", "vx_partition",
-                 "vx_cdf_loss_grad", "vx_cdf_forward", "vx_cdf_train"):
+                 "vx_cdf_loss_grad", "vx_cdf_forward", "vx_cdf_train", "vx_calibrate"):
         getattr(L, name).restype = st
     _lib = L
     return L
@@ -275,6 +282,19 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def calibrate(self, nbytes=1 << 30):
+        """vx_calibrate over a fresh pinned buffer; returns a dict of the measured rates."""
+        hb = HostBuffer(nbytes // 8, np.int64)
+        hb.array[:] = 1
+        c = LinkCalib()
+        try:
+            _check(lib().vx_calibrate(self.h, hb.ptr, nbytes, C.byref(c)))
+        finally:
+            hb.free()
+        return {"h2d_gbs": c.h2d_gbs, "zc_read_gbs": c.zc_read_gbs, "hbm_read_gbs": c.hbm_read_gbs,
+                "zc_granule": c.zc_granule,
+                "zc_stride": {int(c.zc_stride_bytes[i]): c.zc_stride_gelems[i] for i in range(8)}}
 
     def arena_used(self):
         return int(lib().vx_ctx_arena_used(self.h))

@@ -112,6 +112,7 @@ struct vx_ctx {
   uint8_t* host_scratch = nullptr;
   uint64_t host_scratch_bytes = 0;
   std::vector<hipEvent_t> ev_pool;
+  uint32_t zc_line = 128;   // zero-copy transfer granule (bytes), measured by vx_calibrate
 };
 
 namespace vx {
@@ -134,10 +135,8 @@ void put_event(vx_ctx* ctx, hipEvent_t e);
 void fill_zero(uint64_t* p, uint64_t words, hipStream_t s);
 
 // Estimated zero-copy wire bytes of reading `count` matching rows, of elsize bytes each,
-// spread over `n` rows: the touched 128-byte lines under independent selection.
-double zc_wire_bytes(uint64_t n, uint64_t count, int elsize);
-
-constexpr uint64_t kZcLine = 128;       // zero-copy transfer granule measured on MI355X
+// spread over `n` rows: the touched lines of `line` bytes under independent selection.
+double zc_wire_bytes(uint64_t n, uint64_t count, int elsize, uint32_t line);
 constexpr int kAccWords = 9;            // count + 8 sums per aggregate row
 
 }  // namespace vx

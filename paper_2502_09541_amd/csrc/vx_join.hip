@@ -260,6 +260,16 @@ __global__ void __launch_bounds__(256) k_probe(TableView t, ProbeCols q, unsigne
       uint64_t i = base + (uint64_t)j * blockDim.x + threadIdx.x;
       keys[j] = i < q.n ? __builtin_nontemporal_load(((const K*)q.key) + i) : (K)0;
     }
+    // first slot of every row loaded together (independent random reads in flight), then
+    // each row resolved, continuing its linear probe only past an occupied, different slot
+    uint64_t h[ITEMS];
+    U sk[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      h[j] = slot_of(key_bits(keys[j]), t.log2cap);
+      uint64_t i = base + (uint64_t)j * blockDim.x + threadIdx.x;
+      sk[j] = i < q.n ? *(const U*)(t.slots + (h[j] << t.slot_shift)) : kEmpty;
+    }
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
       uint64_t i = base + (uint64_t)j * blockDim.x + threadIdx.x;
@@ -275,11 +285,12 @@ __global__ void __launch_bounds__(256) k_probe(TableView t, ProbeCols q, unsigne
         }
         continue;
       }
-      uint64_t h = slot_of(key_bits(keys[j]), t.log2cap);
+      uint64_t hh = h[j];
+      U cur = sk[j];
       for (uint64_t step = 0; step <= t.mask; ++step) {
-        const uint8_t* slot = t.slots + (h << t.slot_shift);
-        U sk = *(const U*)slot;
-        if (sk == kb) {
+        const uint8_t* slot = t.slots + (hh << t.slot_shift);
+        if (step) cur = *(const U*)slot;
+        if (cur == kb) {
           if (PREAGG) {
             const unsigned long long* w = (const unsigned long long*)(slot + 8);
             mb[j] = w[0];
@@ -293,8 +304,8 @@ __global__ void __launch_bounds__(256) k_probe(TableView t, ProbeCols q, unsigne
           }
           break;
         }
-        if (sk == kEmpty) break;
-        h = (h + 1) & t.mask;
+        if (cur == kEmpty) break;
+        hh = (hh + 1) & t.mask;
       }
     }
     // late materialization: probe payloads of matching rows only
@@ -486,9 +497,10 @@ int build_group_lanes() {
 
 // Per probe payload column: read by zero-copy (true) or streamed with the keys (false),
 // given the selectivity measured on the first chunk.
-static bool choose_zero_copy(int32_t late_mat, double sel, uint64_t rows, uint64_t matches, int es) {
-  if (late_mat == VX_LATE_PAPER) return sel < (double)es / (double)kZcLine;  // TH = E/(C_l2 * 1)
-  double wire = zc_wire_bytes(rows, std::min(matches, rows), es) / (double)std::max<uint64_t>(rows, 1);
+static bool choose_zero_copy(int32_t late_mat, double sel, uint64_t rows, uint64_t matches, int es,
+                             uint32_t line) {
+  if (late_mat == VX_LATE_PAPER) return sel < (double)es / (double)line;  // TH = E/(C_l2 * 1)
+  double wire = zc_wire_bytes(rows, std::min(matches, rows), es, line) / (double)std::max<uint64_t>(rows, 1);
   return wire < 0.95 * es;
 }
 
@@ -553,7 +565,8 @@ vx_status probe_impl(vx_ctx* ctx, const vx_table* t, const vx_probe_desc* d, vx_
       double sel = rows0 ? (double)first[0] / (double)rows0 : 0.0;
       for (uint32_t p = 0; p < d->n_pay; ++p)
         if (cs[1 + p].may_copy)
-          cs[1 + p].copy = !choose_zero_copy(d->late_mat, sel, rows0, first[0], cs[1 + p].info.elsize);
+          cs[1 + p].copy = !choose_zero_copy(d->late_mat, sel, rows0, first[0], cs[1 + p].info.elsize,
+                                             ctx->zc_line);
       return VX_OK;
     };
   }
@@ -587,7 +600,7 @@ vx_status probe_impl(vx_ctx* ctx, const vx_table* t, const vx_probe_desc* d, vx_
     for (uint64_t k = 0; k < n_chunks; ++k) {
       uint64_t rows = std::min(pipe.chunk_rows(), n - k * pipe.chunk_rows());
       uint64_t m = k < acc_rows ? ctx->host_acc[k * kAccWords] : 0;
-      s.zc_bytes_est += (uint64_t)zc_wire_bytes(rows, std::min(m, rows), c.info.elsize);
+      s.zc_bytes_est += (uint64_t)zc_wire_bytes(rows, std::min(m, rows), c.info.elsize, ctx->zc_line);
     }
   }
   s.zc_mask = zc_mask;

@@ -1,4 +1,5 @@
 // Context, arena, error reporting, host memory and column classification.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -190,14 +191,14 @@ void fill_zero(uint64_t* p, uint64_t words, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, s, p, words);
 }
 
-double zc_wire_bytes(uint64_t n, uint64_t count, int elsize) {
+double zc_wire_bytes(uint64_t n, uint64_t count, int elsize, uint32_t line) {
   if (n == 0 || count == 0) return 0.0;
   double s = (double)count / (double)n;
   if (s > 1.0) s = 1.0;
-  double per_line = (double)kZcLine / elsize;
+  double per_line = std::max(1.0, (double)line / elsize);
   double lines = (double)n / per_line;
   double touched = 1.0 - std::pow(1.0 - s, per_line);
-  return lines * touched * (double)kZcLine;
+  return lines * touched * per_line * elsize;
 }
 
 }  // namespace vx

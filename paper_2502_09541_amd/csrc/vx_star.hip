@@ -17,7 +17,6 @@
 
 namespace vx {
 
-constexpr int kStarItems = 4;
 
 // ---------------------------------------------------------------- dimension build
 
@@ -130,7 +129,7 @@ struct StarArgs {
   unsigned long long* survivors;
 };
 
-template <typename K>
+template <typename K, int kStarItems>
 __global__ void __launch_bounds__(256) k_star(StarArgs a) {
   using U = typename KeyTraits<K>::U;
   const U kEmpty = KeyTraits<K>::kEmpty;
@@ -192,6 +191,12 @@ __global__ void __launch_bounds__(256) k_star(StarArgs a) {
 }
 
 // ---------------------------------------------------------------- host side
+
+// rows per lane in flight in the fact scan (VX_STAR_ITEMS = 4 or 8; default 8)
+static int star_items() {
+  const char* e = getenv("VX_STAR_ITEMS");
+  return e && atoi(e) == 4 ? 4 : 8;
+}
 
 vx_status join_star(vx_ctx* ctx, const vx_star_join* d, vx_join_out* out) {
   double t0 = now_ms();
@@ -327,8 +332,8 @@ vx_status join_star(vx_ctx* ctx, const vx_star_join* d, vx_join_out* out) {
     if (c == 0) zc = false;                         // the first probed key is always streamed
     else if (d->late_mat == VX_LATE_SDMA) zc = false;
     else if (d->late_mat == VX_LATE_ZC) zc = true;
-    else if (d->late_mat == VX_LATE_PAPER) zc = col_sel[c] < (double)es / (double)kZcLine;
-    else zc = zc_wire_bytes(1000000, (uint64_t)(col_sel[c] * 1e6), es) / 1e6 < 0.95 * es;
+    else if (d->late_mat == VX_LATE_PAPER) zc = col_sel[c] < (double)es / (double)ctx->zc_line;
+    else zc = zc_wire_bytes(1000000, (uint64_t)(col_sel[c] * 1e6), es, ctx->zc_line) / 1e6 < 0.95 * es;
     cols[c].copy = cols[c].may_copy = !zc;
   }
 
@@ -390,10 +395,16 @@ vx_status join_star(vx_ctx* ctx, const vx_star_join* d, vx_join_out* out) {
           if ((v.global_mask >> (nd + c)) & 1u) a.meas_global |= 1u << c;
         }
         if (a.n == 0) return VX_OK;
-        unsigned g = (unsigned)std::min<uint64_t>((a.n + 256 * kStarItems - 1) / (256 * kStarItems),
+        const int items = star_items();
+        unsigned g = (unsigned)std::min<uint64_t>((a.n + 256 * items - 1) / (256 * items),
                                                   (uint64_t)ctx->cu_count * 8);
-        if (ktype == VX_I64) hipLaunchKernelGGL(k_star<int64_t>, dim3(g), dim3(256), 0, ctx->compute, a);
-        else hipLaunchKernelGGL(k_star<int32_t>, dim3(g), dim3(256), 0, ctx->compute, a);
+        if (items == 8) {
+          if (ktype == VX_I64) hipLaunchKernelGGL((k_star<int64_t, 8>), dim3(g), dim3(256), 0, ctx->compute, a);
+          else hipLaunchKernelGGL((k_star<int32_t, 8>), dim3(g), dim3(256), 0, ctx->compute, a);
+        } else {
+          if (ktype == VX_I64) hipLaunchKernelGGL((k_star<int64_t, 4>), dim3(g), dim3(256), 0, ctx->compute, a);
+          else hipLaunchKernelGGL((k_star<int32_t, 4>), dim3(g), dim3(256), 0, ctx->compute, a);
+        }
         VX_HIP(hipGetLastError());
         return VX_OK;
       };
@@ -452,7 +463,7 @@ vx_status join_star(vx_ctx* ctx, const vx_star_join* d, vx_join_out* out) {
     if (cols[c].info.where != Where::Host || cols[c].copy) continue;
     s.zc_mask |= 1u << c;
     s.zc_bytes_est += (uint64_t)zc_wire_bytes(d->n_fact, (uint64_t)(col_sel[c] * d->n_fact),
-                                              cols[c].info.elsize);
+                                              cols[c].info.elsize, ctx->zc_line);
   }
   s.probe_ms = now_ms() - tp0;
   s.total_ms = now_ms() - t0;

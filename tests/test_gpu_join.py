@@ -180,3 +180,14 @@ def test_streamed_budget_forces_smaller_chunks(gpu):
     assert got == oracle.join_agg(bk, [b0, b1], pk, [p0, p1])
     assert st["chunk_rows"] * 24 * 2 < (6 << 20)
     c.close()
+
+
+def test_calibration_properties(gpu, ctx):
+    """vx_calibrate: link rates are positive and bounded by PCIe 5.0 x16, the zero-copy granule is a
+    power of two between 8 and 2048 bytes, and device memory reads faster than the link."""
+    _say("calibration")
+    c = ctx.calibrate(256 << 20)
+    assert 5 < c["h2d_gbs"] < 64 and 5 < c["zc_read_gbs"] < 64
+    g = c["zc_granule"]
+    assert 8 <= g <= 2048 and g & (g - 1) == 0
+    assert c["hbm_read_gbs"] > 4 * c["h2d_gbs"]
