@@ -96,9 +96,11 @@ vx_status vx_host_free(void* p);
  * Measure the host link and device memory on this machine: host-to-device copy rate (64 MiB
  * copies), zero-copy read rate (contiguous and strided) and the zero-copy transfer granule (the
  * largest stride at which every touched line still crosses the link), and a device streaming
- * read.  `pinned` is caller-owned pinned host memory of `bytes` (>= 64 MiB) whose contents are
- * read only.  The granule becomes the line size of the context's late-materialization model
- * (Sec. 6.3, C_l2); before a calibration it is 128 bytes.
+ * read, plus the device-to-host direction (copies and kernel stores) alone and beside
+ * host-to-device copies.  `pinned` is caller-owned pinned host memory of `bytes` (>= 64 MiB) whose
+ * contents are read only; the device-to-host legs write into the context's own pinned scratch.
+ * The granule becomes the line size of the context's late-materialization model (Sec. 6.3,
+ * C_l2); before a calibration it is 128 bytes.
  */
 typedef struct {
   double h2d_gbs;
@@ -107,6 +109,10 @@ typedef struct {
   uint32_t zc_granule;
   uint32_t zc_stride_bytes[8];
   double zc_stride_gelems[8];   /* elements per ns at each stride */
+  double d2h_gbs;               /* device-to-host copy rate (64 MiB copies) */
+  double duplex_sdma_gbs;       /* host-to-device and device-to-host copies at once, both directions summed */
+  double zc_write_gbs;          /* kernel stores to mapped pinned host memory */
+  double duplex_zcw_gbs;        /* host-to-device copies beside kernel stores to host, summed */
 } vx_link_calib;
 
 vx_status vx_calibrate(vx_ctx* ctx, void* pinned, uint64_t bytes, vx_link_calib* out);

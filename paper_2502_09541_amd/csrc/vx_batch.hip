@@ -82,48 +82,27 @@ __device__ __forceinline__ void batch_probe_rows(const BatchJob& jb, uint64_t r0
                                                  unsigned long long& sum) {
   using U = typename KeyTraits<K>::U;
   const U kEmpty = KeyTraits<K>::kEmpty;
-  constexpr int IT = 4;
-  for (uint64_t base = r0; base < r1; base += (uint64_t)blockDim.x * IT) {
-    K k[IT];
-    U sk[IT];
-    uint64_t h[IT];
-    // keys, then every row's first slot, loaded before any row is resolved
-#pragma unroll
-    for (int j = 0; j < IT; ++j) {
-      uint64_t i = base + (uint64_t)j * blockDim.x + threadIdx.x;
-      k[j] = i < r1 ? __builtin_nontemporal_load(((const K*)jb.pkey) + i) : (K)0;
+  for (uint64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+    K k = __builtin_nontemporal_load(((const K*)jb.pkey) + i);
+    U kb = (U)k;
+    if (kb == kEmpty) {
+      unsigned long long c = jb.side[0];
+      cnt += c;
+      if (c) sum += jb.side[1];
+      continue;
     }
-#pragma unroll
-    for (int j = 0; j < IT; ++j) {
-      uint64_t i = base + (uint64_t)j * blockDim.x + threadIdx.x;
-      h[j] = slot_of(key_bits(k[j]), jb.log2cap);
-      sk[j] = i < r1 ? *(const U*)(jb.slots + (h[j] << slot_shift)) : kEmpty;
-    }
-#pragma unroll
-    for (int j = 0; j < IT; ++j) {
-      uint64_t i = base + (uint64_t)j * blockDim.x + threadIdx.x;
-      if (i >= r1) continue;
-      U kb = (U)k[j];
-      if (kb == kEmpty) {
-        unsigned long long c = jb.side[0];
-        cnt += c;
-        if (c) sum += jb.side[1];
-        continue;
+    uint64_t h = slot_of(key_bits(k), jb.log2cap);
+    for (uint64_t step = 0; step <= jb.mask; ++step) {
+      const uint8_t* slot = jb.slots + (h << slot_shift);
+      U sk = *(const U*)slot;
+      if (sk == kb) {
+        cnt += 1;
+        if (jb.pay_size == 4) sum += (unsigned long long)(long long)*(const int*)(slot + sizeof(K));
+        else if (jb.pay_size == 8) sum += (unsigned long long)*(const long long*)(slot + 8);
+        break;
       }
-      uint64_t hh = h[j];
-      U cur = sk[j];
-      for (uint64_t step = 0; step <= jb.mask; ++step) {
-        const uint8_t* slot = jb.slots + (hh << slot_shift);
-        if (step) cur = *(const U*)slot;
-        if (cur == kb) {
-          cnt += 1;
-          if (jb.pay_size == 4) sum += (unsigned long long)(long long)*(const int*)(slot + sizeof(K));
-          else if (jb.pay_size == 8) sum += (unsigned long long)*(const long long*)(slot + 8);
-          break;
-        }
-        if (cur == kEmpty) break;
-        hh = (hh + 1) & jb.mask;
-      }
+      if (sk == kEmpty) break;
+      h = (h + 1) & jb.mask;
     }
   }
 }

@@ -24,6 +24,13 @@ __global__ void k_calib_fill(unsigned long long* p, uint64_t n) {
     p[i] = i * 0x9E3779B97F4A7C15ull;
 }
 
+// Writes n 8-byte words (device memory or mapped host memory) with vector stores.
+__global__ void k_calib_write(unsigned long long* p, uint64_t n) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = i;
+}
+
 static vx_status time_read(vx_ctx* ctx, const void* p, uint64_t bytes, uint64_t step, unsigned grid,
                            unsigned long long* sink, float* ms) {
   hipEvent_t a = get_event(ctx), b = get_event(ctx);
@@ -100,5 +107,73 @@ extern "C" vx_status vx_calibrate(vx_ctx* ctx, void* pinned, uint64_t bytes, vx_
   VX_TRY(time_read(ctx, d.p, dbytes, 1, grid / 2, sink, &ms));
   out->hbm_read_gbs = dbytes / (ms * 1e6);
   ctx->zc_line = granule;
+
+  // device-to-host: copies alone, both copy directions at once, kernel stores alone, and
+  // host-to-device copies beside kernel stores
+  uint8_t* hs = nullptr;
+  VX_TRY(host_scratch(ctx, dbytes, &hs));
+  void* hs_dev = nullptr;
+  VX_HIP(hipHostGetDevicePointer(&hs_dev, hs, 0));
+  VX_HIP(hipDeviceSynchronize());
+  hipEvent_t e0 = get_event(ctx), e1 = get_event(ctx), e2 = get_event(ctx);
+  VX_CHECK(e0 && e1 && e2, VX_EHIP, "vx_calibrate: event creation failed");
+  auto span_ms = [&](hipEvent_t a, hipEvent_t b, hipEvent_t c, float* out_ms) -> vx_status {
+    VX_HIP(hipEventSynchronize(b));
+    VX_HIP(hipEventSynchronize(c));
+    float x = 0, y = 0;
+    VX_HIP(hipEventElapsedTime(&x, a, b));
+    VX_HIP(hipEventElapsedTime(&y, a, c));
+    *out_ms = std::max(x, y);
+    return VX_OK;
+  };
+  auto d2h_copies = [&]() -> vx_status {
+    for (uint64_t off = 0; off < dbytes; off += chunk)
+      VX_HIP(hipMemcpyAsync(hs + off, d.p + off, chunk, hipMemcpyDeviceToHost, ctx->d2h));
+    return VX_OK;
+  };
+  auto h2d_copies = [&]() -> vx_status {
+    for (uint64_t off = 0; off < dbytes; off += chunk)
+      VX_HIP(hipMemcpyAsync(d.p + off, (const uint8_t*)hi.host + off, chunk, hipMemcpyHostToDevice, ctx->copy));
+    return VX_OK;
+  };
+  // warm the device-to-host path, then time it alone
+  VX_HIP(hipMemcpyAsync(hs, d.p, chunk, hipMemcpyDeviceToHost, ctx->d2h));
+  VX_HIP(hipEventRecord(e0, ctx->d2h));
+  VX_TRY(d2h_copies());
+  VX_HIP(hipEventRecord(e1, ctx->d2h));
+  VX_TRY(span_ms(e0, e1, e1, &ms));
+  out->d2h_gbs = dbytes / (ms * 1e6);
+  // both directions: the two copy streams start from one event
+  VX_HIP(hipEventRecord(e0, ctx->compute));
+  VX_HIP(hipStreamWaitEvent(ctx->copy, e0, 0));
+  VX_HIP(hipStreamWaitEvent(ctx->d2h, e0, 0));
+  VX_TRY(h2d_copies());
+  VX_TRY(d2h_copies());
+  VX_HIP(hipEventRecord(e1, ctx->copy));
+  VX_HIP(hipEventRecord(e2, ctx->d2h));
+  VX_TRY(span_ms(e0, e1, e2, &ms));
+  out->duplex_sdma_gbs = 2.0 * dbytes / (ms * 1e6);
+  // kernel stores to mapped host memory, alone
+  hipLaunchKernelGGL(k_calib_write, dim3(grid), dim3(256), 0, ctx->compute, (unsigned long long*)hs_dev,
+                     chunk / 8);
+  VX_HIP(hipEventRecord(e0, ctx->compute));
+  hipLaunchKernelGGL(k_calib_write, dim3(grid), dim3(256), 0, ctx->compute, (unsigned long long*)hs_dev,
+                     dbytes / 8);
+  VX_HIP(hipEventRecord(e1, ctx->compute));
+  VX_TRY(span_ms(e0, e1, e1, &ms));
+  out->zc_write_gbs = dbytes / (ms * 1e6);
+  // host-to-device copies beside kernel stores to host
+  VX_HIP(hipEventRecord(e0, ctx->compute));
+  VX_HIP(hipStreamWaitEvent(ctx->copy, e0, 0));
+  VX_TRY(h2d_copies());
+  hipLaunchKernelGGL(k_calib_write, dim3(grid), dim3(256), 0, ctx->compute, (unsigned long long*)hs_dev,
+                     dbytes / 8);
+  VX_HIP(hipEventRecord(e1, ctx->copy));
+  VX_HIP(hipEventRecord(e2, ctx->compute));
+  VX_TRY(span_ms(e0, e1, e2, &ms));
+  out->duplex_zcw_gbs = 2.0 * dbytes / (ms * 1e6);
+  put_event(ctx, e0);
+  put_event(ctx, e1);
+  put_event(ctx, e2);
   return VX_OK;
 }

@@ -17,6 +17,7 @@ namespace vx {
 
 constexpr unsigned long long kGolden = 0x9E3779B97F4A7C15ull;
 constexpr uint32_t kPartialStride = kModelParams + 1;   // gradient components + loss
+constexpr uint64_t kTrainMax = 1ull << 20;              // training points taken from the sample
 
 // SplitMix64 output function (Steele, Lea and Flood, OOPSLA 2014).
 __device__ __forceinline__ unsigned long long splitmix_out(unsigned long long z) {
@@ -28,23 +29,45 @@ __device__ __forceinline__ unsigned long long splitmix_out(unsigned long long z)
 // ---------------------------------------------------------------- sample
 
 // Row i is sampled iff the (i+1)-th SplitMix64 output of the stream seeded by `seed` is below thr.
-__global__ void k_sample(const void* key, uint32_t ks, uint64_t n, uint64_t seed, uint64_t thr,
-                         long long* out, uint64_t cap, unsigned long long* count) {
-  const uint32_t lane = threadIdx.x & 63;
+// Only sampled rows are read.  Each wave gathers its sampled keys in LDS and reserves room in
+// `out` once per kSampleBuf - 64 keys, so the shared counter sees few atomics.
+constexpr uint32_t kSampleBuf = 512;
+
+__global__ void __launch_bounds__(256) k_sample(const void* key, uint32_t ks, uint64_t n, uint64_t seed,
+                                                uint64_t thr, long long* out, uint64_t cap,
+                                                unsigned long long* count) {
+  __shared__ long long buf[4][kSampleBuf];
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   const uint64_t first = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x - lane;
+  uint32_t held = 0;   // wave-uniform
+  auto flush = [&]() {
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(count, (unsigned long long)held);
+    base = __shfl(base, 0, 64);
+    for (uint32_t j = lane; j < held; j += 64)
+      if (base + j < cap) out[base + j] = buf[wave][j];
+    held = 0;
+  };
   for (uint64_t wb = first; wb < n; wb += stride) {
     uint64_t i = wb + lane;
     bool take = i < n && splitmix_out(seed + kGolden * (i + 1)) < thr;
     unsigned long long m = __ballot(take);
     if (!m) continue;
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(count, (unsigned long long)__popcll(m));
-    base = __shfl(base, 0, 64);
     if (take) {
-      uint64_t pos = base + (uint64_t)__popcll(m & ((1ull << lane) - 1));
-      if (pos < cap) out[pos] = ks == 4 ? (long long)((const int*)key)[i] : ((const long long*)key)[i];
+      uint32_t pos = held + (uint32_t)__popcll(m & ((1ull << lane) - 1));
+      buf[wave][pos] = ks == 4 ? (long long)((const int*)key)[i] : ((const long long*)key)[i];
     }
+    held += (uint32_t)__popcll(m);
+    if (held > kSampleBuf - 64) {
+      __builtin_amdgcn_wave_barrier();
+      flush();
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  if (held) {
+    __builtin_amdgcn_wave_barrier();
+    flush();
   }
 }
 
@@ -213,13 +236,21 @@ __global__ void __launch_bounds__(256) k_mlp_grad(const float* x, const float* t
   }
 }
 
-// grad[c] = sum over waves in wave order of partial[w][c]; grad[kModelParams] = loss
-__global__ void k_mlp_reduce(const double* partial, uint32_t waves, uint64_t n, double* grad) {
-  uint32_t c = threadIdx.x;
-  if (c >= kPartialStride) return;
+// grad[c] = SUM over waves of partial[w][c] in a fixed order (block c: thread t adds waves
+// t, t + 256, ... in turn, then a fixed tree over the threads); grad[kModelParams] = loss.
+__global__ void __launch_bounds__(256) k_mlp_reduce(const double* partial, uint32_t waves, uint64_t n,
+                                                    double* grad) {
+  __shared__ double red[256];
+  const uint32_t c = blockIdx.x;
   double s = 0;
-  for (uint32_t w = 0; w < waves; ++w) s += partial[(uint64_t)w * kPartialStride + c];
-  grad[c] = c == kModelParams ? s / (double)n : s;
+  for (uint32_t w = threadIdx.x; w < waves; w += blockDim.x) s += partial[(uint64_t)w * kPartialStride + c];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (uint32_t h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) grad[c] = c == kModelParams ? red[0] / (double)n : red[0];
 }
 
 // Adam (Kingma and Ba, 2015) on FP32 parameters and moments, evaluated in FP64.
@@ -250,6 +281,16 @@ __global__ void k_cross(const float* x, const float* t, uint64_t m, const float*
     while (c < (long long)P - 1 && y >= (double)(c + 1) / (double)P) ++c;
     while (c > 0 && !(y >= (double)c / (double)P)) --c;
     if (c >= 1) atomicMin(first + c, (unsigned long long)i);
+  }
+}
+
+// x_s[i] = x[i * stride], t_s[i] = t[i * stride]: evenly spaced order statistics of the sorted sample
+__global__ void k_stride_gather(const float* x, const float* t, uint64_t m_s, uint64_t stride, float* xs,
+                                float* ts) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < m_s;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    xs[i] = x[i * stride];
+    ts[i] = t[i * stride];
   }
 }
 
@@ -346,7 +387,7 @@ static vx_status grad_pass(vx_ctx* ctx, const Model& md, const float* x, const f
   hipStream_t s = ctx->compute;
   hipLaunchKernelGGL(k_mlp_grad, dim3(md.waves / 4), dim3(256), 0, s, x, t, n, md.params, md.per_wave,
                      md.partial);
-  hipLaunchKernelGGL(k_mlp_reduce, dim3(1), dim3(256), 0, s, md.partial, md.waves, n, md.grad);
+  hipLaunchKernelGGL(k_mlp_reduce, dim3(kPartialStride), dim3(256), 0, s, md.partial, md.waves, n, md.grad);
   VX_HIP(hipGetLastError());
   return VX_OK;
 }
@@ -452,9 +493,26 @@ vx_status cdf_splitters(vx_ctx* ctx, const ColInfo& key, uint64_t n, const vx_pa
   hipLaunchKernelGGL(k_targets, dim3(grid1(ctx, m)), dim3(256), 0, s, sorted, m, ends[0], scale, fx, ft);
   VX_HIP(hipGetLastError());
 
-  // model
+  // model, fit to at most kTrainMax evenly spaced points of the sorted sample
+  const float* tx = fx;
+  const float* tt = ft;
+  uint64_t mt = m;
+  ArenaBlock tb;
+  if (m > kTrainMax) {
+    const uint64_t stride = (m + kTrainMax - 1) / kTrainMax;
+    mt = (m + stride - 1) / stride;
+    tb.a = &ctx->arena;
+    tb.p = ctx->arena.alloc(mt * 8 + 256);
+    VX_CHECK(tb.p, VX_EBUDGET, "cdf: no room for the training points");
+    float* sx = (float*)tb.p;
+    float* st = sx + mt;
+    hipLaunchKernelGGL(k_stride_gather, dim3(grid1(ctx, mt)), dim3(256), 0, s, fx, ft, mt, stride, sx, st);
+    VX_HIP(hipGetLastError());
+    tx = sx;
+    tt = st;
+  }
   ModelMem mm;
-  VX_TRY(mm.alloc(ctx, m));
+  VX_TRY(mm.alloc(ctx, mt));
   float hp[kModelParams];
   init_params(hp);
   VX_HIP(hipMemcpyAsync(mm.md.params, hp, sizeof hp, hipMemcpyHostToDevice, s));
@@ -462,9 +520,9 @@ vx_status cdf_splitters(vx_ctx* ctx, const ColInfo& key, uint64_t n, const vx_pa
   if (o.method == VX_PART_LEARNED || o.method == VX_PART_AUTO) {
     uint32_t steps = o.train_steps ? o.train_steps : 300;
     double lr = o.lr > 0 ? (double)o.lr : 1e-2;
-    VX_TRY(train(ctx, mm.md, fx, ft, m, steps, lr, &rep->final_loss));
+    VX_TRY(train(ctx, mm.md, tx, tt, mt, steps, lr, &rep->final_loss));
   } else if (use_model) {
-    VX_TRY(grad_pass(ctx, mm.md, fx, ft, m));
+    VX_TRY(grad_pass(ctx, mm.md, tx, tt, mt));
     double hg[kPartialStride];
     VX_HIP(hipMemcpyAsync(hg, mm.md.grad, sizeof hg, hipMemcpyDeviceToHost, s));
     VX_HIP(hipStreamSynchronize(s));

@@ -260,16 +260,6 @@ __global__ void __launch_bounds__(256) k_probe(TableView t, ProbeCols q, unsigne
       uint64_t i = base + (uint64_t)j * blockDim.x + threadIdx.x;
       keys[j] = i < q.n ? __builtin_nontemporal_load(((const K*)q.key) + i) : (K)0;
     }
-    // first slot of every row loaded together (independent random reads in flight), then
-    // each row resolved, continuing its linear probe only past an occupied, different slot
-    uint64_t h[ITEMS];
-    U sk[ITEMS];
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-      h[j] = slot_of(key_bits(keys[j]), t.log2cap);
-      uint64_t i = base + (uint64_t)j * blockDim.x + threadIdx.x;
-      sk[j] = i < q.n ? *(const U*)(t.slots + (h[j] << t.slot_shift)) : kEmpty;
-    }
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
       uint64_t i = base + (uint64_t)j * blockDim.x + threadIdx.x;
@@ -285,12 +275,11 @@ __global__ void __launch_bounds__(256) k_probe(TableView t, ProbeCols q, unsigne
         }
         continue;
       }
-      uint64_t hh = h[j];
-      U cur = sk[j];
+      uint64_t h = slot_of(key_bits(keys[j]), t.log2cap);
       for (uint64_t step = 0; step <= t.mask; ++step) {
-        const uint8_t* slot = t.slots + (hh << t.slot_shift);
-        if (step) cur = *(const U*)slot;
-        if (cur == kb) {
+        const uint8_t* slot = t.slots + (h << t.slot_shift);
+        U sk = *(const U*)slot;
+        if (sk == kb) {
           if (PREAGG) {
             const unsigned long long* w = (const unsigned long long*)(slot + 8);
             mb[j] = w[0];
@@ -304,8 +293,8 @@ __global__ void __launch_bounds__(256) k_probe(TableView t, ProbeCols q, unsigne
           }
           break;
         }
-        if (cur == kEmpty) break;
-        hh = (hh + 1) & t.mask;
+        if (sk == kEmpty) break;
+        h = (h + 1) & t.mask;
       }
     }
     // late materialization: probe payloads of matching rows only

@@ -43,6 +43,35 @@ struct PartIO {
   uint64_t out_base;             // row offset added to every output position
 };
 
+// Partition id of key k: hash, raw bits, or the count of splitters <= k (split[] ascending,
+// ps.n_split entries, usually staged in LDS by the caller).
+__device__ __forceinline__ unsigned long long fmix64(unsigned long long h) {
+  h ^= h >> 33;
+  h *= 0xff51afd7ed558ccdull;
+  h ^= h >> 33;
+  h *= 0xc4ceb9fe1a85ec53ull;
+  h ^= h >> 33;
+  return h;
+}
+
+__device__ __forceinline__ uint32_t part_of(const PartSpec& ps, long long k, const long long* split) {
+  if (ps.fn == kPartHash) {
+    return ps.log2p ? (uint32_t)(fmix64((unsigned long long)k) >> (64 - ps.log2p)) : 0u;
+  }
+  if (ps.fn == kPartBits) {
+    unsigned long long u = (unsigned long long)k;
+    if (ps.flip_sign) u ^= 0x8000000000000000ull;
+    return (uint32_t)((u >> ps.shift) & (unsigned long long)(ps.n_parts - 1));
+  }
+  uint32_t lo = 0, hi = ps.n_split;
+  while (lo < hi) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (split[mid] <= k) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
 // Launch geometry shared by hist and scatter: waves and rows per wave tile.
 struct PartGeom {
   uint32_t blocks;

@@ -12,33 +12,6 @@ namespace vx {
 
 // ---------------------------------------------------------------- device side
 
-__device__ __forceinline__ unsigned long long fmix64(unsigned long long h) {
-  h ^= h >> 33;
-  h *= 0xff51afd7ed558ccdull;
-  h ^= h >> 33;
-  h *= 0xc4ceb9fe1a85ec53ull;
-  h ^= h >> 33;
-  return h;
-}
-
-__device__ __forceinline__ uint32_t part_of(const PartSpec& ps, long long k, const long long* split) {
-  if (ps.fn == kPartHash) {
-    return ps.log2p ? (uint32_t)(fmix64((unsigned long long)k) >> (64 - ps.log2p)) : 0u;
-  }
-  if (ps.fn == kPartBits) {
-    unsigned long long u = (unsigned long long)k;
-    if (ps.flip_sign) u ^= 0x8000000000000000ull;
-    return (uint32_t)((u >> ps.shift) & (unsigned long long)(ps.n_parts - 1));
-  }
-  uint32_t lo = 0, hi = ps.n_split;
-  while (lo < hi) {
-    uint32_t mid = (lo + hi) >> 1;
-    if (split[mid] <= k) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
-}
-
 __device__ __forceinline__ long long load_any(const void* p, uint64_t i, uint32_t size) {
   return size == 4 ? (long long)((const int*)p)[i] : ((const long long*)p)[i];
 }

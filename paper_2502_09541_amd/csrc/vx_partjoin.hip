@@ -13,6 +13,8 @@
 // pass 2: pass 1 already counts its build rows, sums their payload and counts its probe rows,
 // and its contribution is count_b * count_p pairs and sum_b * count_p.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -48,30 +50,67 @@ __device__ __forceinline__ uint64_t seg_source(const unsigned long long* st,
   return st[lo] + (idx - pre[lo]);
 }
 
-__global__ void k_pj_init(uint32_t* slots, uint64_t capacity, uint32_t slot_words, uint32_t key_size,
-                          unsigned long long* side) {
+constexpr uint32_t kSideWords = 8;   // per-partition side record: count, payload sum (padded)
+constexpr uint32_t kSlotShift = 5;   // 32-byte slots: key, count, payload sum, padding
+
+// Empty every slot of a pre-aggregating table; zero a side record if one is given.
+__global__ void k_pj_init(uint32_t* slots, uint64_t capacity, uint32_t key_size, unsigned long long* side) {
+  const uint32_t words = 1u << (kSlotShift - 2);
   for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < capacity;
        s += (uint64_t)gridDim.x * blockDim.x) {
-    uint32_t* w = slots + s * slot_words;
-    for (uint32_t i = 0; i < slot_words; ++i) w[i] = 0;
+    uint32_t* w = slots + s * words;
+    for (uint32_t i = 0; i < words; ++i) w[i] = 0;
     if (key_size == 4) w[0] = 0x80000000u;
     else w[1] = 0x80000000u;
   }
-  if (blockIdx.x == 0 && threadIdx.x < 1 + kMaxPay) side[threadIdx.x] = 0;
+  if (side && blockIdx.x == 0 && threadIdx.x < kSideWords) side[threadIdx.x] = 0;
+}
+
+// Add (cnt, sum) to key k's record; returns 1 when this call claimed a new slot.
+template <typename K>
+__device__ __forceinline__ uint32_t preagg_claim_add(const TableView& t, K k, unsigned long long cnt,
+                                                     unsigned long long sum, unsigned int* flags) {
+  using U = typename KeyTraits<K>::U;
+  const U kEmpty = KeyTraits<K>::kEmpty;
+  const U kb = (U)k;
+  if (kb == kEmpty) {
+    atomicAdd(t.side, cnt);
+    if (t.n_pay) atomicAdd(t.side + 1, sum);
+    return 0;
+  }
+  uint64_t h = slot_of(key_bits(k), t.log2cap);
+  for (uint64_t step = 0; step <= t.mask; ++step) {
+    uint8_t* slot = t.slots + (h << kSlotShift);
+    U prev = atomicCAS((U*)slot, kEmpty, kb);
+    if (prev == kEmpty || prev == kb) {
+      unsigned long long* w = (unsigned long long*)(slot + 8);
+      atomicAdd(w, cnt);
+      if (t.n_pay) atomicAdd(w + 1, sum);
+      return prev == kEmpty ? 1u : 0u;
+    }
+    h = (h + 1) & t.mask;
+  }
+  atomicOr(flags, kFlagFull);
+  return 0;
 }
 
 constexpr int kPjLds = 1024;
 constexpr int kPjTile = 4096;
 
+// Pre-aggregate one partition's build segments (read in place from host memory) into the
+// transient table: a per-tile LDS table absorbs repeated keys, its entries are then added to
+// the global table.  The number of distinct keys claimed is added to *distinct.
 template <typename K>
 __global__ void __launch_bounds__(256) k_pj_build(TableView t, const void* key, const void* pay0,
-                                                  uint32_t pay_size, SegList sl, unsigned int* flags) {
+                                                  uint32_t pay_size, SegList sl, unsigned int* flags,
+                                                  unsigned long long* distinct) {
   __shared__ unsigned long long sst[kMaxSegs], spre[kMaxSegs + 1];
   __shared__ unsigned long long lkey[kPjLds], lcnt[kPjLds], lsum[kPjLds];
   const unsigned long long kFree = ~0ull;
   for (uint32_t j = threadIdx.x; j < sl.nseg; j += blockDim.x) sst[j] = sl.start[j];
   for (uint32_t j = threadIdx.x; j <= sl.nseg; j += blockDim.x) spre[j] = sl.prefix[j];
   __syncthreads();
+  uint32_t claimed = 0;
   for (uint64_t base = (uint64_t)blockIdx.x * kPjTile; base < sl.total;
        base += (uint64_t)gridDim.x * kPjTile) {
     for (int j = threadIdx.x; j < kPjLds; j += blockDim.x) {
@@ -100,58 +139,158 @@ __global__ void __launch_bounds__(256) k_pj_build(TableView t, const void* key, 
           }
         }
       }
-      if (!placed) {
-        unsigned long long sums[kMaxPay] = {v, 0, 0, 0};
-        global_preagg_add<K>(t, k, 1ull, sums, flags);
-      }
+      if (!placed) claimed += preagg_claim_add<K>(t, k, 1ull, v, flags);
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < kPjLds; j += blockDim.x) {
-      if (lkey[j] != kFree) {
-        unsigned long long sums[kMaxPay] = {lsum[j], 0, 0, 0};
-        global_preagg_add<K>(t, (K)(long long)lkey[j], lcnt[j], sums, flags);
-      }
-    }
+    for (int j = threadIdx.x; j < kPjLds; j += blockDim.x)
+      if (lkey[j] != kFree) claimed += preagg_claim_add<K>(t, (K)(long long)lkey[j], lcnt[j], lsum[j], flags);
     __syncthreads();
+  }
+  for (int o = 32; o > 0; o >>= 1) claimed += __shfl_xor(claimed, o, 64);
+  if ((threadIdx.x & 63) == 0 && claimed) atomicAdd(distinct, (unsigned long long)claimed);
+}
+
+// Move every record of the transient table into partition p's compact table (sized from its
+// distinct-key count) and empty the transient slot, so the next partition finds it clean.
+template <typename K>
+__global__ void k_pj_compact(uint8_t* tslots, uint64_t tcap, TableView c) {
+  using U = typename KeyTraits<K>::U;
+  const U kEmpty = KeyTraits<K>::kEmpty;
+  for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < tcap;
+       s += (uint64_t)gridDim.x * blockDim.x) {
+    uint8_t* src = tslots + (s << kSlotShift);
+    U k = *(U*)src;
+    if (k == kEmpty) continue;
+    unsigned long long* w = (unsigned long long*)(src + 8);
+    unsigned long long cnt = w[0], sum = w[1];
+    *(U*)src = kEmpty;
+    w[0] = 0;
+    w[1] = 0;
+    uint64_t h = slot_of(key_bits((K)k), c.log2cap);
+    for (uint64_t step = 0; step <= c.mask; ++step) {
+      uint8_t* d = c.slots + (h << kSlotShift);
+      if (atomicCAS((U*)d, kEmpty, k) == kEmpty) {
+        unsigned long long* dw = (unsigned long long*)(d + 8);
+        dw[0] = cnt;
+        dw[1] = sum;
+        break;
+      }
+      h = (h + 1) & c.mask;
+    }
   }
 }
 
+// Streamed probe side: route every key to its partition (the function that clustered the build
+// side), count the partition's probe rows (first pass only), and look the key up in the
+// partition's compact table when that table is resident in this pass.  Per-partition
+// (probe rows, matched build rows, SUM of matched build payloads) accumulate in LDS and are
+// added to this block's own row of acc (no atomics: the chunks' kernels run in stream order).
 template <typename K>
-__global__ void __launch_bounds__(256) k_pj_probe(TableView t, const void* key, SegList sl,
-                                                  unsigned long long* acc_out) {
+__global__ void __launch_bounds__(256) k_pj_stream(const void* keys, uint64_t n, PartSpec ps,
+                                                   const unsigned long long* tab_slots,
+                                                   const uint32_t* tab_log2, const unsigned long long* side,
+                                                   uint32_t count_rows, unsigned long long* acc) {
   using U = typename KeyTraits<K>::U;
   const U kEmpty = KeyTraits<K>::kEmpty;
-  __shared__ unsigned long long sst[kMaxSegs], spre[kMaxSegs + 1];
-  for (uint32_t j = threadIdx.x; j < sl.nseg; j += blockDim.x) sst[j] = sl.start[j];
-  for (uint32_t j = threadIdx.x; j <= sl.nseg; j += blockDim.x) spre[j] = sl.prefix[j];
+  extern __shared__ unsigned long long lds[];
+  const uint32_t P = ps.n_parts;
+  unsigned long long* lacc = lds;                          // 3 * P
+  unsigned long long* lslots = lacc + 3 * P;               // P
+  long long* lsplit = (long long*)(lslots + P);            // n_split
+  uint32_t* llog2 = (uint32_t*)(lsplit + ps.n_split);      // P
+  for (uint32_t j = threadIdx.x; j < 3 * P; j += blockDim.x) lacc[j] = 0;
+  for (uint32_t j = threadIdx.x; j < P; j += blockDim.x) {
+    lslots[j] = tab_slots[j];
+    llog2[j] = tab_log2[j];
+  }
+  if (ps.fn == kPartRange)
+    for (uint32_t j = threadIdx.x; j < ps.n_split; j += blockDim.x) lsplit[j] = ps.splitters[j];
   __syncthreads();
-  unsigned long long acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   constexpr int ITEMS = 4;
   const uint64_t tile = (uint64_t)blockDim.x * ITEMS;
-  for (uint64_t base = blockIdx.x * tile; base < sl.total; base += (uint64_t)gridDim.x * tile) {
-    K keys[ITEMS];
+  for (uint64_t base = blockIdx.x * tile; base < n; base += (uint64_t)gridDim.x * tile) {
+    K kk[ITEMS];
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
       uint64_t i = base + (uint64_t)j * blockDim.x + threadIdx.x;
-      keys[j] = i < sl.total ? load_key<K>(key, seg_source(sst, spre, sl.nseg, i)) : (K)0;
+      kk[j] = i < n ? ((const K*)keys)[i] : (K)0;
     }
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
       uint64_t i = base + (uint64_t)j * blockDim.x + threadIdx.x;
-      if (i >= sl.total) continue;
+      if (i >= n) continue;
+      const uint32_t pid = part_of(ps, (long long)kk[j], lsplit);
+      if (count_rows) atomicAdd(&lacc[3 * pid], 1ull);
+      const unsigned long long sl = lslots[pid];
+      if (!sl) continue;
       const unsigned long long* w;
-      if ((U)keys[j] == kEmpty) {
-        w = t.side;
+      if ((U)kk[j] == kEmpty) {
+        w = side + (uint64_t)pid * kSideWords;
       } else {
-        const uint8_t* s = find_slot<K>(t, keys[j]);
+        TableView t{};
+        t.slots = (uint8_t*)sl;
+        t.log2cap = llog2[pid];
+        t.mask = (1ull << t.log2cap) - 1;
+        t.slot_shift = kSlotShift;
+        const uint8_t* s = find_slot<K>(t, kk[j]);
         if (!s) continue;
         w = (const unsigned long long*)(s + 8);
       }
-      acc[0] += w[0];
-      for (uint32_t p = 0; p < t.n_pay; ++p) acc[1 + p] += w[1 + p];
+      if (w[0]) {
+        atomicAdd(&lacc[3 * pid + 1], w[0]);
+        atomicAdd(&lacc[3 * pid + 2], w[1]);
+      }
     }
   }
-  block_flush<9>(acc, 1 + (int)t.n_pay, acc_out);
+  __syncthreads();
+  unsigned long long* mine = acc + (uint64_t)blockIdx.x * 3 * P;
+  for (uint32_t j = threadIdx.x; j < 3 * P; j += blockDim.x)
+    if (lacc[j]) mine[j] += lacc[j];
+}
+
+// out[j] = SUM over blocks of acc[b][j]
+__global__ void k_pj_reduce(const unsigned long long* acc, uint32_t blocks, uint32_t width,
+                            unsigned long long* out) {
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < width; j += gridDim.x * blockDim.x) {
+    unsigned long long s = 0;
+    for (uint32_t b = 0; b < blocks; ++b) s += acc[(uint64_t)b * width + j];
+    out[j] = s;
+  }
+}
+
+// Copy one clustered chunk from its device staging to its rows of the pinned host copy with
+// vector stores.  Kernel stores to host memory run beside the host-to-device copy engine,
+// where a device-to-host copy would share it.  Rows of singleton partitions (skip[p] >= 0)
+// are never read again and are left out.
+__global__ void __launch_bounds__(256) k_pj_writeback(const uint8_t* skey, const uint8_t* spay, uint32_t ks,
+                                                      uint32_t psz, uint32_t n_pay, uint64_t rows,
+                                                      const unsigned long long* bnd, uint32_t P,
+                                                      const int* skip, uint8_t* hkey, uint8_t* hpay) {
+  __shared__ unsigned long long sb[kMaxParts + 1];
+  __shared__ int sk[kMaxParts];
+  if (skip) {
+    for (uint32_t j = threadIdx.x; j <= P; j += blockDim.x) sb[j] = bnd[j];
+    for (uint32_t j = threadIdx.x; j < P; j += blockDim.x) sk[j] = skip[j];
+  }
+  __syncthreads();
+  for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < rows;
+       r += (uint64_t)gridDim.x * blockDim.x) {
+    if (skip) {
+      uint32_t lo = 0, hi = P;   // partition p with sb[p] <= r < sb[p + 1]
+      while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (sb[mid] <= r) lo = mid;
+        else hi = mid;
+      }
+      if (sk[lo] >= 0) continue;
+    }
+    if (ks == 8) ((unsigned long long*)hkey)[r] = ((const unsigned long long*)skey)[r];
+    else ((unsigned int*)hkey)[r] = ((const unsigned int*)skey)[r];
+    if (n_pay) {
+      if (psz == 8) ((unsigned long long*)hpay)[r] = ((const unsigned long long*)spay)[r];
+      else ((unsigned int*)hpay)[r] = ((const unsigned int*)spay)[r];
+    }
+  }
 }
 
 // ---------------------------------------------------------------- host side
@@ -165,6 +304,8 @@ struct Side {
   uint64_t n = 0;
   uint8_t* host_key = nullptr;          // clustered copy in pinned host memory
   uint8_t* host_pay[kMaxPay] = {};
+  uint8_t* mapped_key = nullptr;        // the same memory as the device addresses it
+  uint8_t* mapped_pay[kMaxPay] = {};
   uint64_t chunk_rows = 0, n_chunks = 0;
   std::vector<unsigned long long> bnd;  // n_chunks * (P + 1)
   std::vector<unsigned long long> slot_sums;   // 2 * kMaxSumSlots: count, payload-0 sum
@@ -172,6 +313,11 @@ struct Side {
 };
 
 uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+
+// grid-stride launch over n items: at most 8 workgroups per compute unit
+unsigned grid_for(const vx_ctx* ctx, uint64_t n) {
+  return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, (uint64_t)ctx->cu_count * 8));
+}
 
 // Pass 1 for one table: stream, cluster each chunk by partition, write it back with its
 // boundary array.
@@ -212,6 +358,7 @@ vx_status cluster_side(vx_ctx* ctx, const PartSpec& ps, const int* sum_slot_dev,
   hipEvent_t done[2] = {get_event(ctx), get_event(ctx)};
   hipEvent_t wrote[2] = {get_event(ctx), get_event(ctx)};
   bool pending[2] = {false, false};
+  const unsigned wb_grid = (unsigned)ctx->cu_count * 2;
   auto kernel = [&](const ChunkView& v) -> vx_status {
     uint32_t b = (uint32_t)(v.index % 2);
     if (pending[b]) VX_HIP(hipStreamWaitEvent(ctx->compute, wrote[b], 0));
@@ -239,11 +386,13 @@ vx_status cluster_side(vx_ctx* ctx, const PartSpec& ps, const int* sum_slot_dev,
     VX_HIP(hipEventRecord(done[b], ctx->compute));
     // write the clustered chunk back to host memory at the chunk's own rows
     VX_HIP(hipStreamWaitEvent(ctx->d2h, done[b], 0));
-    VX_HIP(hipMemcpyAsync(sd.host_key + v.row0 * sd.key.elsize, io.out_key, v.rows * sd.key.elsize,
-                          hipMemcpyDeviceToHost, ctx->d2h));
-    for (uint32_t c = 0; c < sd.n_pay; ++c)
-      VX_HIP(hipMemcpyAsync(sd.host_pay[c] + v.row0 * sd.pay[c].elsize, io.out_pay[c],
-                            v.rows * sd.pay[c].elsize, hipMemcpyDeviceToHost, ctx->d2h));
+    VX_CHECK(sd.n_pay <= 1, VX_EUNSUPPORTED, "partition pass: at most one payload column");
+    hipLaunchKernelGGL(k_pj_writeback, dim3(wb_grid), dim3(256), 0, ctx->d2h, (const uint8_t*)io.out_key,
+                       (const uint8_t*)(sd.n_pay ? io.out_pay[0] : nullptr), (uint32_t)sd.key.elsize,
+                       sd.n_pay ? (uint32_t)sd.pay[0].elsize : 0u, sd.n_pay, v.rows, bnd + v.index * (P + 1), P,
+                       sum_slot_dev, sd.mapped_key + v.row0 * sd.key.elsize,
+                       sd.n_pay ? sd.mapped_pay[0] + v.row0 * sd.pay[0].elsize : nullptr);
+    VX_HIP(hipGetLastError());
     VX_HIP(hipEventRecord(wrote[b], ctx->d2h));
     pending[b] = true;
     return VX_OK;
@@ -319,6 +468,11 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
     }
   }
   double train_ms = now_ms() - tt0;
+  const bool trace = getenv("VX_TRACE") != nullptr;
+  if (trace && rep.sample_rows)
+    fprintf(stderr, "[vx] splitters: sample %llu rows %.1f ms, sort %.1f ms, fit %.1f ms, split %.1f ms, loss %.3g\n",
+            (unsigned long long)rep.sample_rows, rep.sample_ms, rep.sort_ms, rep.train_ms, rep.split_ms,
+            rep.final_loss);
   vx_part_opts eff = o;
   eff.method = (method == VX_PART_LEARNED || method == VX_PART_QUANTILE || method == VX_PART_UNTRAINED)
                    ? VX_PART_RANGE
@@ -349,56 +503,71 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
     slot_dev = (const int*)slot_mem.p;
   }
 
-  // pinned host memory for the clustered tables
-  uint64_t hbytes = align_up(B.n * ks, 256) + align_up(Q.n * ks, 256);
+  // pinned host memory for the clustered build side
+  uint64_t hbytes = align_up(B.n * ks, 256);
   for (uint32_t c = 0; c < B.n_pay; ++c) hbytes += align_up(B.n * bs.pay[c].elsize, 256);
   uint8_t* hs = nullptr;
   VX_TRY(host_scratch(ctx, hbytes + 256, &hs));
+  void* hs_dev = nullptr;
+  VX_HIP(hipHostGetDevicePointer(&hs_dev, hs, 0));
   bs.host_key = hs;
+  bs.mapped_key = (uint8_t*)hs_dev;
   uint64_t off = align_up(B.n * ks, 256);
   for (uint32_t c = 0; c < B.n_pay; ++c) {
     bs.host_pay[c] = hs + off;
+    bs.mapped_pay[c] = (uint8_t*)hs_dev + off;
     off += align_up(B.n * bs.pay[c].elsize, 256);
   }
-  qs.host_key = hs + off;
 
-  // pass 1
+  // pass 1: cluster the build side
   double tp0 = now_ms();
   VX_TRY(cluster_side(ctx, ps, slot_dev, bs));
-  VX_TRY(cluster_side(ctx, ps, slot_dev, qs));
   double part_ms = now_ms() - tp0;
-
-  // per-partition sizes
-  std::vector<uint64_t> brows(P, 0), qrows(P, 0);
+  std::vector<uint64_t> brows(P, 0);
   for (uint64_t c = 0; c < bs.n_chunks; ++c)
     for (uint32_t p = 0; p < P; ++p) brows[p] += bs.bnd[c * (P + 1) + p + 1] - bs.bnd[c * (P + 1) + p];
-  for (uint64_t c = 0; c < qs.n_chunks; ++c)
-    for (uint32_t p = 0; p < P; ++p) qrows[p] += qs.bnd[c * (P + 1) + p + 1] - qs.bnd[c * (P + 1) + p];
 
-  // pass 2: one pre-aggregating table, sized for the largest non-singleton partition
+  // pass 2 memory: transient table (largest non-singleton partition, worst case all keys
+  // distinct at load 0.8), side records, partition directory, per-block accumulators,
+  // build segment lists, the probe pipeline's buffers, and the compact tables in the rest
   double tj0 = now_ms();
   uint64_t max_rows = 0;
   for (uint32_t p = 0; p < P; ++p)
-    if (slot[p] < 0 && qrows[p]) max_rows = std::max(max_rows, brows[p]);
-  const uint32_t slot_bytes = 32;   // key, count, payload sum (+ padding)
-  uint64_t max_cap = 64;
-  while (max_cap < 2 * max_rows) max_cap <<= 1;
-  ArenaBlock tmem, segmem;
-  uint64_t pass2_rows = 0;
-  for (uint32_t p = 0; p < P; ++p)
-    if (slot[p] < 0 && brows[p] && qrows[p]) pass2_rows += brows[p] + qrows[p];
-  tmem.a = &ctx->arena;
-  tmem.p = ctx->arena.alloc(max_cap * slot_bytes + 256);
+    if (slot[p] < 0) max_rows = std::max(max_rows, brows[p]);
+  auto pow2_at_least = [](uint64_t v) {
+    uint64_t c = 64;
+    while (c < v) c <<= 1;
+    return c;
+  };
+  const uint64_t tcap_max = pow2_at_least(max_rows + max_rows / 4);
+  const unsigned G = (unsigned)ctx->cu_count * 2;   // probe-stream grid (fixed: accumulator rows)
+  const uint64_t seg_stride = 2 * (uint64_t)(kMaxSegs + 1);
+  uint8_t* mem_t = nullptr;
+  ArenaBlock tmem, aux;
+  tmem.a = aux.a = &ctx->arena;
+  tmem.p = ctx->arena.alloc((tcap_max << kSlotShift) + 256);
   VX_CHECK(tmem.p, VX_EBUDGET,
-           "partitioned join: the largest partition (%llu build rows, %llu slots) does not fit the "
-           "arena; use more partitions", (unsigned long long)max_rows, (unsigned long long)max_cap);
-  // segment lists of every partition, uploaded once: [p][start | prefix] for build, then probe
-  const uint64_t seg_stride = 4 * (uint64_t)(kMaxSegs + 1);
-  segmem.a = &ctx->arena;
-  segmem.p = ctx->arena.alloc((uint64_t)P * seg_stride * 8);
-  VX_CHECK(segmem.p, VX_EBUDGET, "partitioned join: no room for segment lists");
+           "partitioned join: the largest partition (%llu build rows, %llu transient slots) does not fit "
+           "the arena; use more partitions", (unsigned long long)max_rows, (unsigned long long)tcap_max);
+  mem_t = tmem.p;
+  const uint64_t aux_words = (uint64_t)P * kSideWords + (uint64_t)P + (uint64_t)P +
+                             (uint64_t)G * 3 * P + 3ull * P + (uint64_t)P * seg_stride + 8;
+  aux.p = ctx->arena.alloc(aux_words * 8);
+  VX_CHECK(aux.p, VX_EBUDGET, "partitioned join: no room for the partition directory");
+  unsigned long long* side_all = (unsigned long long*)aux.p;
+  unsigned long long* tab_slots = side_all + (uint64_t)P * kSideWords;
+  uint32_t* tab_log2 = (uint32_t*)(tab_slots + P);
+  unsigned long long* accb = tab_slots + 2 * (uint64_t)P;    // tab_log2 takes P/2 words; P words reserved
+  unsigned long long* acc_out = accb + (uint64_t)G * 3 * P;
+  unsigned long long* segdev = acc_out + 3ull * P;
+  unsigned long long* distinct = segdev + (uint64_t)P * seg_stride;
+  fill_zero((uint64_t*)aux.p, aux_words, ctx->compute);
+  hipLaunchKernelGGL(k_pj_init, dim3(grid_for(ctx, tcap_max)), dim3(256), 0, ctx->compute, (uint32_t*)mem_t,
+                     tcap_max, (uint32_t)ks, (unsigned long long*)nullptr);
+  fill_zero((uint64_t*)ctx->dev_flags, 1, ctx->compute);
+  // build segment lists of every partition: [p][start | prefix]
   std::vector<unsigned long long> hseg((uint64_t)P * seg_stride, 0);
-  std::vector<uint64_t> nb_of(P, 0), nq_of(P, 0), sb_of(P, 0), sq_of(P, 0);
+  std::vector<uint64_t> nb_of(P, 0), sb_of(P, 0);
   {
     std::vector<unsigned long long> st, pre;
     for (uint32_t p = 0; p < P; ++p) {
@@ -407,82 +576,153 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
       sb_of[p] = st.size();
       std::copy(st.begin(), st.end(), h);
       std::copy(pre.begin(), pre.end(), h + (kMaxSegs + 1));
-      nq_of[p] = segments(qs, P, p, st, pre);
-      sq_of[p] = st.size();
-      std::copy(st.begin(), st.end(), h + 2 * (kMaxSegs + 1));
-      std::copy(pre.begin(), pre.end(), h + 3 * (kMaxSegs + 1));
     }
   }
-  VX_HIP(hipMemcpyAsync(segmem.p, hseg.data(), hseg.size() * 8, hipMemcpyHostToDevice, ctx->compute));
-  const uint64_t acc_rows = std::min<uint64_t>(P, ctx->dev_acc_words / kAccWords);
-  fill_zero((uint64_t*)ctx->dev_acc, acc_rows * kAccWords, ctx->compute);
-  fill_zero((uint64_t*)ctx->dev_flags, 1, ctx->compute);
-  const bool k64 = B.key.type == VX_I64;
-  uint64_t launches = 0;
-  void* hs_dev = nullptr;
-  VX_HIP(hipHostGetDevicePointer(&hs_dev, hs, 0));
-  const uint8_t* dk_b = (const uint8_t*)hs_dev + (bs.host_key - hs);
-  const uint8_t* dp_b = B.n_pay ? (const uint8_t*)hs_dev + (bs.host_pay[0] - hs) : nullptr;
-  const uint8_t* dk_q = (const uint8_t*)hs_dev + (qs.host_key - hs);
+  VX_HIP(hipMemcpyAsync(segdev, hseg.data(), hseg.size() * 8, hipMemcpyHostToDevice, ctx->compute));
+  // probe pipeline (keys only)
+  std::vector<PipeCol> qcols(1);
+  qcols[0].info = qs.key;
+  qcols[0].may_copy = qcols[0].copy = true;
+  Pipeline pipe;
+  VX_TRY(pipe.plan(ctx, Q.n, Q.chunk_rows, Q.n_buffers, qcols));
+  // compact tables: most of what is left
+  ArenaBlock cmem;
+  cmem.a = &ctx->arena;
+  uint64_t cbytes = ctx->arena.largest_free() / 256 * 256;
+  cbytes = cbytes > (1u << 20) ? cbytes - (1u << 20) : 0;
+  VX_CHECK(cbytes >= 4096, VX_EBUDGET, "partitioned join: no room left for the partition tables");
+  cmem.p = ctx->arena.alloc(cbytes);
+  VX_CHECK(cmem.p, VX_EBUDGET, "partitioned join: no room left for the partition tables");
+
+  const uint8_t* dk_b = bs.mapped_key;
+  const uint8_t* dp_b = B.n_pay ? bs.mapped_pay[0] : nullptr;
   const uint32_t psz = B.n_pay ? (uint32_t)bs.pay[0].elsize : 8;
+  const bool k64 = B.key.type == VX_I64;
+  uint64_t launches = 0, stream_passes = 0;
+  const size_t lds_bytes = (size_t)(5 * P + ps.n_split) * 8;
+  std::vector<unsigned long long> h_slots(P, 0);
+  std::vector<uint32_t> h_log2(P, 0);
+
+  // one pass over the probe side against the partitions resident now
+  auto stream_probe = [&]() -> vx_status {
+    VX_HIP(hipMemcpyAsync(tab_slots, h_slots.data(), P * 8, hipMemcpyHostToDevice, ctx->compute));
+    VX_HIP(hipMemcpyAsync(tab_log2, h_log2.data(), P * 4, hipMemcpyHostToDevice, ctx->compute));
+    const uint32_t count_rows = stream_passes == 0 ? 1u : 0u;
+    auto kern = [&](const ChunkView& v) -> vx_status {
+      const void* keys = (v.global_mask & 1u) ? (const uint8_t*)v.ptr[0] + v.row0 * ks : v.ptr[0];
+      if (k64)
+        hipLaunchKernelGGL(k_pj_stream<int64_t>, dim3(G), dim3(256), lds_bytes, ctx->compute, keys, v.rows, ps,
+                           tab_slots, tab_log2, side_all, count_rows, accb);
+      else
+        hipLaunchKernelGGL(k_pj_stream<int32_t>, dim3(G), dim3(256), lds_bytes, ctx->compute, keys, v.rows, ps,
+                           tab_slots, tab_log2, side_all, count_rows, accb);
+      VX_HIP(hipGetLastError());
+      return VX_OK;
+    };
+    VX_TRY(pipe.run(kern));
+    ++stream_passes;
+    return VX_OK;
+  };
+
+  // pass 2: per non-singleton partition, pre-aggregate its build segments into the transient
+  // table, then compact it into a table sized by its distinct keys; when the compact tables
+  // fill their region, stream the probe side against them and start over
+  uint64_t cused = 0;
+  bool any_resident = false;
   for (uint32_t p = 0; p < P; ++p) {
-    if (slot[p] >= 0 || brows[p] == 0 || qrows[p] == 0) continue;
-    const uint64_t nb = nb_of[p], nq = nq_of[p];
+    if (slot[p] >= 0 || brows[p] == 0) continue;
+    const uint64_t nb = nb_of[p];
     TableView t{};
-    uint64_t cap = 64;
-    while (cap < 2 * nb) cap <<= 1;
-    t.slots = tmem.p;
-    t.mask = cap - 1;
-    while ((1ull << t.log2cap) < cap) ++t.log2cap;
-    t.slot_shift = 5;
-    t.side = (unsigned long long*)(tmem.p + max_cap * slot_bytes);
+    const uint64_t tcap = pow2_at_least(nb + nb / 4);
+    t.slots = mem_t;
+    t.mask = tcap - 1;
+    while ((1ull << t.log2cap) < tcap) ++t.log2cap;
+    t.slot_shift = kSlotShift;
+    t.side = side_all + (uint64_t)p * kSideWords;
     t.n_pay = B.n_pay;
-    t.pay_off[0] = 16;
-    t.pay_size[0] = 8;
     t.preagg = 1;
     t.key_size = (uint32_t)ks;
-    const unsigned long long* h = (const unsigned long long*)segmem.p + (uint64_t)p * seg_stride;
+    const unsigned long long* h = segdev + (uint64_t)p * seg_stride;
     SegList lb{h, h + (kMaxSegs + 1), (uint32_t)sb_of[p], nb};
-    SegList lq{h + 2 * (kMaxSegs + 1), h + 3 * (kMaxSegs + 1), (uint32_t)sq_of[p], nq};
-    unsigned ig = (unsigned)std::min<uint64_t>((cap + 255) / 256, (uint64_t)ctx->cu_count * 8);
-    hipLaunchKernelGGL(k_pj_init, dim3(ig), dim3(256), 0, ctx->compute, (uint32_t*)tmem.p, cap,
-                       slot_bytes / 4, (uint32_t)ks, t.side);
     unsigned gb = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((nb + kPjTile - 1) / kPjTile,
                                                                      (uint64_t)ctx->cu_count * 3));
-    unsigned gq = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((nq + 1023) / 1024, (uint64_t)ctx->cu_count * 8));
-    unsigned long long* acc = (unsigned long long*)ctx->dev_acc + (p % acc_rows) * kAccWords;
-    if (k64) {
+    fill_zero((uint64_t*)distinct, 1, ctx->compute);
+    if (k64)
       hipLaunchKernelGGL(k_pj_build<int64_t>, dim3(gb), dim3(256), 0, ctx->compute, t, dk_b, dp_b, psz, lb,
-                         ctx->dev_flags);
-      hipLaunchKernelGGL(k_pj_probe<int64_t>, dim3(gq), dim3(256), 0, ctx->compute, t, dk_q, lq, acc);
-    } else {
+                         ctx->dev_flags, distinct);
+    else
       hipLaunchKernelGGL(k_pj_build<int32_t>, dim3(gb), dim3(256), 0, ctx->compute, t, dk_b, dp_b, psz, lb,
-                         ctx->dev_flags);
-      hipLaunchKernelGGL(k_pj_probe<int32_t>, dim3(gq), dim3(256), 0, ctx->compute, t, dk_q, lq, acc);
-    }
+                         ctx->dev_flags, distinct);
     VX_HIP(hipGetLastError());
-    launches += 3;
+    unsigned long long nd = 0;
+    VX_HIP(hipMemcpyAsync(&nd, distinct, 8, hipMemcpyDeviceToHost, ctx->compute));
+    VX_HIP(hipStreamSynchronize(ctx->compute));
+    VX_TRY(check_flags(ctx, "partitioned join (build)"));
+    const uint64_t ccap = pow2_at_least(nd + nd / 2);
+    const uint64_t need = ccap << kSlotShift;
+    VX_CHECK(need <= cbytes, VX_EBUDGET,
+             "partitioned join: partition %u's table (%llu distinct keys) does not fit the arena", p,
+             (unsigned long long)nd);
+    if (cused + need > cbytes) {
+      VX_TRY(stream_probe());
+      VX_HIP(hipStreamSynchronize(ctx->compute));
+      std::fill(h_slots.begin(), h_slots.end(), 0ull);
+      std::fill(h_log2.begin(), h_log2.end(), 0u);
+      cused = 0;
+      any_resident = false;
+    }
+    TableView c{};
+    c.slots = cmem.p + cused;
+    c.mask = ccap - 1;
+    while ((1ull << c.log2cap) < ccap) ++c.log2cap;
+    c.slot_shift = kSlotShift;
+    hipLaunchKernelGGL(k_pj_init, dim3(grid_for(ctx, ccap)), dim3(256), 0, ctx->compute, (uint32_t*)c.slots, ccap,
+                       (uint32_t)ks, (unsigned long long*)nullptr);
+    if (k64)
+      hipLaunchKernelGGL(k_pj_compact<int64_t>, dim3(grid_for(ctx, tcap)), dim3(256), 0, ctx->compute, mem_t, tcap, c);
+    else
+      hipLaunchKernelGGL(k_pj_compact<int32_t>, dim3(grid_for(ctx, tcap)), dim3(256), 0, ctx->compute, mem_t, tcap, c);
+    VX_HIP(hipGetLastError());
+    h_slots[p] = (unsigned long long)(uintptr_t)c.slots;
+    h_log2[p] = c.log2cap;
+    cused += need;
+    any_resident = true;
+    launches += 4;
   }
+  // the last pass also counts the probe rows of partitions no pass has seen (singletons,
+  // empty build partitions) when no earlier pass ran
+  const double tb1 = now_ms();
+  if (any_resident || stream_passes == 0) VX_TRY(stream_probe());
+  launches += pipe.kernel_launches();
+  hipLaunchKernelGGL(k_pj_reduce, dim3((3 * P + 255) / 256), dim3(256), 0, ctx->compute, accb, G, 3 * P, acc_out);
+  VX_HIP(hipGetLastError());
+  std::vector<unsigned long long> accs(3ull * P);
+  VX_HIP(hipMemcpyAsync(accs.data(), acc_out, accs.size() * 8, hipMemcpyDeviceToHost, ctx->compute));
   VX_HIP(hipStreamSynchronize(ctx->compute));
   VX_TRY(check_flags(ctx, "partitioned join"));
-  std::vector<unsigned long long> accs(acc_rows * kAccWords);
-  VX_HIP(hipMemcpy(accs.data(), ctx->dev_acc, accs.size() * 8, hipMemcpyDeviceToHost));
   double join_ms = now_ms() - tj0;
+  if (trace)
+    fprintf(stderr, "[vx] partitioned join: pass 1 %.1f ms; pass 2 builds until %.1f ms, probe stream %.1f ms, "
+            "%llu probe pass(es), transient slots %llu, compact tables %.1f MiB of %.1f MiB\n",
+            part_ms, tb1 - tj0, now_ms() - tb1, (unsigned long long)stream_passes, (unsigned long long)tcap_max,
+            cused / 1048576.0, cbytes / 1048576.0);
 
   // per-partition aggregates: pass 2 results, or the singleton closed form
   std::vector<vx_agg> per(P);
+  std::vector<uint64_t> qrows(P, 0);
   uint64_t single_rows = 0;
   for (uint32_t p = 0; p < P; ++p) {
     std::memset(&per[p], 0, sizeof(vx_agg));
+    qrows[p] = accs[3 * p];
     if (slot[p] >= 0) {
       uint64_t cb = bs.slot_sums[2 * slot[p]], sb = bs.slot_sums[2 * slot[p] + 1];
-      uint64_t cq = qs.slot_sums[2 * slot[p]];
+      uint64_t cq = qrows[p];
       per[p].match_count = cb * cq;
       per[p].sum[0] = sb * cq;
       single_rows += cb + cq;
-    } else if (P <= acc_rows) {
-      per[p].match_count = accs[p * kAccWords];
-      for (uint32_t c = 0; c < B.n_pay; ++c) per[p].sum[c] = accs[p * kAccWords + 1 + c];
+    } else {
+      per[p].match_count = accs[3 * p + 1];
+      if (B.n_pay) per[p].sum[0] = accs[3 * p + 2];
     }
   }
   std::memset(&out->agg, 0, sizeof out->agg);
@@ -503,19 +743,22 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
   vx_stats& s = out->stats;
   std::memset(&s, 0, sizeof s);
   s.rows = Q.n;
+  s.chunks = pipe.n_chunks();
+  s.chunk_rows = pipe.chunk_rows();
+  s.n_buffers = pipe.n_buffers();
   s.n_parts = P;
   s.imbalance = tot > 0 ? mx / (tot / P) : 0.0;
   s.part_ms = part_ms;
   s.train_ms = train_ms;
   s.singleton_rows = single_rows;
-  s.sdma_bytes = bs.sdma + qs.sdma;
+  s.sdma_bytes = bs.sdma + pipe.sdma_bytes();
   uint64_t pass2_bytes = 0;
   for (uint32_t p = 0; p < P; ++p)
-    if (slot[p] < 0 && brows[p] && qrows[p])
-      pass2_bytes += brows[p] * (ks + (B.n_pay ? bs.pay[0].elsize : 0)) + qrows[p] * ks;
+    if (slot[p] < 0) pass2_bytes += brows[p] * (ks + (B.n_pay ? bs.pay[0].elsize : 0));
   s.zc_bytes_est = pass2_bytes;
   s.build_ms = 0;
   s.probe_ms = join_ms;
+  s.kernel_ms = pipe.kernel_ms();
   s.kernel_launches = launches;
   s.total_ms = now_ms() - t0;
   out->part_method_used = method;
