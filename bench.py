@@ -22,6 +22,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "probe rows/s + % host-link peak; learned vs hash partitioning, bit-exact"
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E datasheet peak
+# HBM bytes per launch of the dominant kernel, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs
+# scaled by what the same counters read for a plain 1 GiB device read and write (the summaries
+# under profiles/ give the commands).  Valid for the kernel source they were measured on.
+TRAFFIC_BYTES = {"k_probe_stream": 1.5647e9,    # 8,388,608 probe rows per launch
+                 "k_probe_plain": 1.8964e9,     # 16,777,216 probe rows per launch
+                 "k_star": 2.1670e9}            # 16,666,667 fact rows per launch
 GiB = 1 << 30
 
 
@@ -162,7 +168,7 @@ def main():
                    "late_mat": {-1: "auto", 0: "sdma", 1: "zero-copy", 2: "paper-TH"}[args.late_mat],
                    "zero_copy_columns": bin(st["zc_mask"]).count("1")},
         "roofline": {"bound": "hbm", "kernel": "k_probe", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": hbm_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": hbm_gbs / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES["k_probe_stream"],
                      "avg_launch_ms": k_avg_ms, "rows_per_launch": rows_per_launch},
         "host_link": {"peak_measured_gbs": b_peak,
                       "achieved_wire_gbs": wire_bytes / (ms * 1e6),
@@ -247,7 +253,7 @@ def run_plain(args):
                    {"workload": "plain_join_device_resident", "build_rows": nb, "probe_rows": np_,
                     "key": "int32", "build_payloads": "1 x int32"},
                    {"bound": "hbm", "kernel": "k_probe", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": k_ms,
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES["k_probe_plain"], "avg_launch_ms": k_ms,
                     "rows_per_launch": np_},
                    {"result": {"match_count": agg[0], "sum": agg[1]}, "checked_against_oracle": True,
                     "build_ms": st["build_ms"], "probe_ms": st["probe_ms"],
@@ -309,7 +315,8 @@ def run_star(args):
                    # per launch: 4 B foreign key from the chunk buffer + one 8 B slot of the first table
                    "achieved": (nf / st["kernel_launches"]) * 12 / (k_ms * 1e6), "peak": HBM_PEAK_GBS,
                    "unit": "GB/s", "frac": (nf / st["kernel_launches"]) * 12 / (k_ms * 1e6) / HBM_PEAK_GBS,
-                   "traffic": None, "avg_launch_ms": k_ms, "rows_per_launch": nf / st["kernel_launches"]},
+                   "traffic": TRAFFIC_BYTES["k_star"], "avg_launch_ms": k_ms,
+                   "rows_per_launch": nf / st["kernel_launches"]},
                   {"host_link": {"peak_measured_gbs": b_peak, "achieved_wire_gbs": wire / (ms * 1e6),
                                  "frac_wire": wire / (ms * 1e6) / b_peak,
                                  "achieved_algorithmic_gbs": alg / (ms * 1e6),
@@ -388,6 +395,9 @@ def run_skew(args):
         raise SystemExit("partitioned join results differ across partitioners")
     st = a["st"]
     h2d = st["sdma_bytes"] + st["zc_bytes_est"]
+    # dominant kernel: the probe stream (one launch per probe chunk, HIP events on its stream)
+    k_avg = st["kernel_ms"] / max(1, st["chunks"])
+    ach = (8.0 * np_ + 32.0 * st["survivors"]) / st["chunks"] / (k_avg * 1e6)
     ctx.close()
     for h in (bk, bp, pk):
         h.free()
@@ -395,8 +405,10 @@ def run_skew(args):
                    {"workload": "skewed_partitioned_join", "build_rows": nb, "probe_rows": np_, "zipf_s": 1.1,
                     "key_range": "[1, 2^40]", "device_budget_gib": 32, "method": args.method,
                     "n_parts": st["n_parts"]},
-                   {"bound": "hbm", "kernel": "k_part_scatter/k_pj_probe", "achieved": None, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": None, "traffic": None},
+                   {"bound": "hbm", "kernel": "k_pj_stream", "achieved": ach, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": k_avg,
+                    "rows_per_launch": np_ / st["chunks"],
+                    "algorithmic_bytes": "8 B per probe key + 32 B table slot per probe row routed to a table"},
                    {"host_link": {"peak_measured_gbs": b_peak, "h2d_bytes_per_step": h2d,
                                   "achieved_gbs": h2d / (a["ms"] * 1e6), "frac": h2d / (a["ms"] * 1e6) / b_peak},
                     "result": {"match_count": a["agg"][0], "sum": a["agg"][1]},

@@ -138,7 +138,8 @@ typedef struct {
   double part_ms;           /* partition pass wall time */
   double train_ms;          /* CDF model training wall time */
   uint64_t singleton_rows;  /* rows resolved through singleton partitions */
-  uint64_t survivors;       /* star join: fact rows that pass every dimension */
+  uint64_t survivors;       /* star join: fact rows that pass every dimension; partitioned join:
+                               probe rows routed to a partition table (not a singleton) */
 } vx_stats;
 
 /* ------------------------------------------------------------------------ build / probe */

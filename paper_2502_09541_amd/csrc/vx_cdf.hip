@@ -17,7 +17,7 @@ namespace vx {
 
 constexpr unsigned long long kGolden = 0x9E3779B97F4A7C15ull;
 constexpr uint32_t kPartialStride = kModelParams + 1;   // gradient components + loss
-constexpr uint64_t kTrainMax = 1ull << 20;              // training points taken from the sample
+constexpr uint64_t kTrainMax = 1ull << 16;              // training points taken from the sample
 
 // SplitMix64 output function (Steele, Lea and Flood, OOPSLA 2014).
 __device__ __forceinline__ unsigned long long splitmix_out(unsigned long long z) {
@@ -280,7 +280,10 @@ __global__ void k_cross(const float* x, const float* t, uint64_t m, const float*
     long long c = yp >= (double)(P - 1) ? (long long)(P - 1) : (yp < 0.0 ? 0 : (long long)floor(yp));
     while (c < (long long)P - 1 && y >= (double)(c + 1) / (double)P) ++c;
     while (c > 0 && !(y >= (double)c / (double)P)) --c;
-    if (c >= 1) atomicMin(first + c, (unsigned long long)i);
+    // lanes hold consecutive rows, so only the first lane of each run of equal counts can hold
+    // its run's smallest row
+    long long cp = __shfl_up(c, 1, 64);
+    if (c >= 1 && ((threadIdx.x & 63) == 0 || cp != c)) atomicMin(first + c, (unsigned long long)i);
   }
 }
 

@@ -102,6 +102,7 @@ struct vx_ctx {
   uint64_t* dev_acc = nullptr;
   uint64_t dev_acc_words = 0;
   unsigned int* dev_flags = nullptr;   // error flags written by kernels
+  uint64_t* dev_scan = nullptr;        // kScanTilesMax + 1 words: tile sums of the partition scan
   int cu_count = 256;
   uint64_t l2_bytes = 4u << 20;
   // pinned host mirror of results
@@ -137,6 +138,7 @@ void fill_zero(uint64_t* p, uint64_t words, hipStream_t s);
 // Estimated zero-copy wire bytes of reading `count` matching rows, of elsize bytes each,
 // spread over `n` rows: the touched lines of `line` bytes under independent selection.
 double zc_wire_bytes(uint64_t n, uint64_t count, int elsize, uint32_t line);
+constexpr uint32_t kScanTilesMax = 1024;
 constexpr int kAccWords = 9;            // count + 8 sums per aggregate row
 
 }  // namespace vx

@@ -86,32 +86,81 @@ __global__ void __launch_bounds__(256) k_part_hist(PartSpec ps, PartIO io, uint6
 }
 
 // single-block exclusive scan over count entries (partition-major hist)
-__global__ void __launch_bounds__(1024) k_scan_full(const uint32_t* hist, uint64_t count,
-                                                    unsigned long long* offs, uint32_t n_parts,
-                                                    uint32_t waves, unsigned long long* boundary) {
-  __shared__ unsigned long long part[1024];
-  const uint64_t per = (count + blockDim.x - 1) / blockDim.x;
-  const uint64_t a = threadIdx.x * per, b = a + per < count ? a + per : count;
-  unsigned long long s = 0;
-  for (uint64_t i = a; i < b; ++i) s += hist[i];
-  part[threadIdx.x] = s;
+// Exclusive scan of the partition-major histogram, in three launches: per-tile sums, a scan of
+// the tile sums, and each tile rescanned from its base.  boundary[p] (optional) receives the
+// offset of entry p * waves, i.e. partition p's first row, and boundary[n_parts] the total.
+constexpr uint32_t kScanThreads = 256;
+
+// exclusive prefix of v over the block (256 threads); *total receives the block's sum
+__device__ __forceinline__ unsigned long long block_excl_scan(unsigned long long v, unsigned long long* ws,
+                                                              unsigned long long* total) {
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  unsigned long long x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    unsigned long long y = __shfl_up(x, o, 64);
+    if (lane >= (uint32_t)o) x += y;
+  }
+  if (lane == 63) ws[wave] = x;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long run = 0;
-    for (uint32_t t = 0; t < blockDim.x; ++t) {
-      unsigned long long v = part[t];
-      part[t] = run;
-      run += v;
-    }
-    if (boundary) boundary[n_parts] = run;
+  unsigned long long base = 0, tot = 0;
+  for (uint32_t w = 0; w < kScanThreads / 64; ++w) {
+    if (w < wave) base += ws[w];
+    tot += ws[w];
   }
   __syncthreads();
-  unsigned long long run = part[threadIdx.x];
-  for (uint64_t i = a; i < b; ++i) {
+  *total = tot;
+  return base + x - v;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const uint32_t* hist, uint64_t count, uint64_t tile,
+                                                             unsigned long long* tsum) {
+  __shared__ unsigned long long ws[kScanThreads / 64];
+  const uint64_t a = blockIdx.x * tile, e = a + tile < count ? a + tile : count;
+  unsigned long long s = 0;
+  for (uint64_t i = a + threadIdx.x; i < e; i += blockDim.x) s += hist[i];
+  unsigned long long tot = 0;
+  block_excl_scan(s, ws, &tot);
+  if (threadIdx.x == 0) tsum[blockIdx.x] = tot;
+}
+
+// tsum[0..nt) becomes its exclusive scan; tsum[nt] the total (nt <= 4 * kScanThreads)
+__global__ void __launch_bounds__(kScanThreads) k_scan_top(unsigned long long* tsum, uint32_t nt) {
+  __shared__ unsigned long long ws[kScanThreads / 64];
+  const uint32_t a = threadIdx.x * 4;
+  unsigned long long v[4], s = 0;
+  for (uint32_t j = 0; j < 4; ++j) {
+    v[j] = a + j < nt ? tsum[a + j] : 0ull;
+    s += v[j];
+  }
+  unsigned long long tot = 0;
+  unsigned long long run = block_excl_scan(s, ws, &tot);
+  for (uint32_t j = 0; j < 4; ++j)
+    if (a + j < nt) {
+      tsum[a + j] = run;
+      run += v[j];
+    }
+  if (threadIdx.x == 0) tsum[nt] = tot;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_apply(const uint32_t* hist, uint64_t count, uint64_t tile,
+                                                             const unsigned long long* tsum, uint32_t nt,
+                                                             unsigned long long* offs, uint32_t n_parts,
+                                                             uint32_t waves, unsigned long long* boundary) {
+  __shared__ unsigned long long ws[kScanThreads / 64];
+  const uint64_t a = blockIdx.x * tile, e = a + tile < count ? a + tile : count;
+  const uint64_t per = (tile + kScanThreads - 1) / kScanThreads;
+  const uint64_t ta = a + threadIdx.x * per < e ? a + threadIdx.x * per : e;
+  const uint64_t te = ta + per < e ? ta + per : e;
+  unsigned long long s = 0;
+  for (uint64_t i = ta; i < te; ++i) s += hist[i];
+  unsigned long long tot = 0;
+  unsigned long long run = tsum[blockIdx.x] + block_excl_scan(s, ws, &tot);
+  for (uint64_t i = ta; i < te; ++i) {
     offs[i] = run;
     if (boundary && i % waves == 0) boundary[i / waves] = run;
     run += hist[i];
   }
+  if (boundary && blockIdx.x == 0 && threadIdx.x == 0) boundary[n_parts] = tsum[nt];
 }
 
 // one block per partition: offs[p*W + w] = base[p] + sum of hist[p*W + w'] for w' < w
@@ -214,11 +263,17 @@ vx_status part_hist(vx_ctx* ctx, const PartSpec& ps, const PartIO& io, const Par
 vx_status part_scan(vx_ctx* ctx, const uint32_t* hist, uint32_t n_parts, uint32_t waves,
                     const unsigned long long* part_base, unsigned long long* offs,
                     unsigned long long* boundary, hipStream_t s) {
-  (void)ctx;
   if (part_base) {
     hipLaunchKernelGGL(k_scan_seg, dim3(n_parts), dim3(256), 0, s, hist, waves, part_base, offs);
   } else {
-    hipLaunchKernelGGL(k_scan_full, dim3(1), dim3(1024), 0, s, hist, (uint64_t)n_parts * waves, offs,
+    const uint64_t count = (uint64_t)n_parts * waves;
+    uint64_t tile = 4096;
+    while ((count + tile - 1) / tile > kScanTilesMax) tile *= 2;
+    const uint32_t nt = (uint32_t)std::max<uint64_t>(1, (count + tile - 1) / tile);
+    unsigned long long* tsum = (unsigned long long*)ctx->dev_scan;
+    hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(kScanThreads), 0, s, hist, count, tile, tsum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, tsum, nt);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(kScanThreads), 0, s, hist, count, tile, tsum, nt, offs,
                        n_parts, waves, boundary);
   }
   VX_HIP(hipGetLastError());

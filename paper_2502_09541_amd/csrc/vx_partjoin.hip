@@ -358,7 +358,7 @@ vx_status cluster_side(vx_ctx* ctx, const PartSpec& ps, const int* sum_slot_dev,
   hipEvent_t done[2] = {get_event(ctx), get_event(ctx)};
   hipEvent_t wrote[2] = {get_event(ctx), get_event(ctx)};
   bool pending[2] = {false, false};
-  const unsigned wb_grid = (unsigned)ctx->cu_count * 2;
+  const unsigned wb_grid = (unsigned)ctx->cu_count * 8;
   auto kernel = [&](const ChunkView& v) -> vx_status {
     uint32_t b = (uint32_t)(v.index % 2);
     if (pending[b]) VX_HIP(hipStreamWaitEvent(ctx->compute, wrote[b], 0));
@@ -751,6 +751,8 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
   s.part_ms = part_ms;
   s.train_ms = train_ms;
   s.singleton_rows = single_rows;
+  for (uint32_t p = 0; p < P; ++p)
+    if (slot[p] < 0) s.survivors += qrows[p];
   s.sdma_bytes = bs.sdma + pipe.sdma_bytes();
   uint64_t pass2_bytes = 0;
   for (uint32_t p = 0; p < P; ++p)

@@ -235,15 +235,17 @@ vx_status vx_ctx_create(int device, void* arena, uint64_t arena_bytes, void* str
     c->l2_bytes = (uint64_t)pr.l2CacheSize;
   }
   c->dev_acc_words = kAccRows * kAccWords;
-  uint8_t* scratch = c->arena.alloc(c->dev_acc_words * 8 + 256);
+  const uint64_t scratch_bytes = c->dev_acc_words * 8 + 256 + (kScanTilesMax + 1) * 8;
+  uint8_t* scratch = c->arena.alloc(scratch_bytes);
   if (!scratch) {
     delete c;
     set_error("vx_ctx_create: arena of %llu bytes cannot hold the %llu-byte result scratch",
-              (unsigned long long)arena_bytes, (unsigned long long)(kAccRows * kAccWords * 8 + 256));
+              (unsigned long long)arena_bytes, (unsigned long long)scratch_bytes);
     return VX_EBUDGET;
   }
   c->dev_acc = (uint64_t*)scratch;
   c->dev_flags = (unsigned int*)(scratch + c->dev_acc_words * 8);
+  c->dev_scan = (uint64_t*)(scratch + c->dev_acc_words * 8 + 256);
   if (stream) {
     c->compute = (hipStream_t)stream;
   } else {

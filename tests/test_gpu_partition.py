@@ -236,6 +236,40 @@ def test_auto_method_reports_estimates(gpu, ctx):
     assert r["hist"].sum() == len(key)
 
 
+def _largest_table_partition(r):
+    """Rows of the largest partition that has to be joined through a hash table: every partition
+    except the singletons [s, s + 1), whose single key is resolved from its counts."""
+    spl = np.asarray(r["splitters"], np.int64)
+    hist = np.asarray(r["hist"], np.int64)
+    single = np.zeros(len(hist), bool)
+    if len(spl) > 1:
+        single[1:len(spl)] = spl[1:] == spl[:-1] + 1
+    return int(hist[~single].max()), int(hist[single].sum())
+
+
+def test_trained_network_gain(gpu, ctx):
+    """What training buys on Zipf(1.1) keys: the trained CDF network's splitters isolate the heavy
+    keys and balance the rest, so its largest table-joined partition is several times smaller than
+    with the same network untrained (initial weights) or with radix-hash partitioning, whose
+    partition holding the heaviest key takes about a tenth of all rows."""
+    rng = np.random.default_rng(21)
+    key = rng.zipf(1.1, 2_000_000).astype(np.int64)
+    n, P = len(key), 64
+    _say("trained network gain")
+    got = {}
+    for m in ("learned", "untrained", "radix_hash"):
+        r = ctx.partition(dev(key), method=m, n_parts=P, seed=3, sample_frac=0.02, train_steps=300)
+        assert r["hist"].sum() == n
+        got[m] = _largest_table_partition(r) if m != "radix_hash" else (int(r["hist"].max()), 0)
+    mean = n / P
+    print("largest table-joined partition / mean:", {m: round(v[0] / mean, 2) for m, v in got.items()},
+          "singleton rows:", {m: v[1] for m, v in got.items()}, flush=True)
+    assert got["learned"][1] > 0.1 * n               # heavy keys go to singleton partitions
+    assert got["learned"][0] * 3 < got["untrained"][0]
+    assert got["learned"][0] * 3 < got["radix_hash"][0]
+    assert got["radix_hash"][0] > 0.09 * n
+
+
 # ----------------------------------------------------------------------------- partitioned join
 
 def _zipf_join(n_b, n_p, seed):
