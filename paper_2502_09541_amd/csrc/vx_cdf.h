@@ -17,6 +17,10 @@ struct CdfReport {
   uint64_t sample_rows = 0;
   uint32_t radix_parts = 0;
   double sample_ms = 0, sort_ms = 0, train_ms = 0, split_ms = 0;
+  // shape of the sample under the range splitters, for planning the partitioned join
+  double single_share = 0;     // share of sample rows in singleton partitions
+  double max_share = 0;        // largest other partition's share of the sample rows
+  double distinct_share = 0;   // distinct keys / rows in the sample
 };
 
 // Samples keys (Bernoulli, SplitMix64 draws keyed by row), sorts the sample on the GPU,

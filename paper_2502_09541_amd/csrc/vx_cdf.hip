@@ -297,6 +297,16 @@ __global__ void k_stride_gather(const float* x, const float* t, uint64_t m_s, ui
   }
 }
 
+// *out += number of rows i >= 1 with s[i] != s[i - 1] (distinct keys - 1 of a sorted array)
+__global__ void k_count_changes(const long long* s, uint64_t m, unsigned long long* out) {
+  unsigned long long c = 0;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x + 1; i < m;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    c += s[i] != s[i - 1];
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+}
+
 __global__ void k_gather_i64(const long long* s, const unsigned long long* idx, uint32_t cnt,
                              long long* out) {
   uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -626,8 +636,21 @@ vx_status cdf_splitters(vx_ctx* ctx, const ColInfo& key, uint64_t n, const vx_pa
     VX_TRY(part_hist(ctx, pr2, io, g, hist, tot, nullptr, nullptr, s));
     h.assign(pr2.n_parts, 0);
     VX_HIP(hipMemcpyAsync(h.data(), tot, h.size() * 8, hipMemcpyDeviceToHost, s));
+    fill_zero((uint64_t*)tot, 1, s);
+    hipLaunchKernelGGL(k_count_changes, dim3(grid1(ctx, m)), dim3(256), 0, s, sorted, m, tot);
+    unsigned long long changes = 0;
+    VX_HIP(hipMemcpyAsync(&changes, tot, 8, hipMemcpyDeviceToHost, s));
     VX_HIP(hipStreamSynchronize(s));
     rep->imbalance_range = imbalance_of(h);
+    uint64_t single = 0, mx = 0;
+    for (uint32_t p = 0; p < pr2.n_parts; ++p) {
+      bool one = p >= 1 && p + 1 < pr2.n_parts && (*splitters)[p] == (*splitters)[p - 1] + 1;
+      if (one) single += h[p];
+      else mx = std::max<uint64_t>(mx, h[p]);
+    }
+    rep->single_share = (double)single / (double)m;
+    rep->max_share = (double)mx / (double)m;
+    rep->distinct_share = (double)(changes + 1) / (double)m;
   }
   return VX_OK;
 }

@@ -306,6 +306,7 @@ struct Side {
   uint8_t* host_pay[kMaxPay] = {};
   uint8_t* mapped_key = nullptr;        // the same memory as the device addresses it
   uint8_t* mapped_pay[kMaxPay] = {};
+  bool on_device = false;               // the clustered copy lives in the arena instead
   uint64_t chunk_rows = 0, n_chunks = 0;
   std::vector<unsigned long long> bnd;  // n_chunks * (P + 1)
   std::vector<unsigned long long> slot_sums;   // 2 * kMaxSumSlots: count, payload-0 sum
@@ -341,7 +342,8 @@ vx_status cluster_side(vx_ctx* ctx, const PartSpec& ps, const int* sum_slot_dev,
   // staging for clustered chunks (double-buffered against the write-back), per-wave
   // histograms, offsets, per-chunk boundaries and singleton sums
   PartGeom g0 = part_geom(ctx, sd.chunk_rows);
-  uint64_t stage_bytes = align_up(sd.chunk_rows * row_bytes + 256 * (1 + kMaxPay), 256);
+  // (a device-resident clustered copy is scattered into directly: no staging, no write-back)
+  uint64_t stage_bytes = sd.on_device ? 0 : align_up(sd.chunk_rows * row_bytes + 256 * (1 + kMaxPay), 256);
   uint64_t scratch = 2 * stage_bytes + (uint64_t)P * g0.waves * 12 +
                      std::max<uint64_t>(sd.n_chunks, 1) * (P + 1) * 8 + 2 * kMaxSumSlots * 8 + 1024;
   ArenaBlock blk;
@@ -368,14 +370,14 @@ vx_status cluster_side(vx_ctx* ctx, const PartSpec& ps, const int* sum_slot_dev,
     io.n = v.rows;
     io.n_pay = sd.n_pay;
     uint8_t* out = stage[b];
-    io.out_key = out;
+    io.out_key = sd.on_device ? sd.mapped_key + v.row0 * sd.key.elsize : out;
     uint64_t off = align_up(v.rows * sd.key.elsize, 256);
     for (uint32_t c = 0; c < sd.n_pay; ++c) {
       io.pay[c] = ((v.global_mask >> (1 + c)) & 1u)
                       ? (const uint8_t*)v.ptr[1 + c] + v.row0 * sd.pay[c].elsize
                       : v.ptr[1 + c];
       io.pay_size[c] = (uint32_t)sd.pay[c].elsize;
-      io.out_pay[c] = out + off;
+      io.out_pay[c] = sd.on_device ? sd.mapped_pay[c] + v.row0 * sd.pay[c].elsize : out + off;
       off += align_up(v.rows * sd.pay[c].elsize, 256);
     }
     PartGeom g = part_geom(ctx, v.rows);
@@ -383,6 +385,7 @@ vx_status cluster_side(vx_ctx* ctx, const PartSpec& ps, const int* sum_slot_dev,
                      ctx->compute));
     VX_TRY(part_scan(ctx, hist, P, g.waves, nullptr, offs, bnd + v.index * (P + 1), ctx->compute));
     VX_TRY(part_scatter(ctx, ps, io, g, offs, ctx->compute));
+    if (sd.on_device) return VX_OK;
     VX_HIP(hipEventRecord(done[b], ctx->compute));
     // write the clustered chunk back to host memory at the chunk's own rows
     VX_HIP(hipStreamWaitEvent(ctx->d2h, done[b], 0));
@@ -503,13 +506,44 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
     slot_dev = (const int*)slot_mem.p;
   }
 
-  // pinned host memory for the clustered build side
+  // Where the clustered build side lives.  In the arena when the range splitters' sample
+  // predicts that pass 2 fits beside it: the clustered rows, the transient table of the largest
+  // partition, and compact tables sized from the sample's distinct-key share (about 2.1 slots of
+  // 32 B per distinct key after power-of-two rounding).  Otherwise in pinned host memory, read
+  // back by zero-copy.  Radix-hash partitions come with no size prediction and take the host plan.
   uint64_t hbytes = align_up(B.n * ks, 256);
   for (uint32_t c = 0; c < B.n_pay; ++c) hbytes += align_up(B.n * bs.pay[c].elsize, 256);
+  {
+    const uint64_t mode = env_u64("VX_PJ_DEVICE", 2);   // 0 host, 1 device, 2 planned
+    if (mode == 1) {
+      bs.on_device = true;
+    } else if (mode == 2 && ps.fn == kPartRange && rep.sample_rows > 0) {
+      const double ns_rows = (double)B.n * (1.0 - rep.single_share);
+      const double part_rows = (double)B.n * rep.max_share * 1.25 + 1024.0;
+      const double tbytes = 32.0 * 2.0 * 1.25 * part_rows;
+      const double cbytes = 32.0 * 2.1 * rep.distinct_share * ns_rows;
+      const double pipe_bytes = 3.0 * (64 << 20) * 2.0 + (512 << 20);
+      bs.on_device = (double)hbytes + tbytes + cbytes + pipe_bytes <= (double)ctx->arena.largest_free();
+      if (trace)
+        fprintf(stderr, "[vx] plan: clustered %.2f GiB + transient %.2f GiB + compact %.2f GiB (distinct share "
+                "%.3f, singleton share %.3f) vs %.2f GiB free: %s\n", hbytes / 1073741824.0, tbytes / 1073741824.0,
+                cbytes / 1073741824.0, rep.distinct_share, rep.single_share,
+                ctx->arena.largest_free() / 1073741824.0, bs.on_device ? "device" : "host");
+    }
+  }
+  ArenaBlock cl_mem;
   uint8_t* hs = nullptr;
-  VX_TRY(host_scratch(ctx, hbytes + 256, &hs));
-  void* hs_dev = nullptr;
-  VX_HIP(hipHostGetDevicePointer(&hs_dev, hs, 0));
+  if (bs.on_device) {
+    cl_mem.a = &ctx->arena;
+    cl_mem.p = ctx->arena.alloc(hbytes + 256);
+    VX_CHECK(cl_mem.p, VX_EBUDGET, "partitioned join: no room for the clustered build side (%llu B)",
+             (unsigned long long)hbytes);
+    hs = cl_mem.p;
+  } else {
+    VX_TRY(host_scratch(ctx, hbytes + 256, &hs));
+  }
+  void* hs_dev = hs;
+  if (!bs.on_device) VX_HIP(hipHostGetDevicePointer(&hs_dev, hs, 0));
   bs.host_key = hs;
   bs.mapped_key = (uint8_t*)hs_dev;
   uint64_t off = align_up(B.n * ks, 256);
@@ -703,9 +737,9 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
   double join_ms = now_ms() - tj0;
   if (trace)
     fprintf(stderr, "[vx] partitioned join: pass 1 %.1f ms; pass 2 builds until %.1f ms, probe stream %.1f ms, "
-            "%llu probe pass(es), transient slots %llu, compact tables %.1f MiB of %.1f MiB\n",
+            "%llu probe pass(es), transient slots %llu, compact tables %.1f MiB of %.1f MiB, clustered copy in %s\n",
             part_ms, tb1 - tj0, now_ms() - tb1, (unsigned long long)stream_passes, (unsigned long long)tcap_max,
-            cused / 1048576.0, cbytes / 1048576.0);
+            cused / 1048576.0, cbytes / 1048576.0, bs.on_device ? "device memory" : "host memory");
 
   // per-partition aggregates: pass 2 results, or the singleton closed form
   std::vector<vx_agg> per(P);
@@ -756,7 +790,7 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
   s.sdma_bytes = bs.sdma + pipe.sdma_bytes();
   uint64_t pass2_bytes = 0;
   for (uint32_t p = 0; p < P; ++p)
-    if (slot[p] < 0) pass2_bytes += brows[p] * (ks + (B.n_pay ? bs.pay[0].elsize : 0));
+    if (slot[p] < 0 && !bs.on_device) pass2_bytes += brows[p] * (ks + (B.n_pay ? bs.pay[0].elsize : 0));
   s.zc_bytes_est = pass2_bytes;
   s.build_ms = 0;
   s.probe_ms = join_ms;

@@ -295,6 +295,22 @@ def test_partitioned_join_methods_exact(gpu, ctx, method, monkeypatch):
         assert st["singleton_rows"] == 0 and st["n_parts"] == 64
 
 
+@pytest.mark.parametrize("placement", ["0", "1"])
+def test_partitioned_join_clustered_copy_placement(gpu, ctx, placement, monkeypatch):
+    """The clustered build side in pinned host memory (read back by zero-copy) or in device
+    memory gives the same exact aggregates and per-partition results."""
+    monkeypatch.setenv("VX_CHUNK_BYTES", str(8 * 40_000))
+    monkeypatch.setenv("VX_PJ_DEVICE", placement)
+    bk, bp, pk = _zipf_join(250_000, 600_001, 13)
+    _say("clustered copy placement", placement)
+    got, st, used, per = ctx.join_partitioned(pinned(gpu, bk), [pinned(gpu, bp)], pinned(gpu, pk),
+                                              method="learned", n_parts=32, seed=4, train_steps=60,
+                                              per_partition=True)
+    assert got == oracle.join_agg(bk, [bp], pk, [])
+    assert [sum(x) % (1 << 64) for x in zip(*per)] == got
+    assert (st["zc_bytes_est"] == 0) == (placement == "1")
+
+
 def test_partitioned_join_per_partition_radix(gpu, ctx):
     bk, bp, pk = _zipf_join(100_000, 300_000, 7)
     _say("partitioned per-partition")
