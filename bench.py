@@ -27,7 +27,9 @@ HBM_PEAK_GBS = 8000.0       # MI355X HBM3E datasheet peak
 # under profiles/ give the commands).  Valid for the kernel source they were measured on.
 TRAFFIC_BYTES = {"k_probe_stream": 1.5647e9,    # 8,388,608 probe rows per launch
                  "k_probe_plain": 1.8964e9,     # 16,777,216 probe rows per launch
-                 "k_star": 2.1670e9}            # 16,666,667 fact rows per launch
+                 "k_star": 2.1670e9,            # 16,666,667 fact rows per launch
+                 "batch_graph": 6.0252e11,      # one graph launch: build phase + probe phase, all 256 jobs
+                 "k_pj_stream": 5.066e8}        # 8,388,608 probe rows per launch (mean over the partitioners)
 GiB = 1 << 30
 
 
@@ -357,7 +359,7 @@ def run_batch(args):
                     "tile_rows": st["chunk_rows"], "block": st["n_buffers"], "load_factor": st["imbalance"]},
                    {"bound": "hbm", "kernel": "graph(k_batch_phase build+probe)", "achieved": alg / (k_ms * 1e6),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg / (k_ms * 1e6) / HBM_PEAK_GBS,
-                    "traffic": None, "avg_launch_ms": k_ms, "rows_per_launch": rows},
+                    "traffic": TRAFFIC_BYTES["batch_graph"], "avg_launch_ms": k_ms, "rows_per_launch": rows},
                    {"baseline_separate_launches": {"ms_per_step": ms1, "value": rows / (ms1 / 1e3),
                                                    "launches": res1[0][1]["kernel_launches"]},
                     "speedup_vs_separate_launches": ms1 / ms})
@@ -406,7 +408,8 @@ def run_skew(args):
                     "key_range": "[1, 2^40]", "device_budget_gib": 32, "method": args.method,
                     "n_parts": st["n_parts"]},
                    {"bound": "hbm", "kernel": "k_pj_stream", "achieved": ach, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": k_avg,
+                    "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES["k_pj_stream"],
+                    "avg_launch_ms": k_avg,
                     "rows_per_launch": np_ / st["chunks"],
                     "algorithmic_bytes": "8 B per probe key + 32 B table slot per probe row routed to a table"},
                    {"host_link": {"peak_measured_gbs": b_peak, "h2d_bytes_per_step": h2d,
