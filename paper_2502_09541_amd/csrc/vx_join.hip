@@ -518,6 +518,8 @@ vx_status probe_impl(vx_ctx* ctx, const vx_table* t, const vx_probe_desc* d, vx_
   s.table_bytes = t->bytes;
 
   Pipeline pipe;
+  VX_CHECK(d->n_buffers == 0 || (d->n_buffers >= 2 && d->n_buffers <= 4), VX_EINVAL,
+           "probe: n_buffers %u outside 2..4", d->n_buffers);
   VX_TRY(pipe.plan(ctx, n, d->chunk_rows, d->n_buffers, cols));
   const uint64_t n_chunks = pipe.n_chunks();
   const uint64_t acc_rows_cap = ctx->dev_acc_words / kAccWords;

@@ -513,6 +513,7 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
   // back by zero-copy.  Radix-hash partitions come with no size prediction and take the host plan.
   uint64_t hbytes = align_up(B.n * ks, 256);
   for (uint32_t c = 0; c < B.n_pay; ++c) hbytes += align_up(B.n * bs.pay[c].elsize, 256);
+  double plan_compact = 0;   // expected bytes of the compact tables (device plan only)
   {
     const uint64_t mode = env_u64("VX_PJ_DEVICE", 2);   // 0 host, 1 device, 2 planned
     if (mode == 1) {
@@ -524,6 +525,7 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
       const double cbytes = 32.0 * 2.1 * rep.distinct_share * ns_rows;
       const double pipe_bytes = 3.0 * (64 << 20) * 2.0 + (512 << 20);
       bs.on_device = (double)hbytes + tbytes + cbytes + pipe_bytes <= (double)ctx->arena.largest_free();
+      plan_compact = cbytes;
       if (trace)
         fprintf(stderr, "[vx] plan: clustered %.2f GiB + transient %.2f GiB + compact %.2f GiB (distinct share "
                 "%.3f, singleton share %.3f) vs %.2f GiB free: %s\n", hbytes / 1073741824.0, tbytes / 1073741824.0,
@@ -613,12 +615,20 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
     }
   }
   VX_HIP(hipMemcpyAsync(segdev, hseg.data(), hseg.size() * 8, hipMemcpyHostToDevice, ctx->compute));
-  // probe pipeline (keys only)
+  // probe pipeline (keys only).  On the device plan pass 2 reads HBM and leaves the host link
+  // idle, so the pipeline takes every chunk buffer the arena spares beside the expected
+  // compact tables and starts their copies before the builds.
   std::vector<PipeCol> qcols(1);
   qcols[0].info = qs.key;
   qcols[0].may_copy = qcols[0].copy = true;
+  uint32_t qbuf = Q.n_buffers;
+  if (bs.on_device && qs.key.where == Where::Host && Q.n_buffers == 0) {
+    const uint64_t chunk_bytes = env_u64("VX_CHUNK_BYTES", 64ull << 20) + 256;
+    const double spare = (double)ctx->arena.largest_free() - 1.05 * plan_compact - (double)(256u << 20);
+    qbuf = (uint32_t)std::max<double>(2.0, std::min<double>((double)kMaxBuffers, spare / (double)chunk_bytes));
+  }
   Pipeline pipe;
-  VX_TRY(pipe.plan(ctx, Q.n, Q.chunk_rows, Q.n_buffers, qcols));
+  VX_TRY(pipe.plan(ctx, Q.n, Q.chunk_rows, qbuf, qcols));
   // compact tables: most of what is left
   ArenaBlock cmem;
   cmem.a = &ctx->arena;
@@ -661,6 +671,7 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
   // pass 2: per non-singleton partition, pre-aggregate its build segments into the transient
   // table, then compact it into a table sized by its distinct keys; when the compact tables
   // fill their region, stream the probe side against them and start over
+  VX_TRY(pipe.prefetch(pipe.n_buffers()));
   uint64_t cused = 0;
   bool any_resident = false;
   for (uint32_t p = 0; p < P; ++p) {

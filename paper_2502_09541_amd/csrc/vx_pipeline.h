@@ -17,6 +17,7 @@
 namespace vx {
 
 constexpr int kMaxPipeCols = 12;
+constexpr uint32_t kMaxBuffers = 128;
 
 struct PipeCol {
   ColInfo info;
@@ -42,6 +43,9 @@ class Pipeline {
   vx_status plan(vx_ctx* ctx, uint64_t n, uint64_t chunk_rows, uint32_t n_buffers,
                  std::vector<PipeCol> cols, uint64_t default_chunk_bytes = 64ull << 20);
   vx_status run(const KernelFn& fn, const DecideFn& decide = nullptr);
+  // Enqueues the copies of the first min(k, buffers - 1, chunks) chunks now, so that they proceed
+  // while the caller runs other work on the compute stream; the next run() starts from them.
+  vx_status prefetch(uint64_t k);
 
   std::vector<PipeCol>& cols() { return cols_; }
   uint64_t chunk_rows() const { return chunk_rows_; }
@@ -63,9 +67,10 @@ class Pipeline {
   uint32_t nbuf_ = 2;
   bool streamed_ = false;
   std::vector<PipeCol> cols_;
-  ArenaBlock bufs_[4];
-  hipEvent_t ev_copied_[4] = {}, ev_free_[4] = {};
-  bool free_pending_[4] = {};
+  uint64_t prefetched_ = 0;
+  ArenaBlock bufs_[kMaxBuffers];
+  hipEvent_t ev_copied_[kMaxBuffers] = {}, ev_free_[kMaxBuffers] = {};
+  bool free_pending_[kMaxBuffers] = {};
   std::vector<std::pair<hipEvent_t, hipEvent_t>> kev_;
 };
 

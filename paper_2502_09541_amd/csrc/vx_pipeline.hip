@@ -22,7 +22,7 @@ Pipeline::~Pipeline() {
 
 void Pipeline::release_events() {
   if (!ctx_) return;
-  for (uint32_t b = 0; b < 4; ++b) {
+  for (uint32_t b = 0; b < kMaxBuffers; ++b) {
     put_event(ctx_, ev_copied_[b]);
     put_event(ctx_, ev_free_[b]);
     ev_copied_[b] = ev_free_[b] = nullptr;
@@ -44,7 +44,8 @@ vx_status Pipeline::plan(vx_ctx* ctx, uint64_t n, uint64_t chunk_rows, uint32_t 
   VX_CHECK(cols_.size() <= (size_t)kMaxPipeCols, VX_EINVAL, "pipeline: %zu columns (max %d)",
            cols_.size(), kMaxPipeCols);
   nbuf_ = n_buffers ? n_buffers : (uint32_t)env_u64("VX_BUFFERS", 2);
-  VX_CHECK(nbuf_ >= 2 && nbuf_ <= 4, VX_EINVAL, "pipeline: n_buffers %u outside 2..4", nbuf_);
+  VX_CHECK(nbuf_ >= 2 && nbuf_ <= kMaxBuffers, VX_EINVAL, "pipeline: n_buffers %u outside 2..%u", nbuf_,
+           kMaxBuffers);
   uint64_t row_bytes = 0;
   int widest = 0;
   streamed_ = false;
@@ -155,21 +156,36 @@ vx_status Pipeline::issue_kernel(uint64_t c, const KernelFn& fn) {
   return VX_OK;
 }
 
+vx_status Pipeline::prefetch(uint64_t k) {
+  if (!streamed_) return VX_OK;
+  // one buffer stays free, so run() always has a kernel queued ahead of the copy it waits to issue
+  k = std::min<uint64_t>(std::min<uint64_t>(k, nbuf_ - 1), n_chunks_);
+  for (uint64_t c = prefetched_; c < k; ++c) VX_TRY(issue_copy(c));
+  prefetched_ = std::max(prefetched_, k);
+  return VX_OK;
+}
+
 vx_status Pipeline::run(const KernelFn& fn, const DecideFn& decide) {
   if (n_chunks_ == 0) return VX_OK;
   if (!streamed_) {
     for (uint64_t c = 0; c < n_chunks_; ++c) VX_TRY(issue_kernel(c, fn));
     return VX_OK;
   }
-  uint64_t start = 0, issued = 0;
+  uint64_t start = 0, issued = prefetched_;
+  prefetched_ = 0;
   if (decide && n_chunks_ > 1) {
-    VX_TRY(issue_copy(0));
+    // the decision may change which columns are copied: nothing past chunk 0 may be in flight
+    VX_CHECK(issued <= 1, VX_EINVAL, "pipeline: prefetch and a chunk-0 decision do not combine");
+    if (issued == 0) {
+      VX_TRY(issue_copy(0));
+      issued = 1;
+    }
     VX_TRY(issue_kernel(0, fn));
     VX_HIP(hipStreamSynchronize(ctx_->compute));
     VX_TRY(decide(cols_));
     for (auto& c : cols_)
       if (c.copy && !c.may_copy) c.copy = false;
-    start = issued = 1;
+    start = 1;
   }
   uint64_t ahead = std::min<uint64_t>(n_chunks_, start + nbuf_ - 1);
   for (uint64_t c = issued; c < ahead; ++c) VX_TRY(issue_copy(c));
