@@ -1,17 +1,19 @@
-// Partitioned join for a build side larger than the device budget.
+// Partitioned join for a build side whose table would not fit the device budget.
 //
-// Pass 1 (the paper's radix-partition step, Sec. 6.2.1): both tables stream through the chunk
-// pipeline; each chunk is clustered by partition on the GPU (stable multisplit) and written back
-// to pinned host memory together with its boundary array, on a device-to-host stream that runs
-// beside the host-to-device copies.  Pass 2 (Sec. 6.2.2): for each partition, its segments of
-// every clustered chunk are located through the boundary arrays and read in place by zero-copy;
-// a pre-aggregating hash table (key -> count, payload sums) is built from the build segments
-// and probed with the probe segments.
+// Pass 1 (the paper's radix-partition step, Sec. 6.2.1): the build side streams through the
+// chunk pipeline and each chunk is clustered by partition on the GPU (stable multisplit), with
+// its boundary array.  The clustered copy lives in the arena when the range splitters' sample
+// predicts that pass 2 fits beside it, otherwise in pinned host memory, written by a kernel that
+// stores to mapped memory beside the host-to-device copies.
+// Pass 2 (Sec. 6.2.2): each partition's segments of every clustered chunk are located through
+// the boundary arrays and read in place; they are pre-aggregated (key -> count, payload sum)
+// into a transient table, which is then compacted into a table sized by the partition's
+// distinct keys.  The probe side streams once: every key goes to its partition's table.
 //
 // With range partitioning (learned or sample-quantile splitters) a key that carries several
-// quantiles gets a partition of its own.  Such a singleton partition never goes through
-// pass 2: pass 1 already counts its build rows, sums their payload and counts its probe rows,
-// and its contribution is count_b * count_p pairs and sum_b * count_p.
+// quantiles gets a partition of its own.  A singleton partition needs no table: pass 1 counts
+// its build rows and sums their payload, the probe stream counts its probe rows, and its
+// contribution is count_b * count_p pairs and sum_b * count_p.
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -302,11 +304,10 @@ struct Side {
   ColInfo pay[kMaxPay];
   uint32_t n_pay = 0;
   uint64_t n = 0;
-  uint8_t* host_key = nullptr;          // clustered copy in pinned host memory
-  uint8_t* host_pay[kMaxPay] = {};
-  uint8_t* mapped_key = nullptr;        // the same memory as the device addresses it
-  uint8_t* mapped_pay[kMaxPay] = {};
-  bool on_device = false;               // the clustered copy lives in the arena instead
+  // the clustered copy, as device addresses: arena memory, or mapped pinned host memory
+  uint8_t* clu_key = nullptr;
+  uint8_t* clu_pay[kMaxPay] = {};
+  bool on_device = false;               // the clustered copy lives in the arena
   uint64_t chunk_rows = 0, n_chunks = 0;
   std::vector<unsigned long long> bnd;  // n_chunks * (P + 1)
   std::vector<unsigned long long> slot_sums;   // 2 * kMaxSumSlots: count, payload-0 sum
@@ -370,14 +371,14 @@ vx_status cluster_side(vx_ctx* ctx, const PartSpec& ps, const int* sum_slot_dev,
     io.n = v.rows;
     io.n_pay = sd.n_pay;
     uint8_t* out = stage[b];
-    io.out_key = sd.on_device ? sd.mapped_key + v.row0 * sd.key.elsize : out;
+    io.out_key = sd.on_device ? sd.clu_key + v.row0 * sd.key.elsize : out;
     uint64_t off = align_up(v.rows * sd.key.elsize, 256);
     for (uint32_t c = 0; c < sd.n_pay; ++c) {
       io.pay[c] = ((v.global_mask >> (1 + c)) & 1u)
                       ? (const uint8_t*)v.ptr[1 + c] + v.row0 * sd.pay[c].elsize
                       : v.ptr[1 + c];
       io.pay_size[c] = (uint32_t)sd.pay[c].elsize;
-      io.out_pay[c] = sd.on_device ? sd.mapped_pay[c] + v.row0 * sd.pay[c].elsize : out + off;
+      io.out_pay[c] = sd.on_device ? sd.clu_pay[c] + v.row0 * sd.pay[c].elsize : out + off;
       off += align_up(v.rows * sd.pay[c].elsize, 256);
     }
     PartGeom g = part_geom(ctx, v.rows);
@@ -393,8 +394,8 @@ vx_status cluster_side(vx_ctx* ctx, const PartSpec& ps, const int* sum_slot_dev,
     hipLaunchKernelGGL(k_pj_writeback, dim3(wb_grid), dim3(256), 0, ctx->d2h, (const uint8_t*)io.out_key,
                        (const uint8_t*)(sd.n_pay ? io.out_pay[0] : nullptr), (uint32_t)sd.key.elsize,
                        sd.n_pay ? (uint32_t)sd.pay[0].elsize : 0u, sd.n_pay, v.rows, bnd + v.index * (P + 1), P,
-                       sum_slot_dev, sd.mapped_key + v.row0 * sd.key.elsize,
-                       sd.n_pay ? sd.mapped_pay[0] + v.row0 * sd.pay[0].elsize : nullptr);
+                       sum_slot_dev, sd.clu_key + v.row0 * sd.key.elsize,
+                       sd.n_pay ? sd.clu_pay[0] + v.row0 * sd.pay[0].elsize : nullptr);
     VX_HIP(hipGetLastError());
     VX_HIP(hipEventRecord(wrote[b], ctx->d2h));
     pending[b] = true;
@@ -546,12 +547,10 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
   }
   void* hs_dev = hs;
   if (!bs.on_device) VX_HIP(hipHostGetDevicePointer(&hs_dev, hs, 0));
-  bs.host_key = hs;
-  bs.mapped_key = (uint8_t*)hs_dev;
+  bs.clu_key = (uint8_t*)hs_dev;
   uint64_t off = align_up(B.n * ks, 256);
   for (uint32_t c = 0; c < B.n_pay; ++c) {
-    bs.host_pay[c] = hs + off;
-    bs.mapped_pay[c] = (uint8_t*)hs_dev + off;
+    bs.clu_pay[c] = (uint8_t*)hs_dev + off;
     off += align_up(B.n * bs.pay[c].elsize, 256);
   }
 
@@ -638,8 +637,8 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
   cmem.p = ctx->arena.alloc(cbytes);
   VX_CHECK(cmem.p, VX_EBUDGET, "partitioned join: no room left for the partition tables");
 
-  const uint8_t* dk_b = bs.mapped_key;
-  const uint8_t* dp_b = B.n_pay ? bs.mapped_pay[0] : nullptr;
+  const uint8_t* dk_b = bs.clu_key;
+  const uint8_t* dp_b = B.n_pay ? bs.clu_pay[0] : nullptr;
   const uint32_t psz = B.n_pay ? (uint32_t)bs.pay[0].elsize : 8;
   const bool k64 = B.key.type == VX_I64;
   uint64_t launches = 0, stream_passes = 0;
