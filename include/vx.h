@@ -261,7 +261,9 @@ typedef struct {
 } vx_batch_join;
 
 typedef enum {
-  VX_PART_AUTO = 0,            /* learned if its estimated imbalance beats radix-hash, else radix-hash */
+  VX_PART_AUTO = 0,            /* vx_partition: the lower imbalance on the key sample (learned or
+                                  radix-hash); partitioned join: learned when its splitters
+                                  isolate a heavy key (a singleton partition), else radix-hash */
   VX_PART_RADIX_HASH = 1,      /* top bits of a 64-bit mix of the key */
   VX_PART_RADIX_BITS = 2,      /* raw key bits [shift, shift + log2 P) as in the paper */
   VX_PART_LEARNED = 3,         /* CDF-model range splitters, trained on the GPU */
@@ -272,7 +274,8 @@ typedef enum {
 
 typedef struct {
   uint32_t method;             /* vx_part_method */
-  uint32_t n_parts;            /* 0 = planned from the budget; radix methods round up to 2^k */
+  uint32_t n_parts;            /* 0 = 256; radix methods round up to 2^k; range methods may
+                                  return fewer (repeated quantiles merge) */
   uint32_t shift;              /* VX_PART_RADIX_BITS */
   uint32_t train_steps;        /* 0 = 300 */
   float sample_frac;           /* 0 = 0.01 */
@@ -283,9 +286,26 @@ typedef struct {
   uint32_t reserved;
 } vx_part_opts;
 
+/*
+ * Partitioned join (Sec. 6.2): count and SUM(build payload) over all matching pairs, for a build
+ * side whose table would not fit the budget.  The build side (key + at most one payload, host
+ * or device) is clustered by partition in one pass.  The clustered copy goes in the arena when
+ * the range splitters' key sample predicts that the partition tables fit beside it, else in
+ * the context's pinned host scratch.  Each partition is pre-aggregated per key (duplicates
+ * allowed) into a table sized by its distinct keys.  The probe keys (host or device, no
+ * payloads) then stream once through the chunk pipeline.  Keys that carry several quantiles of
+ * the sample get singleton partitions, which are resolved from counts alone.  When
+ * probe.chunk_aggs is set it receives one vx_agg per partition (chunk_aggs_cap >= n_parts).
+ * stats: n_parts, imbalance (max/mean build + probe rows per partition), singleton_rows,
+ * survivors (probe rows routed to a table), part_ms (pass 1), train_ms (splitters),
+ * probe_ms (pass 2), sdma_bytes and zc_bytes_est (host-link bytes).
+ * Errors: VX_EBUDGET when the largest partition's transient table or the partition scratch
+ * does not fit; VX_ENOMEM when pinned host scratch cannot be had; VX_EUNSUPPORTED for more than
+ * one build payload or any probe payload.
+ */
 typedef struct {
-  vx_build_desc build;         /* host-resident; VX_PREAGG implied */
-  vx_probe_desc probe;         /* host-resident keys; no probe payloads */
+  vx_build_desc build;         /* host or device; VX_PREAGG implied */
+  vx_probe_desc probe;         /* host or device keys; no probe payloads; chunk_aggs per partition */
   vx_part_opts part;
 } vx_partitioned_join;
 
