@@ -514,25 +514,24 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
   // back by zero-copy.  Radix-hash partitions come with no size prediction and take the host plan.
   uint64_t hbytes = align_up(B.n * ks, 256);
   for (uint32_t c = 0; c < B.n_pay; ++c) hbytes += align_up(B.n * bs.pay[c].elsize, 256);
-  double plan_compact = 0;   // expected bytes of the compact tables (device plan only)
+  double plan_compact = 0;   // expected bytes of the compact tables (0: no prediction)
   {
     const uint64_t mode = env_u64("VX_PJ_DEVICE", 2);   // 0 host, 1 device, 2 planned
-    if (mode == 1) {
-      bs.on_device = true;
-    } else if (mode == 2 && ps.fn == kPartRange && rep.sample_rows > 0) {
+    bool fits = false;
+    if (ps.fn == kPartRange && rep.sample_rows > 0) {
       const double ns_rows = (double)B.n * (1.0 - rep.single_share);
       const double part_rows = (double)B.n * rep.max_share * 1.25 + 1024.0;
       const double tbytes = 32.0 * 2.0 * 1.25 * part_rows;
-      const double cbytes = 32.0 * 2.1 * rep.distinct_share * ns_rows;
+      plan_compact = 32.0 * 2.1 * rep.distinct_share * ns_rows;
       const double pipe_bytes = 3.0 * (64 << 20) * 2.0 + (512 << 20);
-      bs.on_device = (double)hbytes + tbytes + cbytes + pipe_bytes <= (double)ctx->arena.largest_free();
-      plan_compact = cbytes;
+      fits = (double)hbytes + tbytes + plan_compact + pipe_bytes <= (double)ctx->arena.largest_free();
       if (trace)
         fprintf(stderr, "[vx] plan: clustered %.2f GiB + transient %.2f GiB + compact %.2f GiB (distinct share "
                 "%.3f, singleton share %.3f) vs %.2f GiB free: %s\n", hbytes / 1073741824.0, tbytes / 1073741824.0,
-                cbytes / 1073741824.0, rep.distinct_share, rep.single_share,
-                ctx->arena.largest_free() / 1073741824.0, bs.on_device ? "device" : "host");
+                plan_compact / 1073741824.0, rep.distinct_share, rep.single_share,
+                ctx->arena.largest_free() / 1073741824.0, fits ? "fits" : "does not fit");
     }
+    bs.on_device = mode == 1 || (mode == 2 && fits);
   }
   ArenaBlock cl_mem;
   uint8_t* hs = nullptr;
@@ -621,7 +620,7 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
   qcols[0].info = qs.key;
   qcols[0].may_copy = qcols[0].copy = true;
   uint32_t qbuf = Q.n_buffers;
-  if (bs.on_device && qs.key.where == Where::Host && Q.n_buffers == 0) {
+  if (bs.on_device && plan_compact > 0 && qs.key.where == Where::Host && Q.n_buffers == 0) {
     const uint64_t chunk_bytes = env_u64("VX_CHUNK_BYTES", 64ull << 20) + 256;
     const double spare = (double)ctx->arena.largest_free() - 1.05 * plan_compact - (double)(256u << 20);
     qbuf = (uint32_t)std::max<double>(2.0, std::min<double>((double)kMaxBuffers, spare / (double)chunk_bytes));
