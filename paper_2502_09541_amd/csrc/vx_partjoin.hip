@@ -68,9 +68,10 @@ __global__ void k_pj_init(uint32_t* slots, uint64_t capacity, uint32_t key_size,
   if (side && blockIdx.x == 0 && threadIdx.x < kSideWords) side[threadIdx.x] = 0;
 }
 
-// Add (cnt, sum) to key k's record; returns 1 when this call claimed a new slot.
+// Add (cnt, sum) to key k's record; returns the slot index when this call claimed a new slot,
+// else ~0.
 template <typename K>
-__device__ __forceinline__ uint32_t preagg_claim_add(const TableView& t, K k, unsigned long long cnt,
+__device__ __forceinline__ uint64_t preagg_claim_add(const TableView& t, K k, unsigned long long cnt,
                                                      unsigned long long sum, unsigned int* flags) {
   using U = typename KeyTraits<K>::U;
   const U kEmpty = KeyTraits<K>::kEmpty;
@@ -78,7 +79,7 @@ __device__ __forceinline__ uint32_t preagg_claim_add(const TableView& t, K k, un
   if (kb == kEmpty) {
     atomicAdd(t.side, cnt);
     if (t.n_pay) atomicAdd(t.side + 1, sum);
-    return 0;
+    return ~0ull;
   }
   uint64_t h = slot_of(key_bits(k), t.log2cap);
   for (uint64_t step = 0; step <= t.mask; ++step) {
@@ -88,31 +89,50 @@ __device__ __forceinline__ uint32_t preagg_claim_add(const TableView& t, K k, un
       unsigned long long* w = (unsigned long long*)(slot + 8);
       atomicAdd(w, cnt);
       if (t.n_pay) atomicAdd(w + 1, sum);
-      return prev == kEmpty ? 1u : 0u;
+      return prev == kEmpty ? h : ~0ull;
     }
     h = (h + 1) & t.mask;
   }
   atomicOr(flags, kFlagFull);
-  return 0;
+  return ~0ull;
+}
+
+// Appends the slots claimed by the active lanes to the workgroup's LDS claim buffer: one LDS
+// atomic per wave.
+__device__ __forceinline__ void append_claims(uint64_t slot, uint32_t* lbuf, uint32_t* lcount) {
+  const bool c = slot != ~0ull;
+  const unsigned long long m = __ballot(c);
+  if (!m) return;
+  const unsigned long long active = __ballot(true);
+  const uint32_t lane = threadIdx.x & 63, leader = (uint32_t)__ffsll((long long)active) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(lcount, (uint32_t)__popcll(m));
+  base = __shfl(base, leader, 64);
+  if (c) lbuf[base + (uint32_t)__popcll(m & ((1ull << lane) - 1))] = (uint32_t)slot;
 }
 
 constexpr int kPjLds = 1024;
 constexpr int kPjTile = 4096;
+constexpr int kPjLdsProbes = 16;  // past this, a row goes straight to the global table
 
-// Pre-aggregate one partition's build segments (read in place from host memory) into the
-// transient table: a per-tile LDS table absorbs repeated keys, its entries are then added to
-// the global table.  The number of distinct keys claimed is added to *distinct.
+// Pre-aggregate one partition's build segments (read in place: device memory or mapped host
+// memory) into the transient table: a per-tile LDS table absorbs repeated keys, its entries are
+// then added to the global table.  Every slot claimed in the global table is appended to
+// `claims` (*n_claims counts them: the partition's distinct keys), a tile at a time through an
+// LDS buffer, so the shared counter sees one atomic per tile.
 template <typename K>
 __global__ void __launch_bounds__(256) k_pj_build(TableView t, const void* key, const void* pay0,
                                                   uint32_t pay_size, SegList sl, unsigned int* flags,
-                                                  unsigned long long* distinct) {
+                                                  uint32_t* claims, unsigned long long* n_claims) {
   __shared__ unsigned long long sst[kMaxSegs], spre[kMaxSegs + 1];
   __shared__ unsigned long long lkey[kPjLds], lcnt[kPjLds], lsum[kPjLds];
+  __shared__ uint32_t lclaim[kPjTile + kPjLds];   // a tile claims at most one slot per row + per entry
+  __shared__ uint32_t n_lclaim;
+  __shared__ unsigned long long claim_base;
   const unsigned long long kFree = ~0ull;
   for (uint32_t j = threadIdx.x; j < sl.nseg; j += blockDim.x) sst[j] = sl.start[j];
   for (uint32_t j = threadIdx.x; j <= sl.nseg; j += blockDim.x) spre[j] = sl.prefix[j];
   __syncthreads();
-  uint32_t claimed = 0;
   for (uint64_t base = (uint64_t)blockIdx.x * kPjTile; base < sl.total;
        base += (uint64_t)gridDim.x * kPjTile) {
     for (int j = threadIdx.x; j < kPjLds; j += blockDim.x) {
@@ -120,6 +140,7 @@ __global__ void __launch_bounds__(256) k_pj_build(TableView t, const void* key, 
       lcnt[j] = 0;
       lsum[j] = 0;
     }
+    if (threadIdx.x == 0) n_lclaim = 0;
     __syncthreads();
     uint64_t end = base + kPjTile < sl.total ? base + kPjTile : sl.total;
     for (uint64_t i = base + threadIdx.x; i < end; i += blockDim.x) {
@@ -130,7 +151,7 @@ __global__ void __launch_bounds__(256) k_pj_build(TableView t, const void* key, 
       bool placed = false;
       if (kb != kFree) {
         uint32_t h = (uint32_t)slot_of(kb, 10);
-        for (int s = 0; s < 32; ++s) {
+        for (int s = 0; s < kPjLdsProbes; ++s) {
           uint32_t j = (h + s) & (kPjLds - 1);
           unsigned long long prev = atomicCAS(&lkey[j], kFree, kb);
           if (prev == kFree || prev == kb) {
@@ -141,28 +162,32 @@ __global__ void __launch_bounds__(256) k_pj_build(TableView t, const void* key, 
           }
         }
       }
-      if (!placed) claimed += preagg_claim_add<K>(t, k, 1ull, v, flags);
+      append_claims(placed ? ~0ull : preagg_claim_add<K>(t, k, 1ull, v, flags), lclaim, &n_lclaim);
     }
     __syncthreads();
     for (int j = threadIdx.x; j < kPjLds; j += blockDim.x)
-      if (lkey[j] != kFree) claimed += preagg_claim_add<K>(t, (K)(long long)lkey[j], lcnt[j], lsum[j], flags);
+      append_claims(lkey[j] != kFree ? preagg_claim_add<K>(t, (K)(long long)lkey[j], lcnt[j], lsum[j], flags)
+                                     : ~0ull,
+                    lclaim, &n_lclaim);
+    __syncthreads();
+    if (threadIdx.x == 0) claim_base = n_lclaim ? atomicAdd(n_claims, (unsigned long long)n_lclaim) : 0ull;
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < n_lclaim; j += blockDim.x) claims[claim_base + j] = lclaim[j];
     __syncthreads();
   }
-  for (int o = 32; o > 0; o >>= 1) claimed += __shfl_xor(claimed, o, 64);
-  if ((threadIdx.x & 63) == 0 && claimed) atomicAdd(distinct, (unsigned long long)claimed);
 }
 
-// Move every record of the transient table into partition p's compact table (sized from its
-// distinct-key count) and empty the transient slot, so the next partition finds it clean.
+// Move every claimed record of the transient table into the partition's compact table (sized
+// from its distinct-key count) and empty the transient slot, so the next partition finds it
+// clean.
 template <typename K>
-__global__ void k_pj_compact(uint8_t* tslots, uint64_t tcap, TableView c) {
+__global__ void k_pj_compact(uint8_t* tslots, const uint32_t* claims, uint64_t n_claims, TableView c) {
   using U = typename KeyTraits<K>::U;
   const U kEmpty = KeyTraits<K>::kEmpty;
-  for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < tcap;
-       s += (uint64_t)gridDim.x * blockDim.x) {
-    uint8_t* src = tslots + (s << kSlotShift);
+  for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < n_claims;
+       q += (uint64_t)gridDim.x * blockDim.x) {
+    uint8_t* src = tslots + ((uint64_t)claims[q] << kSlotShift);
     U k = *(U*)src;
-    if (k == kEmpty) continue;
     unsigned long long* w = (unsigned long long*)(src + 8);
     unsigned long long cnt = w[0], sum = w[1];
     *(U*)src = kEmpty;
@@ -579,11 +604,12 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
   uint8_t* mem_t = nullptr;
   ArenaBlock tmem, aux;
   tmem.a = aux.a = &ctx->arena;
-  tmem.p = ctx->arena.alloc((tcap_max << kSlotShift) + 256);
+  tmem.p = ctx->arena.alloc((tcap_max << kSlotShift) + 256 + tcap_max * 4);
   VX_CHECK(tmem.p, VX_EBUDGET,
            "partitioned join: the largest partition (%llu build rows, %llu transient slots) does not fit "
            "the arena; use more partitions", (unsigned long long)max_rows, (unsigned long long)tcap_max);
   mem_t = tmem.p;
+  uint32_t* claims = (uint32_t*)(mem_t + (tcap_max << kSlotShift) + 256);   // slots claimed by a build
   const uint64_t aux_words = (uint64_t)P * kSideWords + (uint64_t)P + (uint64_t)P +
                              (uint64_t)G * 3 * P + 3ull * P + (uint64_t)P * seg_stride + 8;
   aux.p = ctx->arena.alloc(aux_words * 8);
@@ -594,7 +620,7 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
   unsigned long long* accb = tab_slots + 2 * (uint64_t)P;    // tab_log2 takes P/2 words; P words reserved
   unsigned long long* acc_out = accb + (uint64_t)G * 3 * P;
   unsigned long long* segdev = acc_out + 3ull * P;
-  unsigned long long* distinct = segdev + (uint64_t)P * seg_stride;
+  unsigned long long* distinct = segdev + (uint64_t)P * seg_stride;   // claims in the transient table
   fill_zero((uint64_t*)aux.p, aux_words, ctx->compute);
   hipLaunchKernelGGL(k_pj_init, dim3(grid_for(ctx, tcap_max)), dim3(256), 0, ctx->compute, (uint32_t*)mem_t,
                      tcap_max, (uint32_t)ks, (unsigned long long*)nullptr);
@@ -692,10 +718,10 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
     fill_zero((uint64_t*)distinct, 1, ctx->compute);
     if (k64)
       hipLaunchKernelGGL(k_pj_build<int64_t>, dim3(gb), dim3(256), 0, ctx->compute, t, dk_b, dp_b, psz, lb,
-                         ctx->dev_flags, distinct);
+                         ctx->dev_flags, claims, distinct);
     else
       hipLaunchKernelGGL(k_pj_build<int32_t>, dim3(gb), dim3(256), 0, ctx->compute, t, dk_b, dp_b, psz, lb,
-                         ctx->dev_flags, distinct);
+                         ctx->dev_flags, claims, distinct);
     VX_HIP(hipGetLastError());
     unsigned long long nd = 0;
     VX_HIP(hipMemcpyAsync(&nd, distinct, 8, hipMemcpyDeviceToHost, ctx->compute));
@@ -722,9 +748,11 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
     hipLaunchKernelGGL(k_pj_init, dim3(grid_for(ctx, ccap)), dim3(256), 0, ctx->compute, (uint32_t*)c.slots, ccap,
                        (uint32_t)ks, (unsigned long long*)nullptr);
     if (k64)
-      hipLaunchKernelGGL(k_pj_compact<int64_t>, dim3(grid_for(ctx, tcap)), dim3(256), 0, ctx->compute, mem_t, tcap, c);
+      hipLaunchKernelGGL(k_pj_compact<int64_t>, dim3(grid_for(ctx, nd)), dim3(256), 0, ctx->compute, mem_t, claims,
+                         (uint64_t)nd, c);
     else
-      hipLaunchKernelGGL(k_pj_compact<int32_t>, dim3(grid_for(ctx, tcap)), dim3(256), 0, ctx->compute, mem_t, tcap, c);
+      hipLaunchKernelGGL(k_pj_compact<int32_t>, dim3(grid_for(ctx, nd)), dim3(256), 0, ctx->compute, mem_t, claims,
+                         (uint64_t)nd, c);
     VX_HIP(hipGetLastError());
     h_slots[p] = (unsigned long long)(uintptr_t)c.slots;
     h_log2[p] = c.log2cap;
