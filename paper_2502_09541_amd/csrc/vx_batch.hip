@@ -10,6 +10,8 @@
 // a small autotuner that times candidates on the batch itself and caches the winner per
 // workload class (optionally in the file named by VX_TUNE_CACHE).
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <fstream>
@@ -481,9 +483,11 @@ vx_status join_batch(vx_ctx* ctx, const vx_batch_join* d, vx_join_out* out) {
   }
   const uint32_t ps = pt ? (uint32_t)elsize_of(pt) : 0;
   const uint32_t J = d->n_jobs;
+  const double t_checked = now_ms();
   BatchConfig cfg;
   bool tuned = d->tile_rows == 0 || d->block == 0 || d->load_factor == 0.0f;
   if (tuned && d->mode == 0) VX_TRY(autotune(ctx, d, ks, ps, &cfg));
+  const double t_tuned = now_ms();
   if (d->tile_rows) cfg.tile_rows = d->tile_rows;
   if (d->block) cfg.block = d->block;
   if (d->load_factor > 0) cfg.load_factor = d->load_factor;
@@ -589,6 +593,9 @@ vx_status join_batch(vx_ctx* ctx, const vx_batch_join* d, vx_join_out* out) {
   }
   s.rows = rows;
   s.total_ms = now_ms() - t0;
+  if (getenv("VX_TRACE"))
+    fprintf(stderr, "[vx] batch mode %d: checks %.2f ms, tuning %.2f ms, run %.2f ms (kernels %.2f ms)\n", d->mode,
+            t_checked - t0, t_tuned - t_checked, now_ms() - t_tuned, s.kernel_ms);
   return VX_OK;
 }
 
