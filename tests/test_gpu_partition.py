@@ -311,6 +311,27 @@ def test_partitioned_join_clustered_copy_placement(gpu, ctx, placement, monkeypa
     assert (st["zc_bytes_est"] == 0) == (placement == "1")
 
 
+@pytest.mark.parametrize("placement", ["0", "1"])
+@pytest.mark.parametrize("method", ["learned", "radix_hash"])
+def test_partitioned_join_int32_no_payload_one_partition(gpu, ctx, placement, method, monkeypatch):
+    """int32 keys (with the empty-marker key), no build payload, and a single partition, on both
+    placements of the clustered copy."""
+    monkeypatch.setenv("VX_CHUNK_BYTES", str(8 * 30_000))
+    monkeypatch.setenv("VX_PJ_DEVICE", placement)
+    i32 = np.iinfo(np.int32)
+    rng = np.random.default_rng(31)
+    bk = rng.zipf(1.2, 200_000).astype(np.int32)
+    pk = rng.zipf(1.2, 333_333).astype(np.int32)
+    bk[::5000] = i32.min
+    pk[::7000] = i32.min
+    _say("partitioned int32", method, placement)
+    got, st, used = ctx.join_partitioned(dev(bk), [], pinned(gpu, pk), method=method, n_parts=32, seed=2,
+                                         train_steps=40)
+    assert got == oracle.join_agg(bk, [], pk, [])
+    got1 = ctx.join_partitioned(dev(bk), [], dev(pk), method=method, n_parts=1, seed=2, train_steps=20)[0]
+    assert got1 == got
+
+
 def test_partitioned_join_per_partition_radix(gpu, ctx):
     bk, bp, pk = _zipf_join(100_000, 300_000, 7)
     _say("partitioned per-partition")
