@@ -29,7 +29,7 @@ TRAFFIC_BYTES = {"k_probe_stream": 1.5647e9,    # 8,388,608 probe rows per launc
                  "k_probe_plain": 1.8964e9,     # 16,777,216 probe rows per launch
                  "k_star": 2.1670e9,            # 16,666,667 fact rows per launch
                  "batch_graph": 6.0252e11,      # one graph launch: build phase + probe phase, all 256 jobs
-                 "k_pj_stream": 5.066e8}        # 8,388,608 probe rows per launch (mean over the partitioners)
+                 "k_pj_stream": 4.976e8}        # 8,388,608 probe rows per launch (mean over the partitioners)
 GiB = 1 << 30
 
 
