@@ -534,7 +534,7 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
 
   // Where the clustered build side lives.  In the arena when the range splitters' sample
   // predicts that pass 2 fits beside it: the clustered rows, the transient table of the largest
-  // partition, and compact tables sized from the sample's distinct-key share (about 2.1 slots of
+  // partition, and compact tables sized from the sample's distinct-key share (about 1.8 slots of
   // 32 B per distinct key after power-of-two rounding).  Otherwise in pinned host memory, read
   // back by zero-copy.  Radix-hash partitions come with no size prediction and take the host plan.
   uint64_t hbytes = align_up(B.n * ks, 256);
@@ -547,7 +547,7 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
       const double ns_rows = (double)B.n * (1.0 - rep.single_share);
       const double part_rows = (double)B.n * rep.max_share * 1.25 + 1024.0;
       const double tbytes = 32.0 * 2.0 * 1.25 * part_rows;
-      plan_compact = 32.0 * 2.1 * rep.distinct_share * ns_rows;
+      plan_compact = 32.0 * 1.8 * rep.distinct_share * ns_rows;
       const double pipe_bytes = 3.0 * (64 << 20) * 2.0 + (512 << 20);
       fits = (double)hbytes + tbytes + plan_compact + pipe_bytes <= (double)ctx->arena.largest_free();
       if (trace)
@@ -727,7 +727,7 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
     VX_HIP(hipMemcpyAsync(&nd, distinct, 8, hipMemcpyDeviceToHost, ctx->compute));
     VX_HIP(hipStreamSynchronize(ctx->compute));
     VX_TRY(check_flags(ctx, "partitioned join (build)"));
-    const uint64_t ccap = pow2_at_least(nd + nd / 2);
+    const uint64_t ccap = pow2_at_least(nd + nd / 4);   // load factor 0.4 .. 0.8
     const uint64_t need = ccap << kSlotShift;
     VX_CHECK(need <= cbytes, VX_EBUDGET,
              "partitioned join: partition %u's table (%llu distinct keys) does not fit the arena", p,
