@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <vector>
 
 #include "vx_cdf.h"
@@ -348,21 +349,36 @@ unsigned grid_for(const vx_ctx* ctx, uint64_t n) {
 
 // Pass 1 for one table: stream, cluster each chunk by partition, write it back with its
 // boundary array.
-vx_status cluster_side(vx_ctx* ctx, const PartSpec& ps, const int* sum_slot_dev, Side& sd) {
-  const uint32_t P = ps.n_parts;
+// Plans pass 1's pipeline over one side: chunks of 64 MiB of keys (at most kMaxSegs chunks), and
+// up to `deep` chunk buffers when the arena can spare an eighth of its free bytes for them.
+vx_status plan_pass1(vx_ctx* ctx, Side& sd, uint32_t deep, Pipeline& pipe) {
   std::vector<PipeCol> cols(1 + sd.n_pay);
   cols[0].info = sd.key;
   cols[0].may_copy = cols[0].copy = true;
+  uint64_t row_bytes = (uint64_t)sd.key.elsize;
   for (uint32_t c = 0; c < sd.n_pay; ++c) {
     cols[1 + c].info = sd.pay[c];
     cols[1 + c].may_copy = cols[1 + c].copy = true;
+    row_bytes += (uint64_t)sd.pay[c].elsize;
   }
-  uint64_t min_rows = (sd.n + kMaxSegs - 1) / kMaxSegs;
-  uint64_t want = env_u64("VX_CHUNK_BYTES", 64ull << 20) / 8;
-  Pipeline pipe;
-  VX_TRY(pipe.plan(ctx, sd.n, std::max(min_rows, std::min<uint64_t>(want, std::max<uint64_t>(sd.n, 1))), 0, cols));
+  const uint64_t min_rows = (sd.n + kMaxSegs - 1) / kMaxSegs;
+  const uint64_t want = env_u64("VX_CHUNK_BYTES", 64ull << 20) / 8;
+  const uint64_t rows = std::max(min_rows, std::min<uint64_t>(want, std::max<uint64_t>(sd.n, 1)));
+  uint32_t nbuf = 0;
+  if (deep > 2) {
+    const uint64_t spare = (ctx->arena.capacity() - ctx->arena.used()) / 8;
+    nbuf = (uint32_t)std::max<uint64_t>(2, std::min<uint64_t>(deep, spare / (rows * row_bytes + 1024)));
+  }
+  VX_TRY(pipe.plan(ctx, sd.n, rows, nbuf, cols));
   sd.chunk_rows = pipe.chunk_rows();
   sd.n_chunks = pipe.n_chunks();
+  return VX_OK;
+}
+
+// Pass 1 over one side through its planned pipeline (whose first copies may already be in
+// flight): cluster each chunk and record its boundary array.
+vx_status cluster_side(vx_ctx* ctx, const PartSpec& ps, const int* sum_slot_dev, Side& sd, Pipeline& pipe) {
+  const uint32_t P = ps.n_parts;
   uint64_t row_bytes = (uint64_t)sd.key.elsize;
   for (uint32_t c = 0; c < sd.n_pay; ++c) row_bytes += (uint64_t)sd.pay[c].elsize;
   // staging for clustered chunks (double-buffered against the write-back), per-wave
@@ -486,6 +502,13 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
   std::vector<int64_t> split;
   CdfReport rep{};
   uint32_t method = o.method;
+  // pass 1's pipeline is planned first: while the splitters are computed from the key sample,
+  // the copies of its first chunks already run (pass 1 needs the splitters only for its kernels)
+  const bool sampled = method == VX_PART_LEARNED || method == VX_PART_QUANTILE ||
+                       method == VX_PART_UNTRAINED || method == VX_PART_AUTO;
+  std::unique_ptr<Pipeline> pipe1(new Pipeline);
+  VX_TRY(plan_pass1(ctx, bs, sampled ? 24u : 0u, *pipe1));
+  if (sampled) VX_TRY(pipe1->prefetch(pipe1->n_buffers()));
   double tt0 = now_ms();
   if (method == VX_PART_LEARNED || method == VX_PART_QUANTILE || method == VX_PART_UNTRAINED ||
       method == VX_PART_AUTO) {
@@ -580,7 +603,8 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
 
   // pass 1: cluster the build side
   double tp0 = now_ms();
-  VX_TRY(cluster_side(ctx, ps, slot_dev, bs));
+  VX_TRY(cluster_side(ctx, ps, slot_dev, bs, *pipe1));
+  pipe1.reset();   // pass 1's chunk buffers go back to the arena before pass 2
   double part_ms = now_ms() - tp0;
   std::vector<uint64_t> brows(P, 0);
   for (uint64_t c = 0; c < bs.n_chunks; ++c)
@@ -648,7 +672,9 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
   uint32_t qbuf = Q.n_buffers;
   if (bs.on_device && plan_compact > 0 && qs.key.where == Where::Host && Q.n_buffers == 0) {
     const uint64_t chunk_bytes = env_u64("VX_CHUNK_BYTES", 64ull << 20) + 256;
-    const double spare = (double)ctx->arena.largest_free() - 1.05 * plan_compact - (double)(256u << 20);
+    // buffers fill holes first (first fit); the compact tables then need one contiguous block
+    const double spare = (double)(ctx->arena.capacity() - ctx->arena.used()) - 1.05 * plan_compact -
+                         (double)(512u << 20);
     qbuf = (uint32_t)std::max<double>(2.0, std::min<double>((double)kMaxBuffers, spare / (double)chunk_bytes));
   }
   Pipeline pipe;
