@@ -53,6 +53,7 @@ def parse():
                     help="stream (default) is the headline line; the others print their own line")
     ap.add_argument("--method", default="learned", help="skew workload: partitioner to time")
     ap.add_argument("--n-parts", type=int, default=256)
+    ap.add_argument("--train-steps", type=int, default=0, help="skew workload: Adam steps (0 = library default)")
     return ap.parse_args()
 
 
@@ -404,7 +405,8 @@ def run_skew(args):
     b_peak = ctx.calibrate()["h2d_gbs"]
     lines = {}
     for method in (args.method, "quantile", "radix_hash"):
-        ms, res = _timed(lambda: ctx.join_partitioned(bk, [bp], pk, method=method, n_parts=args.n_parts, seed=7),
+        ms, res = _timed(lambda: ctx.join_partitioned(bk, [bp], pk, method=method, n_parts=args.n_parts, seed=7,
+                                                      train_steps=args.train_steps),
                          args, torch)
         agg, st, used = res[0]
         lines[method] = dict(ms=ms, value=np_ / (ms / 1e3), agg=agg, st=st, used=used)
@@ -433,12 +435,15 @@ def run_skew(args):
                                   "achieved_gbs": h2d / (a["ms"] * 1e6), "frac": h2d / (a["ms"] * 1e6) / b_peak},
                     "result": {"match_count": a["agg"][0], "sum": a["agg"][1]},
                     "learned": {"ms_per_step": a["ms"], "value": a["value"], "imbalance": st["imbalance"],
+                                "imbalance_table_partitions": st["imbalance_tables"],
                                 "singleton_rows": st["singleton_rows"], "part_ms": st["part_ms"],
                                 "train_ms": st["train_ms"], "join_ms": st["probe_ms"]},
                     "radix_hash": {"ms_per_step": r["ms"], "value": r["value"], "imbalance": r["st"]["imbalance"],
+                                   "imbalance_table_partitions": r["st"]["imbalance_tables"],
                                    "part_ms": r["st"]["part_ms"], "join_ms": r["st"]["probe_ms"]},
                     "sample_quantile": {"ms_per_step": lines["quantile"]["ms"], "value": lines["quantile"]["value"],
                                         "imbalance": lines["quantile"]["st"]["imbalance"],
+                                        "imbalance_table_partitions": lines["quantile"]["st"]["imbalance_tables"],
                                         "singleton_rows": lines["quantile"]["st"]["singleton_rows"]},
                     "learned_speedup_vs_radix_hash": r["ms"] / a["ms"], "bit_exact_across_methods": True})
 

@@ -140,6 +140,8 @@ typedef struct {
   uint64_t singleton_rows;  /* rows resolved through singleton partitions */
   uint64_t survivors;       /* star join: fact rows that pass every dimension; partitioned join:
                                probe rows routed to a partition table (not a singleton) */
+  double imbalance_tables;  /* partitioned join: max/mean build + probe rows over the partitions
+                               joined through a table (singletons excluded) */
 } vx_stats;
 
 /* ------------------------------------------------------------------------ build / probe */
@@ -277,7 +279,7 @@ typedef struct {
   uint32_t n_parts;            /* 0 = 256; radix methods round up to 2^k; range methods may
                                   return fewer (repeated quantiles merge) */
   uint32_t shift;              /* VX_PART_RADIX_BITS */
-  uint32_t train_steps;        /* 0 = 300 */
+  uint32_t train_steps;        /* 0 = 1000 */
   float sample_frac;           /* 0 = 0.01 */
   float lr;                    /* 0 = 1e-2 */
   uint64_t seed;               /* sampling seed */
@@ -379,8 +381,9 @@ vx_status vx_partition(vx_ctx* ctx, const vx_partition_desc* desc, vx_partition_
  *   one forward/backward pass (relu'(0) = 0); gradient accumulated in FP64 in a fixed order
  *   and rounded to FP32.  Deterministic.
  * vx_cdf_forward: y_i for every x_i (the evaluation used to place splitters).
- * vx_cdf_train: `steps` full-batch Adam steps (beta 0.9 / 0.999, eps 1e-8, learning rate lr,
- *   0 = 1e-2) from the given parameters, updated in place; *final_loss = loss after training.
+ * vx_cdf_train: `steps` full-batch Adam steps (beta 0.9 / 0.999, eps 1e-8) from the given
+ *   parameters, updated in place; the learning rate at step k is lr * (1 + cos(pi (k-1) / steps)) / 2
+ *   (lr at the first step; lr 0 = 1e-2); *final_loss = loss after training.
  */
 vx_status vx_cdf_loss_grad(vx_ctx* ctx, const float* x, const float* t, uint64_t n,
                            const float* params, float* grad, double* loss);

@@ -253,18 +253,37 @@ __global__ void __launch_bounds__(256) k_mlp_reduce(const double* partial, uint3
   if (threadIdx.x == 0) grad[c] = c == kModelParams ? red[0] / (double)n : red[0];
 }
 
-// Adam (Kingma and Ba, 2015) on FP32 parameters and moments, evaluated in FP64.
-__global__ void k_adam(float* params, float* m, float* v, const double* grad, double lr, double b1,
-                       double b2, double eps, double c1, double c2) {
-  uint32_t j = threadIdx.x;
-  if (j >= kModelParams) return;
-  double g = (double)(float)grad[j];
-  double mj = b1 * (double)m[j] + (1.0 - b1) * g;
-  double vj = b2 * (double)v[j] + (1.0 - b2) * g * g;
-  m[j] = (float)mj;
-  v[j] = (float)vj;
-  params[j] = (float)((double)params[j] - lr * (mj / c1) / (sqrt(vj / c2) + eps));
+// One training step's second half: block c reduces gradient component c over the waves (the
+// fixed order of k_mlp_reduce) and applies Adam (Kingma and Ba, 2015) to parameter c, on FP32
+// parameters and moments evaluated in FP64 (components are independent).
+__global__ void __launch_bounds__(256) k_mlp_reduce_adam(const double* partial, uint32_t waves, uint64_t n,
+                                                         double* grad, float* params, float* m, float* v,
+                                                         double lr, double b1, double b2, double eps, double c1,
+                                                         double c2) {
+  __shared__ double red[256];
+  const uint32_t c = blockIdx.x;
+  double s = 0;
+  for (uint32_t w = threadIdx.x; w < waves; w += blockDim.x) s += partial[(uint64_t)w * kPartialStride + c];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (uint32_t h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  if (c == kModelParams) {
+    grad[c] = red[0] / (double)n;
+    return;
+  }
+  grad[c] = red[0];
+  const double g = (double)(float)red[0];
+  const double mj = b1 * (double)m[c] + (1.0 - b1) * g;
+  const double vj = b2 * (double)v[c] + (1.0 - b2) * g * g;
+  m[c] = (float)mj;
+  v[c] = (float)vj;
+  params[c] = (float)((double)params[c] - lr * (mj / c1) / (sqrt(vj / c2) + eps));
 }
+
 
 // c = the number of quantiles j/P (1 <= j < P) the value reaches; first[c] = min row reaching c
 __global__ void k_cross(const float* x, const float* t, uint64_t m, const float* params,
@@ -410,12 +429,16 @@ static vx_status train(vx_ctx* ctx, Model& md, const float* x, const float* t, u
   const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
   fill_zero((uint64_t*)md.m, (kModelParams + 1) / 2, ctx->compute);
   fill_zero((uint64_t*)md.v, (kModelParams + 1) / 2, ctx->compute);
+  // cosine learning-rate decay: lr at the first step, towards 0 at the last
   for (uint32_t st = 1; st <= steps; ++st) {
-    VX_TRY(grad_pass(ctx, md, x, t, n));
+    const double lr_t = lr * 0.5 * (1.0 + std::cos(M_PI * (double)(st - 1) / (double)steps));
     double c1 = 1.0 - std::pow(b1, (double)st), c2 = 1.0 - std::pow(b2, (double)st);
-    hipLaunchKernelGGL(k_adam, dim3(1), dim3(256), 0, ctx->compute, md.params, md.m, md.v, md.grad, lr,
-                       b1, b2, eps, c1, c2);
+    hipLaunchKernelGGL(k_mlp_grad, dim3(md.waves / 4), dim3(256), 0, ctx->compute, x, t, n, md.params,
+                       md.per_wave, md.partial);
+    hipLaunchKernelGGL(k_mlp_reduce_adam, dim3(kPartialStride), dim3(256), 0, ctx->compute, md.partial, md.waves,
+                       n, md.grad, md.params, md.m, md.v, lr_t, b1, b2, eps, c1, c2);
   }
+  VX_HIP(hipGetLastError());
   VX_TRY(grad_pass(ctx, md, x, t, n));
   double hg[kPartialStride];
   VX_HIP(hipMemcpyAsync(hg, md.grad, sizeof hg, hipMemcpyDeviceToHost, ctx->compute));
@@ -531,7 +554,7 @@ vx_status cdf_splitters(vx_ctx* ctx, const ColInfo& key, uint64_t n, const vx_pa
   VX_HIP(hipMemcpyAsync(mm.md.params, hp, sizeof hp, hipMemcpyHostToDevice, s));
   const bool use_model = o.method != VX_PART_QUANTILE;
   if (o.method == VX_PART_LEARNED || o.method == VX_PART_AUTO) {
-    uint32_t steps = o.train_steps ? o.train_steps : 300;
+    uint32_t steps = o.train_steps ? o.train_steps : 1000;
     double lr = o.lr > 0 ? (double)o.lr : 1e-2;
     VX_TRY(train(ctx, mm.md, tx, tt, mt, steps, lr, &rep->final_loss));
   } else if (use_model) {

@@ -350,7 +350,7 @@ unsigned grid_for(const vx_ctx* ctx, uint64_t n) {
 // Pass 1 for one table: stream, cluster each chunk by partition, write it back with its
 // boundary array.
 // Plans pass 1's pipeline over one side: chunks of 64 MiB of keys (at most kMaxSegs chunks), and
-// up to `deep` chunk buffers when the arena can spare an eighth of its free bytes for them.
+// up to `deep` chunk buffers when the arena can spare a quarter of its free bytes for them.
 vx_status plan_pass1(vx_ctx* ctx, Side& sd, uint32_t deep, Pipeline& pipe) {
   std::vector<PipeCol> cols(1 + sd.n_pay);
   cols[0].info = sd.key;
@@ -366,7 +366,7 @@ vx_status plan_pass1(vx_ctx* ctx, Side& sd, uint32_t deep, Pipeline& pipe) {
   const uint64_t rows = std::max(min_rows, std::min<uint64_t>(want, std::max<uint64_t>(sd.n, 1)));
   uint32_t nbuf = 0;
   if (deep > 2) {
-    const uint64_t spare = (ctx->arena.capacity() - ctx->arena.used()) / 8;
+    const uint64_t spare = (ctx->arena.capacity() - ctx->arena.used()) / 4;
     nbuf = (uint32_t)std::max<uint64_t>(2, std::min<uint64_t>(deep, spare / (rows * row_bytes + 1024)));
   }
   VX_TRY(pipe.plan(ctx, sd.n, rows, nbuf, cols));
@@ -507,7 +507,7 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
   const bool sampled = method == VX_PART_LEARNED || method == VX_PART_QUANTILE ||
                        method == VX_PART_UNTRAINED || method == VX_PART_AUTO;
   std::unique_ptr<Pipeline> pipe1(new Pipeline);
-  VX_TRY(plan_pass1(ctx, bs, sampled ? 24u : 0u, *pipe1));
+  VX_TRY(plan_pass1(ctx, bs, sampled ? 48u : 0u, *pipe1));
   if (sampled) VX_TRY(pipe1->prefetch(pipe1->n_buffers()));
   double tt0 = now_ms();
   if (method == VX_PART_LEARNED || method == VX_PART_QUANTILE || method == VX_PART_UNTRAINED ||
@@ -572,7 +572,13 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
       const double tbytes = 32.0 * 2.0 * 1.25 * part_rows;
       plan_compact = 32.0 * 1.8 * rep.distinct_share * ns_rows;
       const double pipe_bytes = 3.0 * (64 << 20) * 2.0 + (512 << 20);
-      fits = (double)hbytes + tbytes + plan_compact + pipe_bytes <= (double)ctx->arena.largest_free();
+      // pass 1 holds the clustered copy beside its own chunk buffers; pass 2 gets those back
+      uint64_t row_bytes = (uint64_t)ks;
+      for (uint32_t c = 0; c < B.n_pay; ++c) row_bytes += (uint64_t)bs.pay[c].elsize;
+      const double pass1_bytes = (double)pipe1->n_buffers() * (double)(bs.chunk_rows * row_bytes);
+      const double free_now = (double)(ctx->arena.capacity() - ctx->arena.used());
+      fits = (double)hbytes + (64 << 20) <= (double)ctx->arena.largest_free() &&
+             free_now + pass1_bytes - (double)hbytes >= tbytes + plan_compact + pipe_bytes;
       if (trace)
         fprintf(stderr, "[vx] plan: clustered %.2f GiB + transient %.2f GiB + compact %.2f GiB (distinct share "
                 "%.3f, singleton share %.3f) vs %.2f GiB free: %s\n", hbytes / 1073741824.0, tbytes / 1073741824.0,
@@ -848,8 +854,16 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
   s.part_ms = part_ms;
   s.train_ms = train_ms;
   s.singleton_rows = single_rows;
+  double tmx = 0, ttot = 0;
+  uint32_t tparts = 0;
   for (uint32_t p = 0; p < P; ++p)
-    if (slot[p] < 0) s.survivors += qrows[p];
+    if (slot[p] < 0) {
+      s.survivors += qrows[p];
+      tmx = std::max(tmx, (double)(brows[p] + qrows[p]));
+      ttot += (double)(brows[p] + qrows[p]);
+      ++tparts;
+    }
+  s.imbalance_tables = ttot > 0 ? tmx / (ttot / tparts) : 0.0;
   s.sdma_bytes = bs.sdma + pipe.sdma_bytes();
   uint64_t pass2_bytes = 0;
   for (uint32_t p = 0; p < P; ++p)
