@@ -50,6 +50,10 @@ def _load():
     lib.or_join_agg_hash.argtypes = [_Col, C.POINTER(_Col), C.c_uint32, C.c_uint64, _Col,
                                      C.POINTER(_Col), C.c_uint32, C.c_uint64, u64p]
     lib.or_join_agg_sortmerge.argtypes = lib.or_join_agg_hash.argtypes
+    lib.or_join_rows.argtypes = [_Col, C.POINTER(_Col), C.c_uint32, C.c_uint64, _Col, C.POINTER(_Col),
+                                 C.c_uint32, C.c_uint64, C.c_uint64, C.POINTER(C.c_uint64),
+                                 C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    lib.or_join_rows.restype = C.c_uint64
     lib.or_build_create.argtypes = [_Col, C.POINTER(_Col), C.c_uint32, C.c_uint64]
     lib.or_build_create.restype = C.c_void_p
     lib.or_build_free.argtypes = [C.c_void_p]
@@ -113,6 +117,23 @@ def join_agg(bkey, bpays, pkey, ppays, method: str = "hash"):
     fn = lib.or_join_agg_hash if method == "hash" else lib.or_join_agg_sortmerge
     fn(_col(bkey), bp, nbp, len(bkey), _col(pkey), pp, npp, len(pkey), _ptr(out, C.c_uint64))
     return [int(v) for v in out]
+
+
+def join_rows(bkey, bpays, pkey, ppays):
+    """The join's output rows in probe order (then build order): (probe row indices,
+    [build payload columns], [probe payload columns]), payloads as int64."""
+    lib = _load()
+    bp, nbp = _cols(bpays)
+    pp, npp = _cols(ppays)
+    n = join_agg(bkey, [], pkey, [])[0]
+    cap = max(int(n), 1)
+    rows = np.zeros(cap, np.uint64)
+    ob = np.zeros((max(nbp, 1), cap), np.int64)
+    op = np.zeros((max(npp, 1), cap), np.int64)
+    got = lib.or_join_rows(_col(bkey), bp, nbp, len(bkey), _col(pkey), pp, npp, len(pkey), cap,
+                           _ptr(rows, C.c_uint64), _ptr(ob, C.c_int64), _ptr(op, C.c_int64))
+    assert got == n
+    return rows[:n], [ob[c, :n] for c in range(nbp)], [op[c, :n] for c in range(npp)]
 
 
 class PreparedBuild:

@@ -101,6 +101,36 @@ int or_join_agg_hash(or_col bkey, const or_col* bpay, uint32_t nbp, uint64_t nb,
   return 0;
 }
 
+/*
+ * The inner equi-join's rows themselves (the join output before any aggregation): for every
+ * pair (b, p) with b.key == p.key, in probe order and, within one probe row, in build order,
+ * one output row (probe row index p, the build payloads of b, the probe payloads of p), payloads
+ * sign-extended to int64.  Columns are written column-major: out_bpay[c * cap + r].
+ * Returns the number of pairs; rows past `cap` are counted but not written.
+ * Pinned by: a nested-loop brute force, and by its sums and count equalling or_join_agg_hash.
+ */
+uint64_t or_join_rows(or_col bkey, const or_col* bpay, uint32_t nbp, uint64_t nb, or_col pkey,
+                      const or_col* ppay, uint32_t npp, uint64_t np, uint64_t cap, uint64_t* out_row,
+                      int64_t* out_bpay, int64_t* out_ppay) {
+  std::unordered_map<int64_t, std::vector<uint64_t>> rows_of;
+  rows_of.reserve(nb ? nb : 1);
+  for (uint64_t b = 0; b < nb; ++b) rows_of[at(bkey, b)].push_back(b);
+  uint64_t n = 0;
+  for (uint64_t i = 0; i < np; ++i) {
+    auto it = rows_of.find(at(pkey, i));
+    if (it == rows_of.end()) continue;
+    for (uint64_t b : it->second) {
+      if (n < cap) {
+        out_row[n] = i;
+        for (uint32_t c = 0; c < nbp; ++c) out_bpay[c * cap + n] = at(bpay[c], b);
+        for (uint32_t c = 0; c < npp; ++c) out_ppay[c * cap + n] = at(ppay[c], i);
+      }
+      ++n;
+    }
+  }
+  return n;
+}
+
 /* A prepared build side, so one build can serve several probe slices (used to
  * check sampled probe chunks of a full-size run). */
 struct or_build {
