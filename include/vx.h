@@ -209,6 +209,30 @@ typedef struct {
 vx_status vx_probe_stream(vx_ctx* ctx, const vx_table* table, const vx_probe_desc* desc,
                           vx_agg* out, vx_stats* stats);
 
+/*
+ * The join's rows themselves (an ExKernel's outputs, Sec. 5.2, saved back as the executor runs,
+ * Sec. 5.3): probe like vx_probe_stream, against a table built with VX_UNIQUE, and also write
+ * one output row per probe row whose key is in the table:
+ *   row[r] = the probe row's index, build_pay[c][r] = the table's payload c, probe_pay[c][r] =
+ *   the probe's payload c (payloads sign-extended to int64), in no particular order.
+ * Each column is caller-owned memory of `cap` rows, device memory or pinned host memory; the
+ * probe kernel writes it directly (stores to host memory run beside the host-to-device
+ * copies).  NULL payload columns are skipped.  `n_out` receives the number of output rows;
+ * when it exceeds `cap` the call returns VX_ECAPACITY and nothing past `cap` is written.
+ * `out` and `stats` are as for vx_probe_stream.  VX_EUNSUPPORTED for a pre-aggregating table.
+ */
+typedef struct {
+  uint64_t* row;               /* probe row index per output row */
+  int64_t* build_pay[4];       /* one column per table payload (NULL: skipped) */
+  int64_t* probe_pay[4];       /* one column per probe payload (NULL: skipped) */
+  uint64_t cap;                /* rows each column holds */
+  uint64_t n_out;              /* [out] output rows */
+} vx_join_rows;
+
+vx_status vx_probe_rows(vx_ctx* ctx, const vx_table* table, const vx_probe_desc* desc, vx_join_rows* rows,
+                        vx_agg* out, vx_stats* stats);
+
+
 /* ------------------------------------------------------------------------ one-shot joins */
 
 typedef enum {

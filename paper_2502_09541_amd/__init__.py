@@ -66,6 +66,11 @@ class LinkCalib(C.Structure):
                 ("zc_write_gbs", C.c_double), ("duplex_zcw_gbs", C.c_double)]
 
 
+class JoinRows(C.Structure):
+    _fields_ = [("row", C.c_void_p), ("build_pay", C.c_void_p * 4), ("probe_pay", C.c_void_p * 4),
+                ("cap", C.c_uint64), ("n_out", C.c_uint64)]
+
+
 class BuildDesc(C.Structure):
     _fields_ = [("key", Col), ("pay", C.POINTER(Col)), ("n_pay", C.c_uint32), ("flags", C.c_uint32),
                 ("n", C.c_uint64), ("load_factor", C.c_float), ("reserved", C.c_uint32)]
@@ -153,7 +158,8 @@ class PartitionOut(C.Structure):
 
 EXPORTS = ["vx_ctx_create", "vx_ctx_destroy", "vx_last_error", "vx_ctx_arena_used", "vx_host_alloc",
            "vx_host_free", "vx_build", "vx_table_destroy", "vx_probe_stream", "vx_join_agg",
-           "vx_partition", "vx_cdf_loss_grad", "vx_cdf_forward", "vx_cdf_train", "vx_calibrate"]
+           "vx_partition", "vx_cdf_loss_grad", "vx_cdf_forward", "vx_cdf_train", "vx_calibrate",
+           "vx_probe_rows"]
 N_MODEL_PARAMS = 193
 
 
@@ -176,6 +182,7 @@ def lib():
     L.vx_build.argtypes = [vp, C.POINTER(BuildDesc), C.POINTER(vp)]
     L.vx_table_destroy.argtypes = [vp]
     L.vx_probe_stream.argtypes = [vp, vp, C.POINTER(ProbeDesc), C.POINTER(Agg), C.POINTER(Stats)]
+    L.vx_probe_rows.argtypes = [vp, vp, C.POINTER(ProbeDesc), C.POINTER(JoinRows), C.POINTER(Agg), C.POINTER(Stats)]
     L.vx_join_agg.argtypes = [vp, C.POINTER(JoinDesc), C.POINTER(JoinOut)]
     L.vx_partition.argtypes = [vp, C.POINTER(PartitionDesc), C.POINTER(PartitionOut)]
     fp = C.POINTER(C.c_float)
@@ -502,6 +509,41 @@ class Table:
         if chunk_aggs:
             return res, st.as_dict(), [ca[i].to_list(self.n_pay + npay) for i in range(cap)]
         return res, st.as_dict()
+
+    def probe_rows(self, key, pays=(), cap=None, out=None, late_mat=VX_LATE_AUTO, chunk_rows=0, n_buffers=0):
+        """Probe, aggregate and write the join's rows.  `out` = (row, [build pay cols], [probe pay cols])
+        of uint64 / int64 arrays (pinned host: HostBuffer.array, or CUDA tensors), each of `cap` rows;
+        allocated as pinned HostBuffers of `cap` (default: probe rows) when None.  Returns
+        ([count, sums...], stats, n_out, (row, build cols, probe cols))."""
+        pa, npay = _cols(pays)
+        n = _len(key)
+        keep = []
+        if out is None:
+            cap = n if cap is None else cap
+            hb = [HostBuffer(max(cap, 1), np.uint64)] + [HostBuffer(max(cap, 1), np.int64)
+                                                          for _ in range(self.n_pay + npay)]
+            keep = hb
+            out = (hb[0].array, [h.array for h in hb[1:1 + self.n_pay]], [h.array for h in hb[1 + self.n_pay:]])
+        row, bcols, pcols = out
+        cap = _len(row) if cap is None else cap
+
+        def ptr(a):
+            return None if a is None else (a.data_ptr() if hasattr(a, "data_ptr") else a.ctypes.data)
+        r = JoinRows()
+        r.row = ptr(row)
+        for c, a in enumerate(bcols):
+            r.build_pay[c] = ptr(a)
+        for c, a in enumerate(pcols):
+            r.probe_pay[c] = ptr(a)
+        r.cap = int(cap)
+        d = ProbeDesc(col(key), pa, npay, late_mat, n, int(chunk_rows), int(n_buffers), 0, None, 0)
+        agg, st = Agg(), Stats()
+        status = lib().vx_probe_rows(self.ctx.h, self.h, C.byref(d), C.byref(r), C.byref(agg), C.byref(st))
+        self._keep_rows = keep
+        if status == VX_ECAPACITY:
+            raise VxError(status, lib().vx_last_error().decode() + f" (n_out {r.n_out})")
+        _check(status)
+        return agg.to_list(self.n_pay + npay), st.as_dict(), int(r.n_out), (row, bcols, pcols)
 
     def destroy(self):
         if self.h:

@@ -313,6 +313,113 @@ __global__ void __launch_bounds__(256) k_probe(TableView t, ProbeCols q, unsigne
   block_flush<NACC>(acc, 1 + (int)nb + (int)q.n_pay, acc_out);
 }
 
+// Where k_probe_rows writes the join's rows (device-visible addresses: device memory or mapped
+// pinned host memory), and the running count of rows.
+struct RowsOut {
+  unsigned long long* row;
+  long long* bpay[kMaxPay];
+  long long* ppay[kMaxPay];
+  uint64_t cap;
+  unsigned long long* count;
+};
+
+// k_probe for a unique-key table that also emits one output row per matching probe row:
+// (global probe row, build payloads, probe payloads), payloads sign-extended.  A workgroup
+// counts its tile's matches, reserves that many rows with one atomic, and its waves write them
+// at consecutive positions (coalesced stores, to host memory beside the host-to-device copies).
+template <typename K, int ITEMS>
+__global__ void __launch_bounds__(256) k_probe_rows(TableView t, ProbeCols q, unsigned long long* acc_out,
+                                                    RowsOut o) {
+  using U = typename KeyTraits<K>::U;
+  const U kEmpty = KeyTraits<K>::kEmpty;
+  constexpr int NACC = 9;
+  __shared__ unsigned long long wsum[4];
+  __shared__ unsigned long long tile_base;
+  unsigned long long acc[NACC];
+#pragma unroll
+  for (int a = 0; a < NACC; ++a) acc[a] = 0;
+  const uint32_t nb = t.n_pay;
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t tile = (uint64_t)blockDim.x * ITEMS;
+  for (uint64_t base = blockIdx.x * tile; base < q.n; base += (uint64_t)gridDim.x * tile) {
+    bool hit[ITEMS];
+    long long bv[ITEMS][kMaxPay], pv[ITEMS][kMaxPay];
+    K keys[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      uint64_t i = base + (uint64_t)j * blockDim.x + threadIdx.x;
+      keys[j] = i < q.n ? __builtin_nontemporal_load(((const K*)q.key) + i) : (K)0;
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      uint64_t i = base + (uint64_t)j * blockDim.x + threadIdx.x;
+      hit[j] = false;
+      for (uint32_t p = 0; p < kMaxPay; ++p) bv[j][p] = pv[j][p] = 0;
+      if (i >= q.n) continue;
+      const U kb = (U)keys[j];
+      if (kb == kEmpty) {
+        if (t.side[0]) {
+          hit[j] = true;
+          for (uint32_t p = 0; p < nb; ++p) bv[j][p] = (long long)t.side[1 + p];   // the one row's payload
+        }
+      } else {
+        uint64_t h = slot_of(key_bits(keys[j]), t.log2cap);
+        for (uint64_t step = 0; step <= t.mask; ++step) {
+          const uint8_t* slot = t.slots + (h << t.slot_shift);
+          U sk = *(const U*)slot;
+          if (sk == kb) {
+            hit[j] = true;
+            for (uint32_t p = 0; p < nb; ++p) bv[j][p] = slot_signed(slot, t.pay_off[p], t.pay_size[p]);
+            break;
+          }
+          if (sk == kEmpty) break;
+          h = (h + 1) & t.mask;
+        }
+      }
+      if (!hit[j]) continue;
+      acc[0] += 1;
+      for (uint32_t p = 0; p < nb; ++p) acc[1 + p] += (unsigned long long)bv[j][p];
+      // late materialization: probe payloads of matching rows only
+      for (uint32_t p = 0; p < q.n_pay; ++p) {
+        const bool glob = (q.pay_global >> p) & 1u;
+        pv[j][p] = load_signed(q.pay[p], glob ? q.row0 + i : i, q.pay_size[p]);
+        acc[1 + nb + p] += (unsigned long long)pv[j][p];
+      }
+    }
+    // reserve the tile's rows: per-wave counts, one atomic per workgroup
+    unsigned long long mine = 0;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) mine += (unsigned long long)__popcll(__ballot(hit[j]));
+    if (lane == 0) wsum[wave] = mine;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long tot = 0;
+      for (uint32_t w = 0; w < blockDim.x / 64; ++w) tot += wsum[w];
+      tile_base = tot ? atomicAdd(o.count, tot) : 0ull;
+    }
+    __syncthreads();
+    unsigned long long r0 = tile_base;
+    for (uint32_t w = 0; w < wave; ++w) r0 += wsum[w];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const unsigned long long m = __ballot(hit[j]);
+      if (hit[j]) {
+        const uint64_t r = r0 + (uint64_t)__popcll(m & ((1ull << lane) - 1));
+        if (r < o.cap) {
+          o.row[r] = q.row0 + base + (uint64_t)j * blockDim.x + threadIdx.x;
+          for (uint32_t p = 0; p < nb; ++p)
+            if (o.bpay[p]) o.bpay[p][r] = bv[j][p];
+          for (uint32_t p = 0; p < q.n_pay; ++p)
+            if (o.ppay[p]) o.ppay[p][r] = pv[j][p];
+        }
+      }
+      r0 += (unsigned long long)__popcll(m);
+    }
+    __syncthreads();   // wsum and tile_base are reused by the next tile
+  }
+  block_flush<NACC>(acc, 1 + (int)nb + (int)q.n_pay, acc_out);
+}
+
 // ---------------------------------------------------------------- host side
 
 static int ilog2(uint64_t v) {
@@ -460,12 +567,15 @@ vx_status table_insert(vx_ctx* ctx, vx_table* t, const ColInfo& key, const ColIn
 
 // Launch one probe kernel over q.n rows, accumulating into acc (9 words).
 static vx_status launch_probe(vx_ctx* ctx, const vx_table* t, const ProbeCols& q,
-                              unsigned long long* acc, hipStream_t s) {
+                              unsigned long long* acc, hipStream_t s, const RowsOut* ro = nullptr) {
   if (q.n == 0) return VX_OK;
   constexpr int ITEMS = 4;
   unsigned g = grid_for(ctx, q.n, 256 * ITEMS, 8);
   const bool k64 = t->key_type == VX_I64;
-  if (t->view.preagg) {
+  if (ro) {
+    if (k64) hipLaunchKernelGGL((k_probe_rows<int64_t, ITEMS>), dim3(g), dim3(256), 0, s, t->view, q, acc, *ro);
+    else hipLaunchKernelGGL((k_probe_rows<int32_t, ITEMS>), dim3(g), dim3(256), 0, s, t->view, q, acc, *ro);
+  } else if (t->view.preagg) {
     if (k64) hipLaunchKernelGGL((k_probe<int64_t, true, ITEMS>), dim3(g), dim3(256), 0, s, t->view, q, acc);
     else hipLaunchKernelGGL((k_probe<int32_t, true, ITEMS>), dim3(g), dim3(256), 0, s, t->view, q, acc);
   } else {
@@ -494,7 +604,7 @@ static bool choose_zero_copy(int32_t late_mat, double sel, uint64_t rows, uint64
 }
 
 vx_status probe_impl(vx_ctx* ctx, const vx_table* t, const vx_probe_desc* d, vx_agg* out,
-                     vx_stats* st) {
+                     vx_stats* st, vx_join_rows* rows) {
   double t0 = now_ms();
   VX_CHECK(d->key.type == t->key_type, VX_EINVAL, "probe: key type %d differs from the table's %d",
            d->key.type, t->key_type);
@@ -530,6 +640,34 @@ vx_status probe_impl(vx_ctx* ctx, const vx_table* t, const vx_probe_desc* d, vx_
              (unsigned long long)d->chunk_aggs_cap);
   fill_zero((uint64_t*)ctx->dev_acc, acc_rows * kAccWords, ctx->compute);
 
+  // output rows (vx_probe_rows): device-visible addresses of the caller's columns and a counter
+  RowsOut ro{};
+  ArenaBlock counter;
+  if (rows) {
+    VX_CHECK(!t->view.preagg, VX_EUNSUPPORTED, "probe rows: the table must have unique keys");
+    VX_CHECK(rows->row != nullptr, VX_EINVAL, "probe rows: the row column is NULL");
+    ColInfo ci;
+    VX_TRY(classify(ctx, vx_col{rows->row, VX_I64, 0}, rows->cap, &ci, "probe rows: row column"));
+    ro.row = (unsigned long long*)ci.dev;
+    for (uint32_t p = 0; p < t->view.n_pay; ++p)
+      if (rows->build_pay[p]) {
+        VX_TRY(classify(ctx, vx_col{rows->build_pay[p], VX_I64, 0}, rows->cap, &ci, "probe rows: build payload"));
+        ro.bpay[p] = (long long*)ci.dev;
+      }
+    for (uint32_t p = 0; p < d->n_pay; ++p)
+      if (rows->probe_pay[p]) {
+        VX_TRY(classify(ctx, vx_col{rows->probe_pay[p], VX_I64, 0}, rows->cap, &ci, "probe rows: probe payload"));
+        ro.ppay[p] = (long long*)ci.dev;
+      }
+    ro.cap = rows->cap;
+    counter.a = &ctx->arena;
+    counter.p = ctx->arena.alloc(256);
+    VX_CHECK(counter.p, VX_EBUDGET, "probe rows: no room for the row counter");
+    ro.count = (unsigned long long*)counter.p;
+    fill_zero((uint64_t*)ro.count, 1, ctx->compute);
+    rows->n_out = 0;
+  }
+
   auto kernel = [&](const ChunkView& v) -> vx_status {
     ProbeCols q{};
     q.key = v.ptr[0];
@@ -543,7 +681,7 @@ vx_status probe_impl(vx_ctx* ctx, const vx_table* t, const vx_probe_desc* d, vx_
       if ((v.global_mask >> (1 + p)) & 1u) q.pay_global |= 1u << p;
     }
     return launch_probe(ctx, t, q, (unsigned long long*)ctx->dev_acc + (v.index % acc_rows) * kAccWords,
-                        ctx->compute);
+                        ctx->compute, rows ? &ro : nullptr);
   };
   Pipeline::DecideFn decide = nullptr;
   bool any_host_pay = false;
@@ -566,6 +704,7 @@ vx_status probe_impl(vx_ctx* ctx, const vx_table* t, const vx_probe_desc* d, vx_
   if (status != VX_OK) return status;   // the pipeline's destructor drains both streams
   VX_HIP(hipMemcpyAsync(ctx->host_acc, ctx->dev_acc, acc_rows * kAccWords * 8, hipMemcpyDeviceToHost,
                         ctx->compute));
+  if (rows) VX_HIP(hipMemcpyAsync(&rows->n_out, ro.count, 8, hipMemcpyDeviceToHost, ctx->compute));
   VX_HIP(hipStreamSynchronize(ctx->compute));
   double tk1 = now_ms();
   std::vector<unsigned long long> total(kAccWords, 0);
@@ -589,9 +728,9 @@ vx_status probe_impl(vx_ctx* ctx, const vx_table* t, const vx_probe_desc* d, vx_
     zc_mask |= 1u << p;
     // zero-copy wire estimate from per-chunk match counts (unique keys: matches = rows)
     for (uint64_t k = 0; k < n_chunks; ++k) {
-      uint64_t rows = std::min(pipe.chunk_rows(), n - k * pipe.chunk_rows());
+      uint64_t crows = std::min(pipe.chunk_rows(), n - k * pipe.chunk_rows());
       uint64_t m = k < acc_rows ? ctx->host_acc[k * kAccWords] : 0;
-      s.zc_bytes_est += (uint64_t)zc_wire_bytes(rows, std::min(m, rows), c.info.elsize, ctx->zc_line);
+      s.zc_bytes_est += (uint64_t)zc_wire_bytes(crows, std::min(m, crows), c.info.elsize, ctx->zc_line);
     }
   }
   s.zc_mask = zc_mask;
@@ -604,6 +743,9 @@ vx_status probe_impl(vx_ctx* ctx, const vx_table* t, const vx_probe_desc* d, vx_
   s.probe_ms = tk1 - tk0;
   s.total_ms = now_ms() - t0;
   if (st) *st = s;
+  VX_CHECK(!rows || rows->n_out <= rows->cap, VX_ECAPACITY,
+           "probe rows: %llu output rows exceed cap %llu (n_out holds the count)",
+           (unsigned long long)rows->n_out, (unsigned long long)rows->cap);
   return VX_OK;
 }
 
@@ -666,7 +808,14 @@ vx_status vx_probe_stream(vx_ctx* ctx, const vx_table* t, const vx_probe_desc* d
                           vx_stats* st) {
   VX_CHECK(ctx && t && d && out, VX_EINVAL, "vx_probe_stream: null argument");
   VX_CHECK(t->ctx == ctx, VX_EINVAL, "vx_probe_stream: table belongs to another context");
-  return probe_impl(ctx, t, d, out, st);
+  return probe_impl(ctx, t, d, out, st, nullptr);
+}
+
+vx_status vx_probe_rows(vx_ctx* ctx, const vx_table* t, const vx_probe_desc* d, vx_join_rows* rows,
+                        vx_agg* out, vx_stats* st) {
+  VX_CHECK(ctx && t && d && rows && out, VX_EINVAL, "vx_probe_rows: null argument");
+  VX_CHECK(t->ctx == ctx, VX_EINVAL, "vx_probe_rows: table belongs to another context");
+  return probe_impl(ctx, t, d, out, st, rows);
 }
 
 vx_status vx_join_agg(vx_ctx* ctx, const vx_join_desc* d, vx_join_out* out) {
@@ -677,7 +826,7 @@ vx_status vx_join_agg(vx_ctx* ctx, const vx_join_desc* d, vx_join_out* out) {
       double t0 = now_ms(), bms = 0;
       vx_table* t = nullptr;
       VX_TRY(build_impl(ctx, &d->u.plain.build, &t, &bms));
-      vx_status st = probe_impl(ctx, t, &d->u.plain.probe, &out->agg, &out->stats);
+      vx_status st = probe_impl(ctx, t, &d->u.plain.probe, &out->agg, &out->stats, nullptr);
       vx_table_destroy(t);
       out->stats.build_ms = bms;
       out->stats.total_ms = now_ms() - t0;
