@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--chunk-rows", type=int, default=0)
     ap.add_argument("--n-buffers", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="stream", choices=["stream", "plain", "star", "batch", "skew", "calib"],
+    ap.add_argument("--workload", default="stream", choices=["stream", "plain", "star", "batch", "skew", "rows", "calib"],
                     help="stream (default) is the headline line; the others print their own line")
     ap.add_argument("--method", default="learned", help="skew workload: partitioner to time")
     ap.add_argument("--n-parts", type=int, default=256)
@@ -98,7 +98,7 @@ def main():
         sys.exit(2)
     if args.workload != "stream":
         out = {"plain": run_plain, "star": run_star, "batch": run_batch, "skew": run_skew,
-               "calib": run_calib}[args.workload](args)
+               "rows": run_rows, "calib": run_calib}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
     import numpy as np
@@ -236,6 +236,68 @@ def _timed(step, args, torch):
     if any(r[0] != first for r in res) or (ref is not None and ref[0] != first):
         raise SystemExit("non-deterministic results across steps")
     return ms, res
+
+
+def run_rows(args):
+    """The streamed join of the default line with its rows materialized: every match writes
+    (probe row, 2 build payloads, 2 probe payloads) as int64 into pinned host memory, 40 B per
+    output row.  Timed next to the same join reduced to aggregates only."""
+    import numpy as np
+    import torch
+    import datagen
+    import paper_2502_09541_amd as vx
+    nb, np_ = 1 << args.log2_build, 1 << args.log2_probe
+    ctx = vx.Context(int(args.budget_gib * GiB))
+    b_peak = ctx.calibrate()["h2d_gbs"]
+    H = {}
+    for name, n, dt in (("bk", nb, np.int64), ("b0", nb, np.int32), ("b1", nb, np.int32),
+                        ("pk", np_, np.int64), ("p0", np_, np.int64), ("p1", np_, np.int64)):
+        H[name] = vx.HostBuffer(n, dt)
+    datagen.stream_build(nb, out=(H["bk"].array, H["b0"].array, H["b1"].array))
+    step_rows = 1 << 27
+    for r0 in range(0, np_, step_rows):
+        r1 = min(np_, r0 + step_rows)
+        datagen.stream_probe(nb, r1 - r0, out=(H["pk"].array[r0:r1], H["p0"].array[r0:r1],
+                                               H["p1"].array[r0:r1]), row0=r0)
+    cap = int(np_ * 0.1 * 1.01) + (1 << 20)
+    O = [vx.HostBuffer(cap, np.uint64)] + [vx.HostBuffer(cap, np.int64) for _ in range(4)]
+    out = (O[0].array, [O[1].array, O[2].array], [O[3].array, O[4].array])
+    log(f"rows: {np_} probe rows, output capacity {cap} rows ({5 * 8 * cap / GiB:.1f} GiB pinned)")
+    t = ctx.build(H["bk"], [H["b0"], H["b1"]])
+
+    def step_rows_():
+        return t.probe_rows(H["pk"], [H["p0"], H["p1"]], out=out, cap=cap)
+
+    def step_agg():
+        return t.probe(H["pk"], [H["p0"], H["p1"]])
+
+    ms, res = _timed(step_rows_, args, torch)
+    ms_agg, res_agg = _timed(step_agg, args, torch)
+    agg, st, n_out, _ = res[0]
+    if agg != res_agg[0][0] or any(r[0] != agg or r[2] != n_out for r in res):
+        raise SystemExit("materialized join disagrees with the aggregate-only join")
+    t.destroy()
+    ctx.close()
+    for h in list(H.values()) + O:
+        h.free()
+    d2h = n_out * 40
+    # dominant kernel: per probe row 8 B key from the chunk buffer + one 16 B slot, as k_probe
+    launches = max(1, st["kernel_launches"])
+    k_avg = st["kernel_ms"] / launches
+    ach = 24.0 * (np_ / launches) / (k_avg * 1e6)
+    return _common("probe rows/s", np_ / (ms / 1e3), ms, args, "int64",
+                   {"workload": "streamed_join_rows_materialized", "build_rows": nb, "probe_rows": np_,
+                    "output_rows": n_out, "output_bytes_per_row": 40, "match_frac": 0.1,
+                    "device_budget_gib": args.budget_gib},
+                   {"bound": "hbm", "kernel": "k_probe_rows", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": ach / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": k_avg,
+                    "rows_per_launch": np_ / launches},
+                   {"host_link": {"peak_measured_gbs": b_peak,
+                                  "h2d_gbs": (nb * 16 + st["sdma_bytes"] + st["zc_bytes_est"]) / (ms * 1e6),
+                                  "d2h_output_gbs": d2h / (ms * 1e6)},
+                    "aggregate_only_ms_per_step": ms_agg,
+                    "materialization_cost": ms / ms_agg - 1.0,
+                    "result": {"match_count": agg[0], "output_rows": n_out}})
 
 
 def run_calib(args):

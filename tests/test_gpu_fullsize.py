@@ -1,4 +1,5 @@
-"""Full-size parity of the streamed join in the launch configuration bench.py times.
+"""Full-size parity of the streamed join in the launch configuration bench.py times, with its
+rows materialized as well.
 
 2^26 build rows and 2^31 host-resident probe rows (48 GiB pinned), 16 GiB budget, automatic
 late materialization.  The oracle's hash map of 2^26 keys is too slow to build here, so the
@@ -32,12 +33,20 @@ def test_streamed_join_full_size_closed_form(gpu):
             datagen.stream_probe(nb, step, out=(H["pk"].array[r0:r0 + step], H["p0"].array[r0:r0 + step],
                                                 H["p1"].array[r0:r0 + step]), row0=r0)
         print("generated; running the join", flush=True)
+        cap = int(np_ * 0.1 * 1.01)
+        for name, dt in (("row", np.uint64), ("ob0", np.int64), ("ob1", np.int64), ("op0", np.int64),
+                         ("op1", np.int64)):
+            H[name] = gpu.HostBuffer(cap, dt)
         with gpu.Context(16 * GiB) as ctx:
             t = ctx.build(H["bk"], [H["b0"], H["b1"]])
             tot, st, per = t.probe(H["pk"], [H["p0"], H["p1"]], chunk_aggs=True,
                                    chunk_rows=(64 << 20) // 8)
             tot2, _ = t.probe(H["pk"], [H["p0"], H["p1"]])
+            print("materializing the join's rows", flush=True)
+            out = (H["row"].array, [H["ob0"].array, H["ob1"].array], [H["op0"].array, H["op1"].array])
+            tot3, _, n_out, _ = t.probe_rows(H["pk"], [H["p0"], H["p1"]], out=out, cap=cap)
             t.destroy()
+        assert tot3 == tot and n_out == tot[0]
         assert tot == tot2
         assert st["chunks"] == 256 and st["zc_mask"] == 3
         print("closed form over", np_, "rows", flush=True)
@@ -55,6 +64,17 @@ def test_streamed_join_full_size_closed_form(gpu):
                     int(H["p0"].array[r0:r0 + cr][h].sum()), int(H["p1"].array[r0:r0 + cr][h].sum())]
             if c in (0, 77, np_ // cr - 1):
                 assert per[c] == [v % M64 for v in vals], f"chunk {c}"
+                # the materialized rows of this chunk: exactly its matching rows, with their values
+                row = H["row"].array[:n_out]
+                sel = np.nonzero((row >= r0) & (row < r0 + cr))[0]
+                order = np.argsort(row[sel])
+                got_rows = row[sel][order].astype(np.int64) - r0
+                exp_rows = np.nonzero(h)[0]
+                assert np.array_equal(got_rows, exp_rows), f"rows of chunk {c}"
+                assert np.array_equal(H["ob0"].array[:n_out][sel][order], b0[hit[h]])
+                assert np.array_equal(H["ob1"].array[:n_out][sel][order], b1[hit[h]])
+                assert np.array_equal(H["op0"].array[:n_out][sel][order], H["p0"].array[r0:r0 + cr][h])
+                assert np.array_equal(H["op1"].array[:n_out][sel][order], H["p1"].array[r0:r0 + cr][h])
             exp = [e + v for e, v in zip(exp, vals)]
         assert tot == [e % M64 for e in exp]
         assert [sum(x) % M64 for x in zip(*per)] == tot
