@@ -29,7 +29,8 @@ TRAFFIC_BYTES = {"k_probe_stream": 1.5647e9,    # 8,388,608 probe rows per launc
                  "k_probe_plain": 1.8964e9,     # 16,777,216 probe rows per launch
                  "k_star": 2.1670e9,            # 16,666,667 fact rows per launch
                  "batch_graph": 6.0252e11,      # one graph launch: build phase + probe phase, all 256 jobs
-                 "k_pj_stream": 4.976e8}        # 8,388,608 probe rows per launch (mean over the partitioners)
+                 "k_pj_stream": 4.976e8,        # 8,388,608 probe rows per launch (mean over the partitioners)
+                 "k_probe_rows": 1.4712e9}      # 8,388,608 probe rows per launch, output rows included
 GiB = 1 << 30
 
 
@@ -290,7 +291,7 @@ def run_rows(args):
                     "output_rows": n_out, "output_bytes_per_row": 40, "match_frac": 0.1,
                     "device_budget_gib": args.budget_gib},
                    {"bound": "hbm", "kernel": "k_probe_rows", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": ach / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": k_avg,
+                    "frac": ach / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES["k_probe_rows"], "avg_launch_ms": k_avg,
                     "rows_per_launch": np_ / launches},
                    {"host_link": {"peak_measured_gbs": b_peak,
                                   "h2d_gbs": (nb * 16 + st["sdma_bytes"] + st["zc_bytes_est"]) / (ms * 1e6),
