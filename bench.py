@@ -50,11 +50,13 @@ def parse():
     ap.add_argument("--chunk-rows", type=int, default=0)
     ap.add_argument("--n-buffers", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="stream", choices=["stream", "plain", "star", "batch", "skew", "rows", "calib"],
+    ap.add_argument("--workload", default="stream", choices=["stream", "plain", "star", "batch", "skew", "rows", "radix", "calib"],
                     help="stream (default) is the headline line; the others print their own line")
     ap.add_argument("--method", default="learned", help="skew workload: partitioner to time")
     ap.add_argument("--n-parts", type=int, default=256)
     ap.add_argument("--train-steps", type=int, default=0, help="skew workload: Adam steps (0 = library default)")
+    ap.add_argument("--radix-log2", type=int, default=29, help="radix workload: log2 rows of each table")
+    ap.add_argument("--radix-budget-gib", type=float, default=4.0, help="radix workload: device budget")
     return ap.parse_args()
 
 
@@ -99,7 +101,7 @@ def main():
         sys.exit(2)
     if args.workload != "stream":
         out = {"plain": run_plain, "star": run_star, "batch": run_batch, "skew": run_skew,
-               "rows": run_rows, "calib": run_calib}[args.workload](args)
+               "rows": run_rows, "radix": run_radix, "calib": run_calib}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
     import numpy as np
@@ -509,6 +511,88 @@ def run_skew(args):
                                         "imbalance_table_partitions": lines["quantile"]["st"]["imbalance_tables"],
                                         "singleton_rows": lines["quantile"]["st"]["singleton_rows"]},
                     "learned_speedup_vs_radix_hash": r["ms"] / a["ms"], "bit_exact_across_methods": True})
+
+
+def run_radix(args):
+    """Two-table radix-partitioned join (the paper's hash-join case study): A and B of 2^29
+    rows each, 16 B tuples <int64 key, int64 val> in pinned host memory (8 GiB per table),
+    A.key unique (a permutation of [0, 2^29)), B.key a uniform foreign key into A; device budget
+    4 GiB, so neither table's hash table fits; result = SUM(A.val + B.val) and the match count."""
+    import numpy as np
+    import torch
+    import datagen
+    import oracle
+    import paper_2502_09541_amd as vx
+    n = 1 << args.radix_log2
+    ak, av, bk, bv = (vx.HostBuffer(n, np.int64) for _ in range(4))
+    t0 = time.perf_counter()
+    step_rows = 1 << 27
+    for r0 in range(0, n, step_rows):
+        m = min(step_rows, n - r0)
+        datagen.radix_a(n, out=(ak.array[r0:r0 + m], av.array[r0:r0 + m]), row0=r0)
+        datagen.radix_b(n, m, out=(bk.array[r0:r0 + m], bv.array[r0:r0 + m]), row0=r0)
+    log(f"radix: inputs generated in {time.perf_counter() - t0:.1f} s")
+    ctx = vx.Context(int(args.radix_budget_gib * GiB))
+    cal = ctx.calibrate()
+    ms, res = _timed(lambda: ctx.join_radix(ak, [av], bk, [bv]), args, torch)
+    agg, st = res[0]
+    log(f"radix: {ms:.1f} ms/step, {st['n_parts']} partitions, pass 1 {st['part_ms']:.1f} ms, "
+        f"pass 2 {st['probe_ms']:.1f} ms, {st['chunks']} build slices")
+    ctx.close()
+    # exact check against the generator's closed form: every B row matches the one A row with its key
+    a_of_key = np.empty(n, np.uint64)
+    a_of_key[ak.array] = av.array.view(np.uint64)
+    want = [n, int(a_of_key[bk.array].sum(dtype=np.uint64)), int(bv.array.view(np.uint64).sum(dtype=np.uint64))]
+    del a_of_key
+    if agg != want:
+        raise SystemExit(f"radix join result {agg} differs from the closed form {want}")
+    # the oracle on a bounded sample of the same workload: the rows of both tables whose key is
+    # below n/16 (a key range, so the sample's join is the whole join restricted to those keys)
+    cpu = None
+    if not args.no_cpu_baseline:
+        lim = n // 16
+        ma, mb = ak.array < lim, bk.array < lim
+        sak, sav, sbk, sbv = ak.array[ma], av.array[ma], bk.array[mb], bv.array[mb]
+        t0 = time.perf_counter()
+        got = oracle.join_agg(sak, [sav], sbk, [sbv])
+        dt = time.perf_counter() - t0
+        if got[0] != len(sbk):
+            raise SystemExit("oracle sample: unexpected match count")
+        cpu = {"value": (len(sak) + len(sbk)) / dt, "unit": "tuples/s", "cores": 1, "kind": "oracle",
+               "sample": f"rows of A and B with key < 2^{args.radix_log2 - 4}: {len(sak)} + {len(sbk)} rows, "
+                         f"joined in {dt:.1f} s on 1 host thread"}
+    for h in (ak, av, bk, bv):
+        h.free()
+    tuples = 2 * n
+    h2d = st["sdma_bytes"] + st["zc_bytes_est"]
+    d2h = st["sdma_bytes"] if st["n_parts"] > 1 and st["zc_bytes_est"] > 0 else 0   # clustered copies written back
+    # dominant kernel: the pass-2 probe (B's rows of a partition read in place from host memory)
+    k_avg = st["kernel_ms"] / max(1, st["chunks"])
+    rows_per_launch = n / max(1, st["chunks"])
+    ach = 16.0 * rows_per_launch / (k_avg * 1e6)
+    b_peak = cal["h2d_gbs"]
+    # link-time model: pass 1 moves every tuple in and back out (both directions together at the
+    # measured duplex rate of copies beside kernel stores to host), pass 2 reads them in again
+    t_model = (2 * 16.0 * tuples) / (cal["duplex_zcw_gbs"] * 1e9) + 16.0 * tuples / (b_peak * 1e9)
+    return _common("tuples/s", tuples / (ms / 1e3), ms, args, "int64",
+                   {"workload": "two_table_radix_join", "rows_a": n, "rows_b": n, "tuple_bytes": 16,
+                    "device_budget_gib": args.radix_budget_gib, "n_parts": st["n_parts"],
+                    "partition_fn": "raw key bits [0, log2 n_parts)"},
+                   {"bound": "host_link", "kernel": "k_rj_probe", "achieved": ach, "peak": b_peak, "unit": "GB/s",
+                    "frac": ach / b_peak, "traffic": None, "avg_launch_ms": k_avg,
+                    "rows_per_launch": rows_per_launch,
+                    "algorithmic_bytes": "16 B per B row read in place from pinned host memory"},
+                   {"cpu_baseline": cpu,
+                    "host_link": {"h2d_peak_measured_gbs": b_peak, "duplex_measured_gbs": cal["duplex_zcw_gbs"],
+                                  "h2d_bytes_per_step": h2d, "d2h_bytes_per_step": d2h,
+                                  "h2d_gbs": h2d / (ms * 1e6), "d2h_gbs": d2h / (ms * 1e6),
+                                  "model_ms": t_model * 1e3, "frac_of_model": t_model * 1e3 / ms},
+                    "phases": {"pass1_ms": st["part_ms"], "pass2_ms": st["probe_ms"],
+                               "pass2_build_kernels_ms": st["build_ms"], "pass2_probe_kernels_ms": st["kernel_ms"],
+                               "build_slices": st["chunks"], "imbalance": st["imbalance"]},
+                    "result": {"match_count": agg[0], "sum_a_val": agg[1], "sum_b_val": agg[2],
+                               "sum_a_plus_b": (agg[1] + agg[2]) % (1 << 64)},
+                    "probe_rows_per_s": n / (ms / 1e3), "bit_exact_closed_form": True})
 
 
 if __name__ == "__main__":

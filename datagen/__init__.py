@@ -117,9 +117,10 @@ def loguniform(seed, col, cnt, lo, hi):
 # ---------------------------------------------------------------------------
 
 SEED_PLAIN, SEED_STREAM, SEED_STAR, SEED_BATCH, SEED_SKEW = 0xC1, 0xC2, 0xC3, 0xC4, 0xC5
+SEED_RADIX = 0xC6
 
 # column ids
-COL_BKEY, COL_BPAY0, COL_BPAY1, COL_PKEY = 1, 2, 3, 4
+COL_BKEY, COL_BPAY0, COL_BPAY1, COL_PKEY, COL_PPAY0 = 1, 2, 3, 4, 5
 
 
 def plain_join(n_build=1 << 20, n_probe=1 << 24, seed=SEED_PLAIN, key_range_mult=2):
@@ -219,4 +220,26 @@ def skew_probe(n, seed=SEED_SKEW, out=None, row0=0):
     if out is None:
         out = np.empty(n, np.int64)
     fill_zipf(out, seed, COL_PKEY, ZIPF_S, ZIPF_N, row0=row0)
+    return out
+
+
+def radix_a(n_a, seed=SEED_RADIX, out=None, row0=0):
+    """Two-table join, table A: unique int64 keys (a seeded permutation of [0, n_a)) and int64
+    values uniform in [0, 2^32)."""
+    if out is None:
+        out = (np.empty(n_a, np.int64), np.empty(n_a, np.int64))
+    k, v = out
+    fill_perm(k, seed, COL_BKEY, n_a, row0=row0)
+    fill_uniform(v, seed, COL_BPAY0, 0, 1 << 32, row0=row0)
+    return out
+
+
+def radix_b(n_a, n_b, seed=SEED_RADIX, out=None, row0=0):
+    """Two-table join, table B: int64 foreign keys uniform over A's keys [0, n_a) and int64
+    values uniform in [0, 2^32)."""
+    if out is None:
+        out = (np.empty(n_b, np.int64), np.empty(n_b, np.int64))
+    k, v = out
+    fill_uniform(k, seed, COL_PKEY, 0, n_a, row0=row0)
+    fill_uniform(v, seed, COL_PPAY0, 0, 1 << 32, row0=row0)
     return out

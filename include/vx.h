@@ -239,7 +239,8 @@ typedef enum {
   VX_JOIN_PLAIN = 1,        /* build + probe of two tables */
   VX_JOIN_STAR = 2,         /* star join with GROUP BY */
   VX_JOIN_BATCH = 3,        /* many independent device-resident joins in one launch */
-  VX_JOIN_PARTITIONED = 4   /* build side too large for the budget: partition, then join */
+  VX_JOIN_PARTITIONED = 4,  /* build side too large for the budget: partition, then join */
+  VX_JOIN_RADIX = 5         /* both tables too large for the budget: cluster both, join per partition */
 } vx_join_kind;
 
 typedef struct {
@@ -335,6 +336,45 @@ typedef struct {
   vx_part_opts part;
 } vx_partitioned_join;
 
+/*
+ * Radix-partitioned join of two large tables A and B (Sec. 6.2, the hash-join case study):
+ * count and SUM(payload) of each side over all pairs with A.key == B.key, so that
+ * SUM(A.val + B.val) = agg.sum[0] + agg.sum[1] (mod 2^64) with one payload per side.
+ * Pass 1 clusters each table by partition, chunk by chunk through the chunk pipeline (the
+ * paper's radix-partition step: raw key bits [shift, shift + log2 n_parts), or the top bits
+ * of a 64-bit mix of the key), and keeps each chunk's boundary array.  The clustered copies go
+ * in pinned host scratch (written by a kernel that stores to mapped memory beside the
+ * host-to-device copies) or, when both fit beside pass 2, in the arena.  Pass 2 takes the
+ * partitions in turn: A's rows of partition p, read in place from every clustered chunk, are
+ * pre-aggregated per key (count, payload sum) into a table in the arena, and B's rows of p look
+ * it up.  A partition whose A rows exceed the largest table the arena holds is built in slices,
+ * each probed by all of B's rows of that partition.  With one partition nothing is clustered:
+ * both tables are read in place.
+ * Keys: any value, duplicates on both sides (multiset semantics); both sides share one type.
+ * Payloads: at most one per side; sums wrap mod 2^64 (int32 sign-extended).
+ * agg: match_count; sum[0..n_pay_a) A's payload, then B's.  When b.chunk_aggs is set it receives
+ * one vx_agg per partition (chunk_aggs_cap >= n_parts), partition p holding the pairs whose key
+ * maps to p.
+ * stats: n_parts, imbalance (max/mean A + B rows per partition), part_ms (pass 1), probe_ms
+ * (pass 2), build_ms and kernel_ms (pass 2's build and probe kernels, summed from HIP events
+ * around each launch), sdma_bytes (pass 1 copies), zc_bytes_est (bytes read in place from host
+ * memory), table_bytes (the pass-2 table), chunks (pass-2 build slices: one build and one probe
+ * launch each), rows = b.n.
+ * Errors: VX_EINVAL for a bad argument (n_parts not a power of two or above 1024, shift > 63,
+ * key types that differ); VX_EUNSUPPORTED for more than one payload on a side; VX_EBUDGET when
+ * the arena cannot hold pass 1's buffers or a pass-2 table of 64 slots; VX_ENOMEM when pinned
+ * host scratch cannot be had.
+ */
+typedef struct {
+  vx_build_desc a;             /* host or device; flags ignored (duplicates allowed) */
+  vx_probe_desc b;             /* host or device; chunk_aggs: one per partition */
+  uint32_t n_parts;            /* power of two <= 1024; 0 = the fewest whose expected largest
+                                  table fits the arena */
+  uint32_t shift;              /* first key bit of the partition id (raw-bits partitioning) */
+  uint32_t hash;               /* 0: raw key bits as in the paper; 1: top bits of a 64-bit mix */
+  int32_t placement;           /* clustered copies: 0 auto, 1 pinned host scratch, 2 arena */
+} vx_radix_join;
+
 typedef struct {
   int32_t kind;                /* vx_join_kind */
   int32_t reserved;
@@ -343,11 +383,12 @@ typedef struct {
     vx_star_join star;
     vx_batch_join batch;
     vx_partitioned_join part;
+    vx_radix_join radix;
   } u;
 } vx_join_desc;
 
 typedef struct {
-  vx_agg agg;                  /* PLAIN, PARTITIONED */
+  vx_agg agg;                  /* PLAIN, PARTITIONED, RADIX */
   uint64_t n_groups;           /* STAR: groups with count > 0 (required capacity on VX_ECAPACITY) */
   uint32_t part_method_used;   /* PARTITIONED */
   uint32_t reserved;

@@ -27,7 +27,7 @@ STATUS_NAMES = ["VX_OK", "VX_EINVAL", "VX_EBUDGET", "VX_ENOMEM", "VX_EHIP", "VX_
 VX_I32, VX_I64 = 1, 2
 VX_UNIQUE, VX_PREAGG = 1, 2
 VX_LATE_AUTO, VX_LATE_SDMA, VX_LATE_ZC, VX_LATE_PAPER = -1, 0, 1, 2
-VX_JOIN_PLAIN, VX_JOIN_STAR, VX_JOIN_BATCH, VX_JOIN_PARTITIONED = 1, 2, 3, 4
+VX_JOIN_PLAIN, VX_JOIN_STAR, VX_JOIN_BATCH, VX_JOIN_PARTITIONED, VX_JOIN_RADIX = 1, 2, 3, 4, 5
 (VX_PART_AUTO, VX_PART_RADIX_HASH, VX_PART_RADIX_BITS, VX_PART_LEARNED, VX_PART_QUANTILE,
  VX_PART_UNTRAINED, VX_PART_RANGE) = range(7)
 PART_METHODS = {"auto": 0, "radix_hash": 1, "radix_bits": 2, "learned": 3, "quantile": 4,
@@ -124,13 +124,18 @@ class PartitionedJoin(C.Structure):
     _fields_ = [("build", BuildDesc), ("probe", ProbeDesc), ("part", PartOpts)]
 
 
+class RadixJoin(C.Structure):
+    _fields_ = [("a", BuildDesc), ("b", ProbeDesc), ("n_parts", C.c_uint32), ("shift", C.c_uint32),
+                ("hash", C.c_uint32), ("placement", C.c_int32)]
+
+
 class _PlainJoin(C.Structure):
     _fields_ = [("build", BuildDesc), ("probe", ProbeDesc)]
 
 
 class _JoinUnion(C.Union):
     _fields_ = [("plain", _PlainJoin), ("star", StarJoin), ("batch", BatchJoin),
-                ("part", PartitionedJoin)]
+                ("part", PartitionedJoin), ("radix", RadixJoin)]
 
 
 class JoinDesc(C.Structure):
@@ -416,6 +421,28 @@ class Context:
         if per_partition:
             P = int(out.stats.n_parts)
             return res + ([pa[i].to_list(nbp) for i in range(P)],)
+        return res
+
+    def join_radix(self, akey, apays, bkey, bpays, n_parts=0, shift=0, hash=False, placement=0,
+                   per_partition=False):
+        """Two-table radix-partitioned join.  Returns ([count, A sums..., B sums...], stats
+        [, per-partition aggregate lists])."""
+        ap, nap = _cols(apays)
+        bp, nbp = _cols(bpays)
+        d = JoinDesc()
+        d.kind = VX_JOIN_RADIX
+        rj = d.u.radix
+        rj.a = BuildDesc(col(akey), ap, nap, 0, _len(akey), 0.0, 0)
+        cap = 1024 if per_partition else 0
+        pa = (Agg * cap)() if cap else None
+        rj.b = ProbeDesc(col(bkey), bp, nbp, VX_LATE_AUTO, _len(bkey), 0, 0, 0, pa, cap)
+        rj.n_parts, rj.shift, rj.hash, rj.placement = int(n_parts), int(shift), int(bool(hash)), int(placement)
+        out = JoinOut()
+        _check(lib().vx_join_agg(self.h, C.byref(d), C.byref(out)))
+        res = (out.agg.to_list(nap + nbp), out.stats.as_dict())
+        if per_partition:
+            P = int(out.stats.n_parts)
+            return res + ([pa[i].to_list(nap + nbp) for i in range(P)],)
         return res
 
     def join_batch(self, bkeys, bpays, pkeys, mode=0, tile_rows=0, block=0, load_factor=0.0):

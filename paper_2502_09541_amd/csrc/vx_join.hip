@@ -784,6 +784,7 @@ vx_status build_impl(vx_ctx* ctx, const vx_build_desc* d, vx_table** out, double
 vx_status join_star(vx_ctx* ctx, const vx_star_join* d, vx_join_out* out);
 vx_status join_batch(vx_ctx* ctx, const vx_batch_join* d, vx_join_out* out);
 vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_out* out);
+vx_status join_radix(vx_ctx* ctx, const vx_radix_join* d, vx_join_out* out);
 
 }  // namespace vx
 
@@ -835,6 +836,7 @@ vx_status vx_join_agg(vx_ctx* ctx, const vx_join_desc* d, vx_join_out* out) {
     case VX_JOIN_STAR: return join_star(ctx, &d->u.star, out);
     case VX_JOIN_BATCH: return join_batch(ctx, &d->u.batch, out);
     case VX_JOIN_PARTITIONED: return join_partitioned(ctx, &d->u.part, out);
+    case VX_JOIN_RADIX: return join_radix(ctx, &d->u.radix, out);
     default: break;
   }
   set_error("vx_join_agg: unknown kind %d", d->kind);

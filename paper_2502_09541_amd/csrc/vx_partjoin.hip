@@ -35,9 +35,10 @@ constexpr uint32_t kMaxSegs = 1024;
 
 struct SegList {
   const unsigned long long* start;    // first source row of each segment
-  const unsigned long long* prefix;   // flattened start of each segment; prefix[nseg] = total
+  const unsigned long long* prefix;   // flattened start of each segment; prefix[nseg] = all rows
   uint32_t nseg;
-  uint64_t total;
+  uint64_t total;                     // rows taken: flattened indices [base, base + total)
+  uint64_t base = 0;
 };
 
 // source row of flattened index idx (the last segment whose prefix is <= idx)
@@ -120,7 +121,7 @@ constexpr int kPjLdsProbes = 16;  // past this, a row goes straight to the globa
 // memory) into the transient table: a per-tile LDS table absorbs repeated keys, its entries are
 // then added to the global table.  Every slot claimed in the global table is appended to
 // `claims` (*n_claims counts them: the partition's distinct keys), a tile at a time through an
-// LDS buffer, so the shared counter sees one atomic per tile.
+// LDS buffer, so the shared counter sees one atomic per tile; claims may be null (no list).
 template <typename K>
 __global__ void __launch_bounds__(256) k_pj_build(TableView t, const void* key, const void* pay0,
                                                   uint32_t pay_size, SegList sl, unsigned int* flags,
@@ -145,7 +146,7 @@ __global__ void __launch_bounds__(256) k_pj_build(TableView t, const void* key, 
     __syncthreads();
     uint64_t end = base + kPjTile < sl.total ? base + kPjTile : sl.total;
     for (uint64_t i = base + threadIdx.x; i < end; i += blockDim.x) {
-      uint64_t src = seg_source(sst, spre, sl.nseg, i);
+      uint64_t src = seg_source(sst, spre, sl.nseg, sl.base + i);
       K k = load_key<K>(key, src);
       unsigned long long v = t.n_pay ? (unsigned long long)load_signed(pay0, src, pay_size) : 0ull;
       unsigned long long kb = (unsigned long long)(long long)k;
@@ -171,9 +172,11 @@ __global__ void __launch_bounds__(256) k_pj_build(TableView t, const void* key, 
                                      : ~0ull,
                     lclaim, &n_lclaim);
     __syncthreads();
-    if (threadIdx.x == 0) claim_base = n_lclaim ? atomicAdd(n_claims, (unsigned long long)n_lclaim) : 0ull;
-    __syncthreads();
-    for (uint32_t j = threadIdx.x; j < n_lclaim; j += blockDim.x) claims[claim_base + j] = lclaim[j];
+    if (claims) {   // uniform across the workgroup
+      if (threadIdx.x == 0) claim_base = n_lclaim ? atomicAdd(n_claims, (unsigned long long)n_lclaim) : 0ull;
+      __syncthreads();
+      for (uint32_t j = threadIdx.x; j < n_lclaim; j += blockDim.x) claims[claim_base + j] = lclaim[j];
+    }
     __syncthreads();
   }
 }
@@ -319,6 +322,59 @@ __global__ void __launch_bounds__(256) k_pj_writeback(const uint8_t* skey, const
       else ((unsigned int*)hpay)[r] = ((const unsigned int*)spay)[r];
     }
   }
+}
+
+// Pass 2 probe of the two-table radix join: B's rows of one partition, read in place through
+// their segment list, look up the partition's pre-aggregated A table.  A matching row adds A's
+// row count for its key to the pair count, A's payload sum for the key to SUM(A), and the count
+// times its own payload to SUM(B).  The three sums go to acc[0..2] (one atomic per workgroup).
+template <typename K>
+__global__ void __launch_bounds__(256) k_rj_probe(TableView t, const void* key, const void* pay,
+                                                  uint32_t pay_size, SegList sl, unsigned long long* acc) {
+  using U = typename KeyTraits<K>::U;
+  const U kEmpty = KeyTraits<K>::kEmpty;
+  __shared__ unsigned long long sst[kMaxSegs], spre[kMaxSegs + 1];
+  for (uint32_t j = threadIdx.x; j < sl.nseg; j += blockDim.x) sst[j] = sl.start[j];
+  for (uint32_t j = threadIdx.x; j <= sl.nseg; j += blockDim.x) spre[j] = sl.prefix[j];
+  __syncthreads();
+  unsigned long long a[3] = {0, 0, 0};
+  constexpr int ITEMS = 4;
+  const uint64_t tile = (uint64_t)blockDim.x * ITEMS;
+  for (uint64_t base = blockIdx.x * tile; base < sl.total; base += (uint64_t)gridDim.x * tile) {
+    K kk[ITEMS];
+    unsigned long long vv[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const uint64_t i = base + (uint64_t)j * blockDim.x + threadIdx.x;
+      kk[j] = (K)0;
+      vv[j] = 0;
+      if (i < sl.total) {
+        const uint64_t src = seg_source(sst, spre, sl.nseg, i);
+        kk[j] = load_key<K>(key, src);
+        if (pay) vv[j] = (unsigned long long)load_signed(pay, src, pay_size);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const uint64_t i = base + (uint64_t)j * blockDim.x + threadIdx.x;
+      if (i >= sl.total) continue;
+      const unsigned long long* w;
+      if ((U)kk[j] == kEmpty) {
+        w = t.side;
+      } else {
+        const uint8_t* s = find_slot<K>(t, kk[j]);
+        if (!s) continue;
+        w = (const unsigned long long*)(s + 8);
+      }
+      const unsigned long long c = w[0];
+      if (c) {
+        a[0] += c;
+        a[1] += w[1];
+        a[2] += c * vv[j];
+      }
+    }
+  }
+  block_flush<3>(a, 3, acc);
 }
 
 // ---------------------------------------------------------------- host side
@@ -875,6 +931,329 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
   s.kernel_launches = launches;
   s.total_ms = now_ms() - t0;
   out->part_method_used = method;
+  return VX_OK;
+}
+
+
+// ---------------------------------------------------------------- two-table radix join
+
+namespace {
+
+uint64_t pow2_ge(uint64_t v) {
+  uint64_t c = 64;
+  while (c < v) c <<= 1;
+  return c;
+}
+
+uint64_t side_row_bytes(const Side& sd) {
+  uint64_t r = (uint64_t)sd.key.elsize;
+  for (uint32_t c = 0; c < sd.n_pay; ++c) r += (uint64_t)sd.pay[c].elsize;
+  return r;
+}
+
+uint64_t side_clustered_bytes(const Side& sd) {
+  uint64_t b = align_up(sd.n * sd.key.elsize, 256);
+  for (uint32_t c = 0; c < sd.n_pay; ++c) b += align_up(sd.n * sd.pay[c].elsize, 256);
+  return b;
+}
+
+// Point a side's clustered copy at `base` (device address): key column, then payloads.
+void place_side(Side& sd, uint8_t* base) {
+  sd.clu_key = base;
+  uint64_t off = align_up(sd.n * sd.key.elsize, 256);
+  for (uint32_t c = 0; c < sd.n_pay; ++c) {
+    sd.clu_pay[c] = base + off;
+    off += align_up(sd.n * sd.pay[c].elsize, 256);
+  }
+}
+
+// One partition: the input itself, read in place (no clustering pass).
+void whole_side(Side& sd) {
+  sd.clu_key = (uint8_t*)sd.key.dev;
+  for (uint32_t c = 0; c < sd.n_pay; ++c) sd.clu_pay[c] = (uint8_t*)sd.pay[c].dev;
+  sd.on_device = sd.key.where == Where::Device;
+  sd.chunk_rows = sd.n;
+  sd.n_chunks = 1;
+  sd.bnd = {0ull, (unsigned long long)sd.n};
+}
+
+}  // namespace
+
+vx_status join_radix(vx_ctx* ctx, const vx_radix_join* d, vx_join_out* out) {
+  const double t0 = now_ms();
+  const vx_build_desc& A = d->a;
+  const vx_probe_desc& Bd = d->b;
+  VX_CHECK(A.key.type == Bd.key.type, VX_EINVAL, "radix join: key types differ");
+  VX_CHECK(A.n_pay <= 1 && Bd.n_pay <= 1, VX_EUNSUPPORTED, "radix join: at most one payload per side");
+  VX_CHECK(A.n_pay == 0 || A.pay, VX_EINVAL, "radix join: A pay is NULL");
+  VX_CHECK(Bd.n_pay == 0 || Bd.pay, VX_EINVAL, "radix join: B pay is NULL");
+  VX_CHECK(d->n_parts == 0 || (d->n_parts <= kMaxParts && (d->n_parts & (d->n_parts - 1)) == 0), VX_EINVAL,
+           "radix join: n_parts %u is not a power of two <= %u", d->n_parts, kMaxParts);
+  VX_CHECK(d->shift < 64, VX_EINVAL, "radix join: shift %u > 63", d->shift);
+  VX_CHECK(d->hash <= 1, VX_EINVAL, "radix join: hash must be 0 or 1");
+  VX_CHECK(d->placement >= 0 && d->placement <= 2, VX_EINVAL, "radix join: placement must be 0, 1 or 2");
+  VX_HIP(hipSetDevice(ctx->device));
+  Side as, bs;
+  as.n = A.n;
+  bs.n = Bd.n;
+  VX_TRY(classify(ctx, A.key, A.n, &as.key, "radix join A key"));
+  VX_TRY(classify(ctx, Bd.key, Bd.n, &bs.key, "radix join B key"));
+  as.n_pay = A.n_pay;
+  bs.n_pay = Bd.n_pay;
+  if (A.n_pay) VX_TRY(classify(ctx, A.pay[0], A.n, &as.pay[0], "radix join A payload"));
+  if (Bd.n_pay) VX_TRY(classify(ctx, Bd.pay[0], Bd.n, &bs.pay[0], "radix join B payload"));
+  const int ks = as.key.elsize;
+  const bool k64 = A.key.type == VX_I64;
+  std::memset(&out->agg, 0, sizeof out->agg);
+  vx_stats& s = out->stats;
+  std::memset(&s, 0, sizeof s);
+  s.rows = Bd.n;
+
+  // partition count: the fewest whose expected largest table (5% over an even share, at load
+  // <= 0.8) takes at most 60% of the free arena
+  const uint64_t free0 = ctx->arena.capacity() - ctx->arena.used();
+  auto table_bytes = [](uint64_t rows) { return pow2_ge(rows + rows / 4) << kSlotShift; };
+  uint32_t P = d->n_parts;
+  if (!P) {
+    P = 1;
+    while (P < kMaxParts && (double)table_bytes((uint64_t)(1.05 * (double)A.n / P) + 64) > 0.6 * (double)free0)
+      P <<= 1;
+  }
+  uint32_t log2p = 0;
+  while ((1u << log2p) < P) ++log2p;
+  VX_CHECK(d->hash || d->shift + log2p <= 64, VX_EINVAL, "radix join: shift %u + %u bits exceeds 64", d->shift,
+           log2p);
+  PartSpec ps{};
+  ps.fn = d->hash ? kPartHash : kPartBits;
+  ps.n_parts = P;
+  ps.log2p = log2p;
+  ps.shift = d->shift;
+  const bool trace = getenv("VX_TRACE") != nullptr;
+
+  // pass 1: cluster both tables (P > 1), into the arena or pinned host scratch
+  ArenaBlock cl_mem;
+  const double tp0 = now_ms();
+  uint64_t pass1_launches = 0;
+  if (P > 1 && A.n && Bd.n) {
+    const uint64_t hA = side_clustered_bytes(as), hB = side_clustered_bytes(bs);
+    const uint64_t rb = std::max(side_row_bytes(as), side_row_bytes(bs));
+    const uint64_t exp_rows = (uint64_t)(1.05 * (double)A.n / P) + 64;
+    const uint64_t pass1_est = 4 * std::min<uint64_t>(std::max(A.n, Bd.n), 1ull << 23) * rb + (64ull << 20);
+    const bool dev = d->placement == 2 ||
+                     (d->placement == 0 && hA + hB + 512 + table_bytes(exp_rows) + pass1_est + (256ull << 20) <= free0);
+    as.on_device = bs.on_device = dev;
+    uint8_t* base = nullptr;
+    if (dev) {
+      cl_mem.a = &ctx->arena;
+      cl_mem.p = ctx->arena.alloc(hA + hB + 512);
+      VX_CHECK(cl_mem.p, VX_EBUDGET, "radix join: no room in the arena for the clustered tables (%llu B)",
+               (unsigned long long)(hA + hB));
+      base = cl_mem.p;
+    } else {
+      uint8_t* hs = nullptr;
+      VX_TRY(host_scratch(ctx, hA + hB + 512, &hs));
+      void* hd = nullptr;
+      VX_HIP(hipHostGetDevicePointer(&hd, hs, 0));
+      base = (uint8_t*)hd;
+    }
+    place_side(as, base);
+    place_side(bs, base + align_up(hA, 256));
+    for (Side* sd : {&as, &bs}) {
+      std::unique_ptr<Pipeline> pipe(new Pipeline);
+      VX_TRY(plan_pass1(ctx, *sd, 4, *pipe));
+      VX_TRY(cluster_side(ctx, ps, nullptr, *sd, *pipe));
+      pass1_launches += pipe->kernel_launches();
+    }
+  } else {
+    whole_side(as);
+    whole_side(bs);
+  }
+  const double part_ms = now_ms() - tp0;
+  std::vector<uint64_t> arows(P, 0), brows(P, 0);
+  if (P > 1 && A.n && Bd.n) {
+    for (uint64_t c = 0; c < as.n_chunks; ++c)
+      for (uint32_t p = 0; p < P; ++p) arows[p] += as.bnd[c * (P + 1) + p + 1] - as.bnd[c * (P + 1) + p];
+    for (uint64_t c = 0; c < bs.n_chunks; ++c)
+      for (uint32_t p = 0; p < P; ++p) brows[p] += bs.bnd[c * (P + 1) + p + 1] - bs.bnd[c * (P + 1) + p];
+  } else {
+    arows[0] = A.n;
+    brows[0] = Bd.n;
+  }
+
+  // pass 2 jobs: slices of A's rows of each partition that has rows on both sides
+  const double tj0 = now_ms();
+  uint64_t max_a = 0;
+  for (uint32_t p = 0; p < P; ++p)
+    if (brows[p]) max_a = std::max(max_a, arows[p]);
+  const uint64_t seg_stride = 2 * (uint64_t)(kMaxSegs + 1);
+  struct Job {
+    uint32_t p;
+    uint64_t lo, hi;
+  };
+  std::vector<Job> jobs;
+  uint64_t tcap_max = 64;
+  std::vector<unsigned long long> hseg;
+  ArenaBlock tmem, aux;
+  tmem.a = aux.a = &ctx->arena;
+  // device memory: [side record | acc (3 P) | A segment lists (P) | B segment lists (P)], then
+  // the largest table that fits (no larger than the largest partition needs)
+  const uint64_t aux_words = kSideWords + 3ull * P + 2ull * P * seg_stride + 8;
+  aux.p = ctx->arena.alloc(aux_words * 8);
+  VX_CHECK(aux.p, VX_EBUDGET, "radix join: no room for the partition segment lists");
+  unsigned long long* side = (unsigned long long*)aux.p;
+  unsigned long long* acc = side + kSideWords;
+  unsigned long long* segdev = acc + 3ull * P;
+  fill_zero((uint64_t*)aux.p, kSideWords + 3ull * P, ctx->compute);
+  if (max_a) {
+    const uint64_t need = pow2_ge(max_a + max_a / 4);
+    const uint64_t lf = ctx->arena.largest_free();
+    const uint64_t room = lf > (1u << 20) ? lf - (1u << 20) : 0;
+    while (tcap_max < need && ((tcap_max * 2) << kSlotShift) + 256 <= room) tcap_max <<= 1;
+    VX_CHECK((tcap_max << kSlotShift) + 256 <= room, VX_EBUDGET,
+             "radix join: no room for a pass-2 table of %llu slots", (unsigned long long)tcap_max);
+    // slices of at most 4/5 of the slots: a slice of r rows gets pow2_ge(r + r/4) <= tcap_max slots
+    const uint64_t slice = tcap_max / 5 * 4;
+    for (uint32_t p = 0; p < P; ++p) {
+      if (!arows[p] || !brows[p]) continue;
+      for (uint64_t lo = 0; lo < arows[p]; lo += slice) jobs.push_back({p, lo, std::min(arows[p], lo + slice)});
+    }
+  }
+  const uint64_t n_jobs = jobs.size();
+  if (n_jobs) {
+    tmem.p = ctx->arena.alloc((tcap_max << kSlotShift) + 256);
+    VX_CHECK(tmem.p, VX_EBUDGET, "radix join: no room for a pass-2 table of %llu slots",
+             (unsigned long long)tcap_max);
+  }
+  // segment lists of every partition that has a job: A's at [p], B's at [P + p]
+  std::vector<uint32_t> a_nseg(P, 0), b_nseg(P, 0);
+  if (n_jobs) {
+    hseg.assign(2ull * P * seg_stride, 0ull);
+    std::vector<unsigned long long> st, pre;
+    for (uint32_t p = 0; p < P; ++p) {
+      if (!arows[p] || !brows[p]) continue;
+      unsigned long long* h = hseg.data() + (uint64_t)p * seg_stride;
+      segments(as, P, p, st, pre);
+      a_nseg[p] = (uint32_t)st.size();
+      std::copy(st.begin(), st.end(), h);
+      std::copy(pre.begin(), pre.end(), h + (kMaxSegs + 1));
+      h = hseg.data() + (uint64_t)(P + p) * seg_stride;
+      segments(bs, P, p, st, pre);
+      b_nseg[p] = (uint32_t)st.size();
+      std::copy(st.begin(), st.end(), h);
+      std::copy(pre.begin(), pre.end(), h + (kMaxSegs + 1));
+    }
+    VX_HIP(hipMemcpyAsync(segdev, hseg.data(), hseg.size() * 8, hipMemcpyHostToDevice, ctx->compute));
+  }
+  fill_zero((uint64_t*)ctx->dev_flags, 1, ctx->compute);
+  const uint32_t psz_a = A.n_pay ? (uint32_t)as.pay[0].elsize : 8;
+  const uint32_t psz_b = Bd.n_pay ? (uint32_t)bs.pay[0].elsize : 8;
+  const uint8_t* pay_a = A.n_pay ? as.clu_pay[0] : nullptr;
+  const uint8_t* pay_b = Bd.n_pay ? bs.clu_pay[0] : nullptr;
+  uint64_t zc_bytes = 0;
+  // HIP events around each build and probe launch (on the stream they run on)
+  std::vector<hipEvent_t> ev(3 * n_jobs, nullptr);
+  for (auto& e : ev) {
+    e = get_event(ctx);
+    VX_CHECK(e, VX_EHIP, "radix join: no HIP event");
+  }
+  for (uint64_t j = 0; j < n_jobs; ++j) {
+    const Job& jb = jobs[j];
+    const uint64_t na = jb.hi - jb.lo, nbr = brows[jb.p];
+    TableView t{};
+    const uint64_t tcap = pow2_ge(na + na / 4);
+    VX_CHECK(tcap <= tcap_max, VX_EINVAL, "radix join: slice of %llu rows exceeds the table", (unsigned long long)na);
+    t.slots = tmem.p;
+    t.mask = tcap - 1;
+    while ((1ull << t.log2cap) < tcap) ++t.log2cap;
+    t.slot_shift = kSlotShift;
+    t.side = side;
+    t.n_pay = A.n_pay;
+    t.preagg = 1;
+    t.key_size = (uint32_t)ks;
+    const unsigned long long* ha = segdev + (uint64_t)jb.p * seg_stride;
+    const unsigned long long* hb = segdev + (uint64_t)(P + jb.p) * seg_stride;
+    SegList la{ha, ha + (kMaxSegs + 1), a_nseg[jb.p], na, jb.lo};
+    SegList lb{hb, hb + (kMaxSegs + 1), b_nseg[jb.p], nbr};
+    hipLaunchKernelGGL(k_pj_init, dim3(grid_for(ctx, tcap)), dim3(256), 0, ctx->compute, (uint32_t*)tmem.p, tcap,
+                       (uint32_t)ks, side);
+    const unsigned gb = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((na + kPjTile - 1) / kPjTile,
+                                                                           (uint64_t)ctx->cu_count * 3));
+    const unsigned gp = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((nbr + 1023) / 1024,
+                                                                           (uint64_t)ctx->cu_count * 4));
+    VX_HIP(hipEventRecord(ev[3 * j], ctx->compute));
+    if (k64)
+      hipLaunchKernelGGL(k_pj_build<int64_t>, dim3(gb), dim3(256), 0, ctx->compute, t, as.clu_key, pay_a, psz_a, la,
+                         ctx->dev_flags, (uint32_t*)nullptr, (unsigned long long*)nullptr);
+    else
+      hipLaunchKernelGGL(k_pj_build<int32_t>, dim3(gb), dim3(256), 0, ctx->compute, t, as.clu_key, pay_a, psz_a, la,
+                         ctx->dev_flags, (uint32_t*)nullptr, (unsigned long long*)nullptr);
+    VX_HIP(hipGetLastError());
+    VX_HIP(hipEventRecord(ev[3 * j + 1], ctx->compute));
+    if (k64)
+      hipLaunchKernelGGL(k_rj_probe<int64_t>, dim3(gp), dim3(256), 0, ctx->compute, t, bs.clu_key, pay_b, psz_b, lb,
+                         acc + 3ull * jb.p);
+    else
+      hipLaunchKernelGGL(k_rj_probe<int32_t>, dim3(gp), dim3(256), 0, ctx->compute, t, bs.clu_key, pay_b, psz_b, lb,
+                         acc + 3ull * jb.p);
+    VX_HIP(hipGetLastError());
+    VX_HIP(hipEventRecord(ev[3 * j + 2], ctx->compute));
+    if (!as.on_device && as.key.where == Where::Host) zc_bytes += na * side_row_bytes(as);
+    if (!bs.on_device && bs.key.where == Where::Host) zc_bytes += nbr * side_row_bytes(bs);
+  }
+  std::vector<unsigned long long> accs(3ull * P);
+  VX_HIP(hipMemcpyAsync(accs.data(), acc, accs.size() * 8, hipMemcpyDeviceToHost, ctx->compute));
+  VX_HIP(hipStreamSynchronize(ctx->compute));
+  double build_k_ms = 0, probe_k_ms = 0;
+  for (uint64_t j = 0; j < n_jobs; ++j) {
+    float a = 0, b = 0;
+    VX_HIP(hipEventElapsedTime(&a, ev[3 * j], ev[3 * j + 1]));
+    VX_HIP(hipEventElapsedTime(&b, ev[3 * j + 1], ev[3 * j + 2]));
+    build_k_ms += a;
+    probe_k_ms += b;
+  }
+  for (auto e : ev) put_event(ctx, e);
+  VX_TRY(check_flags(ctx, "radix join"));
+  const double join_ms = now_ms() - tj0;
+  if (trace)
+    fprintf(stderr, "[vx] radix join: %u partitions, pass 1 %.1f ms (clustered copies in %s), pass 2 %.1f ms, "
+            "%llu build slices, table %llu slots\n", P, part_ms, as.on_device ? "device memory" : "host memory",
+            join_ms, (unsigned long long)n_jobs, (unsigned long long)tcap_max);
+
+  for (uint32_t p = 0; p < P; ++p) {
+    out->agg.match_count += accs[3 * p];
+    if (A.n_pay) out->agg.sum[0] += accs[3 * p + 1];
+    if (Bd.n_pay) out->agg.sum[A.n_pay] += accs[3 * p + 2];
+  }
+  if (Bd.chunk_aggs) {
+    VX_CHECK(Bd.chunk_aggs_cap >= P, VX_ECAPACITY, "radix join: chunk_aggs_cap %llu < %u partitions",
+             (unsigned long long)Bd.chunk_aggs_cap, P);
+    for (uint32_t p = 0; p < P; ++p) {
+      vx_agg g;
+      std::memset(&g, 0, sizeof g);
+      g.match_count = accs[3 * p];
+      if (A.n_pay) g.sum[0] = accs[3 * p + 1];
+      if (Bd.n_pay) g.sum[A.n_pay] = accs[3 * p + 2];
+      Bd.chunk_aggs[p] = g;
+    }
+  }
+  double mx = 0, tot = 0;
+  for (uint32_t p = 0; p < P; ++p) {
+    mx = std::max(mx, (double)(arows[p] + brows[p]));
+    tot += (double)(arows[p] + brows[p]);
+  }
+  s.n_parts = P;
+  s.imbalance = tot > 0 ? mx / (tot / P) : 0.0;
+  s.part_ms = part_ms;
+  s.probe_ms = join_ms;
+  s.sdma_bytes = as.sdma + bs.sdma;
+  s.zc_bytes_est = zc_bytes;
+  s.table_bytes = n_jobs ? tcap_max << kSlotShift : 0;
+  s.chunks = n_jobs;
+  s.chunk_rows = as.chunk_rows;
+  s.kernel_launches = pass1_launches + 3 * n_jobs;
+  s.build_ms = build_k_ms;
+  s.kernel_ms = probe_k_ms;
+  s.total_ms = now_ms() - t0;
   return VX_OK;
 }
 
