@@ -102,3 +102,41 @@ def test_batch_full_size_closed_form(gpu):
         hit = pk < len(bk)
         exp = [int(hit.sum()), int(pay_of_key[pk[hit]].sum()) % M64]
         assert got[j] == exp, f"job {j}"
+
+
+def test_radix_join_full_size(gpu):
+    """The two-table radix join at the size bench.py times: A and B of 2^29 rows each (16 B
+    tuples, 8 GiB per table, pinned), 4 GiB budget, automatic partition count.  The whole join
+    is checked against the generator's closed form (every B row matches the one A row with its
+    key), which tests/test_oracle_radix_join.py pins to the oracle; two sampled partitions are
+    checked against the oracle itself on the rows both tables send to them."""
+    import oracle
+    n = 1 << 29
+    print("full-size radix join: allocating 32 GiB pinned", flush=True)
+    ak, av, bk, bv = (gpu.HostBuffer(n, np.int64) for _ in range(4))
+    try:
+        step = 1 << 27
+        for r0 in range(0, n, step):
+            datagen.radix_a(n, out=(ak.array[r0:r0 + step], av.array[r0:r0 + step]), row0=r0)
+            datagen.radix_b(n, step, out=(bk.array[r0:r0 + step], bv.array[r0:r0 + step]), row0=r0)
+        print("generated; running the join", flush=True)
+        with gpu.Context(4 * GiB) as ctx:
+            tot, st, per = ctx.join_radix(ak, [av], bk, [bv], per_partition=True)
+            tot2, _ = ctx.join_radix(ak, [av], bk, [bv])
+        assert tot == tot2
+        P = st["n_parts"]
+        assert P == 32 and st["chunks"] == 32
+        print("closed form", flush=True)
+        a_of_key = np.empty(n, np.uint64)
+        a_of_key[ak.array] = av.array.view(np.uint64)
+        want = [n, int(a_of_key[bk.array].sum(dtype=np.uint64)), int(bv.array.view(np.uint64).sum(dtype=np.uint64))]
+        del a_of_key
+        assert tot == want
+        assert [sum(x) % M64 for x in zip(*per)] == tot
+        for p in (0, P - 1):
+            print("oracle on partition", p, flush=True)
+            ma, mb = (ak.array & (P - 1)) == p, (bk.array & (P - 1)) == p
+            assert per[p] == oracle.join_agg(ak.array[ma], [av.array[ma]], bk.array[mb], [bv.array[mb]])
+    finally:
+        for h in (ak, av, bk, bv):
+            h.free()
