@@ -337,7 +337,7 @@ __global__ void __launch_bounds__(256) k_pj_writeback(const uint8_t* skey, const
 // their segment list, look up the partition's pre-aggregated A table.  A matching row adds A's
 // row count for its key to the pair count, A's payload sum for the key to SUM(A), and the count
 // times its own payload to SUM(B).  The three sums go to acc[0..2] (one atomic per workgroup).
-template <typename K, int ITEMS>
+template <typename K>
 __global__ void __launch_bounds__(256) k_rj_probe(TableView t, const void* key, const void* pay,
                                                   uint32_t pay_size, SegList sl, unsigned long long* acc) {
   using U = typename KeyTraits<K>::U;
@@ -347,6 +347,9 @@ __global__ void __launch_bounds__(256) k_rj_probe(TableView t, const void* key, 
   for (uint32_t j = threadIdx.x; j <= sl.nseg; j += blockDim.x) spre[j] = sl.prefix[j];
   __syncthreads();
   unsigned long long a[3] = {0, 0, 0};
+  // 4 rows per lane: 8 rows, or up to 16 workgroups per compute unit, measured the same (the
+  // host link bounds the kernel)
+  constexpr int ITEMS = 4;
   const uint64_t tile = (uint64_t)blockDim.x * ITEMS;
   for (uint64_t base = blockIdx.x * tile; base < sl.total; base += (uint64_t)gridDim.x * tile) {
     K kk[ITEMS];
@@ -1020,14 +1023,13 @@ vx_status join_radix(vx_ctx* ctx, const vx_radix_join* d, vx_join_out* out) {
   s.rows = Bd.n;
 
   // partition count: the fewest whose expected largest table (5% over an even share, at load
-  // <= 0.8) takes at most 30% of the free arena, so that two tables fit (pass 2 builds the next
-  // partition's table while the current one is probed)
+  // <= 0.8) takes at most 60% of the free arena
   const uint64_t free0 = ctx->arena.capacity() - ctx->arena.used();
   auto table_bytes = [](uint64_t rows) { return pow2_ge(rows + rows / 4) << kSlotShift; };
   uint32_t P = d->n_parts;
   if (!P) {
     P = 1;
-    while (P < kMaxParts && (double)table_bytes((uint64_t)(1.05 * (double)A.n / P) + 64) > 0.3 * (double)free0)
+    while (P < kMaxParts && (double)table_bytes((uint64_t)(1.05 * (double)A.n / P) + 64) > 0.6 * (double)free0)
       P <<= 1;
   }
   uint32_t log2p = 0;
@@ -1103,33 +1105,25 @@ vx_status join_radix(vx_ctx* ctx, const vx_radix_join* d, vx_join_out* out) {
   };
   std::vector<Job> jobs;
   uint64_t tcap_max = 64;
-  uint32_t n_tab = 1;
   std::vector<unsigned long long> hseg;
   ArenaBlock tmem, aux;
   tmem.a = aux.a = &ctx->arena;
-  // device memory: [2 side records | acc (3 P) | A segment lists (P) | B segment lists (P)],
-  // then one or two tables
-  const uint64_t aux_words = 2 * kSideWords + 3ull * P + 2ull * P * seg_stride + 8;
+  // device memory: [side record | acc (3 P) | A segment lists (P) | B segment lists (P)], then
+  // the largest table that fits (no larger than the largest partition needs)
+  const uint64_t aux_words = kSideWords + 3ull * P + 2ull * P * seg_stride + 8;
   aux.p = ctx->arena.alloc(aux_words * 8);
   VX_CHECK(aux.p, VX_EBUDGET, "radix join: no room for the partition segment lists");
-  unsigned long long* sides = (unsigned long long*)aux.p;
-  unsigned long long* acc = sides + 2 * kSideWords;
+  unsigned long long* side = (unsigned long long*)aux.p;
+  unsigned long long* acc = side + kSideWords;
   unsigned long long* segdev = acc + 3ull * P;
-  fill_zero((uint64_t*)aux.p, 2 * kSideWords + 3ull * P, ctx->compute);
+  fill_zero((uint64_t*)aux.p, kSideWords + 3ull * P, ctx->compute);
   if (max_a) {
     const uint64_t need = pow2_ge(max_a + max_a / 4);
     const uint64_t lf = ctx->arena.largest_free();
     const uint64_t room = lf > (1u << 20) ? lf - (1u << 20) : 0;
-    if (2 * ((need << kSlotShift) + 256) <= room) {
-      // two tables of the size the largest partition needs
-      tcap_max = need;
-      n_tab = 2;
-    } else {
-      // one table, as large as fits (partitions beyond it are built in slices)
-      while (tcap_max < need && ((tcap_max * 2) << kSlotShift) + 256 <= room) tcap_max <<= 1;
-      VX_CHECK((tcap_max << kSlotShift) + 256 <= room, VX_EBUDGET,
-               "radix join: no room for a pass-2 table of %llu slots", (unsigned long long)tcap_max);
-    }
+    while (tcap_max < need && ((tcap_max * 2) << kSlotShift) + 256 <= room) tcap_max <<= 1;
+    VX_CHECK((tcap_max << kSlotShift) + 256 <= room, VX_EBUDGET,
+             "radix join: no room for a pass-2 table of %llu slots", (unsigned long long)tcap_max);
     // slices of at most 4/5 of the slots: a slice of r rows gets pow2_ge(r + r/4) <= tcap_max slots
     const uint64_t slice = tcap_max / 5 * 4;
     for (uint32_t p = 0; p < P; ++p) {
@@ -1138,10 +1132,9 @@ vx_status join_radix(vx_ctx* ctx, const vx_radix_join* d, vx_join_out* out) {
     }
   }
   const uint64_t n_jobs = jobs.size();
-  const uint64_t tab_stride = (tcap_max << kSlotShift) + 256;
   if (n_jobs) {
-    tmem.p = ctx->arena.alloc(n_tab * tab_stride);
-    VX_CHECK(tmem.p, VX_EBUDGET, "radix join: no room for %u pass-2 table(s) of %llu slots", n_tab,
+    tmem.p = ctx->arena.alloc((tcap_max << kSlotShift) + 256);
+    VX_CHECK(tmem.p, VX_EBUDGET, "radix join: no room for a pass-2 table of %llu slots",
              (unsigned long long)tcap_max);
   }
   // segment lists of every partition that has a job: A's at [p], B's at [P + p]
@@ -1170,33 +1163,23 @@ vx_status join_radix(vx_ctx* ctx, const vx_radix_join* d, vx_join_out* out) {
   const uint8_t* pay_a = A.n_pay ? as.clu_pay[0] : nullptr;
   const uint8_t* pay_b = Bd.n_pay ? bs.clu_pay[0] : nullptr;
   uint64_t zc_bytes = 0;
-  // probe launch shape: 4 rows per thread, at most 4 workgroups per compute unit (8 rows per
-  // thread or up to 16 workgroups per unit measured the same: the host link bounds the kernel)
-  constexpr uint64_t items = 4, probe_wg = 4;
-  // Builds run on a second stream (the write-back stream, idle in pass 2) and probes on the
-  // compute stream.  Job j uses table j % n_tab: its build waits for the probe that last used
-  // that table, and its probe waits for its build, so with two tables the build of the next
-  // partition overlaps the probe of this one.  HIP events bracket every launch on its stream.
-  hipStream_t sb = ctx->d2h, sp = ctx->compute;
-  std::vector<hipEvent_t> ev(4 * n_jobs + 1, nullptr);
+  // HIP events around each build and probe launch (on the stream they run on)
+  std::vector<hipEvent_t> ev(3 * n_jobs, nullptr);
   for (auto& e : ev) {
     e = get_event(ctx);
     VX_CHECK(e, VX_EHIP, "radix join: no HIP event");
   }
-  VX_HIP(hipEventRecord(ev[4 * n_jobs], sp));   // side records, accumulators and segment lists set
-  VX_HIP(hipStreamWaitEvent(sb, ev[4 * n_jobs], 0));
   for (uint64_t j = 0; j < n_jobs; ++j) {
     const Job& jb = jobs[j];
-    const uint32_t b = (uint32_t)(j % n_tab);
     const uint64_t na = jb.hi - jb.lo, nbr = brows[jb.p];
     TableView t{};
     const uint64_t tcap = pow2_ge(na + na / 4);
     VX_CHECK(tcap <= tcap_max, VX_EINVAL, "radix join: slice of %llu rows exceeds the table", (unsigned long long)na);
-    t.slots = tmem.p + b * tab_stride;
+    t.slots = tmem.p;
     t.mask = tcap - 1;
     while ((1ull << t.log2cap) < tcap) ++t.log2cap;
     t.slot_shift = kSlotShift;
-    t.side = sides + b * kSideWords;
+    t.side = side;
     t.n_pay = A.n_pay;
     t.preagg = 1;
     t.key_size = (uint32_t)ks;
@@ -1204,44 +1187,40 @@ vx_status join_radix(vx_ctx* ctx, const vx_radix_join* d, vx_join_out* out) {
     const unsigned long long* hb = segdev + (uint64_t)(P + jb.p) * seg_stride;
     SegList la{ha, ha + (kMaxSegs + 1), a_nseg[jb.p], na, jb.lo};
     SegList lb{hb, hb + (kMaxSegs + 1), b_nseg[jb.p], nbr};
-    if (j >= n_tab) VX_HIP(hipStreamWaitEvent(sb, ev[4 * (j - n_tab) + 3], 0));
-    hipLaunchKernelGGL(k_pj_init, dim3(grid_for(ctx, tcap)), dim3(256), 0, sb, (uint32_t*)t.slots, tcap,
-                       (uint32_t)ks, t.side);
+    hipLaunchKernelGGL(k_pj_init, dim3(grid_for(ctx, tcap)), dim3(256), 0, ctx->compute, (uint32_t*)tmem.p, tcap,
+                       (uint32_t)ks, side);
     const unsigned gb = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((na + kPjTile - 1) / kPjTile,
                                                                            (uint64_t)ctx->cu_count * 3));
-    const unsigned gp = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((nbr + 256 * items - 1) / (256 * items),
-                                                                           (uint64_t)ctx->cu_count * probe_wg));
-    VX_HIP(hipEventRecord(ev[4 * j], sb));
+    const unsigned gp = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((nbr + 1023) / 1024,
+                                                                           (uint64_t)ctx->cu_count * 4));
+    VX_HIP(hipEventRecord(ev[3 * j], ctx->compute));
     if (k64)
-      hipLaunchKernelGGL(k_pj_build<int64_t>, dim3(gb), dim3(256), 0, sb, t, as.clu_key, pay_a, psz_a, la,
+      hipLaunchKernelGGL(k_pj_build<int64_t>, dim3(gb), dim3(256), 0, ctx->compute, t, as.clu_key, pay_a, psz_a, la,
                          ctx->dev_flags, (uint32_t*)nullptr, (unsigned long long*)nullptr);
     else
-      hipLaunchKernelGGL(k_pj_build<int32_t>, dim3(gb), dim3(256), 0, sb, t, as.clu_key, pay_a, psz_a, la,
+      hipLaunchKernelGGL(k_pj_build<int32_t>, dim3(gb), dim3(256), 0, ctx->compute, t, as.clu_key, pay_a, psz_a, la,
                          ctx->dev_flags, (uint32_t*)nullptr, (unsigned long long*)nullptr);
     VX_HIP(hipGetLastError());
-    VX_HIP(hipEventRecord(ev[4 * j + 1], sb));
-    VX_HIP(hipStreamWaitEvent(sp, ev[4 * j + 1], 0));
-    VX_HIP(hipEventRecord(ev[4 * j + 2], sp));
+    VX_HIP(hipEventRecord(ev[3 * j + 1], ctx->compute));
     if (k64)
-      hipLaunchKernelGGL((k_rj_probe<int64_t, 4>), dim3(gp), dim3(256), 0, sp, t, bs.clu_key, pay_b, psz_b, lb,
+      hipLaunchKernelGGL(k_rj_probe<int64_t>, dim3(gp), dim3(256), 0, ctx->compute, t, bs.clu_key, pay_b, psz_b, lb,
                          acc + 3ull * jb.p);
     else
-      hipLaunchKernelGGL((k_rj_probe<int32_t, 4>), dim3(gp), dim3(256), 0, sp, t, bs.clu_key, pay_b, psz_b, lb,
+      hipLaunchKernelGGL(k_rj_probe<int32_t>, dim3(gp), dim3(256), 0, ctx->compute, t, bs.clu_key, pay_b, psz_b, lb,
                          acc + 3ull * jb.p);
     VX_HIP(hipGetLastError());
-    VX_HIP(hipEventRecord(ev[4 * j + 3], sp));
+    VX_HIP(hipEventRecord(ev[3 * j + 2], ctx->compute));
     if (!as.on_device && as.key.where == Where::Host) zc_bytes += na * side_row_bytes(as);
     if (!bs.on_device && bs.key.where == Where::Host) zc_bytes += nbr * side_row_bytes(bs);
   }
   std::vector<unsigned long long> accs(3ull * P);
   VX_HIP(hipMemcpyAsync(accs.data(), acc, accs.size() * 8, hipMemcpyDeviceToHost, ctx->compute));
-  VX_HIP(hipStreamSynchronize(sp));
-  VX_HIP(hipStreamSynchronize(sb));
+  VX_HIP(hipStreamSynchronize(ctx->compute));
   double build_k_ms = 0, probe_k_ms = 0;
   for (uint64_t j = 0; j < n_jobs; ++j) {
     float a = 0, b = 0;
-    VX_HIP(hipEventElapsedTime(&a, ev[4 * j], ev[4 * j + 1]));
-    VX_HIP(hipEventElapsedTime(&b, ev[4 * j + 2], ev[4 * j + 3]));
+    VX_HIP(hipEventElapsedTime(&a, ev[3 * j], ev[3 * j + 1]));
+    VX_HIP(hipEventElapsedTime(&b, ev[3 * j + 1], ev[3 * j + 2]));
     build_k_ms += a;
     probe_k_ms += b;
   }
@@ -1250,8 +1229,8 @@ vx_status join_radix(vx_ctx* ctx, const vx_radix_join* d, vx_join_out* out) {
   const double join_ms = now_ms() - tj0;
   if (trace)
     fprintf(stderr, "[vx] radix join: %u partitions, pass 1 %.1f ms (clustered copies in %s), pass 2 %.1f ms, "
-            "%llu build slices, %u table(s) of %llu slots\n", P, part_ms, as.on_device ? "device memory" : "host memory",
-            join_ms, (unsigned long long)n_jobs, n_tab, (unsigned long long)tcap_max);
+            "%llu build slices, table %llu slots\n", P, part_ms, as.on_device ? "device memory" : "host memory",
+            join_ms, (unsigned long long)n_jobs, (unsigned long long)tcap_max);
 
   for (uint32_t p = 0; p < P; ++p) {
     out->agg.match_count += accs[3 * p];
@@ -1281,7 +1260,7 @@ vx_status join_radix(vx_ctx* ctx, const vx_radix_join* d, vx_join_out* out) {
   s.probe_ms = join_ms;
   s.sdma_bytes = as.sdma + bs.sdma;
   s.zc_bytes_est = zc_bytes;
-  s.table_bytes = n_jobs ? n_tab * (tcap_max << kSlotShift) : 0;
+  s.table_bytes = n_jobs ? tcap_max << kSlotShift : 0;
   s.chunks = n_jobs;
   s.chunk_rows = as.chunk_rows;
   s.kernel_launches = pass1_launches + 3 * n_jobs;

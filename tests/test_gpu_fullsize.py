@@ -125,7 +125,7 @@ def test_radix_join_full_size(gpu):
             tot2, _ = ctx.join_radix(ak, [av], bk, [bv])
         assert tot == tot2
         P = st["n_parts"]
-        assert P == 32 and st["chunks"] == 32
+        assert P == 16 and st["chunks"] == 16
         print("closed form", flush=True)
         a_of_key = np.empty(n, np.uint64)
         a_of_key[ak.array] = av.array.view(np.uint64)
