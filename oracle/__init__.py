@@ -86,6 +86,8 @@ def _load():
     lib.or_splitters_from_cdf.restype = C.c_uint32
     lib.or_sample_bernoulli.argtypes = [_Col, C.c_uint64, C.c_uint64, C.c_double, C.POINTER(C.c_int64)]
     lib.or_sample_bernoulli.restype = C.c_uint64
+    lib.or_sort.argtypes = [_Col, C.c_uint64, C.POINTER(C.c_int64)]
+    lib.or_merge_cuts.argtypes = [C.POINTER(C.POINTER(C.c_int64)), u64p, C.c_uint32, C.c_uint64, u64p]
     _lib = lib
     return lib
 
@@ -301,3 +303,21 @@ def feature_scale(kmin, kmax):
     r = min((int(kmax) - int(kmin)), (1 << 63) - 1)
     L = (r + 1).bit_length()
     return np.float32(1.0 / (L * 8388608.0))
+
+
+def sort(keys):
+    """The keys in ascending signed order, as int64."""
+    out = np.zeros(len(keys), np.int64)
+    _load().or_sort(_col(keys), len(keys), _ptr(out, C.c_int64))
+    return out
+
+
+def merge_cuts(runs, rank):
+    """Per-run cut of sorted int64 runs at a global rank: the rank smallest elements of their
+    union, ties from lower-numbered runs first."""
+    runs = [np.ascontiguousarray(r, np.int64) for r in runs]
+    ptrs = (C.POINTER(C.c_int64) * max(1, len(runs)))(*[_ptr(r, C.c_int64) for r in runs])
+    lens = np.array([len(r) for r in runs] or [0], np.uint64)
+    cut = np.zeros(max(1, len(runs)), np.uint64)
+    _load().or_merge_cuts(ptrs, _ptr(lens, C.c_uint64), len(runs), int(rank), _ptr(cut, C.c_uint64))
+    return cut[:len(runs)]

@@ -27,6 +27,7 @@
 #include <unordered_map>
 #include <map>
 #include <utility>
+#include <tuple>
 
 extern "C" {
 
@@ -499,6 +500,35 @@ uint32_t or_splitters_from_cdf(const int64_t* sorted, const double* y, uint64_t 
   }
   for (size_t i = 0; i < s.size(); ++i) out[i] = s[i];
   return (uint32_t)s.size();
+}
+
+/* ---------------------------------------------------------------- out-of-core sort (Sec. 6.1)
+ *
+ * The external sort's result has a plain definition: the input keys in
+ * ascending signed order.  or_sort writes that order with the C++ library
+ * sort.  Pinned by tests against numpy's sort and by the permutation and
+ * order invariants on random, duplicate-heavy, extreme and empty inputs.
+ */
+void or_sort(or_col keys, uint64_t n, int64_t* out) {
+  for (uint64_t i = 0; i < n; ++i) out[i] = at(keys, i);
+  std::sort(out, out + n);
+}
+
+/* The regroup step of the merge phase (Sec. 6.1.3): sorted runs are cut at a
+ * global rank r so that the r smallest elements of their union (ties taken
+ * from the lower-numbered run first, and in run order within a run) lie in
+ * front of the cuts.  Written as that definition: every element becomes
+ * (value, run, position), the triples are sorted, and the first r are counted
+ * per run.  Pinned by tests of its invariants (cut sums, order across the cut,
+ * tie order) on small runs. */
+void or_merge_cuts(const int64_t* const* runs, const uint64_t* len, uint32_t n_runs, uint64_t r,
+                   uint64_t* cut) {
+  std::vector<std::tuple<int64_t, uint32_t, uint64_t>> all;
+  for (uint32_t j = 0; j < n_runs; ++j)
+    for (uint64_t i = 0; i < len[j]; ++i) all.emplace_back(runs[j][i], j, i);
+  std::sort(all.begin(), all.end());
+  for (uint32_t j = 0; j < n_runs; ++j) cut[j] = 0;
+  for (uint64_t k = 0; k < r && k < all.size(); ++k) ++cut[std::get<1>(all[k])];
 }
 
 }  // extern "C"
