@@ -67,6 +67,13 @@ def u64(seed, col, row):
     return int(_load().dg_u64(seed, col, row))
 
 
+def fill_u64(out, seed, col, row0=0):
+    """out[i] = the 64-bit SplitMix output for row row0 + i (an int64 view: uniform over all values)."""
+    _chk(out, (np.int64,))
+    _load().dg_fill_u64(seed, col, row0, len(out), _p(out))
+    return out
+
+
 def fill_uniform(out, seed, col, lo, hi, row0=0):
     """out[i] = uniform integer in [lo, hi) for row row0 + i."""
     _chk(out, (np.int32, np.int64))
@@ -118,6 +125,7 @@ def loguniform(seed, col, cnt, lo, hi):
 
 SEED_PLAIN, SEED_STREAM, SEED_STAR, SEED_BATCH, SEED_SKEW = 0xC1, 0xC2, 0xC3, 0xC4, 0xC5
 SEED_RADIX = 0xC6
+SEED_SORT = 0xC7
 
 # column ids
 COL_BKEY, COL_BPAY0, COL_BPAY1, COL_PKEY, COL_PPAY0 = 1, 2, 3, 4, 5
@@ -243,3 +251,10 @@ def radix_b(n_a, n_b, seed=SEED_RADIX, out=None, row0=0):
     fill_uniform(k, seed, COL_PKEY, 0, n_a, row0=row0)
     fill_uniform(v, seed, COL_PPAY0, 0, 1 << 32, row0=row0)
     return out
+
+
+def sort_keys(n, seed=SEED_SORT, out=None, row0=0):
+    """Out-of-core sort input: int64 keys uniform over all 2^64 values."""
+    if out is None:
+        out = np.empty(n, np.int64)
+    return fill_u64(out, seed, COL_BKEY, row0=row0)

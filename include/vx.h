@@ -434,6 +434,47 @@ typedef struct {
  */
 vx_status vx_partition(vx_ctx* ctx, const vx_partition_desc* desc, vx_partition_out* out);
 
+/* ------------------------------------------------------------------------ out-of-core sort */
+
+typedef struct {
+  vx_col key;                  /* pinned host or device; sorted in place */
+  uint64_t n;
+  uint64_t chunk_rows;         /* pass-1 run length; 0 = the largest power of two whose buffers fit */
+  uint32_t n_buffers;          /* pass-1 pipeline buffers; 0 = 2 */
+  uint32_t reserved;
+} vx_sort_desc;
+
+/*
+ * Out-of-core sort (Sec. 6.1): the n keys (int32 or int64) in ascending signed order, written
+ * back in place.
+ * Pass 1 (the paper's SortExKernel) streams runs of chunk_rows keys through the chunk pipeline.
+ * Each run is sorted on the GPU by an LSD radix sort (stable multisplit passes of 8 bits) and
+ * stored to the context's pinned host scratch by a kernel on a second stream.
+ * Pass 2 (the paper's MergeExKernel) cuts every run at the ranks 0, chunk_rows, 2 chunk_rows, ...
+ * (vx_merge_cuts).  For each output range it copies the runs' segments in, merges them in a
+ * tree of merge-path kernels, and stores the result to its place in the key column.  One run is
+ * stored in place directly.
+ * Needs about 5 runs of device memory for pass 1 and 4 for pass 2, plus n keys of pinned host
+ * scratch when there are several runs.
+ * stats (nullable): rows = n, chunks = runs, chunk_rows, n_buffers, part_ms (pass 1), probe_ms
+ * (pass 2), kernel_ms (pass-1 sort kernels) and build_ms (pass-2 merge kernels), both summed from
+ * HIP events; sdma_bytes (host-to-device copies), kernel_launches, total_ms.
+ * Errors: VX_EINVAL (bad column type; NULL column with n > 0); VX_ENOTPINNED; VX_EBUDGET when a
+ * run's buffers do not fit the arena; VX_ENOMEM when pinned host scratch cannot be had.
+ */
+vx_status vx_sort(vx_ctx* ctx, const vx_sort_desc* desc, vx_stats* stats);
+
+/*
+ * The regroup step of the sort's merge phase (Sec. 6.1.3), for callers that merge sorted runs
+ * themselves.  runs[j] holds run_len[j] int64 keys in ascending order (host memory).  cut[j]
+ * receives how many of run j's keys are among the `rank` smallest keys of all runs, with equal
+ * keys taken from lower-numbered runs first.  So cut sums to rank, and every key in front of a
+ * cut is <= every key behind one.  Host work only (binary searches).
+ * Errors: VX_EINVAL for NULL arrays or rank above the total length.
+ */
+vx_status vx_merge_cuts(const int64_t* const* runs, const uint64_t* run_len, uint32_t n_runs, uint64_t rank,
+                        uint64_t* cut);
+
 /* ------------------------------------------------------------------------ CDF model kernels */
 
 /*

@@ -120,6 +120,11 @@ class PartOpts(C.Structure):
                 ("reserved", C.c_uint32)]
 
 
+class SortDesc(C.Structure):
+    _fields_ = [("key", Col), ("n", C.c_uint64), ("chunk_rows", C.c_uint64), ("n_buffers", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
 class PartitionedJoin(C.Structure):
     _fields_ = [("build", BuildDesc), ("probe", ProbeDesc), ("part", PartOpts)]
 
@@ -164,7 +169,7 @@ class PartitionOut(C.Structure):
 EXPORTS = ["vx_ctx_create", "vx_ctx_destroy", "vx_last_error", "vx_ctx_arena_used", "vx_host_alloc",
            "vx_host_free", "vx_build", "vx_table_destroy", "vx_probe_stream", "vx_join_agg",
            "vx_partition", "vx_cdf_loss_grad", "vx_cdf_forward", "vx_cdf_train", "vx_calibrate",
-           "vx_probe_rows"]
+           "vx_probe_rows", "vx_sort", "vx_merge_cuts"]
 N_MODEL_PARAMS = 193
 
 
@@ -195,9 +200,13 @@ def lib():
     L.vx_cdf_forward.argtypes = [vp, vp, C.c_uint64, fp, fp]
     L.vx_cdf_train.argtypes = [vp, vp, vp, C.c_uint64, fp, C.c_uint32, C.c_float, C.POINTER(C.c_double)]
     L.vx_calibrate.argtypes = [vp, vp, C.c_uint64, C.POINTER(LinkCalib)]
+    L.vx_sort.argtypes = [vp, C.POINTER(SortDesc), C.POINTER(Stats)]
+    L.vx_merge_cuts.argtypes = [C.POINTER(C.POINTER(C.c_int64)), C.POINTER(C.c_uint64), C.c_uint32, C.c_uint64,
+                                C.POINTER(C.c_uint64)]
     for name in ("vx_ctx_create", "vx_ctx_destroy", "vx_host_alloc", "vx_host_free", "vx_build",
                  "vx_table_destroy", "vx_probe_stream", "vx_join_agg", "vx_partition",
-                 "vx_cdf_loss_grad", "vx_cdf_forward", "vx_cdf_train", "vx_calibrate"):
+                 "vx_cdf_loss_grad", "vx_cdf_forward", "vx_cdf_train", "vx_calibrate", "vx_sort",
+                 "vx_merge_cuts", "vx_probe_rows"):
         getattr(L, name).restype = st
     _lib = L
     return L
@@ -445,6 +454,13 @@ class Context:
             return res + ([pa[i].to_list(nap + nbp) for i in range(P)],)
         return res
 
+    def sort(self, key, chunk_rows=0, n_buffers=0):
+        """Out-of-core sort of a key column in place.  Returns the stats dict."""
+        d = SortDesc(col(key), _len(key), int(chunk_rows), int(n_buffers), 0)
+        st = Stats()
+        _check(lib().vx_sort(self.h, C.byref(d), C.byref(st)))
+        return st.as_dict()
+
     def join_batch(self, bkeys, bpays, pkeys, mode=0, tile_rows=0, block=0, load_factor=0.0):
         """Batched joins (device-resident). bpays entries may be None. Returns
         ([[count, sum] per job], stats)."""
@@ -582,3 +598,13 @@ class Table:
             self.destroy()
         except Exception:
             pass
+
+
+def merge_cuts(runs, rank):
+    """vx_merge_cuts over sorted int64 numpy runs: the per-run cut at a global rank."""
+    runs = [np.ascontiguousarray(r, np.int64) for r in runs]
+    ptrs = (C.POINTER(C.c_int64) * max(1, len(runs)))(*[r.ctypes.data_as(C.POINTER(C.c_int64)) for r in runs])
+    lens = (C.c_uint64 * max(1, len(runs)))(*[len(r) for r in runs])
+    cut = (C.c_uint64 * max(1, len(runs)))()
+    _check(lib().vx_merge_cuts(ptrs, lens, len(runs), int(rank), cut))
+    return np.array([cut[i] for i in range(len(runs))], np.uint64)

@@ -1,0 +1,446 @@
+// Out-of-core sort of a key column larger than the device budget (Sec. 6.1).
+//
+// Pass 1 (the paper's SortExKernel): the column streams through the chunk pipeline in runs of
+// chunk_rows keys.  Each run is sorted on the GPU by an LSD radix sort whose digit passes are the
+// library's stable multisplit (8 bits per pass, the sign bit flipped so that signed order comes
+// out), and is stored to pinned host scratch by a kernel on a second stream: kernel stores to
+// mapped host memory run beside the host-to-device copies.
+// Pass 2 (the paper's MergeExKernel): every run is cut at the same global ranks (multiples of the
+// run length), found by binary search over the runs on the host.  Output range i then holds one
+// sorted segment of every run.  Its segments are copied in, merged in a tree of pairwise
+// merge-path launches (two device buffers used in turn), and the result is stored to its final
+// place in the key column.  Output range i + 1 copies in while range i merges and is stored.
+#include <algorithm>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#include "vx_part.h"
+#include "vx_pipeline.h"
+
+namespace vx {
+
+namespace {
+
+constexpr int kMergeThreads = 256;
+constexpr int kMergeItems = 8;
+constexpr int kMergeTile = kMergeThreads * kMergeItems;   // outputs per workgroup tile
+
+// Number of the first d outputs of merge(a, b) that come from a (ties: a first).
+template <typename K>
+__device__ __forceinline__ uint64_t merge_split(const K* a, uint64_t na, const K* b, uint64_t nb, uint64_t d) {
+  uint64_t lo = d > nb ? d - nb : 0, hi = d < na ? d : na;
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi) >> 1;
+    if (a[mid] <= b[d - 1 - mid]) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// out[0, na + nb) = the stable merge of sorted a and b.  A workgroup takes a tile of 2048
+// outputs: two lanes find where the tile starts and ends on the merge path, the workgroup
+// stages the tile's inputs in LDS with coalesced loads, every lane merges 8 outputs from LDS
+// (its own start found by a binary search in LDS) into an LDS output tile, and the tile is
+// stored with coalesced writes.
+template <typename K>
+__global__ void __launch_bounds__(kMergeThreads) k_merge(const K* a, uint64_t na, const K* b, uint64_t nb,
+                                                         K* out) {
+  __shared__ K sa[kMergeTile], sb[kMergeTile], so[kMergeTile];
+  __shared__ uint64_t split[2];
+  const uint64_t n = na + nb;
+  for (uint64_t d0 = (uint64_t)blockIdx.x * kMergeTile; d0 < n; d0 += (uint64_t)gridDim.x * kMergeTile) {
+    const uint64_t d1 = d0 + kMergeTile < n ? d0 + kMergeTile : n;
+    if (threadIdx.x < 2) split[threadIdx.x] = merge_split(a, na, b, nb, threadIdx.x ? d1 : d0);
+    __syncthreads();
+    const uint64_t ia = split[0], ib = d0 - split[0];
+    const uint32_t ma = (uint32_t)(split[1] - split[0]), mb = (uint32_t)((d1 - split[1]) - ib);
+    for (uint32_t k = threadIdx.x; k < ma; k += kMergeThreads) sa[k] = a[ia + k];
+    for (uint32_t k = threadIdx.x; k < mb; k += kMergeThreads) sb[k] = b[ib + k];
+    __syncthreads();
+    const uint32_t m = ma + mb, t0 = threadIdx.x * kMergeItems;
+    if (t0 < m) {
+      uint32_t lo = t0 > mb ? t0 - mb : 0, hi = t0 < ma ? t0 : ma;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (sa[mid] <= sb[t0 - 1 - mid]) lo = mid + 1;
+        else hi = mid;
+      }
+      uint32_t i = lo, j = t0 - lo;
+      const uint32_t e1 = t0 + kMergeItems < m ? t0 + kMergeItems : m;
+      for (uint32_t e = t0; e < e1; ++e) {
+        const bool take_a = j >= mb || (i < ma && sa[i] <= sb[j]);
+        so[e] = take_a ? sa[i++] : sb[j++];
+      }
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < m; k += kMergeThreads) out[d0 + k] = so[k];
+    __syncthreads();
+  }
+}
+
+// dst[0, n) = src[0, n) with plain vector stores (dst may be mapped host memory).
+template <typename K>
+__global__ void __launch_bounds__(256) k_store(const K* src, K* dst, uint64_t n) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+unsigned grid_of(const vx_ctx* ctx, uint64_t items, uint64_t per_block, uint64_t per_cu) {
+  return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((items + per_block - 1) / per_block,
+                                                            (uint64_t)ctx->cu_count * per_cu));
+}
+
+// The order-preserving map of a signed key to an unsigned one.
+inline uint64_t ord(int64_t v) { return (uint64_t)v ^ 0x8000000000000000ull; }
+inline int64_t unord(uint64_t u) { return (int64_t)(u ^ 0x8000000000000000ull); }
+
+// Per-run cut at global rank r: the r smallest elements of the union of the sorted runs, ties
+// taken from lower-numbered runs first.  Finds the smallest value v with at least r elements
+// <= v (binary search over the value range, each step a binary search in every run), takes
+// every element below v, then the elements equal to v run by run.
+template <typename K>
+void merge_cuts_t(const K* const* runs, const uint64_t* len, uint32_t n_runs, uint64_t r, uint64_t* cut) {
+  uint64_t total = 0;
+  for (uint32_t j = 0; j < n_runs; ++j) total += len[j];
+  if (r == 0 || r >= total) {
+    for (uint32_t j = 0; j < n_runs; ++j) cut[j] = r == 0 ? 0 : len[j];
+    return;
+  }
+  uint64_t lo = ~0ull, hi = 0;
+  for (uint32_t j = 0; j < n_runs; ++j)
+    if (len[j]) {
+      lo = std::min(lo, ord((int64_t)runs[j][0]));
+      hi = std::max(hi, ord((int64_t)runs[j][len[j] - 1]));
+    }
+  auto count_le = [&](uint64_t u) {
+    const int64_t v = unord(u);
+    uint64_t c = 0;
+    for (uint32_t j = 0; j < n_runs; ++j)
+      c += (uint64_t)(std::upper_bound(runs[j], runs[j] + len[j], v,
+                                       [](int64_t x, const K& y) { return x < (int64_t)y; }) - runs[j]);
+    return c;
+  };
+  while (lo < hi) {
+    const uint64_t mid = lo + (hi - lo) / 2;
+    if (count_le(mid) >= r) hi = mid;
+    else lo = mid + 1;
+  }
+  const int64_t v = unord(lo);
+  uint64_t need = r;
+  std::vector<uint64_t> eq(n_runs);
+  for (uint32_t j = 0; j < n_runs; ++j) {
+    const K* b = runs[j];
+    const K* e = runs[j] + len[j];
+    const K* l = std::lower_bound(b, e, v, [](const K& x, int64_t y) { return (int64_t)x < y; });
+    const K* u = std::upper_bound(b, e, v, [](int64_t x, const K& y) { return x < (int64_t)y; });
+    cut[j] = (uint64_t)(l - b);
+    eq[j] = (uint64_t)(u - l);
+    need -= cut[j];
+  }
+  for (uint32_t j = 0; j < n_runs && need; ++j) {
+    const uint64_t t = std::min(need, eq[j]);
+    cut[j] += t;
+    need -= t;
+  }
+}
+
+// LSD radix sort of rows keys from src (left unchanged) into dst, through alt: multisplit passes
+// of 8 bits over the key's bits (int64: 8 passes; int32: the 4 low bytes, then the sign, from
+// the sign-extended value), each stable.  Passes alternate between dst and alt so the last one
+// writes dst.
+vx_status radix_sort_run(vx_ctx* ctx, const void* src, void* alt, void* dst, uint64_t rows, uint32_t ks,
+                         uint32_t* hist, unsigned long long* offs, hipStream_t s) {
+  static const uint32_t kShift64[] = {0, 8, 16, 24, 32, 40, 48, 56};
+  static const uint32_t kShift32[] = {0, 8, 16, 24, 56};
+  const uint32_t* shifts = ks == 8 ? kShift64 : kShift32;
+  const uint32_t passes = ks == 8 ? 8 : 5;
+  const PartGeom g = part_geom(ctx, rows);
+  const void* in = src;
+  for (uint32_t p = 0; p < passes; ++p) {
+    void* out = ((passes - 1 - p) % 2 == 0) ? dst : alt;
+    PartSpec ps{};
+    ps.fn = kPartBits;
+    ps.n_parts = 256;
+    ps.log2p = 8;
+    ps.shift = shifts[p];
+    ps.flip_sign = 1;
+    PartIO io{};
+    io.key = in;
+    io.key_size = ks;
+    io.n = rows;
+    io.out_key = out;
+    VX_TRY(part_hist(ctx, ps, io, g, hist, nullptr, nullptr, nullptr, s));
+    VX_TRY(part_scan(ctx, hist, 256, g.waves, nullptr, offs, nullptr, s));
+    VX_TRY(part_scatter(ctx, ps, io, g, offs, s));
+    in = out;
+  }
+  return VX_OK;
+}
+
+uint64_t align_to(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+
+vx_status sort_impl(vx_ctx* ctx, const vx_sort_desc* d, vx_stats* stats) {
+  const double t0 = now_ms();
+  VX_HIP(hipSetDevice(ctx->device));
+  ColInfo kc;
+  VX_TRY(classify(ctx, d->key, d->n, &kc, "sort key"));
+  const uint64_t n = d->n;
+  const uint32_t ks = (uint32_t)kc.elsize;
+  vx_stats st;
+  std::memset(&st, 0, sizeof st);
+  st.rows = n;
+  if (n < 2) {
+    if (stats) *stats = st;
+    return VX_OK;
+  }
+  // run length: the largest power of two whose pass-1 buffers (2 pipeline buffers, one radix
+  // buffer, two staging runs) and digit histograms fit the free arena; pass 2 needs 4 runs' room
+  const uint64_t free0 = ctx->arena.capacity() - ctx->arena.used();
+  auto pass1_bytes = [&](uint64_t rows) {
+    return 5 * align_to(rows * ks, 256) + (uint64_t)256 * part_geom(ctx, rows).waves * 12 + (1ull << 20);
+  };
+  uint64_t C = d->chunk_rows;
+  if (!C) {
+    C = 1024;
+    while (C * 2 <= n && pass1_bytes(C * 2) <= free0) C *= 2;
+    if (C < n && pass1_bytes(n) <= free0) C = n;
+    if (C > n) C = n;
+  }
+  VX_CHECK(C >= 1, VX_EINVAL, "sort: chunk_rows is 0");
+  const uint64_t runs = (n + C - 1) / C;
+  const PartGeom gmax = part_geom(ctx, std::min(C, n));
+  const uint64_t run_bytes = align_to(std::min(C, n) * ks, 256);
+  // host scratch for the sorted runs (several runs only)
+  uint8_t* hs = nullptr;
+  if (runs > 1) VX_TRY(host_scratch(ctx, n * ks + 256, &hs));
+  void* hs_dev = nullptr;
+  if (hs) VX_HIP(hipHostGetDevicePointer(&hs_dev, hs, 0));
+  uint8_t* out_dev = (uint8_t*)kc.dev;   // the key column as a device address (sorted in place)
+
+  // ---------------- pass 1: sorted runs
+  const double tp0 = now_ms();
+  double sort_k_ms = 0;
+  uint64_t launches = 0, sdma = 0;
+  uint32_t nbuf_used = 0;
+  {
+    ArenaBlock blk;
+    blk.a = &ctx->arena;
+    const uint64_t hist_bytes = align_to((uint64_t)256 * gmax.waves * 4, 256);
+    blk.p = ctx->arena.alloc(3 * run_bytes + hist_bytes + (uint64_t)256 * gmax.waves * 8 + 256);
+    VX_CHECK(blk.p, VX_EBUDGET, "sort: no room for runs of %llu keys (radix and staging buffers)",
+             (unsigned long long)C);
+    uint8_t* alt = blk.p;
+    uint8_t* stage[2] = {blk.p + run_bytes, blk.p + 2 * run_bytes};
+    uint32_t* hist = (uint32_t*)(blk.p + 3 * run_bytes);
+    unsigned long long* offs = (unsigned long long*)(blk.p + 3 * run_bytes + hist_bytes);
+    std::vector<PipeCol> cols(1);
+    cols[0].info = kc;
+    cols[0].may_copy = cols[0].copy = true;
+    Pipeline pipe;
+    VX_TRY(pipe.plan(ctx, n, C, d->n_buffers, cols));
+    nbuf_used = pipe.n_buffers();
+    hipEvent_t sorted_ev[2] = {get_event(ctx), get_event(ctx)}, wrote[2] = {get_event(ctx), get_event(ctx)};
+    std::vector<hipEvent_t> kev;
+    bool pending[2] = {false, false};
+    auto kernel = [&](const ChunkView& v) -> vx_status {
+      const uint32_t b = (uint32_t)(v.index % 2);
+      if (pending[b]) VX_HIP(hipStreamWaitEvent(ctx->compute, wrote[b], 0));
+      const uint8_t* src = (v.global_mask & 1u) ? (const uint8_t*)v.ptr[0] + v.row0 * ks : (const uint8_t*)v.ptr[0];
+      hipEvent_t e0 = get_event(ctx), e1 = get_event(ctx);
+      VX_CHECK(e0 && e1, VX_EHIP, "sort: no HIP event");
+      kev.push_back(e0);
+      kev.push_back(e1);
+      VX_HIP(hipEventRecord(e0, ctx->compute));
+      VX_TRY(radix_sort_run(ctx, src, alt, stage[b], v.rows, ks, hist, offs, ctx->compute));
+      VX_HIP(hipEventRecord(e1, ctx->compute));
+      launches += ks == 8 ? 40 : 25;   // per digit pass: histogram, three scan launches, scatter
+      VX_HIP(hipEventRecord(sorted_ev[b], ctx->compute));
+      // a single run is the result: store it in place; otherwise to its rows of the scratch
+      uint8_t* dst = (runs > 1 ? (uint8_t*)hs_dev : out_dev) + v.row0 * ks;
+      VX_HIP(hipStreamWaitEvent(ctx->d2h, sorted_ev[b], 0));
+      if (ks == 8)
+        hipLaunchKernelGGL(k_store<long long>, dim3(grid_of(ctx, v.rows, 256, 8)), dim3(256), 0, ctx->d2h,
+                           (const long long*)stage[b], (long long*)dst, v.rows);
+      else
+        hipLaunchKernelGGL(k_store<int>, dim3(grid_of(ctx, v.rows, 256, 8)), dim3(256), 0, ctx->d2h,
+                           (const int*)stage[b], (int*)dst, v.rows);
+      VX_HIP(hipGetLastError());
+      ++launches;
+      VX_HIP(hipEventRecord(wrote[b], ctx->d2h));
+      pending[b] = true;
+      return VX_OK;
+    };
+    vx_status rs = pipe.run(kernel);
+    (void)hipStreamSynchronize(ctx->compute);
+    (void)hipStreamSynchronize(ctx->d2h);
+    for (size_t i = 0; i + 1 < kev.size(); i += 2) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, kev[i], kev[i + 1]) == hipSuccess) sort_k_ms += ms;
+    }
+    for (auto e : kev) put_event(ctx, e);
+    for (int b = 0; b < 2; ++b) {
+      put_event(ctx, sorted_ev[b]);
+      put_event(ctx, wrote[b]);
+    }
+    VX_TRY(rs);
+    sdma = pipe.sdma_bytes();
+  }
+  const double pass1_ms = now_ms() - tp0;
+
+  // ---------------- pass 2: regroup and merge
+  const double tm0 = now_ms();
+  double merge_k_ms = 0;
+  uint64_t max_part = 0;
+  if (runs > 1) {
+    // cuts of every run at ranks 0, C, 2C, ..., n (host binary search over the pinned runs)
+    const uint64_t M = runs;
+    std::vector<uint64_t> rank(M + 1), len(runs);
+    for (uint64_t i = 0; i <= M; ++i) rank[i] = std::min(i * C, n);
+    for (uint64_t j = 0; j < runs; ++j) len[j] = std::min(C, n - j * C);
+    std::vector<uint64_t> cuts((M + 1) * runs);
+    {
+      const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+      std::vector<std::thread> th;
+      for (unsigned t = 0; t < nt; ++t)
+        th.emplace_back([&, t]() {
+          if (ks == 8) {
+            std::vector<const long long*> rp(runs);
+            for (uint64_t j = 0; j < runs; ++j) rp[j] = (const long long*)hs + j * C;
+            for (uint64_t i = t; i <= M; i += nt)
+              merge_cuts_t<long long>(rp.data(), len.data(), (uint32_t)runs, rank[i], &cuts[i * runs]);
+          } else {
+            std::vector<const int*> rp(runs);
+            for (uint64_t j = 0; j < runs; ++j) rp[j] = (const int*)hs + j * C;
+            for (uint64_t i = t; i <= M; i += nt)
+              merge_cuts_t<int>(rp.data(), len.data(), (uint32_t)runs, rank[i], &cuts[i * runs]);
+          }
+        });
+      for (auto& x : th) x.join();
+    }
+    for (uint64_t i = 0; i < M; ++i) max_part = std::max(max_part, rank[i + 1] - rank[i]);
+    // two sets of (input, alternate) buffers: range i + 1 copies in while range i merges
+    const uint64_t pbytes = align_to(max_part * ks, 256);
+    ArenaBlock blk;
+    blk.a = &ctx->arena;
+    blk.p = ctx->arena.alloc(4 * pbytes);
+    VX_CHECK(blk.p, VX_EBUDGET, "sort: no room for the merge buffers (4 x %llu B)", (unsigned long long)pbytes);
+    uint8_t* X[2] = {blk.p, blk.p + pbytes};
+    uint8_t* Y[2] = {blk.p + 2 * pbytes, blk.p + 3 * pbytes};
+    hipEvent_t copied[2] = {get_event(ctx), get_event(ctx)}, merged[2] = {get_event(ctx), get_event(ctx)},
+               stored[2] = {get_event(ctx), get_event(ctx)};
+    std::vector<hipEvent_t> kev;
+    vx_status rs = VX_OK;
+    for (uint64_t i = 0; i < M && rs == VX_OK; ++i) {
+      const uint32_t b = (uint32_t)(i % 2);
+      if (i >= 2) VX_HIP(hipEventSynchronize(stored[b]));   // range i - 2 has left these buffers
+      // copy in the range's segment of every run, back to back
+      std::vector<uint64_t> off(runs + 1, 0);
+      for (uint64_t j = 0; j < runs; ++j) {
+        const uint64_t a = cuts[i * runs + j], e = cuts[(i + 1) * runs + j];
+        off[j + 1] = off[j] + (e - a);
+        if (e > a) {
+          VX_HIP(hipMemcpyAsync(X[b] + off[j] * ks, hs + (j * C + a) * ks, (e - a) * ks, hipMemcpyHostToDevice,
+                                ctx->copy));
+          sdma += (e - a) * ks;
+        }
+      }
+      VX_HIP(hipEventRecord(copied[b], ctx->copy));
+      VX_HIP(hipStreamWaitEvent(ctx->compute, copied[b], 0));
+      // merge rounds: pairs of neighbouring segments, X and Y in turn
+      std::vector<uint64_t> seg;
+      for (uint64_t j = 0; j <= runs; ++j)
+        if (j == 0 || j == runs || off[j] != off[j - 1]) seg.push_back(off[j]);
+      uint8_t* src = X[b];
+      uint8_t* dst = Y[b];
+      hipEvent_t e0 = get_event(ctx), e1 = get_event(ctx);
+      VX_CHECK(e0 && e1, VX_EHIP, "sort: no HIP event");
+      kev.push_back(e0);
+      kev.push_back(e1);
+      VX_HIP(hipEventRecord(e0, ctx->compute));
+      while (seg.size() > 2) {
+        std::vector<uint64_t> next;
+        for (size_t k = 0; k + 1 < seg.size(); k += 2) {
+          const uint64_t a0 = seg[k], a1 = seg[k + 1], b1 = k + 2 < seg.size() ? seg[k + 2] : a1;
+          const unsigned g = grid_of(ctx, b1 - a0, kMergeTile, 4);
+          if (ks == 8)
+            hipLaunchKernelGGL(k_merge<long long>, dim3(g), dim3(kMergeThreads), 0, ctx->compute,
+                               (const long long*)src + a0, a1 - a0, (const long long*)src + a1, b1 - a1,
+                               (long long*)dst + a0);
+          else
+            hipLaunchKernelGGL(k_merge<int>, dim3(g), dim3(kMergeThreads), 0, ctx->compute, (const int*)src + a0,
+                               a1 - a0, (const int*)src + a1, b1 - a1, (int*)dst + a0);
+          VX_HIP(hipGetLastError());
+          ++launches;
+          next.push_back(a0);
+        }
+        next.push_back(seg.back());
+        seg.swap(next);
+        std::swap(src, dst);
+      }
+      VX_HIP(hipEventRecord(e1, ctx->compute));
+      VX_HIP(hipEventRecord(merged[b], ctx->compute));
+      // store the merged range to its place in the key column
+      VX_HIP(hipStreamWaitEvent(ctx->d2h, merged[b], 0));
+      const uint64_t rows = rank[i + 1] - rank[i];
+      if (ks == 8)
+        hipLaunchKernelGGL(k_store<long long>, dim3(grid_of(ctx, rows, 256, 8)), dim3(256), 0, ctx->d2h,
+                           (const long long*)src, (long long*)out_dev + rank[i], rows);
+      else
+        hipLaunchKernelGGL(k_store<int>, dim3(grid_of(ctx, rows, 256, 8)), dim3(256), 0, ctx->d2h, (const int*)src,
+                           (int*)out_dev + rank[i], rows);
+      VX_HIP(hipGetLastError());
+      ++launches;
+      VX_HIP(hipEventRecord(stored[b], ctx->d2h));
+    }
+    (void)hipStreamSynchronize(ctx->copy);
+    (void)hipStreamSynchronize(ctx->compute);
+    (void)hipStreamSynchronize(ctx->d2h);
+    for (size_t k = 0; k + 1 < kev.size(); k += 2) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, kev[k], kev[k + 1]) == hipSuccess) merge_k_ms += ms;
+    }
+    for (auto e : kev) put_event(ctx, e);
+    for (int b = 0; b < 2; ++b) {
+      put_event(ctx, copied[b]);
+      put_event(ctx, merged[b]);
+      put_event(ctx, stored[b]);
+    }
+    VX_TRY(rs);
+  }
+  VX_HIP(hipGetLastError());
+  st.chunks = runs;
+  st.chunk_rows = C;
+  st.n_buffers = nbuf_used;
+  st.part_ms = pass1_ms;
+  st.probe_ms = runs > 1 ? now_ms() - tm0 : 0;
+  st.kernel_ms = sort_k_ms;
+  st.build_ms = merge_k_ms;
+  st.sdma_bytes = sdma;
+  st.kernel_launches = launches;
+  st.total_ms = now_ms() - t0;
+  if (stats) *stats = st;
+  return VX_OK;
+}
+
+}  // namespace
+}  // namespace vx
+
+extern "C" vx_status vx_sort(vx_ctx* ctx, const vx_sort_desc* d, vx_stats* stats) {
+  VX_CHECK(ctx && d, VX_EINVAL, "vx_sort: null argument");
+  return vx::sort_impl(ctx, d, stats);
+}
+
+extern "C" vx_status vx_merge_cuts(const int64_t* const* runs, const uint64_t* run_len, uint32_t n_runs,
+                                   uint64_t rank, uint64_t* cut) {
+  VX_CHECK(n_runs == 0 || (runs && run_len && cut), VX_EINVAL, "vx_merge_cuts: null argument");
+  uint64_t total = 0;
+  for (uint32_t j = 0; j < n_runs; ++j) {
+    VX_CHECK(run_len[j] == 0 || runs[j], VX_EINVAL, "vx_merge_cuts: run %u is NULL", j);
+    total += run_len[j];
+  }
+  VX_CHECK(rank <= total, VX_EINVAL, "vx_merge_cuts: rank %llu exceeds the %llu elements",
+           (unsigned long long)rank, (unsigned long long)total);
+  vx::merge_cuts_t<int64_t>(runs, run_len, n_runs, rank, cut);
+  return VX_OK;
+}

@@ -69,3 +69,26 @@ def test_regroup_then_merge_is_the_sort():
              for lo, hi in zip(cuts[:-1], cuts[1:])]
     assert all(len(p) == hi - lo for p, lo, hi in zip(parts, ranks[:-1], ranks[1:]))
     assert np.array_equal(np.concatenate(parts), np.sort(allk))
+
+
+# ---- the library's host-side regroup step (no GPU work), against the oracle's definition
+
+@pytest.mark.parametrize("seed", range(6))
+def test_library_merge_cuts_match_oracle(seed):
+    import paper_2502_09541_amd as vx
+    rng = np.random.default_rng(100 + seed)
+    k = int(rng.integers(1, 9))
+    lo, hi = (-30, 30) if seed % 2 else (I64.min, I64.max)
+    runs = [np.sort(rng.integers(lo, hi, int(rng.integers(0, 60)), dtype=np.int64)) for _ in range(k)]
+    if seed == 3:
+        runs[0] = np.concatenate([[I64.min] * 3, runs[0], [I64.max] * 2])
+    total = sum(len(r) for r in runs)
+    for r in range(total + 1):
+        assert list(vx.merge_cuts(runs, r)) == list(oracle.merge_cuts(runs, r)), r
+
+
+def test_library_merge_cuts_rejects_rank_past_end():
+    import paper_2502_09541_amd as vx
+    with pytest.raises(vx.VxError) as e:
+        vx.merge_cuts([np.arange(5)], 6)
+    assert e.value.status == vx.VX_EINVAL
