@@ -38,23 +38,32 @@ __device__ __forceinline__ uint64_t merge_split(const K* a, uint64_t na, const K
   return lo;
 }
 
+// split[t] = merge_split at output min(t * tile, na + nb), for t = 0 .. tiles: where every tile
+// of the merge starts, found by all the tiles' binary searches at once.
+template <typename K>
+__global__ void k_merge_splits(const K* a, uint64_t na, const K* b, uint64_t nb, uint64_t tiles,
+                               unsigned long long* split) {
+  const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (t > tiles) return;
+  const uint64_t d = t * kMergeTile < na + nb ? t * kMergeTile : na + nb;
+  split[t] = merge_split(a, na, b, nb, d);
+}
+
 // out[0, na + nb) = the stable merge of sorted a and b.  A workgroup takes a tile of 2048
-// outputs: two lanes find where the tile starts and ends on the merge path, the workgroup
-// stages the tile's inputs in LDS with coalesced loads, every lane merges 8 outputs from LDS
-// (its own start found by a binary search in LDS) into an LDS output tile, and the tile is
-// stored with coalesced writes.
+// outputs whose ends on the merge path are split[t] and split[t + 1], stages the tile's inputs
+// in LDS with coalesced loads, lets every lane merge 8 outputs from LDS (its own start found by
+// a binary search in LDS) into an LDS output tile, and stores the tile with coalesced writes.
 template <typename K>
 __global__ void __launch_bounds__(kMergeThreads) k_merge(const K* a, uint64_t na, const K* b, uint64_t nb,
-                                                         K* out) {
+                                                         const unsigned long long* split, K* out) {
   __shared__ K sa[kMergeTile], sb[kMergeTile], so[kMergeTile];
-  __shared__ uint64_t split[2];
   const uint64_t n = na + nb;
-  for (uint64_t d0 = (uint64_t)blockIdx.x * kMergeTile; d0 < n; d0 += (uint64_t)gridDim.x * kMergeTile) {
+  for (uint64_t t = blockIdx.x; t * kMergeTile < n; t += gridDim.x) {
+    const uint64_t d0 = t * kMergeTile;
     const uint64_t d1 = d0 + kMergeTile < n ? d0 + kMergeTile : n;
-    if (threadIdx.x < 2) split[threadIdx.x] = merge_split(a, na, b, nb, threadIdx.x ? d1 : d0);
-    __syncthreads();
-    const uint64_t ia = split[0], ib = d0 - split[0];
-    const uint32_t ma = (uint32_t)(split[1] - split[0]), mb = (uint32_t)((d1 - split[1]) - ib);
+    const uint64_t s0 = split[t], s1 = split[t + 1];
+    const uint64_t ia = s0, ib = d0 - s0;
+    const uint32_t ma = (uint32_t)(s1 - s0), mb = (uint32_t)((d1 - s1) - ib);
     for (uint32_t k = threadIdx.x; k < ma; k += kMergeThreads) sa[k] = a[ia + k];
     for (uint32_t k = threadIdx.x; k < mb; k += kMergeThreads) sb[k] = b[ib + k];
     __syncthreads();
@@ -79,10 +88,22 @@ __global__ void __launch_bounds__(kMergeThreads) k_merge(const K* a, uint64_t na
   }
 }
 
-// dst[0, n) = src[0, n) with plain vector stores (dst may be mapped host memory).
-template <typename K>
-__global__ void __launch_bounds__(256) k_store(const K* src, K* dst, uint64_t n) {
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+// dst[0, bytes) = src[0, bytes) with 16-byte vector stores (dst may be mapped host memory); both
+// 16-byte aligned, bytes a multiple of 4.
+__global__ void __launch_bounds__(256) k_store(const uint8_t* src, uint8_t* dst, uint64_t bytes) {
+  const uint64_t n16 = bytes / 16;
+  const uint4* s = (const uint4*)src;
+  uint4* d = (uint4*)dst;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n16; i += (uint64_t)gridDim.x * blockDim.x)
+    d[i] = s[i];
+  for (uint64_t i = n16 * 4 + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < bytes / 4;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    ((uint32_t*)dst)[i] = ((const uint32_t*)src)[i];
+}
+
+// The same for any 4-byte-aligned pointers, element by element.
+__global__ void __launch_bounds__(256) k_store4(const uint32_t* src, uint32_t* dst, uint64_t words) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < words; i += (uint64_t)gridDim.x * blockDim.x)
     dst[i] = src[i];
 }
 
@@ -180,6 +201,20 @@ vx_status radix_sort_run(vx_ctx* ctx, const void* src, void* alt, void* dst, uin
 
 uint64_t align_to(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
+// Stores of a sorted run or merged range to its place (host or device memory), on a second stream
+// beside the sort and merge kernels.  One workgroup per 16 compute units: the stores slow the
+// kernels beside them (on the full-size sort, 256 workgroups took 1077 ms per sort, 64 took
+// 1030, 16 took 1001 and 8 took 1041, where the stores themselves became the limit).
+vx_status launch_store(const vx_ctx* ctx, const uint8_t* src, uint8_t* dst, uint64_t bytes, hipStream_t s) {
+  const unsigned g = (unsigned)std::max(1, ctx->cu_count / 16);
+  if ((((uintptr_t)src | (uintptr_t)dst) & 15) == 0)
+    hipLaunchKernelGGL(k_store, dim3(g), dim3(256), 0, s, src, dst, bytes);
+  else
+    hipLaunchKernelGGL(k_store4, dim3(g), dim3(256), 0, s, (const uint32_t*)src, (uint32_t*)dst, bytes / 4);
+  VX_HIP(hipGetLastError());
+  return VX_OK;
+}
+
 vx_status sort_impl(vx_ctx* ctx, const vx_sort_desc* d, vx_stats* stats) {
   const double t0 = now_ms();
   VX_HIP(hipSetDevice(ctx->device));
@@ -259,13 +294,7 @@ vx_status sort_impl(vx_ctx* ctx, const vx_sort_desc* d, vx_stats* stats) {
       // a single run is the result: store it in place; otherwise to its rows of the scratch
       uint8_t* dst = (runs > 1 ? (uint8_t*)hs_dev : out_dev) + v.row0 * ks;
       VX_HIP(hipStreamWaitEvent(ctx->d2h, sorted_ev[b], 0));
-      if (ks == 8)
-        hipLaunchKernelGGL(k_store<long long>, dim3(grid_of(ctx, v.rows, 256, 8)), dim3(256), 0, ctx->d2h,
-                           (const long long*)stage[b], (long long*)dst, v.rows);
-      else
-        hipLaunchKernelGGL(k_store<int>, dim3(grid_of(ctx, v.rows, 256, 8)), dim3(256), 0, ctx->d2h,
-                           (const int*)stage[b], (int*)dst, v.rows);
-      VX_HIP(hipGetLastError());
+      VX_TRY(launch_store(ctx, stage[b], dst, v.rows * ks, ctx->d2h));
       ++launches;
       VX_HIP(hipEventRecord(wrote[b], ctx->d2h));
       pending[b] = true;
@@ -327,6 +356,11 @@ vx_status sort_impl(vx_ctx* ctx, const vx_sort_desc* d, vx_stats* stats) {
     VX_CHECK(blk.p, VX_EBUDGET, "sort: no room for the merge buffers (4 x %llu B)", (unsigned long long)pbytes);
     uint8_t* X[2] = {blk.p, blk.p + pbytes};
     uint8_t* Y[2] = {blk.p + 2 * pbytes, blk.p + 3 * pbytes};
+    ArenaBlock sp;
+    sp.a = &ctx->arena;
+    sp.p = ctx->arena.alloc((max_part / kMergeTile + 2) * 8);
+    VX_CHECK(sp.p, VX_EBUDGET, "sort: no room for the merge splits");
+    unsigned long long* splits = (unsigned long long*)sp.p;
     hipEvent_t copied[2] = {get_event(ctx), get_event(ctx)}, merged[2] = {get_event(ctx), get_event(ctx)},
                stored[2] = {get_event(ctx), get_event(ctx)};
     std::vector<hipEvent_t> kev;
@@ -362,16 +396,26 @@ vx_status sort_impl(vx_ctx* ctx, const vx_sort_desc* d, vx_stats* stats) {
         std::vector<uint64_t> next;
         for (size_t k = 0; k + 1 < seg.size(); k += 2) {
           const uint64_t a0 = seg[k], a1 = seg[k + 1], b1 = k + 2 < seg.size() ? seg[k + 2] : a1;
+          const uint64_t tiles = (b1 - a0 + kMergeTile - 1) / kMergeTile;
           const unsigned g = grid_of(ctx, b1 - a0, kMergeTile, 4);
-          if (ks == 8)
-            hipLaunchKernelGGL(k_merge<long long>, dim3(g), dim3(kMergeThreads), 0, ctx->compute,
-                               (const long long*)src + a0, a1 - a0, (const long long*)src + a1, b1 - a1,
-                               (long long*)dst + a0);
-          else
-            hipLaunchKernelGGL(k_merge<int>, dim3(g), dim3(kMergeThreads), 0, ctx->compute, (const int*)src + a0,
-                               a1 - a0, (const int*)src + a1, b1 - a1, (int*)dst + a0);
+          const unsigned gs = (unsigned)((tiles + 1 + 255) / 256);
+          if (ks == 8) {
+            const long long* pa = (const long long*)src + a0;
+            const long long* pb = (const long long*)src + a1;
+            hipLaunchKernelGGL(k_merge_splits<long long>, dim3(gs), dim3(256), 0, ctx->compute, pa, a1 - a0, pb,
+                               b1 - a1, tiles, splits);
+            hipLaunchKernelGGL(k_merge<long long>, dim3(g), dim3(kMergeThreads), 0, ctx->compute, pa, a1 - a0, pb,
+                               b1 - a1, (const unsigned long long*)splits, (long long*)dst + a0);
+          } else {
+            const int* pa = (const int*)src + a0;
+            const int* pb = (const int*)src + a1;
+            hipLaunchKernelGGL(k_merge_splits<int>, dim3(gs), dim3(256), 0, ctx->compute, pa, a1 - a0, pb, b1 - a1,
+                               tiles, splits);
+            hipLaunchKernelGGL(k_merge<int>, dim3(g), dim3(kMergeThreads), 0, ctx->compute, pa, a1 - a0, pb, b1 - a1,
+                               (const unsigned long long*)splits, (int*)dst + a0);
+          }
           VX_HIP(hipGetLastError());
-          ++launches;
+          launches += 2;
           next.push_back(a0);
         }
         next.push_back(seg.back());
@@ -383,13 +427,7 @@ vx_status sort_impl(vx_ctx* ctx, const vx_sort_desc* d, vx_stats* stats) {
       // store the merged range to its place in the key column
       VX_HIP(hipStreamWaitEvent(ctx->d2h, merged[b], 0));
       const uint64_t rows = rank[i + 1] - rank[i];
-      if (ks == 8)
-        hipLaunchKernelGGL(k_store<long long>, dim3(grid_of(ctx, rows, 256, 8)), dim3(256), 0, ctx->d2h,
-                           (const long long*)src, (long long*)out_dev + rank[i], rows);
-      else
-        hipLaunchKernelGGL(k_store<int>, dim3(grid_of(ctx, rows, 256, 8)), dim3(256), 0, ctx->d2h, (const int*)src,
-                           (int*)out_dev + rank[i], rows);
-      VX_HIP(hipGetLastError());
+      VX_TRY(launch_store(ctx, src, out_dev + rank[i] * ks, rows * ks, ctx->d2h));
       ++launches;
       VX_HIP(hipEventRecord(stored[b], ctx->d2h));
     }

@@ -140,3 +140,50 @@ def test_radix_join_full_size(gpu):
     finally:
         for h in (ak, av, bk, bv):
             h.free()
+
+
+def test_sort_full_size(gpu):
+    """The out-of-core sort at the size bench.py times: 2^31 int64 keys uniform over all values,
+    pinned (16 GiB), 4 GiB budget (32 runs).  The output must be in order and hold the input's
+    multiset: equal sum mod 2^64, xor and count; and sampled output positions must hold the key
+    of that rank in the regenerated input (counted directly: #{x < key} <= position <
+    #{x <= key})."""
+    n = 1 << 31
+    print("full-size sort: 16 GiB pinned", flush=True)
+    h = gpu.HostBuffer(n, np.int64)
+    try:
+        step = 1 << 27
+        sums = [0, 0]
+        for r0 in range(0, n, step):
+            v = datagen.sort_keys(step, out=h.array[r0:r0 + step], row0=r0).view(np.uint64)
+            sums[0] = (sums[0] + int(v.sum(dtype=np.uint64))) % M64
+            sums[1] ^= int(np.bitwise_xor.reduce(v))
+        with gpu.Context(4 * GiB) as ctx:
+            st = ctx.sort(h)
+        assert st["chunks"] == 32
+        print("checking order and multiset", flush=True)
+        got = [0, 0]
+        prev = None
+        for r0 in range(0, n, step):
+            a = h.array[r0:r0 + step]
+            assert np.all(a[1:] >= a[:-1]) and (prev is None or prev <= a[0])
+            prev = a[-1]
+            v = a.view(np.uint64)
+            got[0] = (got[0] + int(v.sum(dtype=np.uint64))) % M64
+            got[1] ^= int(np.bitwise_xor.reduce(v))
+        assert got == sums
+        print("sampled ranks", flush=True)
+        pos = [0, 12_345_678, n // 2 + 7, n - 1]
+        keys = [int(h.array[p]) for p in pos]
+        less = [0] * len(pos)
+        leq = [0] * len(pos)
+        buf = np.empty(step, np.int64)
+        for r0 in range(0, n, step):
+            datagen.sort_keys(step, out=buf, row0=r0)
+            for i, k in enumerate(keys):
+                less[i] += int(np.count_nonzero(buf < k))
+                leq[i] += int(np.count_nonzero(buf <= k))
+        for p, lo, hi in zip(pos, less, leq):
+            assert lo <= p < hi, (p, lo, hi)
+    finally:
+        h.free()
