@@ -119,6 +119,8 @@ vx_status vx_calibrate(vx_ctx* ctx, void* pinned, uint64_t bytes, vx_link_calib*
 
 /* ------------------------------------------------------------------------ statistics */
 
+/* Statistics of one call.  The radix join (VX_JOIN_RADIX) and vx_sort give some fields their
+ * own meaning; their declarations below say which. */
 typedef struct {
   uint64_t rows;            /* probe (or fact) rows processed */
   uint64_t chunks;          /* chunks streamed (0: device-resident input) */

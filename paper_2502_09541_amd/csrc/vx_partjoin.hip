@@ -1165,11 +1165,10 @@ vx_status join_radix(vx_ctx* ctx, const vx_radix_join* d, vx_join_out* out) {
   uint64_t zc_bytes = 0;
   // HIP events around each build and probe launch (on the stream they run on)
   std::vector<hipEvent_t> ev(3 * n_jobs, nullptr);
-  for (auto& e : ev) {
-    e = get_event(ctx);
-    VX_CHECK(e, VX_EHIP, "radix join: no HIP event");
-  }
-  for (uint64_t j = 0; j < n_jobs; ++j) {
+  for (auto& e : ev) e = get_event(ctx);
+  // one job; on an error the stream is still drained before the table goes back to the arena
+  auto job = [&](uint64_t j) -> vx_status {
+    VX_CHECK(ev[3 * j] && ev[3 * j + 1] && ev[3 * j + 2], VX_EHIP, "radix join: no HIP event");
     const Job& jb = jobs[j];
     const uint64_t na = jb.hi - jb.lo, nbr = brows[jb.p];
     TableView t{};
@@ -1212,19 +1211,28 @@ vx_status join_radix(vx_ctx* ctx, const vx_radix_join* d, vx_join_out* out) {
     VX_HIP(hipEventRecord(ev[3 * j + 2], ctx->compute));
     if (!as.on_device && as.key.where == Where::Host) zc_bytes += na * side_row_bytes(as);
     if (!bs.on_device && bs.key.where == Where::Host) zc_bytes += nbr * side_row_bytes(bs);
-  }
+    return VX_OK;
+  };
+  vx_status rs = VX_OK;
+  for (uint64_t j = 0; j < n_jobs && rs == VX_OK; ++j) rs = job(j);
   std::vector<unsigned long long> accs(3ull * P);
-  VX_HIP(hipMemcpyAsync(accs.data(), acc, accs.size() * 8, hipMemcpyDeviceToHost, ctx->compute));
-  VX_HIP(hipStreamSynchronize(ctx->compute));
+  if (rs == VX_OK) {
+    const hipError_t ce = hipMemcpyAsync(accs.data(), acc, accs.size() * 8, hipMemcpyDeviceToHost, ctx->compute);
+    if (ce != hipSuccess) {
+      set_error("radix join: copy of the accumulators: %s", hipGetErrorString(ce));
+      rs = VX_EHIP;
+    }
+  }
+  const hipError_t se = hipStreamSynchronize(ctx->compute);
   double build_k_ms = 0, probe_k_ms = 0;
-  for (uint64_t j = 0; j < n_jobs; ++j) {
+  for (uint64_t j = 0; j < n_jobs && rs == VX_OK; ++j) {
     float a = 0, b = 0;
-    VX_HIP(hipEventElapsedTime(&a, ev[3 * j], ev[3 * j + 1]));
-    VX_HIP(hipEventElapsedTime(&b, ev[3 * j + 1], ev[3 * j + 2]));
-    build_k_ms += a;
-    probe_k_ms += b;
+    if (hipEventElapsedTime(&a, ev[3 * j], ev[3 * j + 1]) == hipSuccess) build_k_ms += a;
+    if (hipEventElapsedTime(&b, ev[3 * j + 1], ev[3 * j + 2]) == hipSuccess) probe_k_ms += b;
   }
   for (auto e : ev) put_event(ctx, e);
+  VX_TRY(rs);
+  VX_HIP(se);
   VX_TRY(check_flags(ctx, "radix join"));
   const double join_ms = now_ms() - tj0;
   if (trace)

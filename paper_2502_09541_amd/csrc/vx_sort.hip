@@ -279,6 +279,7 @@ vx_status sort_impl(vx_ctx* ctx, const vx_sort_desc* d, vx_stats* stats) {
     std::vector<hipEvent_t> kev;
     bool pending[2] = {false, false};
     auto kernel = [&](const ChunkView& v) -> vx_status {
+      for (int b = 0; b < 2; ++b) VX_CHECK(sorted_ev[b] && wrote[b], VX_EHIP, "sort: no HIP event");
       const uint32_t b = (uint32_t)(v.index % 2);
       if (pending[b]) VX_HIP(hipStreamWaitEvent(ctx->compute, wrote[b], 0));
       const uint8_t* src = (v.global_mask & 1u) ? (const uint8_t*)v.ptr[0] + v.row0 * ks : (const uint8_t*)v.ptr[0];
@@ -364,8 +365,9 @@ vx_status sort_impl(vx_ctx* ctx, const vx_sort_desc* d, vx_stats* stats) {
     hipEvent_t copied[2] = {get_event(ctx), get_event(ctx)}, merged[2] = {get_event(ctx), get_event(ctx)},
                stored[2] = {get_event(ctx), get_event(ctx)};
     std::vector<hipEvent_t> kev;
-    vx_status rs = VX_OK;
-    for (uint64_t i = 0; i < M && rs == VX_OK; ++i) {
+    // one output range; on an error the streams are still drained before the buffers go back
+    auto range = [&](uint64_t i) -> vx_status {
+      for (int b = 0; b < 2; ++b) VX_CHECK(copied[b] && merged[b] && stored[b], VX_EHIP, "sort: no HIP event");
       const uint32_t b = (uint32_t)(i % 2);
       if (i >= 2) VX_HIP(hipEventSynchronize(stored[b]));   // range i - 2 has left these buffers
       // copy in the range's segment of every run, back to back
@@ -430,7 +432,10 @@ vx_status sort_impl(vx_ctx* ctx, const vx_sort_desc* d, vx_stats* stats) {
       VX_TRY(launch_store(ctx, src, out_dev + rank[i] * ks, rows * ks, ctx->d2h));
       ++launches;
       VX_HIP(hipEventRecord(stored[b], ctx->d2h));
-    }
+      return VX_OK;
+    };
+    vx_status rs = VX_OK;
+    for (uint64_t i = 0; i < M && rs == VX_OK; ++i) rs = range(i);
     (void)hipStreamSynchronize(ctx->copy);
     (void)hipStreamSynchronize(ctx->compute);
     (void)hipStreamSynchronize(ctx->d2h);
