@@ -9,7 +9,8 @@
 // run length), found by binary search over the runs on the host.  Output range i then holds one
 // sorted segment of every run.  Its segments are copied in, merged in a tree of pairwise
 // merge-path launches (two device buffers used in turn), and the result is stored to its final
-// place in the key column.  Output range i + 1 copies in while range i merges and is stored.
+// place in the key column.  Up to three ranges are in flight: one copies in, one merges, one is
+// stored.
 #include <algorithm>
 #include <cstring>
 #include <thread>
@@ -349,27 +350,35 @@ vx_status sort_impl(vx_ctx* ctx, const vx_sort_desc* d, vx_stats* stats) {
       for (auto& x : th) x.join();
     }
     for (uint64_t i = 0; i < M; ++i) max_part = std::max(max_part, rank[i + 1] - rank[i]);
-    // two sets of (input, alternate) buffers: range i + 1 copies in while range i merges
+    // three sets of (input, alternate) buffers when they fit, else two: a range holds its set from
+    // its copy in to the end of its store, so with three the copies of the next ranges run while
+    // one range merges and another is stored
     const uint64_t pbytes = align_to(max_part * ks, 256);
     ArenaBlock blk;
     blk.a = &ctx->arena;
-    blk.p = ctx->arena.alloc(4 * pbytes);
+    uint32_t nset = 3;
+    blk.p = ctx->arena.largest_free() >= 6 * pbytes + (1u << 20) ? ctx->arena.alloc(6 * pbytes) : nullptr;
+    if (!blk.p) {
+      nset = 2;
+      blk.p = ctx->arena.alloc(4 * pbytes);
+    }
     VX_CHECK(blk.p, VX_EBUDGET, "sort: no room for the merge buffers (4 x %llu B)", (unsigned long long)pbytes);
-    uint8_t* X[2] = {blk.p, blk.p + pbytes};
-    uint8_t* Y[2] = {blk.p + 2 * pbytes, blk.p + 3 * pbytes};
+    uint8_t* X[3] = {blk.p, blk.p + pbytes, blk.p + 2 * pbytes};
+    uint8_t* Y[3] = {blk.p + nset * pbytes, blk.p + (nset + 1) * pbytes, blk.p + (nset + 2) * pbytes};
     ArenaBlock sp;
     sp.a = &ctx->arena;
     sp.p = ctx->arena.alloc((max_part / kMergeTile + 2) * 8);
     VX_CHECK(sp.p, VX_EBUDGET, "sort: no room for the merge splits");
     unsigned long long* splits = (unsigned long long*)sp.p;
-    hipEvent_t copied[2] = {get_event(ctx), get_event(ctx)}, merged[2] = {get_event(ctx), get_event(ctx)},
-               stored[2] = {get_event(ctx), get_event(ctx)};
+    hipEvent_t copied[3] = {get_event(ctx), get_event(ctx), get_event(ctx)},
+               merged[3] = {get_event(ctx), get_event(ctx), get_event(ctx)},
+               stored[3] = {get_event(ctx), get_event(ctx), get_event(ctx)};
     std::vector<hipEvent_t> kev;
     // one output range; on an error the streams are still drained before the buffers go back
     auto range = [&](uint64_t i) -> vx_status {
-      for (int b = 0; b < 2; ++b) VX_CHECK(copied[b] && merged[b] && stored[b], VX_EHIP, "sort: no HIP event");
-      const uint32_t b = (uint32_t)(i % 2);
-      if (i >= 2) VX_HIP(hipEventSynchronize(stored[b]));   // range i - 2 has left these buffers
+      for (int b = 0; b < 3; ++b) VX_CHECK(copied[b] && merged[b] && stored[b], VX_EHIP, "sort: no HIP event");
+      const uint32_t b = (uint32_t)(i % nset);
+      if (i >= nset) VX_HIP(hipEventSynchronize(stored[b]));   // range i - nset has left these buffers
       // copy in the range's segment of every run, back to back
       std::vector<uint64_t> off(runs + 1, 0);
       for (uint64_t j = 0; j < runs; ++j) {
@@ -444,7 +453,7 @@ vx_status sort_impl(vx_ctx* ctx, const vx_sort_desc* d, vx_stats* stats) {
       if (hipEventElapsedTime(&ms, kev[k], kev[k + 1]) == hipSuccess) merge_k_ms += ms;
     }
     for (auto e : kev) put_event(ctx, e);
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < 3; ++b) {
       put_event(ctx, copied[b]);
       put_event(ctx, merged[b]);
       put_event(ctx, stored[b]);
