@@ -14,6 +14,11 @@
 // quantiles gets a partition of its own.  A singleton partition needs no table: pass 1 counts
 // its build rows and sums their payload, the probe stream counts its probe rows, and its
 // contribution is count_b * count_p pairs and sum_b * count_p.
+//
+// The two-table radix join (join_radix, the paper's hash-join case study) uses the same pass 1
+// on both tables, by raw key bits or a key hash.  Its pass 2 takes the partitions in turn:
+// A's rows of a partition are pre-aggregated into one table (in slices when they exceed it),
+// and B's rows of the partition, read in place through their segment list, look it up.
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
