@@ -30,7 +30,9 @@ TRAFFIC_BYTES = {"k_probe_stream": 1.5647e9,    # 8,388,608 probe rows per launc
                  "k_star": 2.1670e9,            # 16,666,667 fact rows per launch
                  "batch_graph": 6.0252e11,      # one graph launch: build phase + probe phase, all 256 jobs
                  "k_pj_stream": 4.976e8,        # 8,388,608 probe rows per launch (mean over the partitioners)
-                 "k_probe_rows": 1.4712e9}      # 8,388,608 probe rows per launch, output rows included
+                 "k_probe_rows": 1.4712e9,      # 8,388,608 probe rows per launch, output rows included
+                 "k_rj_probe": 6.9228e9,        # 33,554,432 B rows per launch (host reads + table lines)
+                 "sort_run": 2.4941e10}         # one 2^26-key run: 8 x (k_part_hist + k_part_scatter)
 GiB = 1 << 30
 
 
@@ -581,7 +583,8 @@ def run_radix(args):
                     "device_budget_gib": args.radix_budget_gib, "n_parts": st["n_parts"],
                     "partition_fn": "raw key bits [0, log2 n_parts)"},
                    {"bound": "host_link", "kernel": "k_rj_probe", "achieved": ach, "peak": b_peak, "unit": "GB/s",
-                    "frac": ach / b_peak, "traffic": None, "avg_launch_ms": k_avg,
+                    "frac": ach / b_peak, "traffic": TRAFFIC_BYTES["k_rj_probe"] if st["n_parts"] == 16 else None,
+                    "avg_launch_ms": k_avg,
                     "rows_per_launch": rows_per_launch,
                     "algorithmic_bytes": "16 B per B row read in place from pinned host memory"},
                    {"cpu_baseline": cpu,
@@ -679,7 +682,8 @@ def run_sort(args):
                    {"workload": "out_of_core_sort", "keys": n, "key_bytes": 8, "distribution": "uniform over int64",
                     "device_budget_gib": args.sort_budget_gib, "runs": runs, "run_keys": rows},
                    {"bound": "hbm", "kernel": "radix sort of one run (8 multisplit passes)", "achieved": ach,
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                    "traffic": TRAFFIC_BYTES["sort_run"] if rows == 1 << 26 else None,
                     "avg_launch_ms": k_avg, "rows_per_launch": rows,
                     "algorithmic_bytes": "24 B per key per digit pass (8 B histogram read, 8 B read + 8 B written by the scatter), 8 passes"},
                    {"cpu_baseline": cpu,
