@@ -552,7 +552,7 @@ def run_radix(args):
         raise SystemExit(f"radix join result {agg} differs from the closed form {want}")
     # the oracle on a bounded sample of the same workload: the rows of both tables whose key is
     # below n/16 (a key range, so the sample's join is the whole join restricted to those keys)
-    cpu = None
+    cpu = cpu_all = None
     if not args.no_cpu_baseline:
         lim = n // 16
         ma, mb = ak.array < lim, bk.array < lim
@@ -565,6 +565,22 @@ def run_radix(args):
         cpu = {"value": (len(sak) + len(sbk)) / dt, "unit": "tuples/s", "cores": 1, "kind": "oracle",
                "sample": f"rows of A and B with key < 2^{args.radix_log2 - 4}: {len(sak)} + {len(sbk)} rows, "
                          f"joined in {dt:.1f} s on 1 host thread"}
+        # the same oracle on all host cores: the sample's key range cut into one range per thread
+        # (each range's join is independent), the C calls run without the GIL
+        from concurrent.futures import ThreadPoolExecutor
+        n_thr = max(1, min(16, len(os.sched_getaffinity(0))))
+        cuts = [lim * t // n_thr for t in range(n_thr + 1)]
+        parts_a = [(sak >= cuts[t]) & (sak < cuts[t + 1]) for t in range(n_thr)]
+        parts_b = [(sbk >= cuts[t]) & (sbk < cuts[t + 1]) for t in range(n_thr)]
+        args_t = [(sak[parts_a[t]], sav[parts_a[t]], sbk[parts_b[t]], sbv[parts_b[t]]) for t in range(n_thr)]
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(n_thr) as ex:
+            outs = list(ex.map(lambda a: oracle.join_agg(a[0], [a[1]], a[2], [a[3]]), args_t))
+        dt_all = time.perf_counter() - t0
+        if [sum(x) % (1 << 64) for x in zip(*outs)] != got:
+            raise SystemExit("threaded oracle run disagrees with the single-threaded one")
+        cpu_all = {"value": (len(sak) + len(sbk)) / dt_all, "unit": "tuples/s", "cores": n_thr, "kind": "oracle",
+                   "sample": f"the same sample cut into {n_thr} key ranges, one per thread, in {dt_all:.1f} s"}
     for h in (ak, av, bk, bv):
         h.free()
     tuples = 2 * n
@@ -587,7 +603,7 @@ def run_radix(args):
                     "avg_launch_ms": k_avg,
                     "rows_per_launch": rows_per_launch,
                     "algorithmic_bytes": "16 B per B row read in place from pinned host memory"},
-                   {"cpu_baseline": cpu,
+                   {"cpu_baseline": cpu, "cpu_baseline_all_cores": cpu_all,
                     "host_link": {"h2d_peak_measured_gbs": b_peak, "duplex_measured_gbs": cal["duplex_zcw_gbs"],
                                   "h2d_bytes_per_step": h2d, "d2h_bytes_per_step": d2h,
                                   "h2d_gbs": h2d / (ms * 1e6), "d2h_gbs": d2h / (ms * 1e6),
