@@ -100,7 +100,7 @@ def cpu_baseline(log2_build, log2_probe):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no "
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the library has no "
               f"multi-GPU path", file=sys.stderr)
         sys.exit(2)
     if args.workload != "stream":

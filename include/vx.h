@@ -55,7 +55,7 @@ typedef enum {
   VX_EHIP = 4,          /* a HIP runtime call failed */
   VX_ENOTPINNED = 5,    /* a host column is not pinned / device-mapped */
   VX_ECAPACITY = 6,     /* an output array is too small (its required size is reported) */
-  VX_EUNSUPPORTED = 7,  /* a valid request this build does not handle */
+  VX_EUNSUPPORTED = 7,  /* a valid request the library does not handle */
   VX_EDUPKEY = 8        /* duplicate key in a build declared unique */
 } vx_status;
 
