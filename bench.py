@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0       # MI355X HBM3E datasheet peak
 TRAFFIC_BYTES = {"k_probe_stream": 1.5647e9,    # 8,388,608 probe rows per launch
                  "k_probe_plain": 1.8964e9,     # 16,777,216 probe rows per launch
                  "k_star": 2.1670e9,            # 16,666,667 fact rows per launch
-                 "batch_graph": 6.0252e11,      # one graph launch: build phase + probe phase, all 256 jobs
+                 "batch_graph": 2.2125e11,      # one graph launch: build phase + probe phase, all 256 jobs
                  "k_pj_stream": 4.976e8,        # 8,388,608 probe rows per launch (mean over the partitioners)
                  "k_probe_rows": 1.4712e9,      # 8,388,608 probe rows per launch, output rows included
                  "k_rj_probe": 6.9228e9,        # 33,554,432 B rows per launch (host reads + table lines)
@@ -439,7 +439,11 @@ def run_batch(args):
         raise SystemExit("batched and per-job results differ")
     st = res[0][1]
     k_ms = sum(r[1]["kernel_ms"] for r in res) / len(res)
-    alg = rows * 12 + int(b.sum()) * 16       # probe: key + slot; build: key/payload + slot write
+    # algorithmic bytes with the direct tables these dense-key jobs take: a probe reads its 4 B key
+    # and, when the key is in its job's range (a match), a 4 B payload; a build row reads its key
+    # and payload and writes the payload
+    matches = sum(int(g[0]) for g in res[0][0])
+    alg = rows * 4 + matches * 4 + int(b.sum()) * 12
     ctx.close()
     return _common("probe rows/s", rows / (ms / 1e3), ms, args, "int32",
                    {"workload": "batched_joins_256", "jobs": 256, "probe_rows": rows, "build_rows": int(b.sum()),

@@ -273,6 +273,13 @@ typedef struct {
   uint64_t groups_cap;
 } vx_star_join;
 
+/*
+ * Batched join: many independent device-resident joins in one call.  A job whose build keys fill
+ * their value range exactly (n unique keys from min to min + n - 1, measured on every call) is
+ * joined through a direct table indexed by key - min; other jobs through hash tables.  Results
+ * do not depend on which.  Errors: VX_EDUPKEY when a job's build keys repeat; VX_EINVAL for
+ * host-resident columns, mixed key types or more than 4096 jobs.
+ */
 typedef struct {
   uint32_t n_jobs;
   int32_t mode;                /* 0: one HIP graph launch: a build-phase and a probe-phase kernel that

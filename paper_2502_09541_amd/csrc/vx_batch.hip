@@ -9,6 +9,12 @@
 // replayed while the batch is unchanged.  Tile size, workgroup size and load factor come from
 // a small autotuner that times candidates on the batch itself and caches the winner per
 // workload class (optionally in the file named by VX_TUNE_CACHE).
+//
+// A job whose build keys fill their value range exactly (n unique keys from min to min + n - 1,
+// found by a min/max pass over every job before the graph runs) gets a direct table instead of
+// a hash table: the payload of key k sits at k - min, and a bitmap of the keys seen catches a
+// duplicate (which would leave a key of the range missing).  A probe key outside the range then
+// costs no memory access, and one inside reads one payload.
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -29,7 +35,11 @@ struct BatchJob {
   const void* bpay;
   const void* pkey;
   uint64_t nb, np;
-  uint8_t* slots;         // capacity slots of 8 (int32 key + int32 payload) or 16 bytes
+  uint8_t* slots;         // hash: capacity slots of 8 (int32 key + int32 payload) or 16 bytes;
+                          // direct: the key bitmap ((nb + 63) / 64 words), then the payloads
+  uint8_t* dpay;          // direct: payload of key kmin + i at index i
+  unsigned long long kmin_ord;   // direct: the smallest key, order-preserving unsigned form
+  uint32_t direct;        // 1: direct table
   uint64_t mask;
   uint32_t log2cap;
   uint32_t pay_size;      // 0 (no payload), 4 or 8
@@ -41,6 +51,12 @@ struct BatchJob {
 
 constexpr uint32_t kMaxBatchJobs = 4096;
 
+// order-preserving unsigned form of a key (sign-extended, sign bit flipped)
+template <typename K>
+__device__ __forceinline__ unsigned long long key_ord(K k) {
+  return (unsigned long long)(long long)k ^ 0x8000000000000000ull;
+}
+
 template <typename K>
 __device__ __forceinline__ void batch_build_rows(const BatchJob& jb, uint64_t r0, uint64_t r1,
                                                  uint32_t slot_shift, unsigned int* flags) {
@@ -50,6 +66,15 @@ __device__ __forceinline__ void batch_build_rows(const BatchJob& jb, uint64_t r0
     K k = ((const K*)jb.bkey)[i];
     U kb = (U)k;
     long long v = jb.pay_size ? load_signed(jb.bpay, i, jb.pay_size) : 0;
+    if (jb.direct) {
+      // every build key lies in [kmin, kmin + nb): the range was measured over these keys
+      const uint64_t idx = key_ord(k) - jb.kmin_ord;
+      const unsigned long long bit = 1ull << (idx & 63);
+      if (atomicOr((unsigned long long*)jb.slots + (idx >> 6), bit) & bit) atomicOr(flags, kFlagDup);
+      if (jb.pay_size == 4) ((int*)jb.dpay)[idx] = (int)v;
+      else if (jb.pay_size == 8) ((long long*)jb.dpay)[idx] = v;
+      continue;
+    }
     if (kb == kEmpty) {
       unsigned long long prev = atomicAdd(jb.side, 1ull);
       if (prev) atomicOr(flags, kFlagDup);
@@ -87,6 +112,15 @@ __device__ __forceinline__ void batch_probe_rows(const BatchJob& jb, uint64_t r0
   for (uint64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
     K k = __builtin_nontemporal_load(((const K*)jb.pkey) + i);
     U kb = (U)k;
+    if (jb.direct) {
+      const uint64_t idx = key_ord(k) - jb.kmin_ord;
+      if (idx < jb.nb) {   // every key of the range is in the table (no duplicates: checked)
+        cnt += 1;
+        if (jb.pay_size == 4) sum += (unsigned long long)(long long)((const int*)jb.dpay)[idx];
+        else if (jb.pay_size == 8) sum += (unsigned long long)((const long long*)jb.dpay)[idx];
+      }
+      continue;
+    }
     if (kb == kEmpty) {
       unsigned long long c = jb.side[0];
       cnt += c;
@@ -190,6 +224,66 @@ __global__ void k_batch_init(uint32_t* slots, uint64_t n_slots, uint32_t slot_wo
   }
 }
 
+// Per-job smallest and largest build key (order-preserving unsigned form) over tiles of
+// tile_rows rows: mm[2 j] = min, mm[2 j + 1] = max (set to ~0 and 0 beforehand).
+struct MmJob {
+  const void* key;
+  uint64_t n;
+  uint64_t tile0;
+};
+
+template <typename K>
+__global__ void __launch_bounds__(256) k_batch_minmax(const MmJob* jobs, uint32_t n_jobs, uint64_t tiles,
+                                                      uint32_t tile_rows, unsigned long long* mm) {
+  __shared__ unsigned long long t0[kMaxBatchJobs];
+  __shared__ unsigned long long rmin[4], rmax[4];
+  for (uint32_t j = threadIdx.x; j < n_jobs; j += blockDim.x) t0[j] = jobs[j].tile0;
+  __syncthreads();
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+    uint32_t lo = 0, hi = n_jobs;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (t0[mid] <= t) lo = mid;
+      else hi = mid;
+    }
+    const MmJob jb = jobs[lo];
+    const uint64_t r0 = (t - jb.tile0) * tile_rows, r1 = r0 + tile_rows < jb.n ? r0 + tile_rows : jb.n;
+    unsigned long long mn = ~0ull, mx = 0;
+    for (uint64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+      const unsigned long long o = key_ord(((const K*)jb.key)[i]);
+      mn = o < mn ? o : mn;
+      mx = o > mx ? o : mx;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const unsigned long long a = __shfl_xor(mn, o, 64), b = __shfl_xor(mx, o, 64);
+      mn = a < mn ? a : mn;
+      mx = b > mx ? b : mx;
+    }
+    if (lane == 0) {
+      rmin[wave] = mn;
+      rmax[wave] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < 4; ++w) {
+        mn = rmin[w] < mn ? rmin[w] : mn;
+        mx = rmax[w] > mx ? rmax[w] : mx;
+      }
+      atomicMin(mm + 2 * (uint64_t)lo, mn);
+      atomicMax(mm + 2 * (uint64_t)lo + 1, mx);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_mm_init(unsigned long long* mm, uint32_t n_jobs) {
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n_jobs; j += gridDim.x * blockDim.x) {
+    mm[2 * (uint64_t)j] = ~0ull;
+    mm[2 * (uint64_t)j + 1] = 0;
+  }
+}
+
 // ---------------------------------------------------------------- host side
 
 struct BatchConfig {
@@ -203,12 +297,71 @@ struct BatchPlan {
   std::vector<uint32_t> job_of;    // caller's job index of jobs[i]
   uint64_t build_tiles = 0, probe_tiles = 0;
   uint64_t total_tiles = 0;
-  uint64_t slots = 0;
+  uint64_t slots = 0;              // hash slots of all hash-table jobs (one region, first)
+  uint64_t direct_bytes = 0;       // bitmaps and payloads of the direct-table jobs (after them)
   uint32_t slot_shift = 3;
 };
 
+// Which jobs get a direct table: per caller's job, direct[j] and the smallest key kmin[j]
+// (order-preserving unsigned form).
+struct DirectInfo {
+  std::vector<uint8_t> direct;
+  std::vector<unsigned long long> kmin;
+  bool operator==(const DirectInfo& o) const { return direct == o.direct && kmin == o.kmin; }
+};
+
+uint64_t align256(uint64_t v) { return (v + 255) / 256 * 256; }
+
+uint64_t direct_region_bytes(uint64_t nb, uint32_t ps) {
+  return align256((nb + 63) / 64 * 8) + align256(nb * ps);
+}
+
+// Min and max build key of every job in one launch; a job is direct when its nb keys could be
+// exactly the nb values from its min to its max.
+static vx_status find_direct(vx_ctx* ctx, const vx_batch_join* d, int ks, DirectInfo* di) {
+  const uint32_t J = d->n_jobs;
+  const uint32_t tile_rows = 65536;
+  std::vector<MmJob> mj(J);
+  uint64_t tiles = 0;
+  for (uint32_t j = 0; j < J; ++j) {
+    mj[j].key = d->build_key[j].data;
+    mj[j].n = d->n_build[j];
+    mj[j].tile0 = tiles;
+    tiles += (d->n_build[j] + tile_rows - 1) / tile_rows;
+  }
+  di->direct.assign(J, 0);
+  di->kmin.assign(J, 0);
+  if (!tiles) return VX_OK;
+  ArenaBlock blk;
+  blk.a = &ctx->arena;
+  blk.p = ctx->arena.alloc(align256((uint64_t)J * sizeof(MmJob)) + (uint64_t)J * 16);
+  VX_CHECK(blk.p, VX_EBUDGET, "batch: no room for the key ranges");
+  MmJob* mjd = (MmJob*)blk.p;
+  unsigned long long* mm = (unsigned long long*)(blk.p + align256((uint64_t)J * sizeof(MmJob)));
+  VX_HIP(hipMemcpyAsync(mjd, mj.data(), (uint64_t)J * sizeof(MmJob), hipMemcpyHostToDevice, ctx->compute));
+  hipLaunchKernelGGL(k_mm_init, dim3((J + 255) / 256), dim3(256), 0, ctx->compute, mm, J);
+  const unsigned g = (unsigned)std::min<uint64_t>(tiles, (uint64_t)ctx->cu_count * 8);
+  if (ks == 8)
+    hipLaunchKernelGGL(k_batch_minmax<int64_t>, dim3(g), dim3(256), 0, ctx->compute, (const MmJob*)mjd, J, tiles,
+                       tile_rows, mm);
+  else
+    hipLaunchKernelGGL(k_batch_minmax<int32_t>, dim3(g), dim3(256), 0, ctx->compute, (const MmJob*)mjd, J, tiles,
+                       tile_rows, mm);
+  VX_HIP(hipGetLastError());
+  std::vector<unsigned long long> h(2 * (uint64_t)J);
+  VX_HIP(hipMemcpyAsync(h.data(), mm, h.size() * 8, hipMemcpyDeviceToHost, ctx->compute));
+  VX_HIP(hipStreamSynchronize(ctx->compute));
+  for (uint32_t j = 0; j < J; ++j) {
+    const uint64_t nb = d->n_build[j];
+    const unsigned long long mn = h[2 * j], mx = h[2 * j + 1];
+    di->direct[j] = nb >= 1 && mx >= mn && mx - mn == nb - 1;
+    di->kmin[j] = mn;
+  }
+  return VX_OK;
+}
+
 static vx_status plan_batch(const vx_batch_join* d, const BatchConfig& cfg, int ks, uint32_t ps,
-                            BatchPlan* pl) {
+                            const DirectInfo& di, BatchPlan* pl) {
   const uint32_t J = d->n_jobs;
   pl->jobs.resize(J);
   pl->job_of.resize(J);
@@ -220,7 +373,7 @@ static vx_status plan_batch(const vx_batch_join* d, const BatchConfig& cfg, int 
   if (ks == 8 && ps) slot_bytes = 16;
   pl->slot_shift = 0;
   while ((1u << pl->slot_shift) < slot_bytes) ++pl->slot_shift;
-  uint64_t bt = 0, pt = 0, slots = 0;
+  uint64_t bt = 0, pt = 0, slots = 0, dbytes = 0;
   for (uint32_t i = 0; i < J; ++i) {
     const uint32_t j = pl->job_of[i];
     BatchJob& b = pl->jobs[i];
@@ -231,14 +384,22 @@ static vx_status plan_batch(const vx_batch_join* d, const BatchConfig& cfg, int 
     b.nb = d->n_build[j];
     b.np = d->n_probe[j];
     b.pay_size = b.bpay ? (uint32_t)ps : 0;
-    uint64_t want = (uint64_t)std::ceil((double)std::max<uint64_t>(b.nb, 1) / cfg.load_factor);
-    uint64_t cap = 64;
-    while (cap < want) cap <<= 1;
-    b.mask = cap - 1;
-    b.log2cap = 0;
-    while ((1ull << b.log2cap) < cap) ++b.log2cap;
-    b.slots = (uint8_t*)(uintptr_t)slots;   // offset, relocated once memory is carved
-    slots += cap;
+    if (di.direct[j]) {
+      // offsets are relocated once memory is carved: direct regions follow the hash slots
+      b.direct = 1;
+      b.kmin_ord = di.kmin[j];
+      b.slots = (uint8_t*)(uintptr_t)dbytes;
+      dbytes += direct_region_bytes(b.nb, b.pay_size);
+    } else {
+      uint64_t want = (uint64_t)std::ceil((double)std::max<uint64_t>(b.nb, 1) / cfg.load_factor);
+      uint64_t cap = 64;
+      while (cap < want) cap <<= 1;
+      b.mask = cap - 1;
+      b.log2cap = 0;
+      while ((1ull << b.log2cap) < cap) ++b.log2cap;
+      b.slots = (uint8_t*)(uintptr_t)slots;
+      slots += cap;
+    }
     b.tile0 = bt;
     b.ptile0 = pt;
     b.build_tiles = (uint32_t)((b.nb + cfg.tile_rows - 1) / cfg.tile_rows);
@@ -250,6 +411,7 @@ static vx_status plan_batch(const vx_batch_join* d, const BatchConfig& cfg, int 
   pl->probe_tiles = pt;
   pl->total_tiles = bt + pt;
   pl->slots = slots;
+  pl->direct_bytes = dbytes;
   return VX_OK;
 }
 
@@ -264,10 +426,11 @@ struct BatchRun {
 };
 
 static vx_status setup_run(vx_ctx* ctx, const vx_batch_join* d, const BatchConfig& cfg, int ks,
-                           uint32_t ps, BatchRun* r) {
-  VX_TRY(plan_batch(d, cfg, ks, ps, &r->plan));
+                           uint32_t ps, const DirectInfo& di, BatchRun* r) {
+  VX_TRY(plan_batch(d, cfg, ks, ps, di, &r->plan));
   const uint32_t J = d->n_jobs;
-  uint64_t slot_bytes = r->plan.slots << r->plan.slot_shift;
+  const uint64_t hash_bytes = align256(r->plan.slots << r->plan.slot_shift);
+  uint64_t slot_bytes = hash_bytes + r->plan.direct_bytes;
   uint64_t side_bytes = (uint64_t)J * 16;
   uint64_t desc_bytes = (uint64_t)J * sizeof(BatchJob);
   // side records and accumulators are contiguous so one fill kernel clears them
@@ -287,7 +450,12 @@ static vx_status setup_run(vx_ctx* ctx, const vx_batch_join* d, const BatchConfi
   (void)side_bytes;
   for (uint32_t j = 0; j < J; ++j) {
     BatchJob& b = r->plan.jobs[j];
-    b.slots = r->slots + (((uint64_t)(uintptr_t)b.slots) << r->plan.slot_shift);
+    if (b.direct) {
+      b.slots = r->slots + hash_bytes + (uint64_t)(uintptr_t)b.slots;
+      b.dpay = b.slots + align256((b.nb + 63) / 64 * 8);
+    } else {
+      b.slots = r->slots + (((uint64_t)(uintptr_t)b.slots) << r->plan.slot_shift);
+    }
     b.side = sides + 2 * (uint64_t)j;
   }
   (void)side_bytes;
@@ -301,8 +469,11 @@ static vx_status enqueue_batch(vx_ctx* ctx, const BatchRun& r, const BatchConfig
                                uint32_t J, hipStream_t s, uint64_t* host_out) {
   uint32_t sw = (1u << r.plan.slot_shift) / 4;
   unsigned ig = (unsigned)std::min<uint64_t>((r.plan.slots + 255) / 256, (uint64_t)ctx->cu_count * 16);
-  hipLaunchKernelGGL(k_batch_init, dim3(std::max(ig, 1u)), dim3(256), 0, s, (uint32_t*)r.slots, r.plan.slots,
-                     sw, (uint32_t)ks);
+  if (r.plan.slots)
+    hipLaunchKernelGGL(k_batch_init, dim3(std::max(ig, 1u)), dim3(256), 0, s, (uint32_t*)r.slots, r.plan.slots,
+                       sw, (uint32_t)ks);
+  if (r.plan.direct_bytes)
+    fill_zero((uint64_t*)(r.slots + align256(r.plan.slots << r.plan.slot_shift)), r.plan.direct_bytes / 8, s);
   fill_zero((uint64_t*)r.counters, r.counter_words, s);
   fill_zero((uint64_t*)ctx->dev_flags, 1, s);
   const uint64_t per_cu = cfg.block >= 512 ? 4 : 8;
@@ -377,9 +548,9 @@ static void store_tuned(const std::string& key, const BatchConfig& c) {
 }
 
 static vx_status time_config(vx_ctx* ctx, const vx_batch_join* d, const BatchConfig& cfg, int ks, uint32_t ps,
-                             float* ms) {
+                             const DirectInfo& di, float* ms) {
   BatchRun r;
-  VX_TRY(setup_run(ctx, d, cfg, ks, ps, &r));
+  VX_TRY(setup_run(ctx, d, cfg, ks, ps, di, &r));
   hipEvent_t a = get_event(ctx), b = get_event(ctx);
   VX_TRY(enqueue_batch(ctx, r, cfg, ks, d->n_jobs, ctx->compute, nullptr));   // warm
   VX_HIP(hipEventRecord(a, ctx->compute));
@@ -392,8 +563,12 @@ static vx_status time_config(vx_ctx* ctx, const vx_batch_join* d, const BatchCon
   return check_flags(ctx, "batch autotune");
 }
 
-static vx_status autotune(vx_ctx* ctx, const vx_batch_join* d, int ks, uint32_t ps, BatchConfig* best) {
+static vx_status autotune(vx_ctx* ctx, const vx_batch_join* d, int ks, uint32_t ps, const DirectInfo& di,
+                          BatchConfig* best) {
   std::string key = class_key(ctx, d, ks);
+  uint32_t n_direct = 0;
+  for (uint8_t x : di.direct) n_direct += x;
+  key += "_d" + std::to_string(n_direct == 0 ? 0 : n_direct == d->n_jobs ? 2 : 1);
   if (load_tuned(key, best)) return VX_OK;
   float best_ms = 1e30f;
   for (uint32_t tile : {2048u, 8192u, 32768u})
@@ -401,7 +576,7 @@ static vx_status autotune(vx_ctx* ctx, const vx_batch_join* d, int ks, uint32_t 
       for (float lf : {0.5f, 0.7f}) {
         BatchConfig c{tile, block, lf};
         float ms = 0;
-        VX_TRY(time_config(ctx, d, c, ks, ps, &ms));
+        VX_TRY(time_config(ctx, d, c, ks, ps, di, &ms));
         if (ms < best_ms) {
           best_ms = ms;
           *best = c;
@@ -431,6 +606,7 @@ struct GraphCache {
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   std::vector<JobKey> key;
+  DirectInfo di;
   BatchConfig cfg;
   BatchRun* run = nullptr;
 };
@@ -483,10 +659,13 @@ vx_status join_batch(vx_ctx* ctx, const vx_batch_join* d, vx_join_out* out) {
   }
   const uint32_t ps = pt ? (uint32_t)elsize_of(pt) : 0;
   const uint32_t J = d->n_jobs;
+  // which jobs take a direct table depends on the keys' values: measured on every call
+  DirectInfo di;
+  VX_TRY(find_direct(ctx, d, ks, &di));
   const double t_checked = now_ms();
   BatchConfig cfg;
   bool tuned = d->tile_rows == 0 || d->block == 0 || d->load_factor == 0.0f;
-  if (tuned && d->mode == 0) VX_TRY(autotune(ctx, d, ks, ps, &cfg));
+  if (tuned && d->mode == 0) VX_TRY(autotune(ctx, d, ks, ps, di, &cfg));
   const double t_tuned = now_ms();
   if (d->tile_rows) cfg.tile_rows = d->tile_rows;
   if (d->block) cfg.block = d->block;
@@ -501,14 +680,15 @@ vx_status join_batch(vx_ctx* ctx, const vx_batch_join* d, vx_join_out* out) {
   std::memset(&s, 0, sizeof s);
   if (d->mode == 0) {
     GraphCache*& gc = g_graphs[ctx];
-    if (!gc || !(gc->key == job_keys(d)) || gc->cfg.tile_rows != cfg.tile_rows || gc->cfg.block != cfg.block ||
-        gc->cfg.load_factor != cfg.load_factor) {
+    if (!gc || !(gc->key == job_keys(d)) || !(gc->di == di) || gc->cfg.tile_rows != cfg.tile_rows ||
+        gc->cfg.block != cfg.block || gc->cfg.load_factor != cfg.load_factor) {
       drop_graph(gc);
       gc = new GraphCache;
       gc->run = new BatchRun;
       gc->cfg = cfg;
-      VX_TRY(setup_run(ctx, d, cfg, ks, ps, gc->run));
+      VX_TRY(setup_run(ctx, d, cfg, ks, ps, di, gc->run));
       gc->key = job_keys(d);
+      gc->di = di;
       VX_HIP(hipStreamSynchronize(ctx->compute));
       VX_HIP(hipStreamBeginCapture(ctx->compute, hipStreamCaptureModeThreadLocal));
       vx_status cst = enqueue_batch(ctx, *gc->run, cfg, ks, J, ctx->compute, ctx->host_acc);
@@ -533,13 +713,13 @@ vx_status join_batch(vx_ctx* ctx, const vx_batch_join* d, vx_join_out* out) {
     VX_CHECK(!(f & kFlagFull), VX_ECAPACITY, "batch: table full (internal sizing error)");
     s.kernel_ms = ms;
     s.kernel_launches = 2;
-    s.table_bytes = gc->run->plan.slots << gc->run->plan.slot_shift;
+    s.table_bytes = (gc->run->plan.slots << gc->run->plan.slot_shift) + gc->run->plan.direct_bytes;
     s.chunk_rows = cfg.tile_rows;
     s.n_buffers = cfg.block;
     s.imbalance = cfg.load_factor;
   } else {
     BatchRun r;
-    VX_TRY(setup_run(ctx, d, cfg, ks, ps, &r));
+    VX_TRY(setup_run(ctx, d, cfg, ks, ps, di, &r));
     uint32_t sw = (1u << r.plan.slot_shift) / 4;
     fill_zero((uint64_t*)r.counters, r.counter_words, ctx->compute);
     fill_zero((uint64_t*)ctx->dev_flags, 1, ctx->compute);
@@ -547,10 +727,14 @@ vx_status join_batch(vx_ctx* ctx, const vx_batch_join* d, vx_join_out* out) {
     VX_HIP(hipEventRecord(a, ctx->compute));
     for (uint32_t j = 0; j < J; ++j) {
       const BatchJob& jb = r.plan.jobs[j];
-      uint64_t cap = jb.mask + 1;
-      unsigned ig = (unsigned)std::min<uint64_t>((cap + 255) / 256, (uint64_t)ctx->cu_count * 16);
-      hipLaunchKernelGGL(k_batch_init, dim3(ig), dim3(256), 0, ctx->compute, (uint32_t*)jb.slots, cap, sw,
-                         (uint32_t)ks);
+      if (jb.direct) {
+        fill_zero((uint64_t*)jb.slots, direct_region_bytes(jb.nb, jb.pay_size) / 8, ctx->compute);
+      } else {
+        uint64_t cap = jb.mask + 1;
+        unsigned ig = (unsigned)std::min<uint64_t>((cap + 255) / 256, (uint64_t)ctx->cu_count * 16);
+        hipLaunchKernelGGL(k_batch_init, dim3(ig), dim3(256), 0, ctx->compute, (uint32_t*)jb.slots, cap, sw,
+                           (uint32_t)ks);
+      }
       unsigned gb = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((jb.nb + cfg.tile_rows - 1) / cfg.tile_rows,
                                                                        (uint64_t)ctx->cu_count * 8));
       unsigned gp = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((jb.np + cfg.tile_rows - 1) / cfg.tile_rows,
@@ -579,7 +763,7 @@ vx_status join_batch(vx_ctx* ctx, const vx_batch_join* d, vx_join_out* out) {
     order = r.plan.job_of;
     s.kernel_ms = ms;
     s.kernel_launches = 3 * (uint64_t)J;
-    s.table_bytes = r.plan.slots << r.plan.slot_shift;
+    s.table_bytes = (r.plan.slots << r.plan.slot_shift) + r.plan.direct_bytes;
   }
   // accumulators are in tile order: entry i belongs to the caller's job job_of[i]
   const std::vector<uint32_t>& job_of = d->mode == 0 ? g_graphs[ctx]->run->plan.job_of : order;

@@ -86,3 +86,56 @@ def test_batch_int64_keys(gpu, ctx):
     _say("batch int64")
     got, _ = ctx.join_batch([dev(x) for x in bk], [dev(x) for x in bp], [dev(x) for x in pk])
     assert got == [oracle.join_agg(a, [b], c, []) for a, b, c in zip(bk, bp, pk)]
+
+
+def test_batch_direct_tables(gpu, ctx):
+    """Jobs whose build keys fill their range exactly take a direct table: a mix of such jobs
+    (int32 ranges anywhere, one starting at the empty-marker key) and hash-table jobs, in both
+    modes, and with the keys changed in place between calls (the choice is made again)."""
+    import torch
+    i32 = np.iinfo(np.int32)
+    rng = np.random.default_rng(8)
+    bk, bp, pk = [], [], []
+    for j, (n, base) in enumerate([(5000, 0), (3000, -1500), (777, i32.min), (4096, 10**9), (2000, None)]):
+        k = (rng.permutation(n) + base).astype(np.int32) if base is not None else \
+            np.unique(rng.integers(-10**6, 10**6, n)).astype(np.int32)
+        bk.append(k)
+        bp.append(rng.integers(i32.min, i32.max, len(k)).astype(np.int32))
+        lo = int(k.min())
+        pk.append(rng.integers(max(i32.min, lo - 500), min(i32.max, lo + 2 * len(k)), 6 * len(k)).astype(np.int32))
+    exp = [oracle.join_agg(a, [b], c, []) for a, b, c in zip(bk, bp, pk)]
+    dk = [dev(x) for x in bk]
+    args = (dk, [dev(x) for x in bp], [dev(x) for x in pk])
+    for mode in (0, 1):
+        _say("batch direct tables, mode", mode)
+        got, st = ctx.join_batch(*args, mode=mode, tile_rows=1024, block=256, load_factor=0.5)
+        assert got == exp
+    # job 0's keys no longer fill their range (one key moved far away), job 4's now do
+    bk[0][0] = 10**8
+    bk[4] = np.arange(len(bk[4]), dtype=np.int32) * 1 + 7
+    dk[0].copy_(torch.from_numpy(bk[0]))
+    dk[4].copy_(torch.from_numpy(bk[4]))
+    exp = [oracle.join_agg(a, [b], c, []) for a, b, c in zip(bk, bp, pk)]
+    got, _ = ctx.join_batch(*args, tile_rows=1024, block=256, load_factor=0.5)
+    assert got == exp
+
+
+def test_batch_direct_duplicate_detected(gpu, ctx):
+    """Keys 0, 1, 1, 3 fill the range 0..3 by count but not by value: the direct table's bitmap
+    sees the second 1."""
+    for mode in (0, 1):
+        with pytest.raises(gpu.VxError) as ei:
+            ctx.join_batch([dev(np.array([0, 1, 1, 3], np.int32))], [None], [dev(np.array([2], np.int32))],
+                           mode=mode, tile_rows=64, block=256, load_factor=0.5)
+        assert ei.value.status == gpu.VX_EDUPKEY
+
+
+def test_batch_direct_int64(gpu, ctx):
+    rng = np.random.default_rng(9)
+    bk = [(rng.permutation(n) + off).astype(np.int64) for n, off in ((3000, -2**62), (1024, 2**40), (1, 5))]
+    bp = [rng.integers(-2**40, 2**40, len(k)).astype(np.int64) for k in bk]
+    pk = [np.concatenate([k[::3], k.min() - 1 - np.arange(50), k.max() + 1 + np.arange(50)]).astype(np.int64)
+          for k in bk]
+    _say("batch direct int64")
+    got, _ = ctx.join_batch([dev(x) for x in bk], [dev(x) for x in bp], [dev(x) for x in pk])
+    assert got == [oracle.join_agg(a, [b], c, []) for a, b, c in zip(bk, bp, pk)]
