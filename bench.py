@@ -26,8 +26,8 @@ HBM_PEAK_GBS = 8000.0       # MI355X HBM3E datasheet peak
 # scaled by what the same counters read for a plain 1 GiB device read and write (the summaries
 # under profiles/ give the commands).  Valid for the kernel source they were measured on.
 TRAFFIC_BYTES = {"k_probe_stream": 1.5647e9,    # 8,388,608 probe rows per launch
-                 "k_probe_plain": 1.8964e9,     # 16,777,216 probe rows per launch
-                 "k_star": 2.1670e9,            # 16,666,667 fact rows per launch
+                 "k_probe_plain": 6.4121e8,     # 16,777,216 probe rows per launch (direct table)
+                 "k_star": 1.9347e9,            # 16,666,667 fact rows per launch (direct dimension tables)
                  "batch_graph": 2.2125e11,      # one graph launch: build phase + probe phase, all 256 jobs
                  "k_pj_stream": 4.976e8,        # 8,388,608 probe rows per launch (mean over the partitioners)
                  "k_probe_rows": 1.4712e9,      # 8,388,608 probe rows per launch, output rows included
@@ -330,7 +330,7 @@ def run_plain(args):
     ms, res = _timed(lambda: ctx.join_plain(d[0], [d[1]], d[2]), args, torch)
     agg, st = res[0]
     k_ms = sum(r[1]["kernel_ms"] for r in res) / sum(r[1]["kernel_launches"] for r in res)
-    # probe kernel: 4 B key + one 8 B slot per probe row (the 16 MiB table lives in MALL)
+    # probe kernel: 4 B key + one 8 B slot per probe row
     achieved = np_ * 12 / (k_ms * 1e6)
     t0 = time.perf_counter()
     exp = oracle.join_agg(bk, [bp], pk, [])

@@ -150,14 +150,15 @@ typedef struct {
 
 enum {
   VX_UNIQUE = 1,  /* keys are unique; a duplicate fails the build with VX_EDUPKEY */
-  VX_PREAGG = 2   /* duplicates allowed: the table stores per key its count and payload sums */
+  VX_PREAGG = 2,  /* duplicates allowed: the table stores per key its count and payload sums */
+  VX_HASHED = 4   /* OR-ed with one of the above: always a hash table, never a direct one */
 };
 
 typedef struct {
   vx_col key;
   const vx_col* pay;   /* n_pay payload columns (NULL if n_pay == 0) */
   uint32_t n_pay;      /* <= 4 */
-  uint32_t flags;      /* VX_UNIQUE or VX_PREAGG */
+  uint32_t flags;      /* VX_UNIQUE or VX_PREAGG, optionally | VX_HASHED */
   uint64_t n;          /* rows */
   float load_factor;   /* 0 = default (0.5); table capacity is a power of two */
   uint32_t reserved;
@@ -170,6 +171,15 @@ typedef struct vx_table vx_table;
  * GPU memory while the other side streams, Sec. 5.1, 7.1).  Host-resident
  * build columns are read in place by zero-copy.  The table is carved from the
  * arena and owned by the library until vx_table_destroy.
+ *
+ * Direct tables: when the keys are device-resident and VX_HASHED is not set,
+ * the build first measures their range (min..max, leaving out the key equal to
+ * the table's empty marker, INT32_MIN or INT64_MIN, which has a record of its
+ * own).  If the range is no wider than the hash table's capacity at the load
+ * factor, key k is stored in slot k - min instead of a hashed slot, with a
+ * power-of-two capacity no smaller than the range.  Results are the same
+ * either way; a probe then reads one slot, or none for keys outside the range.
+ * Host-resident keys always get a hash table.
  */
 vx_status vx_build(vx_ctx* ctx, const vx_build_desc* desc, vx_table** out);
 vx_status vx_table_destroy(vx_table* table);

@@ -25,7 +25,7 @@ VX_OK, VX_EINVAL, VX_EBUDGET, VX_ENOMEM, VX_EHIP, VX_ENOTPINNED, VX_ECAPACITY, V
 STATUS_NAMES = ["VX_OK", "VX_EINVAL", "VX_EBUDGET", "VX_ENOMEM", "VX_EHIP", "VX_ENOTPINNED",
                 "VX_ECAPACITY", "VX_EUNSUPPORTED", "VX_EDUPKEY"]
 VX_I32, VX_I64 = 1, 2
-VX_UNIQUE, VX_PREAGG = 1, 2
+VX_UNIQUE, VX_PREAGG, VX_HASHED = 1, 2, 4
 VX_LATE_AUTO, VX_LATE_SDMA, VX_LATE_ZC, VX_LATE_PAPER = -1, 0, 1, 2
 VX_JOIN_PLAIN, VX_JOIN_STAR, VX_JOIN_BATCH, VX_JOIN_PARTITIONED, VX_JOIN_RADIX = 1, 2, 3, 4, 5
 (VX_PART_AUTO, VX_PART_RADIX_HASH, VX_PART_RADIX_BITS, VX_PART_LEARNED, VX_PART_QUANTILE,
@@ -323,22 +323,23 @@ class Context:
         return int(lib().vx_ctx_arena_used(self.h))
 
     # ------------------------------------------------------------------ build / probe
-    def build(self, key, pays=(), unique=True, load_factor=0.0):
+    def build(self, key, pays=(), unique=True, load_factor=0.0, hashed=False):
         pa, npay = _cols(pays)
-        d = BuildDesc(col(key), pa, npay, VX_UNIQUE if unique else VX_PREAGG, _len(key),
-                      float(load_factor), 0)
+        d = BuildDesc(col(key), pa, npay, (VX_UNIQUE if unique else VX_PREAGG) | (VX_HASHED if hashed else 0),
+                      _len(key), float(load_factor), 0)
         h = C.c_void_p()
         _check(lib().vx_build(self.h, C.byref(d), C.byref(h)))
         return Table(self, h, npay, (pa, key, pays))
 
     def join_plain(self, bkey, bpays, pkey, ppays=(), unique=True, late_mat=VX_LATE_AUTO,
-                   chunk_rows=0, n_buffers=0, load_factor=0.0):
+                   chunk_rows=0, n_buffers=0, load_factor=0.0, hashed=False):
         """One-shot build + probe. Returns ([count, sums...], stats dict)."""
         bp, nbp = _cols(bpays)
         pp, npp = _cols(ppays)
         d = JoinDesc()
         d.kind = VX_JOIN_PLAIN
-        d.u.plain.build = BuildDesc(col(bkey), bp, nbp, VX_UNIQUE if unique else VX_PREAGG,
+        d.u.plain.build = BuildDesc(col(bkey), bp, nbp,
+                                    (VX_UNIQUE if unique else VX_PREAGG) | (VX_HASHED if hashed else 0),
                                     _len(bkey), float(load_factor), 0)
         d.u.plain.probe = ProbeDesc(col(pkey), pp, npp, late_mat, _len(pkey), int(chunk_rows),
                                     int(n_buffers), 0, None, 0)

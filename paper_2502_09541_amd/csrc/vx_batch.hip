@@ -51,12 +51,6 @@ struct BatchJob {
 
 constexpr uint32_t kMaxBatchJobs = 4096;
 
-// order-preserving unsigned form of a key (sign-extended, sign bit flipped)
-template <typename K>
-__device__ __forceinline__ unsigned long long key_ord(K k) {
-  return (unsigned long long)(long long)k ^ 0x8000000000000000ull;
-}
-
 template <typename K>
 __device__ __forceinline__ void batch_build_rows(const BatchJob& jb, uint64_t r0, uint64_t r1,
                                                  uint32_t slot_shift, unsigned int* flags) {

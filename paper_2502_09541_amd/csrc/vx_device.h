@@ -10,6 +10,24 @@ __device__ __forceinline__ uint64_t key_bits(K k) {
   return (uint64_t)(typename KeyTraits<K>::U)k;
 }
 
+// order-preserving unsigned form of a key (sign-extended, sign bit flipped)
+template <typename K>
+__device__ __forceinline__ unsigned long long key_ord(K k) {
+  return (unsigned long long)(long long)k ^ 0x8000000000000000ull;
+}
+
+// First slot of k's probe sequence in t.  False when k cannot be in a direct table (outside
+// its key range); then no slot is read.
+template <typename K>
+__device__ __forceinline__ bool first_slot(const TableView& t, K k, uint64_t& h) {
+  if (t.direct) {
+    h = key_ord(k) - t.kmin_ord;
+    return h < t.direct_range;
+  }
+  h = slot_of(key_bits(k), t.log2cap);
+  return true;
+}
+
 __device__ __forceinline__ long long load_signed(const void* base, uint64_t idx, uint32_t size) {
   if (size == 4) return (long long)((const int*)base)[idx];
   return ((const long long*)base)[idx];
@@ -48,7 +66,8 @@ __device__ __forceinline__ const uint8_t* find_slot(const TableView& t, K k) {
   using U = typename KeyTraits<K>::U;
   const U kEmpty = KeyTraits<K>::kEmpty;
   const U kb = (U)k;
-  uint64_t h = slot_of(key_bits(k), t.log2cap);
+  uint64_t h;
+  if (!first_slot(t, k, h)) return nullptr;
   for (uint64_t step = 0; step <= t.mask; ++step) {
     const uint8_t* slot = t.slots + (h << t.slot_shift);
     U sk = *(const U*)slot;
@@ -77,7 +96,11 @@ __device__ __forceinline__ void global_preagg_add(const TableView& t, K k, unsig
     for (uint32_t p = 0; p < t.n_pay; ++p) atomicAdd(t.side + 1 + p, sums[p]);
     return;
   }
-  uint64_t h = slot_of(key_bits(k), t.log2cap);
+  uint64_t h;
+  if (!first_slot(t, k, h)) {
+    atomicOr(flags, kFlagFull);
+    return;
+  }
   for (uint64_t step = 0; step <= t.mask; ++step) {
     uint8_t* slot = t.slots + (h << t.slot_shift);
     U prev = atomicCAS((U*)slot, kEmpty, kb);

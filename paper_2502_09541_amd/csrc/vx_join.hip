@@ -69,9 +69,12 @@ __global__ void k_build_unique_lane(TableView t, BuildCols c, uint64_t n, unsign
       side_add<K>(t, c, i, flags, true);
       continue;
     }
-    uint64_t h = slot_of(key_bits(k), t.log2cap);
+    uint64_t h;
     bool done = false;
-    for (uint64_t step = 0; step <= t.mask; ++step) {
+    // a key outside a direct table's range cannot occur (the range is measured over these keys);
+    // if it did, the table is reported full
+    const uint64_t steps = first_slot(t, k, h) ? t.mask + 1 : 0;
+    for (uint64_t step = 0; step < steps; ++step) {
       uint8_t* slot = t.slots + (h << t.slot_shift);
       U prev = atomicCAS((U*)slot, kEmpty, kb);
       if (prev == kEmpty) {
@@ -88,6 +91,57 @@ __global__ void k_build_unique_lane(TableView t, BuildCols c, uint64_t n, unsign
     }
     if (!done) atomicOr(flags, kFlagFull);
   }
+}
+
+// Direct table: each row's slot is fixed (key - min), so key and payloads are written with plain
+// stores, no compare-and-swap.  Two rows with one key write the same slot; k_direct_check then
+// finds fewer filled slots than rows and raises the duplicate flag.
+template <typename K>
+__global__ void k_build_direct(TableView t, BuildCols c, uint64_t n, unsigned int* flags) {
+  using U = typename KeyTraits<K>::U;
+  const U kEmpty = KeyTraits<K>::kEmpty;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const K k = ((const K*)c.key)[i];
+    const U kb = (U)k;
+    if (kb == kEmpty) {
+      side_add<K>(t, c, i, flags, true);
+      continue;
+    }
+    uint64_t h;
+    if (!first_slot(t, k, h)) {    // cannot happen: the range was measured over these keys
+      atomicOr(flags, kFlagFull);
+      continue;
+    }
+    uint8_t* slot = t.slots + (h << t.slot_shift);
+    *(U*)slot = kb;
+    write_unique_payloads<K>(t, slot, c, i);
+  }
+}
+
+// Filled slots of a direct table's range (one atomic per workgroup).
+template <typename K>
+__global__ void __launch_bounds__(256) k_direct_count(TableView t, unsigned long long* filled) {
+  using U = typename KeyTraits<K>::U;
+  __shared__ unsigned long long part[4];
+  unsigned long long c = 0;
+  for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < t.direct_range;
+       s += (uint64_t)gridDim.x * blockDim.x)
+    c += *(const U*)(t.slots + (s << t.slot_shift)) != KeyTraits<K>::kEmpty;
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) c += part[w];
+    if (c) atomicAdd(filled, c);
+  }
+}
+
+// n_rows rows were inserted: the filled slots plus the empty-marker key's rows (counted in the
+// side record) fall short of them exactly when two rows shared a key.
+__global__ void k_direct_check(const unsigned long long* filled, const unsigned long long* side,
+                               uint64_t n_rows, unsigned int* flags) {
+  if (threadIdx.x == 0 && filled[0] + side[0] != n_rows) atomicOr(flags, kFlagDup);
 }
 
 // A group of G lanes per row: the group loads G consecutive slots, ballots for the key
@@ -126,9 +180,10 @@ __global__ void k_build_unique_group(TableView t, BuildCols c, uint64_t n, unsig
         if (gl == 0) side_add<K>(t, c, row, flags, true);
         continue;
       }
-      uint64_t h = slot_of(key_bits(k), t.log2cap);
+      uint64_t h;
       bool done = false;
-      for (uint64_t step = 0; step <= t.mask; step += G) {
+      const uint64_t steps = first_slot(t, k, h) ? t.mask + 1 : 0;   // uniform within the group
+      for (uint64_t step = 0; step < steps; step += G) {
         uint64_t pos = (h + gl) & t.mask;
         uint8_t* slot = t.slots + (pos << t.slot_shift);
         U sk = __atomic_load_n((U*)slot, __ATOMIC_RELAXED);
@@ -275,8 +330,9 @@ __global__ void __launch_bounds__(256) k_probe(TableView t, ProbeCols q, unsigne
         }
         continue;
       }
-      uint64_t h = slot_of(key_bits(keys[j]), t.log2cap);
-      for (uint64_t step = 0; step <= t.mask; ++step) {
+      uint64_t h;
+      const uint64_t steps = first_slot(t, keys[j], h) ? t.mask + 1 : 0;
+      for (uint64_t step = 0; step < steps; ++step) {
         const uint8_t* slot = t.slots + (h << t.slot_shift);
         U sk = *(const U*)slot;
         if (sk == kb) {
@@ -363,8 +419,9 @@ __global__ void __launch_bounds__(256) k_probe_rows(TableView t, ProbeCols q, un
           for (uint32_t p = 0; p < nb; ++p) bv[j][p] = (long long)t.side[1 + p];   // the one row's payload
         }
       } else {
-        uint64_t h = slot_of(key_bits(keys[j]), t.log2cap);
-        for (uint64_t step = 0; step <= t.mask; ++step) {
+        uint64_t h;
+        const uint64_t steps = first_slot(t, keys[j], h) ? t.mask + 1 : 0;
+        for (uint64_t step = 0; step < steps; ++step) {
           const uint8_t* slot = t.slots + (h << t.slot_shift);
           U sk = *(const U*)slot;
           if (sk == kb) {
@@ -420,6 +477,60 @@ __global__ void __launch_bounds__(256) k_probe_rows(TableView t, ProbeCols q, un
   block_flush<NACC>(acc, 1 + (int)nb + (int)q.n_pay, acc_out);
 }
 
+// ---------------------------------------------------------------- key range
+
+__global__ void k_range_init(unsigned long long* mm) {
+  if (threadIdx.x == 0) {
+    mm[0] = ~0ull;
+    mm[1] = 0;
+  }
+}
+
+// Min and max of the keys' order-preserving forms, the empty-marker key left out (it lives in
+// the side record, not in a slot).
+template <typename K>
+__global__ void __launch_bounds__(256) k_key_range(const K* key, uint64_t n, unsigned long long* mm) {
+  using U = typename KeyTraits<K>::U;
+  __shared__ unsigned long long rmin[4], rmax[4];
+  unsigned long long mn = ~0ull, mx = 0;
+  auto take = [&](K k) {
+    if ((U)k == KeyTraits<K>::kEmpty) return;
+    const unsigned long long o = key_ord(k);
+    mn = o < mn ? o : mn;
+    mx = o > mx ? o : mx;
+  };
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {      // four loads in flight per lane
+    const K a = __builtin_nontemporal_load(key + i), b = __builtin_nontemporal_load(key + i + stride);
+    const K c = __builtin_nontemporal_load(key + i + 2 * stride), d = __builtin_nontemporal_load(key + i + 3 * stride);
+    take(a);
+    take(b);
+    take(c);
+    take(d);
+  }
+  for (; i < n; i += stride) take(__builtin_nontemporal_load(key + i));
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long a = __shfl_xor(mn, o, 64), b = __shfl_xor(mx, o, 64);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    rmin[wave] = mn;
+    rmax[wave] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+      mn = rmin[w] < mn ? rmin[w] : mn;
+      mx = rmax[w] > mx ? rmax[w] : mx;
+    }
+    if (mn != ~0ull) atomicMin(mm, mn);
+    if (mx != 0) atomicMax(mm + 1, mx);
+  }
+}
+
 // ---------------------------------------------------------------- host side
 
 static int ilog2(uint64_t v) {
@@ -429,7 +540,8 @@ static int ilog2(uint64_t v) {
 }
 
 vx_status make_table(vx_ctx* ctx, int32_t key_type, uint32_t flags, const int32_t* pay_types,
-                     uint32_t n_pay, uint64_t expected_rows, float load_factor, vx_table** out) {
+                     uint32_t n_pay, uint64_t expected_rows, float load_factor, vx_table** out,
+                     const KeyRange* kr) {
   *out = nullptr;
   VX_CHECK(n_pay <= kMaxPay, VX_EINVAL, "build: at most %u payload columns", kMaxPay);
   int ks = elsize_of(key_type);
@@ -441,6 +553,15 @@ vx_status make_table(vx_ctx* ctx, int32_t key_type, uint32_t flags, const int32_
   uint64_t cap = 64;
   while (cap < want) cap <<= 1;
   TableView v{};
+  if (kr && kr->known && kr->max_ord >= kr->min_ord && kr->max_ord - kr->min_ord < cap) {
+    const uint64_t range = kr->max_ord - kr->min_ord + 1;
+    uint64_t dcap = 64;
+    while (dcap < range) dcap <<= 1;
+    cap = dcap;
+    v.direct = 1;
+    v.kmin_ord = kr->min_ord;
+    v.direct_range = range;
+  }
   v.n_pay = n_pay;
   v.preagg = preagg ? 1 : 0;
   v.key_size = (uint32_t)ks;
@@ -529,6 +650,28 @@ static unsigned grid_for(vx_ctx* ctx, uint64_t work_items, uint64_t per_block, u
   return (unsigned)blocks;
 }
 
+vx_status key_range(vx_ctx* ctx, int32_t key_type, const void* dev_keys, uint64_t n, KeyRange* out) {
+  *out = KeyRange{};
+  if (n == 0) return VX_OK;
+  unsigned long long* mm = (unsigned long long*)ctx->dev_acc;   // free between executor steps
+  hipLaunchKernelGGL(k_range_init, dim3(1), dim3(64), 0, ctx->compute, mm);
+  const unsigned g = grid_for(ctx, n, 256 * 16, 1);   // few workgroups: their atomics share two words
+  if (key_type == VX_I64)
+    hipLaunchKernelGGL(k_key_range<int64_t>, dim3(g), dim3(256), 0, ctx->compute, (const int64_t*)dev_keys, n, mm);
+  else
+    hipLaunchKernelGGL(k_key_range<int32_t>, dim3(g), dim3(256), 0, ctx->compute, (const int32_t*)dev_keys, n, mm);
+  VX_HIP(hipGetLastError());
+  unsigned long long h[2];
+  VX_HIP(hipMemcpyAsync(h, mm, sizeof h, hipMemcpyDeviceToHost, ctx->compute));
+  VX_HIP(hipStreamSynchronize(ctx->compute));
+  if (h[0] <= h[1]) {      // at least one key besides the empty marker
+    out->known = true;
+    out->min_ord = h[0];
+    out->max_ord = h[1];
+  }
+  return VX_OK;
+}
+
 vx_status table_insert(vx_ctx* ctx, vx_table* t, const ColInfo& key, const ColInfo* pays,
                        uint64_t n, hipStream_t s, int group_lanes) {
   if (n == 0) return VX_OK;
@@ -543,6 +686,22 @@ vx_status table_insert(vx_ctx* ctx, vx_table* t, const ColInfo& key, const ColIn
     unsigned g = grid_for(ctx, n, kPreaggTile, 3);
     if (k64) hipLaunchKernelGGL(k_build_preagg<int64_t>, dim3(g), dim3(256), 0, s, t->view, c, n, ctx->dev_flags);
     else hipLaunchKernelGGL(k_build_preagg<int32_t>, dim3(g), dim3(256), 0, s, t->view, c, n, ctx->dev_flags);
+  } else if (t->view.direct) {
+    // one insert per direct table: the duplicate check counts every slot against every row
+    VX_CHECK(t->n_rows == 0, VX_EINVAL, "build: a direct table takes its rows in one insert");
+    unsigned long long* filled = (unsigned long long*)ctx->dev_acc;
+    fill_zero((uint64_t*)filled, 1, s);
+    const unsigned g = grid_for(ctx, n, 256, 8);
+    const unsigned gc = grid_for(ctx, t->view.direct_range, 256 * 16, 2);
+    if (k64) {
+      hipLaunchKernelGGL(k_build_direct<int64_t>, dim3(g), dim3(256), 0, s, t->view, c, n, ctx->dev_flags);
+      hipLaunchKernelGGL(k_direct_count<int64_t>, dim3(gc), dim3(256), 0, s, t->view, filled);
+    } else {
+      hipLaunchKernelGGL(k_build_direct<int32_t>, dim3(g), dim3(256), 0, s, t->view, c, n, ctx->dev_flags);
+      hipLaunchKernelGGL(k_direct_count<int32_t>, dim3(gc), dim3(256), 0, s, t->view, filled);
+    }
+    hipLaunchKernelGGL(k_direct_check, dim3(1), dim3(64), 0, s, filled, (const unsigned long long*)t->view.side,
+                       n, ctx->dev_flags);
   } else {
     unsigned g = grid_for(ctx, n, 256, 8);
     switch (group_lanes) {
@@ -753,8 +912,9 @@ vx_status build_impl(vx_ctx* ctx, const vx_build_desc* d, vx_table** out, double
   double t0 = now_ms();
   VX_CHECK(d != nullptr && out != nullptr, VX_EINVAL, "vx_build: null argument");
   *out = nullptr;
-  VX_CHECK(d->flags == VX_UNIQUE || d->flags == VX_PREAGG, VX_EINVAL,
-           "vx_build: flags must be VX_UNIQUE or VX_PREAGG");
+  const uint32_t kind = d->flags & ~(uint32_t)VX_HASHED;
+  VX_CHECK(kind == VX_UNIQUE || kind == VX_PREAGG, VX_EINVAL,
+           "vx_build: flags must be VX_UNIQUE or VX_PREAGG, optionally with VX_HASHED");
   VX_CHECK(d->n_pay <= kMaxPay, VX_EINVAL, "vx_build: at most %u payload columns", kMaxPay);
   VX_CHECK(d->n_pay == 0 || d->pay != nullptr, VX_EINVAL, "vx_build: pay is NULL");
   ColInfo kc;
@@ -766,8 +926,13 @@ vx_status build_impl(vx_ctx* ctx, const vx_build_desc* d, vx_table** out, double
     pt[p] = d->pay[p].type;
   }
   VX_HIP(hipSetDevice(ctx->device));
+  // Device-resident keys are measured first: keys that fill a range no wider than the hash
+  // table get a direct table.  Host-resident keys are not (the pass would cross the host link).
+  KeyRange kr;
+  if (!(d->flags & VX_HASHED) && kc.where == Where::Device)
+    VX_TRY(key_range(ctx, d->key.type, kc.dev, d->n, &kr));
   vx_table* t = nullptr;
-  VX_TRY(make_table(ctx, d->key.type, d->flags, pt, d->n_pay, d->n, d->load_factor, &t));
+  VX_TRY(make_table(ctx, d->key.type, kind, pt, d->n_pay, d->n, d->load_factor, &t, &kr));
   fill_zero((uint64_t*)ctx->dev_flags, 1, ctx->compute);
   vx_status st = table_insert(ctx, t, kc, pc, d->n, ctx->compute, build_group_lanes());
   if (st == VX_OK) st = check_flags(ctx, "vx_build");

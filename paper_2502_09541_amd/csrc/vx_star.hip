@@ -46,9 +46,10 @@ __global__ void k_build_dim(TableView t, const void* key, const void* filt, uint
       if (grp) atomicAdd(t.side + 1, (unsigned long long)(long long)g);
       continue;
     }
-    uint64_t h = slot_of(key_bits(k), t.log2cap);
+    uint64_t h;
     bool done = false;
-    for (uint64_t step = 0; step <= t.mask; ++step) {
+    const uint64_t steps = first_slot(t, k, h) ? t.mask + 1 : 0;
+    for (uint64_t step = 0; step < steps; ++step) {
       uint8_t* slot = t.slots + (h << t.slot_shift);
       U prev = atomicCAS((U*)slot, kEmpty, kb);
       if (prev == kEmpty) {
@@ -243,10 +244,17 @@ vx_status join_star(vx_ctx* ctx, const vx_star_join* d, vx_join_out* out) {
       free_dims();
       return st;
     }
+    // device-resident keys that fill a narrow range get direct tables (slot = key - min)
+    KeyRange kr;
+    if (kc.where == Where::Device) st = key_range(ctx, ktype, kc.dev, sd.n, &kr);
+    if (st != VX_OK) {
+      free_dims();
+      return st;
+    }
     // uniqueness of the dimension's keys (primary key), over every row
     {
       vx_table* u = nullptr;
-      st = make_table(ctx, ktype, VX_UNIQUE, nullptr, 0, sd.n, 0.5f, &u);
+      st = make_table(ctx, ktype, VX_UNIQUE, nullptr, 0, sd.n, 0.5f, &u, &kr);
       if (st == VX_OK) {
         fill_zero((uint64_t*)ctx->dev_flags, 1, ctx->compute);
         st = table_insert(ctx, u, kc, nullptr, sd.n, ctx->compute, 1);
@@ -261,7 +269,7 @@ vx_status join_star(vx_ctx* ctx, const vx_star_join* d, vx_join_out* out) {
     }
     int32_t pt[1] = {VX_I32};
     // worst case every row passes; size the table for all rows
-    st = make_table(ctx, ktype, VX_UNIQUE, pt, sd.group.data ? 1 : 0, sd.n, 0.5f, &dims[k].t);
+    st = make_table(ctx, ktype, VX_UNIQUE, pt, sd.group.data ? 1 : 0, sd.n, 0.5f, &dims[k].t, &kr);
     if (st != VX_OK) {
       free_dims();
       return st;

@@ -43,6 +43,12 @@ struct TableView {
   uint32_t pay_size[kMaxPay]; // 4 or 8 (unique); 8 (pre-aggregated sums)
   uint32_t preagg;
   uint32_t key_size;
+  // Direct layout: key k lives in slot ord(k) - kmin_ord, where ord is the order-preserving
+  // unsigned form of the key, and keys outside [kmin, kmin + direct_range) are absent.  A slot
+  // then holds k or the empty marker, never another key, so every probe ends at its first slot.
+  uint32_t direct;
+  unsigned long long kmin_ord;
+  uint64_t direct_range;
 };
 
 }  // namespace vx
@@ -60,9 +66,21 @@ struct vx_table {
 };
 
 namespace vx {
+// The build keys' range in order-preserving unsigned form (the empty-marker key excluded), or
+// `known == false` when it was not measured.
+struct KeyRange {
+  bool known = false;
+  unsigned long long min_ord = 0, max_ord = 0;
+};
+
 // Launch helpers implemented in vx_join.hip and used by the other executors.
+// make_table lays the table out directly (slot = key - min) when `kr` holds a measured range no
+// wider than the hash table's capacity, so the direct table is never the larger of the two.
 vx_status make_table(vx_ctx* ctx, int32_t key_type, uint32_t flags, const int32_t* pay_types,
-                     uint32_t n_pay, uint64_t expected_rows, float load_factor, vx_table** out);
+                     uint32_t n_pay, uint64_t expected_rows, float load_factor, vx_table** out,
+                     const KeyRange* kr = nullptr);
+// Measure the range of n device-resident keys (one pass over them, then a 16-byte read back).
+vx_status key_range(vx_ctx* ctx, int32_t key_type, const void* dev_keys, uint64_t n, KeyRange* out);
 vx_status table_insert(vx_ctx* ctx, vx_table* t, const ColInfo& key, const ColInfo* pays,
                        uint64_t n, hipStream_t s, int group_lanes);
 vx_status check_flags(vx_ctx* ctx, const char* what);

@@ -38,12 +38,14 @@ def _say(*a):
     print(*a, flush=True)
 
 
+@pytest.mark.parametrize("hashed", [False, True])
 @pytest.mark.parametrize("lanes", ["1", "4", "8"])
-def test_plain_device_resident_ragged(gpu, ctx, lanes, monkeypatch):
+def test_plain_device_resident_ragged(gpu, ctx, lanes, hashed, monkeypatch):
+    """The recipe's keys fill their range, so the build is laid out directly unless VX_HASHED."""
     monkeypatch.setenv("VX_BUILD_LANES", lanes)
     bkey, bpay, pkey = datagen.plain_join(10007, 300_001, seed=3)
-    _say("plain ragged lanes", lanes)
-    got, st = ctx.join_plain(dev(bkey), [dev(bpay)], dev(pkey))
+    _say("plain ragged lanes", lanes, "hashed", hashed)
+    got, st = ctx.join_plain(dev(bkey), [dev(bpay)], dev(pkey), hashed=hashed)
     assert got == oracle.join_agg(bkey, [bpay], pkey, [])
 
 
@@ -51,9 +53,10 @@ def test_plain_full_size_device_resident(gpu, ctx):
     """Plain in-memory join at full size: 2^20 unique int32 build keys, 2^24 probes."""
     bkey, bpay, pkey = datagen.plain_join()
     _say("plain full size")
-    got, st = ctx.join_plain(dev(bkey), [dev(bpay)], dev(pkey))
     exp = oracle.join_agg(bkey, [bpay], pkey, [])
-    assert got == exp
+    for hashed in (False, True):
+        got, st = ctx.join_plain(dev(bkey), [dev(bpay)], dev(pkey), hashed=hashed)
+        assert got == exp
     assert 0.45 < got[0] / len(pkey) < 0.55
 
 
