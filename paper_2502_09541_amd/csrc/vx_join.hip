@@ -19,14 +19,20 @@ namespace vx {
 
 // ---------------------------------------------------------------- table init
 
+// Every slot gets the empty-marker key and zero payloads.  The slots are written as 16-byte
+// stores of four 32-bit words; a slot is 2^k >= 2 words and the capacity is >= 64, so the word
+// count is a multiple of 4.  The marker is INT32_MIN in word 0 of an int32 key, and for an int64
+// key (little-endian INT64_MIN) word 0 is zero and word 1 holds 0x80000000.
 __global__ void k_init_slots(uint32_t* slots, uint64_t capacity, uint32_t slot_words,
                              uint32_t key_size) {
-  for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < capacity;
-       s += (uint64_t)gridDim.x * blockDim.x) {
-    uint32_t* w = slots + s * slot_words;
-    for (uint32_t i = 0; i < slot_words; ++i) w[i] = 0;
-    if (key_size == 4) w[0] = 0x80000000u;
-    else w[1] = 0x80000000u;    // little-endian INT64_MIN: low word 0, high word 0x80000000
+  const uint32_t key_word = key_size == 4 ? 0 : 1;
+  const uint64_t quads = capacity * slot_words / 4;
+  for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < quads;
+       q += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = ((4 * q + j) & (slot_words - 1)) == key_word ? 0x80000000u : 0u;
+    ((uint4*)slots)[q] = make_uint4(v[0], v[1], v[2], v[3]);
   }
 }
 
@@ -94,7 +100,7 @@ __global__ void k_build_unique_lane(TableView t, BuildCols c, uint64_t n, unsign
 }
 
 // Direct table: each row's slot is fixed (key - min), so key and payloads are written with plain
-// stores, no compare-and-swap.  Two rows with one key write the same slot; k_direct_check then
+// stores, no compare-and-swap.  Two rows with one key write the same slot; k_direct_count then
 // finds fewer filled slots than rows and raises the duplicate flag.
 template <typename K>
 __global__ void k_build_direct(TableView t, BuildCols c, uint64_t n, unsigned int* flags) {
@@ -119,9 +125,13 @@ __global__ void k_build_direct(TableView t, BuildCols c, uint64_t n, unsigned in
   }
 }
 
-// Filled slots of a direct table's range (one atomic per workgroup).
+// Filled slots of a direct table's range: one atomic per workgroup into cnt[0], then a ticket in
+// cnt[1].  The last workgroup to take a ticket compares the total plus the empty-marker key's rows
+// (counted in the side record) with the rows inserted: they fall short exactly when two rows
+// shared a key.  cnt[0..1] start at zero.
 template <typename K>
-__global__ void __launch_bounds__(256) k_direct_count(TableView t, unsigned long long* filled) {
+__global__ void __launch_bounds__(256) k_direct_count(TableView t, unsigned long long* cnt,
+                                                      uint64_t n_rows, unsigned int* flags) {
   using U = typename KeyTraits<K>::U;
   __shared__ unsigned long long part[4];
   unsigned long long c = 0;
@@ -133,15 +143,13 @@ __global__ void __launch_bounds__(256) k_direct_count(TableView t, unsigned long
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int w = 1; w < (int)(blockDim.x >> 6); ++w) c += part[w];
-    if (c) atomicAdd(filled, c);
+    atomicAdd(cnt, c);
+    __threadfence();
+    if (atomicAdd(cnt + 1, 1ull) == gridDim.x - 1) {
+      const unsigned long long total = atomicAdd(cnt, 0ull);
+      if (total + atomicAdd(t.side, 0ull) != n_rows) atomicOr(flags, kFlagDup);
+    }
   }
-}
-
-// n_rows rows were inserted: the filled slots plus the empty-marker key's rows (counted in the
-// side record) fall short of them exactly when two rows shared a key.
-__global__ void k_direct_check(const unsigned long long* filled, const unsigned long long* side,
-                               uint64_t n_rows, unsigned int* flags) {
-  if (threadIdx.x == 0 && filled[0] + side[0] != n_rows) atomicOr(flags, kFlagDup);
 }
 
 // A group of G lanes per row: the group loads G consecutive slots, ballots for the key
@@ -479,15 +487,9 @@ __global__ void __launch_bounds__(256) k_probe_rows(TableView t, ProbeCols q, un
 
 // ---------------------------------------------------------------- key range
 
-__global__ void k_range_init(unsigned long long* mm) {
-  if (threadIdx.x == 0) {
-    mm[0] = ~0ull;
-    mm[1] = 0;
-  }
-}
-
 // Min and max of the keys' order-preserving forms, the empty-marker key left out (it lives in
-// the side record, not in a slot).
+// the side record, not in a slot).  Workgroup b writes its own pair to mm[2b], mm[2b + 1]
+// (~0 and 0 when it saw no key); the host reduces the pairs.
 template <typename K>
 __global__ void __launch_bounds__(256) k_key_range(const K* key, uint64_t n, unsigned long long* mm) {
   using U = typename KeyTraits<K>::U;
@@ -526,8 +528,8 @@ __global__ void __launch_bounds__(256) k_key_range(const K* key, uint64_t n, uns
       mn = rmin[w] < mn ? rmin[w] : mn;
       mx = rmax[w] > mx ? rmax[w] : mx;
     }
-    if (mn != ~0ull) atomicMin(mm, mn);
-    if (mx != 0) atomicMax(mm + 1, mx);
+    mm[2 * blockIdx.x] = mn;
+    mm[2 * blockIdx.x + 1] = mx;
   }
 }
 
@@ -608,7 +610,8 @@ vx_status make_table(vx_ctx* ctx, int32_t key_type, uint32_t flags, const int32_
   t->flags = flags;
   for (uint32_t p = 0; p < n_pay; ++p) t->pay_type[p] = (uint32_t)pay_types[p];
   t->view = v;
-  uint64_t blocks = std::min<uint64_t>((cap + 255) / 256, 8192);
+  const uint64_t quads = cap * slot_bytes / 16;   // 16-byte stores of k_init_slots
+  uint64_t blocks = std::min<uint64_t>((quads + 255) / 256, 8192);
   hipLaunchKernelGGL(k_init_slots, dim3((unsigned)blocks), dim3(256), 0, ctx->compute,
                      (uint32_t*)mem, cap, slot_bytes / 4, (uint32_t)ks);
   fill_zero((uint64_t*)v.side, 32, ctx->compute);
@@ -654,20 +657,25 @@ vx_status key_range(vx_ctx* ctx, int32_t key_type, const void* dev_keys, uint64_
   *out = KeyRange{};
   if (n == 0) return VX_OK;
   unsigned long long* mm = (unsigned long long*)ctx->dev_acc;   // free between executor steps
-  hipLaunchKernelGGL(k_range_init, dim3(1), dim3(64), 0, ctx->compute, mm);
-  const unsigned g = grid_for(ctx, n, 256 * 16, 1);   // few workgroups: their atomics share two words
+  const unsigned g = grid_for(ctx, n, 256 * 16, 2);
+  VX_CHECK(2ull * g <= ctx->dev_acc_words, VX_EINVAL, "key range: %u workgroups exceed the scratch", g);
   if (key_type == VX_I64)
     hipLaunchKernelGGL(k_key_range<int64_t>, dim3(g), dim3(256), 0, ctx->compute, (const int64_t*)dev_keys, n, mm);
   else
     hipLaunchKernelGGL(k_key_range<int32_t>, dim3(g), dim3(256), 0, ctx->compute, (const int32_t*)dev_keys, n, mm);
   VX_HIP(hipGetLastError());
-  unsigned long long h[2];
-  VX_HIP(hipMemcpyAsync(h, mm, sizeof h, hipMemcpyDeviceToHost, ctx->compute));
+  std::vector<unsigned long long> h(2 * (size_t)g);
+  VX_HIP(hipMemcpyAsync(h.data(), mm, h.size() * 8, hipMemcpyDeviceToHost, ctx->compute));
   VX_HIP(hipStreamSynchronize(ctx->compute));
-  if (h[0] <= h[1]) {      // at least one key besides the empty marker
+  unsigned long long mn = ~0ull, mx = 0;
+  for (unsigned b = 0; b < g; ++b) {
+    mn = std::min(mn, h[2 * b]);
+    mx = std::max(mx, h[2 * b + 1]);
+  }
+  if (mn <= mx) {      // at least one key besides the empty marker
     out->known = true;
-    out->min_ord = h[0];
-    out->max_ord = h[1];
+    out->min_ord = mn;
+    out->max_ord = mx;
   }
   return VX_OK;
 }
@@ -689,19 +697,17 @@ vx_status table_insert(vx_ctx* ctx, vx_table* t, const ColInfo& key, const ColIn
   } else if (t->view.direct) {
     // one insert per direct table: the duplicate check counts every slot against every row
     VX_CHECK(t->n_rows == 0, VX_EINVAL, "build: a direct table takes its rows in one insert");
-    unsigned long long* filled = (unsigned long long*)ctx->dev_acc;
-    fill_zero((uint64_t*)filled, 1, s);
+    unsigned long long* cnt = (unsigned long long*)ctx->dev_acc;
+    fill_zero((uint64_t*)cnt, 2, s);
     const unsigned g = grid_for(ctx, n, 256, 8);
     const unsigned gc = grid_for(ctx, t->view.direct_range, 256 * 16, 2);
     if (k64) {
       hipLaunchKernelGGL(k_build_direct<int64_t>, dim3(g), dim3(256), 0, s, t->view, c, n, ctx->dev_flags);
-      hipLaunchKernelGGL(k_direct_count<int64_t>, dim3(gc), dim3(256), 0, s, t->view, filled);
+      hipLaunchKernelGGL(k_direct_count<int64_t>, dim3(gc), dim3(256), 0, s, t->view, cnt, n, ctx->dev_flags);
     } else {
       hipLaunchKernelGGL(k_build_direct<int32_t>, dim3(g), dim3(256), 0, s, t->view, c, n, ctx->dev_flags);
-      hipLaunchKernelGGL(k_direct_count<int32_t>, dim3(gc), dim3(256), 0, s, t->view, filled);
+      hipLaunchKernelGGL(k_direct_count<int32_t>, dim3(gc), dim3(256), 0, s, t->view, cnt, n, ctx->dev_flags);
     }
-    hipLaunchKernelGGL(k_direct_check, dim3(1), dim3(64), 0, s, filled, (const unsigned long long*)t->view.side,
-                       n, ctx->dev_flags);
   } else {
     unsigned g = grid_for(ctx, n, 256, 8);
     switch (group_lanes) {
