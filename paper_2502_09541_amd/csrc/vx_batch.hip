@@ -13,8 +13,10 @@
 // A job whose build keys fill their value range exactly (n unique keys from min to min + n - 1,
 // found by a min/max pass over every job before the graph runs) gets a direct table instead of
 // a hash table: the payload of key k sits at k - min, and a bitmap of the keys seen catches a
-// duplicate (which would leave a key of the range missing).  A probe key outside the range then
-// costs no memory access, and one inside reads one payload.
+// duplicate (which would leave a key of the range missing).  The build sets the bits without
+// reading them back; a small kernel between the two phases counts each job's bits, and the host
+// compares the count with the job's rows.  A probe key outside the range then costs no memory
+// access, and one inside reads one payload.
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -45,7 +47,8 @@ struct BatchJob {
   uint32_t pay_size;      // 0 (no payload), 4 or 8
   uint64_t tile0;         // first build-phase tile of the job
   uint64_t ptile0;        // first probe-phase tile of the job
-  uint32_t build_tiles, probe_tiles;
+  uint64_t ctile0;        // first bitmap-count tile of the job (direct tables)
+  uint32_t build_tiles, probe_tiles, count_tiles;
   unsigned long long* side;   // sentinel-key record: count, payload sum
 };
 
@@ -61,10 +64,11 @@ __device__ __forceinline__ void batch_build_rows(const BatchJob& jb, uint64_t r0
     U kb = (U)k;
     long long v = jb.pay_size ? load_signed(jb.bpay, i, jb.pay_size) : 0;
     if (jb.direct) {
-      // every build key lies in [kmin, kmin + nb): the range was measured over these keys
+      // every build key lies in [kmin, kmin + nb): the range was measured over these keys.  The
+      // bit is set without reading it back; k_batch_dupcount counts the bits afterwards, and a
+      // job with fewer than nb bits had a repeated key.
       const uint64_t idx = key_ord(k) - jb.kmin_ord;
-      const unsigned long long bit = 1ull << (idx & 63);
-      if (atomicOr((unsigned long long*)jb.slots + (idx >> 6), bit) & bit) atomicOr(flags, kFlagDup);
+      atomicOr((unsigned long long*)jb.slots + (idx >> 6), 1ull << (idx & 63));
       if (jb.pay_size == 4) ((int*)jb.dpay)[idx] = (int)v;
       else if (jb.pay_size == 8) ((long long*)jb.dpay)[idx] = v;
       continue;
@@ -190,6 +194,42 @@ __global__ void __launch_bounds__(512) k_batch_phase(const BatchJob* jobs, uint3
   }
 }
 
+// Bits set in the direct-table jobs' bitmaps, per job, into cnt[j] (tile order).  Count tile t
+// belongs to the job whose first count tile is the largest one <= t; each covers kCountWords
+// bitmap words.
+constexpr uint32_t kCountWords = 4096;
+
+__global__ void __launch_bounds__(256) k_batch_dupcount(const BatchJob* jobs, uint32_t n_jobs, uint64_t tiles,
+                                                        unsigned long long* cnt) {
+  __shared__ unsigned long long t0[kMaxBatchJobs];
+  __shared__ unsigned long long part[4];
+  for (uint32_t j = threadIdx.x; j < n_jobs; j += blockDim.x) t0[j] = jobs[j].ctile0;
+  __syncthreads();
+  for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+    uint32_t lo = 0, hi = n_jobs;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (t0[mid] <= t) lo = mid;
+      else hi = mid;
+    }
+    const BatchJob& jb = jobs[lo];
+    const uint64_t words = (jb.nb + 63) / 64;
+    const uint64_t w0 = (t - jb.ctile0) * kCountWords;
+    const uint64_t w1 = w0 + kCountWords < words ? w0 + kCountWords : words;
+    unsigned long long c = 0;
+    for (uint64_t w = w0 + threadIdx.x; w < w1; w += blockDim.x)
+      c += (unsigned long long)__popcll(((const unsigned long long*)jb.slots)[w]);
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < (int)(blockDim.x >> 6); ++w) c += part[w];
+      if (c) atomicAdd(cnt + lo, c);
+    }
+    __syncthreads();   // part is reused by the next tile
+  }
+}
+
 // one job, two plain launches (the baseline): build kernel over its rows, probe kernel
 template <typename K>
 __global__ void k_job_build(BatchJob jb, uint32_t slot_shift, unsigned int* flags) {
@@ -289,7 +329,7 @@ struct BatchConfig {
 struct BatchPlan {
   std::vector<BatchJob> jobs;      // in tile order (largest probe side first)
   std::vector<uint32_t> job_of;    // caller's job index of jobs[i]
-  uint64_t build_tiles = 0, probe_tiles = 0;
+  uint64_t build_tiles = 0, probe_tiles = 0, count_tiles = 0;
   uint64_t total_tiles = 0;
   uint64_t slots = 0;              // hash slots of all hash-table jobs (one region, first)
   uint64_t direct_bytes = 0;       // bitmaps and payloads of the direct-table jobs (after them)
@@ -367,7 +407,7 @@ static vx_status plan_batch(const vx_batch_join* d, const BatchConfig& cfg, int 
   if (ks == 8 && ps) slot_bytes = 16;
   pl->slot_shift = 0;
   while ((1u << pl->slot_shift) < slot_bytes) ++pl->slot_shift;
-  uint64_t bt = 0, pt = 0, slots = 0, dbytes = 0;
+  uint64_t bt = 0, pt = 0, ct = 0, slots = 0, dbytes = 0;
   for (uint32_t i = 0; i < J; ++i) {
     const uint32_t j = pl->job_of[i];
     BatchJob& b = pl->jobs[i];
@@ -396,13 +436,17 @@ static vx_status plan_batch(const vx_batch_join* d, const BatchConfig& cfg, int 
     }
     b.tile0 = bt;
     b.ptile0 = pt;
+    b.ctile0 = ct;
     b.build_tiles = (uint32_t)((b.nb + cfg.tile_rows - 1) / cfg.tile_rows);
     b.probe_tiles = (uint32_t)((b.np + cfg.tile_rows - 1) / cfg.tile_rows);
+    b.count_tiles = b.direct ? (uint32_t)(((b.nb + 63) / 64 + kCountWords - 1) / kCountWords) : 0;
     bt += b.build_tiles;
     pt += b.probe_tiles;
+    ct += b.count_tiles;
   }
   pl->build_tiles = bt;
   pl->probe_tiles = pt;
+  pl->count_tiles = ct;
   pl->total_tiles = bt + pt;
   pl->slots = slots;
   pl->direct_bytes = dbytes;
@@ -413,8 +457,9 @@ struct BatchRun {
   ArenaBlock mem;              // slots, side records, descriptors, counters, accumulators
   BatchPlan plan;
   BatchJob* jobs_dev = nullptr;
-  unsigned long long* counters = nullptr;   // sides then accumulators (cleared together)
-  unsigned long long* acc = nullptr;
+  unsigned long long* counters = nullptr;   // sides, accumulators, bit counts (cleared together)
+  unsigned long long* acc = nullptr;         // per job (tile order): count, sum
+  unsigned long long* bits = nullptr;        // per job (tile order): bits set in its direct bitmap
   uint8_t* slots = nullptr;
   uint64_t counter_words = 0;
 };
@@ -428,7 +473,7 @@ static vx_status setup_run(vx_ctx* ctx, const vx_batch_join* d, const BatchConfi
   uint64_t side_bytes = (uint64_t)J * 16;
   uint64_t desc_bytes = (uint64_t)J * sizeof(BatchJob);
   // side records and accumulators are contiguous so one fill kernel clears them
-  r->counter_words = 2 * (uint64_t)J + 2 * (uint64_t)J;
+  r->counter_words = 2 * (uint64_t)J + 2 * (uint64_t)J + (uint64_t)J;
   uint64_t bytes = slot_bytes + 256 + desc_bytes + 256 + r->counter_words * 8 + 256;
   r->mem.a = &ctx->arena;
   r->mem.p = ctx->arena.alloc(bytes);
@@ -441,6 +486,7 @@ static vx_status setup_run(vx_ctx* ctx, const vx_batch_join* d, const BatchConfi
   r->counters = (unsigned long long*)q;
   unsigned long long* sides = r->counters;
   r->acc = sides + 2 * (uint64_t)J;
+  r->bits = r->acc + 2 * (uint64_t)J;
   (void)side_bytes;
   for (uint32_t j = 0; j < J; ++j) {
     BatchJob& b = r->plan.jobs[j];
@@ -455,6 +501,19 @@ static vx_status setup_run(vx_ctx* ctx, const vx_batch_join* d, const BatchConfi
   (void)side_bytes;
   VX_HIP(hipMemcpyAsync(r->jobs_dev, r->plan.jobs.data(), desc_bytes, hipMemcpyHostToDevice, ctx->compute));
   return VX_OK;
+}
+
+static void launch_dupcount(vx_ctx* ctx, const BatchRun& r, uint32_t J, hipStream_t s) {
+  if (!r.plan.count_tiles) return;
+  const unsigned g = (unsigned)std::min<uint64_t>(r.plan.count_tiles, (uint64_t)ctx->cu_count * 4);
+  hipLaunchKernelGGL(k_batch_dupcount, dim3(g), dim3(256), 0, s, r.jobs_dev, J, r.plan.count_tiles, r.bits);
+}
+
+// A direct-table job whose bitmap holds fewer than nb bits had a repeated build key.
+static bool direct_dups(const BatchPlan& pl, const unsigned long long* bits) {
+  for (size_t i = 0; i < pl.jobs.size(); ++i)
+    if (pl.jobs[i].direct && bits[i] != pl.jobs[i].nb) return true;
+  return false;
 }
 
 // the work of one batch on `s`: init tables, clear results, build phase, probe phase, results
@@ -473,21 +532,23 @@ static vx_status enqueue_batch(vx_ctx* ctx, const BatchRun& r, const BatchConfig
   const uint64_t per_cu = cfg.block >= 512 ? 4 : 8;
   unsigned gb = (unsigned)std::min<uint64_t>(std::max<uint64_t>(r.plan.build_tiles, 1), ctx->cu_count * per_cu);
   unsigned gp = (unsigned)std::min<uint64_t>(std::max<uint64_t>(r.plan.probe_tiles, 1), ctx->cu_count * per_cu);
-  if (ks == 8) {
+  if (ks == 8)
     hipLaunchKernelGGL((k_batch_phase<int64_t, true>), dim3(gb), dim3(cfg.block), 0, s, r.jobs_dev, J,
                        r.plan.build_tiles, cfg.tile_rows, r.plan.slot_shift, r.acc, ctx->dev_flags);
-    hipLaunchKernelGGL((k_batch_phase<int64_t, false>), dim3(gp), dim3(cfg.block), 0, s, r.jobs_dev, J,
-                       r.plan.probe_tiles, cfg.tile_rows, r.plan.slot_shift, r.acc, ctx->dev_flags);
-  } else {
+  else
     hipLaunchKernelGGL((k_batch_phase<int32_t, true>), dim3(gb), dim3(cfg.block), 0, s, r.jobs_dev, J,
                        r.plan.build_tiles, cfg.tile_rows, r.plan.slot_shift, r.acc, ctx->dev_flags);
+  launch_dupcount(ctx, r, J, s);
+  if (ks == 8)
+    hipLaunchKernelGGL((k_batch_phase<int64_t, false>), dim3(gp), dim3(cfg.block), 0, s, r.jobs_dev, J,
+                       r.plan.probe_tiles, cfg.tile_rows, r.plan.slot_shift, r.acc, ctx->dev_flags);
+  else
     hipLaunchKernelGGL((k_batch_phase<int32_t, false>), dim3(gp), dim3(cfg.block), 0, s, r.jobs_dev, J,
                        r.plan.probe_tiles, cfg.tile_rows, r.plan.slot_shift, r.acc, ctx->dev_flags);
-  }
   VX_HIP(hipGetLastError());
-  if (host_out) {
-    VX_HIP(hipMemcpyAsync(host_out, r.acc, 2 * (uint64_t)J * 8, hipMemcpyDeviceToHost, s));
-    VX_HIP(hipMemcpyAsync(host_out + 2 * (uint64_t)J, ctx->dev_flags, 4, hipMemcpyDeviceToHost, s));
+  if (host_out) {   // accumulators and bit counts are contiguous: 3 J words, then the flags
+    VX_HIP(hipMemcpyAsync(host_out, r.acc, 3 * (uint64_t)J * 8, hipMemcpyDeviceToHost, s));
+    VX_HIP(hipMemcpyAsync(host_out + 3 * (uint64_t)J, ctx->dev_flags, 4, hipMemcpyDeviceToHost, s));
   }
   return VX_OK;
 }
@@ -702,11 +763,12 @@ vx_status join_batch(vx_ctx* ctx, const vx_batch_join* d, vx_join_out* out) {
     put_event(ctx, b);
     std::memcpy(host.data(), ctx->host_acc, (2 * (uint64_t)J) * 8);
     unsigned int f = 0;
-    std::memcpy(&f, ctx->host_acc + 2 * (uint64_t)J, 4);
-    VX_CHECK(!(f & kFlagDup), VX_EDUPKEY, "batch: duplicate build key");
+    std::memcpy(&f, ctx->host_acc + 3 * (uint64_t)J, 4);
+    VX_CHECK(!(f & kFlagDup) && !direct_dups(gc->run->plan, (const unsigned long long*)ctx->host_acc + 2 * (uint64_t)J),
+             VX_EDUPKEY, "batch: duplicate build key");
     VX_CHECK(!(f & kFlagFull), VX_ECAPACITY, "batch: table full (internal sizing error)");
     s.kernel_ms = ms;
-    s.kernel_launches = 2;
+    s.kernel_launches = gc->run->plan.count_tiles ? 3 : 2;   // build phase, bit count, probe phase
     s.table_bytes = (gc->run->plan.slots << gc->run->plan.slot_shift) + gc->run->plan.direct_bytes;
     s.chunk_rows = cfg.tile_rows;
     s.n_buffers = cfg.block;
@@ -745,10 +807,14 @@ vx_status join_batch(vx_ctx* ctx, const vx_batch_join* d, vx_join_out* out) {
                            r.acc + 2 * (uint64_t)j);
       }
     }
+    launch_dupcount(ctx, r, J, ctx->compute);
     VX_HIP(hipGetLastError());
     VX_HIP(hipEventRecord(b, ctx->compute));
+    std::vector<unsigned long long> bits(J);
     VX_HIP(hipMemcpyAsync(host.data(), r.acc, 2 * (uint64_t)J * 8, hipMemcpyDeviceToHost, ctx->compute));
+    VX_HIP(hipMemcpyAsync(bits.data(), r.bits, (uint64_t)J * 8, hipMemcpyDeviceToHost, ctx->compute));
     VX_HIP(hipStreamSynchronize(ctx->compute));
+    VX_CHECK(!direct_dups(r.plan, bits.data()), VX_EDUPKEY, "batch: duplicate build key");
     float ms = 0;
     (void)hipEventElapsedTime(&ms, a, b);
     put_event(ctx, a);
@@ -756,7 +822,7 @@ vx_status join_batch(vx_ctx* ctx, const vx_batch_join* d, vx_join_out* out) {
     VX_TRY(check_flags(ctx, "batch"));
     order = r.plan.job_of;
     s.kernel_ms = ms;
-    s.kernel_launches = 3 * (uint64_t)J;
+    s.kernel_launches = 3 * (uint64_t)J + (r.plan.count_tiles ? 1 : 0);
     s.table_bytes = (r.plan.slots << r.plan.slot_shift) + r.plan.direct_bytes;
   }
   // accumulators are in tile order: entry i belongs to the caller's job job_of[i]
