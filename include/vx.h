@@ -113,6 +113,7 @@ typedef struct {
   double duplex_sdma_gbs;       /* host-to-device and device-to-host copies at once, both directions summed */
   double zc_write_gbs;          /* kernel stores to mapped pinned host memory */
   double duplex_zcw_gbs;        /* host-to-device copies beside kernel stores to host, summed */
+  double duplex_zcr_gbs;        /* kernel reads of host memory beside device-to-host copies, summed */
 } vx_link_calib;
 
 vx_status vx_calibrate(vx_ctx* ctx, void* pinned, uint64_t bytes, vx_link_calib* out);

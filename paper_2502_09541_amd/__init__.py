@@ -63,7 +63,7 @@ class LinkCalib(C.Structure):
     _fields_ = [("h2d_gbs", C.c_double), ("zc_read_gbs", C.c_double), ("hbm_read_gbs", C.c_double),
                 ("zc_granule", C.c_uint32), ("zc_stride_bytes", C.c_uint32 * 8),
                 ("zc_stride_gelems", C.c_double * 8), ("d2h_gbs", C.c_double), ("duplex_sdma_gbs", C.c_double),
-                ("zc_write_gbs", C.c_double), ("duplex_zcw_gbs", C.c_double)]
+                ("zc_write_gbs", C.c_double), ("duplex_zcw_gbs", C.c_double), ("duplex_zcr_gbs", C.c_double)]
 
 
 class JoinRows(C.Structure):
@@ -317,6 +317,7 @@ class Context:
         return {"h2d_gbs": c.h2d_gbs, "zc_read_gbs": c.zc_read_gbs, "hbm_read_gbs": c.hbm_read_gbs,
                 "zc_granule": c.zc_granule, "d2h_gbs": c.d2h_gbs, "duplex_sdma_gbs": c.duplex_sdma_gbs,
                 "zc_write_gbs": c.zc_write_gbs, "duplex_zcw_gbs": c.duplex_zcw_gbs,
+                "duplex_zcr_gbs": c.duplex_zcr_gbs,
                 "zc_stride": {int(c.zc_stride_bytes[i]): c.zc_stride_gelems[i] for i in range(8)}}
 
     def arena_used(self):

@@ -172,6 +172,16 @@ extern "C" vx_status vx_calibrate(vx_ctx* ctx, void* pinned, uint64_t bytes, vx_
   VX_HIP(hipEventRecord(e2, ctx->compute));
   VX_TRY(span_ms(e0, e1, e2, &ms));
   out->duplex_zcw_gbs = 2.0 * dbytes / (ms * 1e6);
+  // kernel reads of mapped host memory beside device-to-host copies
+  VX_HIP(hipEventRecord(e0, ctx->compute));
+  VX_HIP(hipStreamWaitEvent(ctx->d2h, e0, 0));
+  VX_TRY(d2h_copies());
+  hipLaunchKernelGGL(k_calib_read, dim3(grid), dim3(256), 0, ctx->compute, (const unsigned long long*)hi.dev,
+                     dbytes / 8, 1ull, sink);
+  VX_HIP(hipEventRecord(e1, ctx->d2h));
+  VX_HIP(hipEventRecord(e2, ctx->compute));
+  VX_TRY(span_ms(e0, e1, e2, &ms));
+  out->duplex_zcr_gbs = 2.0 * dbytes / (ms * 1e6);
   put_event(ctx, e0);
   put_event(ctx, e1);
   put_event(ctx, e2);

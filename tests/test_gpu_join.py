@@ -195,4 +195,4 @@ def test_calibration_properties(gpu, ctx):
     assert 8 <= g <= 2048 and g & (g - 1) == 0
     assert c["hbm_read_gbs"] > 4 * c["h2d_gbs"]
     assert 5 < c["d2h_gbs"] < 64 and 0 < c["zc_write_gbs"] < 64
-    assert 5 < c["duplex_sdma_gbs"] < 128 and 5 < c["duplex_zcw_gbs"] < 128
+    assert 5 < c["duplex_sdma_gbs"] < 128 and 5 < c["duplex_zcw_gbs"] < 128 and 5 < c["duplex_zcr_gbs"] < 128
