@@ -1,10 +1,12 @@
 // Many independent device-resident joins, batched into one HIP graph launch.
 //
 // The work is a list of equal-size tiles: every job's build tiles, then every job's probe
-// tiles, largest jobs first.  Two queue-draining kernels cover it: the build kernel walks the
-// build tiles grid-stride and inserts each tile's rows into its job's table; the probe kernel
-// walks the probe tiles and aggregates each tile into its job's result.  The kernel boundary
-// between them is the only dependency, so no workgroup ever waits for another.  Table init,
+// tiles.  Two queue-draining kernels cover it: the build kernel walks the build tiles
+// grid-stride and inserts each tile's rows into its job's table; the probe kernel walks the
+// probe tiles and aggregates each tile into its job's result.  The kernel boundary between them
+// is the only dependency, so no workgroup ever waits for another.  The tiles are placed by XCD
+// (the MI355X has 8, each with its own 4 MB L2): a job whose table fits one L2 is built and
+// probed on one XCD only, so its table is cached once instead of in every L2.  Table init,
 // result reset, both kernels and the copy of the results are captured once in a HIP graph and
 // replayed while the batch is unchanged.  Tile size, workgroup size and load factor come from
 // a small autotuner that times candidates on the batch itself and caches the winner per
@@ -45,8 +47,6 @@ struct BatchJob {
   uint64_t mask;
   uint32_t log2cap;
   uint32_t pay_size;      // 0 (no payload), 4 or 8
-  uint64_t tile0;         // first build-phase tile of the job
-  uint64_t ptile0;        // first probe-phase tile of the job
   uint64_t ctile0;        // first bitmap-count tile of the job (direct tables)
   uint32_t build_tiles, probe_tiles, count_tiles;
   unsigned long long* side;   // sentinel-key record: count, payload sum
@@ -162,26 +162,21 @@ __device__ __forceinline__ void block_add2(unsigned long long cnt, unsigned long
   }
 }
 
-// Tiles of one phase: tile t of the phase belongs to the job whose first tile index (tile0 of
-// the phase) is the largest one <= t.
+// Tiles of one phase: tile_map[t] holds (job << 32 | the job's own tile index), or ~0 for an
+// empty tile.
 template <typename K, bool BUILD>
 __global__ void __launch_bounds__(512) k_batch_phase(const BatchJob* jobs, uint32_t n_jobs,
                                                      uint64_t phase_tiles, uint32_t tile_rows,
                                                      uint32_t slot_shift, unsigned long long* acc,
-                                                     unsigned int* flags) {
-  __shared__ unsigned long long tile0[kMaxBatchJobs];
-  for (uint32_t j = threadIdx.x; j < n_jobs; j += blockDim.x)
-    tile0[j] = BUILD ? jobs[j].tile0 : jobs[j].ptile0;
-  __syncthreads();
+                                                     unsigned int* flags,
+                                                     const unsigned long long* tile_map) {
+  (void)n_jobs;
   for (uint64_t t = blockIdx.x; t < phase_tiles; t += gridDim.x) {
-    uint32_t lo = 0, hi = n_jobs;
-    while (hi - lo > 1) {
-      uint32_t mid = (lo + hi) >> 1;
-      if (tile0[mid] <= t) lo = mid;
-      else hi = mid;
-    }
+    const unsigned long long e = tile_map[t];
+    if (e == ~0ull) continue;     // uniform over the workgroup
+    const uint32_t lo = (uint32_t)(e >> 32);
+    const uint64_t local = e & 0xffffffffull;
     const BatchJob jb = jobs[lo];
-    const uint64_t local = t - (BUILD ? jb.tile0 : jb.ptile0);
     const uint64_t n = BUILD ? jb.nb : jb.np;
     const uint64_t r0 = local * tile_rows, r1 = r0 + tile_rows < n ? r0 + tile_rows : n;
     if (BUILD) {
@@ -332,6 +327,11 @@ struct BatchPlan {
   uint64_t build_tiles = 0, probe_tiles = 0, count_tiles = 0;
   uint64_t total_tiles = 0;
   uint64_t slots = 0;              // hash slots of all hash-table jobs (one region, first)
+  // Tile maps of the two phases, kXcds interleaved lists: entry 8 q + x is list x's q-th tile
+  // (job << 32 | the job's tile), ~0 when list x is shorter.  Workgroup b runs on XCD b mod 8
+  // and a grid of a multiple of 8 workgroups walks tile t on workgroup t mod grid, so list x
+  // runs on XCD x.  A job's build and probe tiles go to the same XCD.
+  std::vector<unsigned long long> build_map, probe_map;
   uint64_t direct_bytes = 0;       // bitmaps and payloads of the direct-table jobs (after them)
   uint32_t slot_shift = 3;
 };
@@ -394,8 +394,52 @@ static vx_status find_direct(vx_ctx* ctx, const vx_batch_join* d, int ks, Direct
   return VX_OK;
 }
 
+constexpr uint32_t kXcds = 8;   // accelerator complex dies of the MI355X, each with its own L2
+
+// The XCD-aware tile maps.  A job whose table fits in 3/4 of one XCD's L2 gets all of its tiles
+// on one XCD (jobs spread over the XCDs longest probe side first, balancing probe tiles), so its
+// table is built and read in that L2 only.  Larger jobs spread their tiles over every XCD in
+// turn and come first in every list.
+static void map_tiles(BatchPlan* pl, uint32_t slot_bytes, uint64_t l2_bytes) {
+  const uint32_t J = (uint32_t)pl->jobs.size();
+  std::vector<std::vector<unsigned long long>> bl(kXcds), pr(kXcds);
+  std::vector<uint32_t> small;
+  uint32_t rb = 0, rp = 0;
+  auto tiles = [](std::vector<unsigned long long>& l, uint32_t i, uint32_t n) {
+    for (uint32_t k = 0; k < n; ++k) l.push_back(((unsigned long long)i << 32) | k);
+  };
+  for (uint32_t i = 0; i < J; ++i) {
+    const BatchJob& b = pl->jobs[i];
+    const uint64_t table = b.direct ? b.nb * (uint64_t)b.pay_size : (b.mask + 1) * (uint64_t)slot_bytes;
+    if (table <= l2_bytes / 4 * 3) {
+      small.push_back(i);
+      continue;
+    }
+    for (uint32_t k = 0; k < b.build_tiles; ++k) bl[rb++ % kXcds].push_back(((unsigned long long)i << 32) | k);
+    for (uint32_t k = 0; k < b.probe_tiles; ++k) pr[rp++ % kXcds].push_back(((unsigned long long)i << 32) | k);
+  }
+  std::stable_sort(small.begin(), small.end(),
+                   [&](uint32_t a, uint32_t b) { return pl->jobs[a].probe_tiles > pl->jobs[b].probe_tiles; });
+  for (uint32_t i : small) {
+    uint32_t x = 0;
+    for (uint32_t y = 1; y < kXcds; ++y)
+      if (pr[y].size() < pr[x].size()) x = y;
+    tiles(bl[x], i, pl->jobs[i].build_tiles);
+    tiles(pr[x], i, pl->jobs[i].probe_tiles);
+  }
+  auto flatten = [](const std::vector<std::vector<unsigned long long>>& lists, std::vector<unsigned long long>* out) {
+    size_t len = 0;
+    for (const auto& l : lists) len = std::max(len, l.size());
+    out->assign(len * kXcds, ~0ull);
+    for (uint32_t x = 0; x < kXcds; ++x)
+      for (size_t q = 0; q < lists[x].size(); ++q) (*out)[q * kXcds + x] = lists[x][q];
+  };
+  flatten(bl, &pl->build_map);
+  flatten(pr, &pl->probe_map);
+}
+
 static vx_status plan_batch(const vx_batch_join* d, const BatchConfig& cfg, int ks, uint32_t ps,
-                            const DirectInfo& di, BatchPlan* pl) {
+                            const DirectInfo& di, uint64_t l2_bytes, BatchPlan* pl) {
   const uint32_t J = d->n_jobs;
   pl->jobs.resize(J);
   pl->job_of.resize(J);
@@ -434,8 +478,6 @@ static vx_status plan_batch(const vx_batch_join* d, const BatchConfig& cfg, int 
       b.slots = (uint8_t*)(uintptr_t)slots;
       slots += cap;
     }
-    b.tile0 = bt;
-    b.ptile0 = pt;
     b.ctile0 = ct;
     b.build_tiles = (uint32_t)((b.nb + cfg.tile_rows - 1) / cfg.tile_rows);
     b.probe_tiles = (uint32_t)((b.np + cfg.tile_rows - 1) / cfg.tile_rows);
@@ -450,6 +492,7 @@ static vx_status plan_batch(const vx_batch_join* d, const BatchConfig& cfg, int 
   pl->total_tiles = bt + pt;
   pl->slots = slots;
   pl->direct_bytes = dbytes;
+  map_tiles(pl, slot_bytes, l2_bytes);
   return VX_OK;
 }
 
@@ -460,13 +503,15 @@ struct BatchRun {
   unsigned long long* counters = nullptr;   // sides, accumulators, bit counts (cleared together)
   unsigned long long* acc = nullptr;         // per job (tile order): count, sum
   unsigned long long* bits = nullptr;        // per job (tile order): bits set in its direct bitmap
+  unsigned long long* probe_map = nullptr;   // the plan's tile maps, in device memory
+  unsigned long long* build_map = nullptr;
   uint8_t* slots = nullptr;
   uint64_t counter_words = 0;
 };
 
 static vx_status setup_run(vx_ctx* ctx, const vx_batch_join* d, const BatchConfig& cfg, int ks,
                            uint32_t ps, const DirectInfo& di, BatchRun* r) {
-  VX_TRY(plan_batch(d, cfg, ks, ps, di, &r->plan));
+  VX_TRY(plan_batch(d, cfg, ks, ps, di, ctx->l2_bytes, &r->plan));
   const uint32_t J = d->n_jobs;
   const uint64_t hash_bytes = align256(r->plan.slots << r->plan.slot_shift);
   uint64_t slot_bytes = hash_bytes + r->plan.direct_bytes;
@@ -474,7 +519,8 @@ static vx_status setup_run(vx_ctx* ctx, const vx_batch_join* d, const BatchConfi
   uint64_t desc_bytes = (uint64_t)J * sizeof(BatchJob);
   // side records and accumulators are contiguous so one fill kernel clears them
   r->counter_words = 2 * (uint64_t)J + 2 * (uint64_t)J + (uint64_t)J;
-  uint64_t bytes = slot_bytes + 256 + desc_bytes + 256 + r->counter_words * 8 + 256;
+  const uint64_t bmap_bytes = r->plan.build_map.size() * 8, map_bytes = r->plan.probe_map.size() * 8;
+  uint64_t bytes = slot_bytes + 256 + desc_bytes + 256 + r->counter_words * 8 + 256 + map_bytes + 256 + bmap_bytes + 256;
   r->mem.a = &ctx->arena;
   r->mem.p = ctx->arena.alloc(bytes);
   VX_CHECK(r->mem.p, VX_EBUDGET, "batch: %llu bytes of tables and descriptors do not fit the arena",
@@ -487,6 +533,8 @@ static vx_status setup_run(vx_ctx* ctx, const vx_batch_join* d, const BatchConfi
   unsigned long long* sides = r->counters;
   r->acc = sides + 2 * (uint64_t)J;
   r->bits = r->acc + 2 * (uint64_t)J;
+  r->probe_map = (unsigned long long*)(q + align256(r->counter_words * 8));
+  r->build_map = (unsigned long long*)((uint8_t*)r->probe_map + align256(map_bytes));
   (void)side_bytes;
   for (uint32_t j = 0; j < J; ++j) {
     BatchJob& b = r->plan.jobs[j];
@@ -500,6 +548,10 @@ static vx_status setup_run(vx_ctx* ctx, const vx_batch_join* d, const BatchConfi
   }
   (void)side_bytes;
   VX_HIP(hipMemcpyAsync(r->jobs_dev, r->plan.jobs.data(), desc_bytes, hipMemcpyHostToDevice, ctx->compute));
+  if (map_bytes)
+    VX_HIP(hipMemcpyAsync(r->probe_map, r->plan.probe_map.data(), map_bytes, hipMemcpyHostToDevice, ctx->compute));
+  if (bmap_bytes)
+    VX_HIP(hipMemcpyAsync(r->build_map, r->plan.build_map.data(), bmap_bytes, hipMemcpyHostToDevice, ctx->compute));
   return VX_OK;
 }
 
@@ -530,21 +582,27 @@ static vx_status enqueue_batch(vx_ctx* ctx, const BatchRun& r, const BatchConfig
   fill_zero((uint64_t*)r.counters, r.counter_words, s);
   fill_zero((uint64_t*)ctx->dev_flags, 1, s);
   const uint64_t per_cu = cfg.block >= 512 ? 4 : 8;
-  unsigned gb = (unsigned)std::min<uint64_t>(std::max<uint64_t>(r.plan.build_tiles, 1), ctx->cu_count * per_cu);
-  unsigned gp = (unsigned)std::min<uint64_t>(std::max<uint64_t>(r.plan.probe_tiles, 1), ctx->cu_count * per_cu);
+  // the tile maps assume grids of a multiple of kXcds workgroups (see BatchPlan::probe_map)
+  const uint64_t bmapped = r.plan.build_map.size(), mapped = r.plan.probe_map.size();
+  unsigned gb = (unsigned)std::min<uint64_t>(std::max<uint64_t>(bmapped, 1), ctx->cu_count * per_cu);
+  gb = std::max(kXcds, gb / kXcds * kXcds);
+  unsigned gp = (unsigned)std::min<uint64_t>(std::max<uint64_t>(mapped, 1), ctx->cu_count * per_cu);
+  gp = std::max(kXcds, gp / kXcds * kXcds);
+  const unsigned long long* bmap = r.build_map;
   if (ks == 8)
     hipLaunchKernelGGL((k_batch_phase<int64_t, true>), dim3(gb), dim3(cfg.block), 0, s, r.jobs_dev, J,
-                       r.plan.build_tiles, cfg.tile_rows, r.plan.slot_shift, r.acc, ctx->dev_flags);
+                       (uint64_t)bmapped, cfg.tile_rows, r.plan.slot_shift, r.acc, ctx->dev_flags, bmap);
   else
     hipLaunchKernelGGL((k_batch_phase<int32_t, true>), dim3(gb), dim3(cfg.block), 0, s, r.jobs_dev, J,
-                       r.plan.build_tiles, cfg.tile_rows, r.plan.slot_shift, r.acc, ctx->dev_flags);
+                       (uint64_t)bmapped, cfg.tile_rows, r.plan.slot_shift, r.acc, ctx->dev_flags, bmap);
   launch_dupcount(ctx, r, J, s);
+  const unsigned long long* pmap = r.probe_map;
   if (ks == 8)
     hipLaunchKernelGGL((k_batch_phase<int64_t, false>), dim3(gp), dim3(cfg.block), 0, s, r.jobs_dev, J,
-                       r.plan.probe_tiles, cfg.tile_rows, r.plan.slot_shift, r.acc, ctx->dev_flags);
+                       (uint64_t)mapped, cfg.tile_rows, r.plan.slot_shift, r.acc, ctx->dev_flags, pmap);
   else
     hipLaunchKernelGGL((k_batch_phase<int32_t, false>), dim3(gp), dim3(cfg.block), 0, s, r.jobs_dev, J,
-                       r.plan.probe_tiles, cfg.tile_rows, r.plan.slot_shift, r.acc, ctx->dev_flags);
+                       (uint64_t)mapped, cfg.tile_rows, r.plan.slot_shift, r.acc, ctx->dev_flags, pmap);
   VX_HIP(hipGetLastError());
   if (host_out) {   // accumulators and bit counts are contiguous: 3 J words, then the flags
     VX_HIP(hipMemcpyAsync(host_out, r.acc, 3 * (uint64_t)J * 8, hipMemcpyDeviceToHost, s));

@@ -196,3 +196,14 @@ def test_host_keys_stay_hashed(gpu, ctx):
     got, st = ctx.join_plain(pinned(gpu, bkey), [], dev(bkey))
     assert got == [n]
     assert st["table_bytes"] == 2 * n * 8 + 256
+
+
+def test_build_flag_errors(gpu, ctx):
+    """VX_HASHED only qualifies VX_UNIQUE or VX_PREAGG; alone, or with unknown bits, it is rejected."""
+    import ctypes as C
+    k = dev(np.arange(100, dtype=np.int64))
+    for flags in (gpu.VX_HASHED, gpu.VX_UNIQUE | gpu.VX_PREAGG, gpu.VX_UNIQUE | 8):
+        d = gpu.BuildDesc(gpu.col(k), None, 0, flags, 100, 0.0, 0)
+        h = C.c_void_p()
+        assert gpu.lib().vx_build(ctx.h, C.byref(d), C.byref(h)) == gpu.VX_EINVAL
+        assert not h.value
