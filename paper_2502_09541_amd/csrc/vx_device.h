@@ -16,16 +16,22 @@ __device__ __forceinline__ unsigned long long key_ord(K k) {
   return (unsigned long long)(long long)k ^ 0x8000000000000000ull;
 }
 
-// First slot of k's probe sequence in t.  False when k cannot be in a direct table (outside
-// its key range); then no slot is read.
-template <typename K>
-__device__ __forceinline__ bool first_slot(const TableView& t, K k, uint64_t& h) {
-  if (t.direct) {
+// First slot of k's probe sequence in t, for a layout known at compile time (DIRECT) or read
+// from the table.  False when k cannot be in a direct table (outside its key range); then no
+// slot is read.
+template <bool DIRECT, typename K>
+__device__ __forceinline__ bool first_slot_as(const TableView& t, K k, uint64_t& h) {
+  if (DIRECT) {
     h = key_ord(k) - t.kmin_ord;
     return h < t.direct_range;
   }
   h = slot_of(key_bits(k), t.log2cap);
   return true;
+}
+
+template <typename K>
+__device__ __forceinline__ bool first_slot(const TableView& t, K k, uint64_t& h) {
+  return t.direct ? first_slot_as<true>(t, k, h) : first_slot_as<false>(t, k, h);
 }
 
 __device__ __forceinline__ long long load_signed(const void* base, uint64_t idx, uint32_t size) {

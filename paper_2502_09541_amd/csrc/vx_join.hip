@@ -79,8 +79,11 @@ __global__ void k_build_unique_lane(TableView t, BuildCols c, uint64_t n, unsign
     bool done = false;
     // a key outside a direct table's range cannot occur (the range is measured over these keys);
     // if it did, the table is reported full
-    const uint64_t steps = first_slot(t, k, h) ? t.mask + 1 : 0;
-    for (uint64_t step = 0; step < steps; ++step) {
+    if (!first_slot(t, k, h)) {
+      atomicOr(flags, kFlagFull);
+      continue;
+    }
+    for (uint64_t step = 0; step <= t.mask; ++step) {
       uint8_t* slot = t.slots + (h << t.slot_shift);
       U prev = atomicCAS((U*)slot, kEmpty, kb);
       if (prev == kEmpty) {
@@ -190,8 +193,11 @@ __global__ void k_build_unique_group(TableView t, BuildCols c, uint64_t n, unsig
       }
       uint64_t h;
       bool done = false;
-      const uint64_t steps = first_slot(t, k, h) ? t.mask + 1 : 0;   // uniform within the group
-      for (uint64_t step = 0; step < steps; step += G) {
+      if (!first_slot(t, k, h)) {   // uniform within the group; cannot happen (see the lane build)
+        if (gl == 0) atomicOr(flags, kFlagFull);
+        continue;
+      }
+      for (uint64_t step = 0; step <= t.mask; step += G) {
         uint64_t pos = (h + gl) & t.mask;
         uint8_t* slot = t.slots + (pos << t.slot_shift);
         U sk = __atomic_load_n((U*)slot, __ATOMIC_RELAXED);
@@ -305,7 +311,9 @@ struct ProbeCols {
   uint32_t pay_size[kMaxPay];
 };
 
-template <typename K, bool PREAGG, int ITEMS>
+// DIRECT: the table's layout (t.direct), fixed at compile time so that the hash loop carries no
+// test of it.
+template <typename K, bool PREAGG, int ITEMS, bool DIRECT>
 __global__ void __launch_bounds__(256) k_probe(TableView t, ProbeCols q, unsigned long long* acc_out) {
   using U = typename KeyTraits<K>::U;
   const U kEmpty = KeyTraits<K>::kEmpty;
@@ -338,9 +346,16 @@ __global__ void __launch_bounds__(256) k_probe(TableView t, ProbeCols q, unsigne
         }
         continue;
       }
+      // the layout is chosen at compile time: the hash instantiation holds no trace of the direct
+      // test (a skip that only folds away after inlining still changes the loop's code)
       uint64_t h;
-      const uint64_t steps = first_slot(t, keys[j], h) ? t.mask + 1 : 0;
-      for (uint64_t step = 0; step < steps; ++step) {
+      if constexpr (DIRECT) {
+        h = key_ord(keys[j]) - t.kmin_ord;
+        if (h >= t.direct_range) continue;   // outside the key range: no slot to read
+      } else {
+        h = slot_of(key_bits(keys[j]), t.log2cap);
+      }
+      for (uint64_t step = 0; step <= t.mask; ++step) {
         const uint8_t* slot = t.slots + (h << t.slot_shift);
         U sk = *(const U*)slot;
         if (sk == kb) {
@@ -391,7 +406,7 @@ struct RowsOut {
 // (global probe row, build payloads, probe payloads), payloads sign-extended.  A workgroup
 // counts its tile's matches, reserves that many rows with one atomic, and its waves write them
 // at consecutive positions (coalesced stores, to host memory beside the host-to-device copies).
-template <typename K, int ITEMS>
+template <typename K, int ITEMS, bool DIRECT>
 __global__ void __launch_bounds__(256) k_probe_rows(TableView t, ProbeCols q, unsigned long long* acc_out,
                                                     RowsOut o) {
   using U = typename KeyTraits<K>::U;
@@ -428,17 +443,25 @@ __global__ void __launch_bounds__(256) k_probe_rows(TableView t, ProbeCols q, un
         }
       } else {
         uint64_t h;
-        const uint64_t steps = first_slot(t, keys[j], h) ? t.mask + 1 : 0;
-        for (uint64_t step = 0; step < steps; ++step) {
-          const uint8_t* slot = t.slots + (h << t.slot_shift);
-          U sk = *(const U*)slot;
-          if (sk == kb) {
-            hit[j] = true;
-            for (uint32_t p = 0; p < nb; ++p) bv[j][p] = slot_signed(slot, t.pay_off[p], t.pay_size[p]);
-            break;
+        bool in_range = true;
+        if constexpr (DIRECT) {   // compile-time layout, as in k_probe
+          h = key_ord(keys[j]) - t.kmin_ord;
+          in_range = h < t.direct_range;
+        } else {
+          h = slot_of(key_bits(keys[j]), t.log2cap);
+        }
+        if (in_range) {
+          for (uint64_t step = 0; step <= t.mask; ++step) {
+            const uint8_t* slot = t.slots + (h << t.slot_shift);
+            U sk = *(const U*)slot;
+            if (sk == kb) {
+              hit[j] = true;
+              for (uint32_t p = 0; p < nb; ++p) bv[j][p] = slot_signed(slot, t.pay_off[p], t.pay_size[p]);
+              break;
+            }
+            if (sk == kEmpty) break;
+            h = (h + 1) & t.mask;
           }
-          if (sk == kEmpty) break;
-          h = (h + 1) & t.mask;
         }
       }
       if (!hit[j]) continue;
@@ -731,21 +754,29 @@ vx_status table_insert(vx_ctx* ctx, vx_table* t, const ColInfo& key, const ColIn
 }
 
 // Launch one probe kernel over q.n rows, accumulating into acc (9 words).
+template <typename K, bool DIRECT>
+static void launch_probe_as(const vx_table* t, const ProbeCols& q, unsigned long long* acc, hipStream_t s,
+                            const RowsOut* ro, unsigned g) {
+  constexpr int ITEMS = 4;
+  if (ro)
+    hipLaunchKernelGGL((k_probe_rows<K, ITEMS, DIRECT>), dim3(g), dim3(256), 0, s, t->view, q, acc, *ro);
+  else if (t->view.preagg)
+    hipLaunchKernelGGL((k_probe<K, true, ITEMS, DIRECT>), dim3(g), dim3(256), 0, s, t->view, q, acc);
+  else
+    hipLaunchKernelGGL((k_probe<K, false, ITEMS, DIRECT>), dim3(g), dim3(256), 0, s, t->view, q, acc);
+}
+
 static vx_status launch_probe(vx_ctx* ctx, const vx_table* t, const ProbeCols& q,
                               unsigned long long* acc, hipStream_t s, const RowsOut* ro = nullptr) {
   if (q.n == 0) return VX_OK;
-  constexpr int ITEMS = 4;
-  unsigned g = grid_for(ctx, q.n, 256 * ITEMS, 8);
-  const bool k64 = t->key_type == VX_I64;
-  if (ro) {
-    if (k64) hipLaunchKernelGGL((k_probe_rows<int64_t, ITEMS>), dim3(g), dim3(256), 0, s, t->view, q, acc, *ro);
-    else hipLaunchKernelGGL((k_probe_rows<int32_t, ITEMS>), dim3(g), dim3(256), 0, s, t->view, q, acc, *ro);
-  } else if (t->view.preagg) {
-    if (k64) hipLaunchKernelGGL((k_probe<int64_t, true, ITEMS>), dim3(g), dim3(256), 0, s, t->view, q, acc);
-    else hipLaunchKernelGGL((k_probe<int32_t, true, ITEMS>), dim3(g), dim3(256), 0, s, t->view, q, acc);
+  const unsigned g = grid_for(ctx, q.n, 256 * 4, 8);
+  const bool k64 = t->key_type == VX_I64, direct = t->view.direct != 0;
+  if (k64) {
+    if (direct) launch_probe_as<int64_t, true>(t, q, acc, s, ro, g);
+    else launch_probe_as<int64_t, false>(t, q, acc, s, ro, g);
   } else {
-    if (k64) hipLaunchKernelGGL((k_probe<int64_t, false, ITEMS>), dim3(g), dim3(256), 0, s, t->view, q, acc);
-    else hipLaunchKernelGGL((k_probe<int32_t, false, ITEMS>), dim3(g), dim3(256), 0, s, t->view, q, acc);
+    if (direct) launch_probe_as<int32_t, true>(t, q, acc, s, ro, g);
+    else launch_probe_as<int32_t, false>(t, q, acc, s, ro, g);
   }
   VX_HIP(hipGetLastError());
   return VX_OK;

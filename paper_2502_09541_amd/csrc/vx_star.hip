@@ -48,8 +48,11 @@ __global__ void k_build_dim(TableView t, const void* key, const void* filt, uint
     }
     uint64_t h;
     bool done = false;
-    const uint64_t steps = first_slot(t, k, h) ? t.mask + 1 : 0;
-    for (uint64_t step = 0; step < steps; ++step) {
+    if (!first_slot(t, k, h)) {    // cannot happen: the range was measured over every dimension row
+      atomicOr(flags, kFlagFull);
+      continue;
+    }
+    for (uint64_t step = 0; step <= t.mask; ++step) {
       uint8_t* slot = t.slots + (h << t.slot_shift);
       U prev = atomicCAS((U*)slot, kEmpty, kb);
       if (prev == kEmpty) {
