@@ -66,14 +66,14 @@ __device__ __forceinline__ void block_flush(unsigned long long (&acc)[NACC], int
 
 
 // Find `k` in a unique table.  Returns the slot, or nullptr when absent; keys equal to the
-// empty marker are looked up in the side record by the caller.
+// empty marker are looked up in the side record by the caller.  find_slot_hashed is for tables
+// known to be hashed: it carries no test of the layout, which would change the loop's code.
 template <typename K>
-__device__ __forceinline__ const uint8_t* find_slot(const TableView& t, K k) {
+__device__ __forceinline__ const uint8_t* find_slot_hashed(const TableView& t, K k) {
   using U = typename KeyTraits<K>::U;
   const U kEmpty = KeyTraits<K>::kEmpty;
   const U kb = (U)k;
-  uint64_t h;
-  if (!first_slot(t, k, h)) return nullptr;
+  uint64_t h = slot_of(key_bits(k), t.log2cap);
   for (uint64_t step = 0; step <= t.mask; ++step) {
     const uint8_t* slot = t.slots + (h << t.slot_shift);
     U sk = *(const U*)slot;
@@ -82,6 +82,16 @@ __device__ __forceinline__ const uint8_t* find_slot(const TableView& t, K k) {
     h = (h + 1) & t.mask;
   }
   return nullptr;
+}
+
+template <typename K>
+__device__ __forceinline__ const uint8_t* find_slot(const TableView& t, K k) {
+  if (!t.direct) return find_slot_hashed(t, k);
+  using U = typename KeyTraits<K>::U;
+  uint64_t h;
+  if (!first_slot_as<true>(t, k, h)) return nullptr;
+  const uint8_t* slot = t.slots + (h << t.slot_shift);
+  return *(const U*)slot == (U)k ? slot : nullptr;   // a direct slot holds k or the empty marker
 }
 
 template <typename K>

@@ -277,7 +277,7 @@ __global__ void __launch_bounds__(256) k_pj_stream(const void* keys, uint64_t n,
         t.log2cap = llog2[pid];
         t.mask = (1ull << t.log2cap) - 1;
         t.slot_shift = kSlotShift;
-        const uint8_t* s = find_slot<K>(t, kk[j]);
+        const uint8_t* s = find_slot_hashed<K>(t, kk[j]);
         if (!s) continue;
         w = (const unsigned long long*)(s + 8);
       }
@@ -380,7 +380,7 @@ __global__ void __launch_bounds__(256) k_rj_probe(TableView t, const void* key, 
       if ((U)kk[j] == kEmpty) {
         w = t.side;
       } else {
-        const uint8_t* s = find_slot<K>(t, kk[j]);
+        const uint8_t* s = find_slot_hashed<K>(t, kk[j]);
         if (!s) continue;
         w = (const unsigned long long*)(s + 8);
       }
