@@ -25,13 +25,13 @@ HBM_PEAK_GBS = 8000.0       # MI355X HBM3E datasheet peak
 # HBM bytes per launch of the dominant kernel, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs
 # scaled by what the same counters read for a plain 1 GiB device read and write (the summaries
 # under profiles/ give the commands).  Valid for the kernel source they were measured on.
-TRAFFIC_BYTES = {"k_probe_stream": 1.5335e9,    # 8,388,608 probe rows per launch
-                 "k_probe_plain": 6.4121e8,     # 16,777,216 probe rows per launch (direct table)
-                 "k_star": 1.9347e9,            # 16,666,667 fact rows per launch (direct dimension tables)
+TRAFFIC_BYTES = {"k_probe_stream": 1.5643e9,    # 8,388,608 probe rows per launch
+                 "k_probe_plain": 6.3886e8,     # 16,777,216 probe rows per launch (direct table)
+                 "k_star": 1.9346e9,            # 16,666,667 fact rows per launch (direct dimension tables)
                  "batch_graph": 1.8282e11,      # one graph launch: build phase, bit count, probe phase, all 256 jobs
                  "k_pj_stream": 4.976e8,        # 8,388,608 probe rows per launch (mean over the partitioners)
-                 "k_probe_rows": 1.4820e9,      # 8,388,608 probe rows per launch, output rows included
-                 "k_rj_probe": 6.8926e9,        # 33,554,432 B rows per launch (host reads + table lines)
+                 "k_probe_rows": 1.4712e9,      # 8,388,608 probe rows per launch, output rows included
+                 "k_rj_probe": 6.9041e9,        # 33,554,432 B rows per launch (host reads + table lines)
                  "sort_run": 2.4941e10}         # one 2^26-key run: 8 x (k_part_hist + k_part_scatter)
 GiB = 1 << 30
 
