@@ -140,3 +140,30 @@ def test_batch_direct_int64(gpu, ctx):
     _say("batch direct int64")
     got, _ = ctx.join_batch([dev(x) for x in bk], [dev(x) for x in bp], [dev(x) for x in pk])
     assert got == [oracle.join_agg(a, [b], c, []) for a, b, c in zip(bk, bp, pk)]
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_batch_mixed_xcd_placement(gpu, ctx, mode):
+    """Jobs whose tables exceed 3/4 of an XCD's L2 (spread over every XCD) beside jobs pinned to
+    one XCD, hash and direct tables, and an empty job: every job's result must match the oracle."""
+    rng = np.random.default_rng(17)
+    sizes = [(1 << 20, 3_000_000), (3 << 18, 2_000_000), (1 << 19, 1_500_000), (5000, 40_000), (0, 1000)]
+    sizes += [(int(n), int(10 * n)) for n in rng.integers(1000, 60_000, 12)]
+    bk, bp, pk = [], [], []
+    for i, (nb, npr) in enumerate(sizes):
+        if i % 3 == 1:    # unique keys with gaps: a hash table
+            k = np.unique(rng.integers(-2**30, 2**30, int(nb * 1.01) + 10)).astype(np.int32)[:nb]
+            rng.shuffle(k)
+        else:             # a permutation of a range: a direct table
+            k = (rng.permutation(nb) + int(rng.integers(-2**20, 2**20))).astype(np.int32)
+        bk.append(k)
+        bp.append(rng.integers(-2**31, 2**31, nb).astype(np.int32))
+        lo = int(k.min()) if nb else 0
+        hi = int(k.max()) if nb else 1
+        pk.append(np.concatenate([rng.choice(k, npr // 2) if nb else np.zeros(0, np.int32),
+                                  rng.integers(lo - 1000, hi + 1000, npr - (npr // 2 if nb else 0))]).astype(np.int32))
+    exp = [oracle.join_agg(a, [b], c, []) for a, b, c in zip(bk, bp, pk)]
+    _say("batch mixed placement, mode", mode)
+    got, _ = ctx.join_batch([dev(x) for x in bk], [dev(x) for x in bp], [dev(x) for x in pk], mode=mode,
+                            tile_rows=8192, block=256, load_factor=0.5)
+    assert got == exp
