@@ -796,19 +796,32 @@ vx_status join_batch(vx_ctx* ctx, const vx_batch_join* d, vx_join_out* out) {
     if (!gc || !(gc->key == job_keys(d)) || !(gc->di == di) || gc->cfg.tile_rows != cfg.tile_rows ||
         gc->cfg.block != cfg.block || gc->cfg.load_factor != cfg.load_factor) {
       drop_graph(gc);
-      gc = new GraphCache;
-      gc->run = new BatchRun;
-      gc->cfg = cfg;
-      VX_TRY(setup_run(ctx, d, cfg, ks, ps, di, gc->run));
-      gc->key = job_keys(d);
-      gc->di = di;
-      VX_HIP(hipStreamSynchronize(ctx->compute));
-      VX_HIP(hipStreamBeginCapture(ctx->compute, hipStreamCaptureModeThreadLocal));
-      vx_status cst = enqueue_batch(ctx, *gc->run, cfg, ks, J, ctx->compute, ctx->host_acc);
-      hipError_t ce = hipStreamEndCapture(ctx->compute, &gc->graph);
-      VX_TRY(cst);
-      VX_HIP(ce);
-      VX_HIP(hipGraphInstantiate(&gc->exec, gc->graph, nullptr, nullptr, 0));
+      gc = nullptr;
+      // the new entry is cached only once its graph is instantiated: a failure part-way leaves
+      // no entry, so the next call builds the graph again
+      GraphCache* ng = new GraphCache;
+      ng->run = new BatchRun;
+      ng->cfg = cfg;
+      auto build = [&]() -> vx_status {
+        VX_TRY(setup_run(ctx, d, cfg, ks, ps, di, ng->run));
+        VX_HIP(hipStreamSynchronize(ctx->compute));
+        VX_HIP(hipStreamBeginCapture(ctx->compute, hipStreamCaptureModeThreadLocal));
+        vx_status cst = enqueue_batch(ctx, *ng->run, cfg, ks, J, ctx->compute, ctx->host_acc);
+        hipError_t ce = hipStreamEndCapture(ctx->compute, &ng->graph);
+        VX_TRY(cst);
+        VX_HIP(ce);
+        VX_HIP(hipGraphInstantiate(&ng->exec, ng->graph, nullptr, nullptr, 0));
+        return VX_OK;
+      };
+      const vx_status bst = build();
+      if (bst != VX_OK) {
+        (void)hipStreamSynchronize(ctx->compute);
+        drop_graph(ng);
+        return bst;
+      }
+      ng->key = job_keys(d);
+      ng->di = di;
+      gc = ng;
     }
     hipEvent_t a = get_event(ctx), b = get_event(ctx);
     VX_HIP(hipEventRecord(a, ctx->compute));

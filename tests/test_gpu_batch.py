@@ -167,3 +167,26 @@ def test_batch_mixed_xcd_placement(gpu, ctx, mode):
     got, _ = ctx.join_batch([dev(x) for x in bk], [dev(x) for x in bp], [dev(x) for x in pk], mode=mode,
                             tile_rows=8192, block=256, load_factor=0.5)
     assert got == exp
+
+
+def test_batch_budget_error_then_success(gpu):
+    """A batch whose tables do not fit the arena fails with VX_EBUDGET and leaves no cached graph
+    behind: a smaller batch on the same context then runs, and the large one fails again."""
+    MiB = 1 << 20
+    c = gpu.Context(64 * MiB)
+    try:
+        rng = np.random.default_rng(23)
+        big = np.unique(rng.integers(-2**31, 2**31 - 1, 5_000_000)).astype(np.int32)[:4_000_000]   # hash: 64 MiB of slots
+        small_k = [rng.permutation(1000).astype(np.int32), np.array([3, 9, -4], np.int32)]
+        small_p = [rng.integers(-2**31, 2**31, len(k)).astype(np.int32) for k in small_k]
+        probes = [rng.integers(-10, 1010, 5000).astype(np.int32), np.array([9, 9, 1], np.int32)]
+        _say("batch budget error")
+        for _ in range(2):
+            with pytest.raises(gpu.VxError) as ei:
+                c.join_batch([dev(big)], [dev(big)], [dev(big[:100])], tile_rows=8192, block=256, load_factor=0.5)
+            assert ei.value.status == gpu.VX_EBUDGET
+            got, _ = c.join_batch([dev(x) for x in small_k], [dev(x) for x in small_p], [dev(x) for x in probes],
+                                  tile_rows=8192, block=256, load_factor=0.5)
+            assert got == [oracle.join_agg(a, [b], p, []) for a, b, p in zip(small_k, small_p, probes)]
+    finally:
+        c.close()
