@@ -41,3 +41,34 @@ def test_struct_sizes_match_c_layout():
     assert ctypes.sizeof(vx.BuildDesc) == 48
     assert ctypes.sizeof(vx.ProbeDesc) == 72
     assert ctypes.sizeof(vx.GroupRow) == 48
+
+
+# binding class -> C typedef in include/vx.h
+_STRUCTS = {"Col": "vx_col", "Stats": "vx_stats", "LinkCalib": "vx_link_calib", "JoinRows": "vx_join_rows",
+            "BuildDesc": "vx_build_desc", "Agg": "vx_agg", "ProbeDesc": "vx_probe_desc", "StarDim": "vx_star_dim",
+            "GroupRow": "vx_group_row", "StarJoin": "vx_star_join", "BatchJoin": "vx_batch_join",
+            "PartOpts": "vx_part_opts", "SortDesc": "vx_sort_desc", "PartitionedJoin": "vx_partitioned_join",
+            "RadixJoin": "vx_radix_join", "JoinDesc": "vx_join_desc", "JoinOut": "vx_join_out",
+            "PartitionDesc": "vx_partition_desc", "PartitionOut": "vx_partition_out"}
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every struct of the binding has the size and field offsets the C compiler gives the
+    header's typedef (a C program built with gcc prints them)."""
+    import subprocess
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "vx.h"', "int main(void) {"]
+    want = {}
+    for py, c in _STRUCTS.items():
+        cls = getattr(vx, py)
+        lines.append(f'  printf("{py} %zu\\n", sizeof({c}));')
+        want[py] = ctypes.sizeof(cls)
+        for f in cls._fields_:
+            lines.append(f'  printf("{py}.{f[0]} %zu\\n", offsetof({c}, {f[0]}));')
+            want[f"{py}.{f[0]}"] = getattr(cls, f[0]).offset
+    lines.append("  return 0;\n}")
+    (tmp_path / "layout.c").write_text("\n".join(lines))
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(tmp_path / "layout.c"), "-o",
+                    str(tmp_path / "layout")], check=True, capture_output=True)
+    out = subprocess.run([str(tmp_path / "layout")], check=True, capture_output=True, text=True).stdout
+    got = {k: int(v) for k, v in (line.split() for line in out.splitlines())}
+    assert got == want
