@@ -36,6 +36,8 @@ void Pipeline::release_events() {
 
 static uint64_t align256(uint64_t v) { return (v + 255) / 256 * 256; }
 
+constexpr uint64_t kMinChunks = 4;
+
 vx_status Pipeline::plan(vx_ctx* ctx, uint64_t n, uint64_t chunk_rows, uint32_t n_buffers,
                          std::vector<PipeCol> cols, uint64_t default_chunk_bytes) {
   ctx_ = ctx;
@@ -63,7 +65,11 @@ vx_status Pipeline::plan(vx_ctx* ctx, uint64_t n, uint64_t chunk_rows, uint32_t 
   }
   bool given = chunk_rows != 0;
   if (!given) {
+    const bool env = getenv("VX_CHUNK_BYTES") != nullptr;
     uint64_t cb = env_u64("VX_CHUNK_BYTES", default_chunk_bytes);
+    // a short column still gets kMinChunks chunks, so that its copies overlap the kernels, but
+    // no chunk under 8 MiB (shorter copies lose rate to their fixed cost)
+    if (!env && streamed_) cb = std::min(cb, std::max<uint64_t>(8ull << 20, n * (uint64_t)widest / kMinChunks));
     chunk_rows = streamed_ ? std::max<uint64_t>(1, cb / (uint64_t)std::max(widest, 1)) : (n ? n : 1);
   }
   if (n && chunk_rows > n) chunk_rows = n;
