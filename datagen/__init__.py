@@ -223,6 +223,21 @@ def skew_build(n, seed=SEED_SKEW, out=None, row0=0):
     return out
 
 
+def scramble40(k):
+    """A bijection of [0, 2^40) applied in place to int64 keys (taken mod 2^40): an odd multiply,
+    an xor-shift and another odd multiply, each invertible mod 2^40.  Scrambled Zipf keys keep
+    their frequencies but lose their order."""
+    m = np.uint64((1 << 40) - 1)
+    u = k.view(np.uint64)
+    u &= m
+    u *= np.uint64(0x9E3779B97F4A7C15)
+    u &= m
+    u ^= u >> np.uint64(20)
+    u *= np.uint64(0xC2B2AE3D27D4EB4F)
+    u &= m
+    return k
+
+
 def skew_probe(n, seed=SEED_SKEW, out=None, row0=0):
     """Skewed probe side: Zipf(1.1) int64 keys over [1, 2^40]."""
     if out is None:

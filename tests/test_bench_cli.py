@@ -21,3 +21,15 @@ def test_workloads_listed():
     assert r.returncode == 0
     for w in ("stream", "plain", "star", "batch", "skew", "rows", "radix", "sort", "calib"):
         assert w in r.stdout
+
+
+def test_scramble40_is_a_bijection_on_samples():
+    """The skew workload's key scramble keeps keys in [0, 2^40) and never maps two keys to one (each
+    step, an odd multiply or an xor-shift mod 2^40, is invertible)."""
+    import numpy as np
+    import datagen
+    rng = np.random.default_rng(4)
+    k = np.unique(np.concatenate([np.arange(1, 1 << 18), rng.integers(0, 1 << 40, 1 << 18)])).astype(np.int64)
+    s = datagen.scramble40(k.copy())
+    assert s.min() >= 0 and s.max() < (1 << 40)
+    assert len(np.unique(s)) == len(k)
