@@ -308,9 +308,12 @@ typedef struct {
 } vx_batch_join;
 
 typedef enum {
-  VX_PART_AUTO = 0,            /* vx_partition: the lower imbalance on the key sample (learned or
-                                  radix-hash); partitioned join: learned when its splitters
-                                  isolate a heavy key (a singleton partition), else radix-hash */
+  VX_PART_AUTO = 0,            /* range splitters from the trained model, or from the sample
+                                  quantiles when their singleton partitions hold 5 points more of
+                                  the sample; then vx_partition: the lower imbalance on the key
+                                  sample (those splitters or radix-hash); partitioned join: the
+                                  range splitters when they isolate a heavy key (a singleton
+                                  partition), else radix-hash.  method_used reports the choice */
   VX_PART_RADIX_HASH = 1,      /* top bits of a 64-bit mix of the key */
   VX_PART_RADIX_BITS = 2,      /* raw key bits [shift, shift + log2 P) as in the paper */
   VX_PART_LEARNED = 3,         /* CDF-model range splitters, trained on the GPU */

@@ -21,6 +21,8 @@ struct CdfReport {
   double single_share = 0;     // share of sample rows in singleton partitions
   double max_share = 0;        // largest other partition's share of the sample rows
   double distinct_share = 0;   // distinct keys / rows in the sample
+  bool auto_quantile = false;  // AUTO kept the sample-quantile splitters (their singleton
+                               // partitions held clearly more of the sample than the model's)
 };
 
 // Samples keys (Bernoulli, SplitMix64 draws keyed by row), sorts the sample on the GPU,

@@ -570,52 +570,105 @@ vx_status cdf_splitters(vx_ctx* ctx, const ColInfo& key, uint64_t n, const vx_pa
   double t3 = now_ms();
   rep->train_ms = t3 - t2;
 
-  // splitters: idx_j = first sample row whose value reaches j / P
+  // splitters: idx_j = first sample row whose value reaches j / P, under the model (or, with
+  // model == false, under the empirical mid-CDF: the sample quantiles)
   const uint32_t P = n_parts;
-  if (P > 1) {
-    ArenaBlock fb;
-    fb.a = &ctx->arena;
-    fb.p = ctx->arena.alloc((uint64_t)P * 8 * 3);
-    VX_CHECK(fb.p, VX_EBUDGET, "cdf: no room for quantile scratch");
-    unsigned long long* first = (unsigned long long*)fb.p;
-    unsigned long long* idxd = first + P;
-    long long* keysd = (long long*)(idxd + P);
-    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(256), 0, s, first, (uint64_t)P, ~0ull);
-    hipLaunchKernelGGL(k_cross, dim3(grid1(ctx, m)), dim3(256), 0, s, fx, ft, m,
-                       use_model ? mm.md.params : nullptr, P, first);
-    std::vector<unsigned long long> fh(P);
-    VX_HIP(hipMemcpyAsync(fh.data(), first, P * 8, hipMemcpyDeviceToHost, s));
-    VX_HIP(hipStreamSynchronize(s));
-    // the first row reaching quantile j is the earliest row reaching any j' >= j
-    std::vector<unsigned long long> idx(P, ~0ull);
-    unsigned long long run = ~0ull;
-    for (int64_t j = (int64_t)P - 1; j >= 1; --j) {
-      run = std::min(run, fh[j]);
-      idx[j] = run;
-    }
-    // distinct rows in quantile order, with how many quantiles each carries
-    std::vector<unsigned long long> rows;
-    std::vector<uint32_t> carried;
-    for (uint32_t j = 1; j < P; ++j) {
-      if (idx[j] == ~0ull) break;
-      if (!rows.empty() && rows.back() == idx[j]) ++carried.back();
-      else {
-        rows.push_back(idx[j]);
-        carried.push_back(1);
-      }
-    }
-    if (!rows.empty()) {
-      VX_HIP(hipMemcpyAsync(idxd, rows.data(), rows.size() * 8, hipMemcpyHostToDevice, s));
-      hipLaunchKernelGGL(k_gather_i64, dim3((unsigned)((rows.size() + 255) / 256)), dim3(256), 0, s,
-                         sorted, idxd, (uint32_t)rows.size(), keysd);
-      std::vector<long long> ks(rows.size());
-      VX_HIP(hipMemcpyAsync(ks.data(), keysd, rows.size() * 8, hipMemcpyDeviceToHost, s));
+  auto make_splitters = [&](bool model, std::vector<int64_t>* out) -> vx_status {
+    out->clear();
+    if (P > 1) {
+      ArenaBlock fb;
+      fb.a = &ctx->arena;
+      fb.p = ctx->arena.alloc((uint64_t)P * 8 * 3);
+      VX_CHECK(fb.p, VX_EBUDGET, "cdf: no room for quantile scratch");
+      unsigned long long* first = (unsigned long long*)fb.p;
+      unsigned long long* idxd = first + P;
+      long long* keysd = (long long*)(idxd + P);
+      hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(256), 0, s, first, (uint64_t)P, ~0ull);
+      hipLaunchKernelGGL(k_cross, dim3(grid1(ctx, m)), dim3(256), 0, s, fx, ft, m,
+                         model ? mm.md.params : nullptr, P, first);
+      std::vector<unsigned long long> fh(P);
+      VX_HIP(hipMemcpyAsync(fh.data(), first, P * 8, hipMemcpyDeviceToHost, s));
       VX_HIP(hipStreamSynchronize(s));
-      for (size_t r = 0; r < rows.size(); ++r) {
-        long long k = ks[r];
-        if (splitters->empty() || splitters->back() < k) splitters->push_back(k);
-        if (carried[r] > 1 && k < INT64_MAX && splitters->back() < k + 1) splitters->push_back(k + 1);
+      // the first row reaching quantile j is the earliest row reaching any j' >= j
+      std::vector<unsigned long long> idx(P, ~0ull);
+      unsigned long long run = ~0ull;
+      for (int64_t j = (int64_t)P - 1; j >= 1; --j) {
+        run = std::min(run, fh[j]);
+        idx[j] = run;
       }
+      // distinct rows in quantile order, with how many quantiles each carries
+      std::vector<unsigned long long> rows;
+      std::vector<uint32_t> carried;
+      for (uint32_t j = 1; j < P; ++j) {
+        if (idx[j] == ~0ull) break;
+        if (!rows.empty() && rows.back() == idx[j]) ++carried.back();
+        else {
+          rows.push_back(idx[j]);
+          carried.push_back(1);
+        }
+      }
+      if (!rows.empty()) {
+        VX_HIP(hipMemcpyAsync(idxd, rows.data(), rows.size() * 8, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_gather_i64, dim3((unsigned)((rows.size() + 255) / 256)), dim3(256), 0, s,
+                           sorted, idxd, (uint32_t)rows.size(), keysd);
+        std::vector<long long> ks(rows.size());
+        VX_HIP(hipMemcpyAsync(ks.data(), keysd, rows.size() * 8, hipMemcpyDeviceToHost, s));
+        VX_HIP(hipStreamSynchronize(s));
+        for (size_t r = 0; r < rows.size(); ++r) {
+          long long k = ks[r];
+          if (out->empty() || out->back() < k) out->push_back(k);
+          if (carried[r] > 1 && k < INT64_MAX && out->back() < k + 1) out->push_back(k + 1);
+        }
+      }
+    }
+    return VX_OK;
+  };
+  // the share of the sample in singleton partitions under range splitters sp (a histogram of
+  // the sorted sample)
+  auto single_share = [&](const std::vector<int64_t>& sp, double* share) -> vx_status {
+    const uint32_t np = (uint32_t)sp.size() + 1;
+    PartGeom g = part_geom(ctx, m);
+    ArenaBlock b;
+    b.a = &ctx->arena;
+    b.p = ctx->arena.alloc((uint64_t)np * g.waves * 4 + (uint64_t)np * 8 + sp.size() * 8 + 256);
+    VX_CHECK(b.p, VX_EBUDGET, "cdf: no room for sample histograms");
+    uint32_t* hist = (uint32_t*)b.p;
+    unsigned long long* tot = (unsigned long long*)(b.p + (uint64_t)np * g.waves * 4);
+    long long* spl = (long long*)(tot + np);
+    PartIO io{};
+    io.key = sorted;
+    io.key_size = 8;
+    io.n = m;
+    PartSpec ps{};
+    ps.fn = kPartRange;
+    ps.n_split = np - 1;
+    ps.n_parts = np;
+    ps.splitters = spl;
+    if (ps.n_split) VX_HIP(hipMemcpyAsync(spl, sp.data(), ps.n_split * 8, hipMemcpyHostToDevice, s));
+    fill_zero((uint64_t*)tot, np, s);
+    VX_TRY(part_hist(ctx, ps, io, g, hist, tot, nullptr, nullptr, s));
+    std::vector<unsigned long long> h(np);
+    VX_HIP(hipMemcpyAsync(h.data(), tot, np * 8, hipMemcpyDeviceToHost, s));
+    VX_HIP(hipStreamSynchronize(s));
+    uint64_t one = 0;
+    for (uint32_t p = 1; p + 1 < np; ++p)
+      if (sp[p] == sp[p - 1] + 1) one += h[p];
+    *share = (double)one / (double)m;
+    return VX_OK;
+  };
+  VX_TRY(make_splitters(use_model, splitters));
+  // AUTO: the sample quantiles are kept instead when their singleton partitions hold clearly more
+  // of the sample (5 points) than the model's: keys whose order carries no skew (scrambled, say)
+  // defeat the model's log-scale feature, not the quantiles
+  if (o.method == VX_PART_AUTO) {
+    std::vector<int64_t> q;
+    VX_TRY(make_splitters(false, &q));
+    double sm = 0, sq = 0;
+    VX_TRY(single_share(*splitters, &sm));
+    VX_TRY(single_share(q, &sq));
+    if (sq > sm + 0.05) {
+      splitters->swap(q);
+      rep->auto_quantile = true;
     }
   }
   rep->split_ms = now_ms() - t3;

@@ -357,7 +357,9 @@ static vx_status partition_impl(vx_ctx* ctx, const vx_partition_desc* d, vx_part
     VX_TRY(cdf_splitters(ctx, kc, n, o, req, &split, &rep, out->model));
     method_used = o.method;
     if (o.method == VX_PART_AUTO)
-      method_used = rep.imbalance_range < rep.imbalance_radix ? VX_PART_LEARNED : VX_PART_RADIX_HASH;
+      method_used = rep.imbalance_range < rep.imbalance_radix
+                        ? (rep.auto_quantile ? VX_PART_QUANTILE : VX_PART_LEARNED)
+                        : VX_PART_RADIX_HASH;
   }
   vx_part_opts eff = o;
   eff.method = method_used == VX_PART_LEARNED || method_used == VX_PART_QUANTILE ||

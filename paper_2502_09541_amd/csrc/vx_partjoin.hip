@@ -590,7 +590,7 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
     if (method == VX_PART_AUTO) {
       bool singleton = false;
       for (size_t i = 1; i < split.size(); ++i) singleton |= split[i] == split[i - 1] + 1;
-      method = singleton ? VX_PART_LEARNED : VX_PART_RADIX_HASH;
+      method = singleton ? (rep.auto_quantile ? VX_PART_QUANTILE : VX_PART_LEARNED) : VX_PART_RADIX_HASH;
     }
   }
   double train_ms = now_ms() - tt0;

@@ -232,7 +232,9 @@ def test_auto_method_reports_estimates(gpu, ctx):
     _say("auto method")
     r = ctx.partition(dev(key), method="auto", n_parts=64, seed=5, train_steps=40)
     assert r["est_imbalance_radix"] > 1.0 and r["est_imbalance_range"] > 0
-    assert r["method_used"] in (1, 3)
+    # AUTO picks among radix-hash, the trained model's splitters and the sample quantiles (these
+    # when their singletons hold clearly more of the sample, as after only 40 training steps)
+    assert r["method_used"] in (gpu.VX_PART_RADIX_HASH, gpu.VX_PART_LEARNED, gpu.VX_PART_QUANTILE)
     assert r["hist"].sum() == len(key)
 
 
@@ -360,3 +362,21 @@ def test_partitioned_join_edges(gpu, ctx):
                                sample_frac=0.5, train_steps=10)[0]
     assert got == oracle.join_agg(same, [same], same[:77], [])
     del e
+
+
+def test_partitioned_join_auto_on_scrambled_keys(gpu, ctx, monkeypatch):
+    """Zipf keys scrambled by a bijection keep their heavy keys but lose the order that the learned
+    model's log-scale feature relies on.  AUTO must still isolate the heavy keys (with the learned
+    splitters, or else the sample quantiles) instead of falling back to radix-hash, and stay exact."""
+    import datagen
+    monkeypatch.setenv("VX_CHUNK_BYTES", str(8 * 50_000))
+    bk, bp, pk = _zipf_join(300_000, 1_000_001, 31)
+    datagen.scramble40(bk)
+    datagen.scramble40(pk)
+    _say("partitioned join auto, scrambled keys")
+    got, st, used = ctx.join_partitioned(pinned(gpu, bk), [pinned(gpu, bp)], pinned(gpu, pk), method="auto",
+                                         n_parts=64, seed=9, train_steps=80)
+    assert got == oracle.join_agg(bk, [bp], pk, [])
+    assert used in (gpu.VX_PART_LEARNED, gpu.VX_PART_QUANTILE)
+    # the heaviest key alone holds about 9.5% of the rows; radix-hash would isolate none
+    assert st["singleton_rows"] > 0.05 * (len(bk) + len(pk))
