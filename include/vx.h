@@ -17,9 +17,10 @@
  *     streamed fact table, with GROUP BY (Sec. 7.1, Star Schema Benchmark plan);
  *   - radix partitioning into groups with a boundary array (Sec. 6.2.1) for the
  *     case where the build side exceeds device memory (Sec. 6.2).
- * Learned (CDF-model) range partitioning and the batched persistent-kernel join
- * are additions of this library; the paper leaves skew-aware partitioning out of
- * its scope (Sec. 6.2.1).
+ * Learned (CDF-model) range partitioning, the batched join (queue-draining
+ * kernels in one HIP graph) and directly indexed tables for keys that fill a
+ * narrow range are additions of this library; the paper leaves skew-aware
+ * partitioning out of its scope (Sec. 6.2.1).
  *
  * Conventions for every entry point:
  *   - Every call returns a vx_status; nothing throws across the ABI.  On a
