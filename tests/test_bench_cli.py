@@ -21,6 +21,8 @@ def test_workloads_listed():
     assert r.returncode == 0
     for w in ("stream", "plain", "star", "batch", "skew", "rows", "radix", "sort", "calib"):
         assert w in r.stdout
+    for opt in ("--skew-budget-gib", "--skew-scramble", "--radix-budget-gib", "--sort-budget-gib"):
+        assert opt in r.stdout
 
 
 def test_scramble40_is_a_bijection_on_samples():
