@@ -527,7 +527,8 @@ def run_skew(args):
             return {"error": failed[name]}
         x = lines[name]
         return {"ms_per_step": x["ms"], "value": x["value"], "imbalance": x["st"]["imbalance"],
-                "imbalance_table_partitions": x["st"]["imbalance_tables"], "part_ms": x["st"]["part_ms"],
+                "imbalance_table_partitions": x["st"]["imbalance_tables"],
+                "imbalance_distinct_keys": x["st"]["imbalance_distinct"], "part_ms": x["st"]["part_ms"],
                 "join_ms": x["st"]["probe_ms"], "singleton_rows": x["st"]["singleton_rows"]}
     st = a["st"]
     h2d = st["sdma_bytes"] + st["zc_bytes_est"]
@@ -553,6 +554,7 @@ def run_skew(args):
                     "result": {"match_count": a["agg"][0], "sum": a["agg"][1]},
                     "learned": {"ms_per_step": a["ms"], "value": a["value"], "imbalance": st["imbalance"],
                                 "imbalance_table_partitions": st["imbalance_tables"],
+                                "imbalance_distinct_keys": st["imbalance_distinct"],
                                 "singleton_rows": st["singleton_rows"], "part_ms": st["part_ms"],
                                 "train_ms": st["train_ms"], "join_ms": st["probe_ms"]},
                     "radix_hash": control("radix_hash"),

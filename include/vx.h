@@ -146,6 +146,8 @@ typedef struct {
                                probe rows routed to a partition table (not a singleton) */
   double imbalance_tables;  /* partitioned join: max/mean build + probe rows over the partitions
                                joined through a table (singletons excluded) */
+  double imbalance_distinct; /* partitioned join: max/mean distinct build keys over the same
+                                partitions (their pre-aggregating tables grow with it) */
 } vx_stats;
 
 /* ------------------------------------------------------------------------ build / probe */

@@ -53,7 +53,8 @@ class Stats(C.Structure):
                 ("total_ms", C.c_double), ("kernel_ms", C.c_double), ("kernel_launches", C.c_uint64),
                 ("table_bytes", C.c_uint64), ("n_parts", C.c_uint64), ("imbalance", C.c_double),
                 ("part_ms", C.c_double), ("train_ms", C.c_double), ("singleton_rows", C.c_uint64),
-                ("survivors", C.c_uint64), ("imbalance_tables", C.c_double)]
+                ("survivors", C.c_uint64), ("imbalance_tables", C.c_double),
+                ("imbalance_distinct", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

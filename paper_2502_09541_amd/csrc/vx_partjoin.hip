@@ -804,6 +804,8 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
   VX_TRY(pipe.prefetch(pipe.n_buffers()));
   uint64_t cused = 0;
   bool any_resident = false;
+  double dmx = 0, dtot = 0;   // distinct build keys of the table partitions
+  uint32_t dparts = 0;
   for (uint32_t p = 0; p < P; ++p) {
     if (slot[p] >= 0 || brows[p] == 0) continue;
     const uint64_t nb = nb_of[p];
@@ -833,6 +835,9 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
     VX_HIP(hipMemcpyAsync(&nd, distinct, 8, hipMemcpyDeviceToHost, ctx->compute));
     VX_HIP(hipStreamSynchronize(ctx->compute));
     VX_TRY(check_flags(ctx, "partitioned join (build)"));
+    dmx = std::max(dmx, (double)nd);
+    dtot += (double)nd;
+    ++dparts;
     const uint64_t ccap = pow2_at_least(nd + nd / 4);   // load factor 0.4 .. 0.8
     const uint64_t need = ccap << kSlotShift;
     VX_CHECK(need <= cbytes, VX_EBUDGET,
@@ -938,6 +943,7 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
       ++tparts;
     }
   s.imbalance_tables = ttot > 0 ? tmx / (ttot / tparts) : 0.0;
+  s.imbalance_distinct = dtot > 0 ? dmx / (dtot / dparts) : 0.0;
   s.sdma_bytes = bs.sdma + pipe.sdma_bytes();
   uint64_t pass2_bytes = 0;
   for (uint32_t p = 0; p < P; ++p)
