@@ -66,6 +66,8 @@ def _load():
     u32p = C.POINTER(C.c_uint32)
     lib.or_part_ids_bits.argtypes = [_Col, C.c_uint64, C.c_uint32, C.c_uint32, u32p]
     lib.or_part_ids_hash.argtypes = [_Col, C.c_uint64, C.c_uint32, u32p]
+    lib.or_hash64.argtypes = [_Col, C.c_uint64, u64p]
+    lib.or_splitmix64.argtypes = [C.c_uint64, C.c_uint64, u64p]
     lib.or_part_ids_range.argtypes = [_Col, C.c_uint64, C.POINTER(C.c_int64), C.c_uint32, u32p]
     lib.or_histogram.argtypes = [u32p, C.c_uint64, C.c_uint32, u64p]
     lib.or_cluster_boundary.argtypes = [u32p, C.c_uint64, C.c_uint32, u64p, u64p]
@@ -210,6 +212,20 @@ def part_ids_hash(keys, log2p):
     ids = np.zeros(len(keys), dtype=np.uint32)
     _load().or_part_ids_hash(_col(keys), len(keys), log2p, _ptr(ids, C.c_uint32))
     return ids
+
+
+def hash64(keys):
+    """The full 64-bit MurmurHash3 finalizer of each key (radix-hash ids are its top bits)."""
+    out = np.zeros(len(keys), dtype=np.uint64)
+    _load().or_hash64(_col(keys), len(keys), _ptr(out, C.c_uint64))
+    return out
+
+
+def splitmix64(seed, n):
+    """The first n outputs of SplitMix64 started from state `seed` (the sampler's stream)."""
+    out = np.zeros(max(1, n), dtype=np.uint64)
+    _load().or_splitmix64(int(seed), n, _ptr(out, C.c_uint64))
+    return out[:n]
 
 
 def part_ids_range(keys, splitters):

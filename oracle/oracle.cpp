@@ -281,17 +281,28 @@ void or_part_ids_bits(or_col keys, uint64_t n, uint32_t shift, uint32_t log2p, u
   for (uint64_t i = 0; i < n; ++i) ids[i] = (uint32_t)(((uint64_t)at(keys, i) >> shift) & mask);
 }
 
+/* The MurmurHash3 64-bit finalizer (Appleby, public domain): a bijection of
+ * the 64-bit words.  Pinned by its published inverse (tests). */
+static uint64_t fmix64(uint64_t h) {
+  h ^= h >> 33;
+  h *= 0xff51afd7ed558ccdULL;
+  h ^= h >> 33;
+  h *= 0xc4ceb9fe1a85ec53ULL;
+  h ^= h >> 33;
+  return h;
+}
+
+/* The whole 64-bit finalizer value of each key, so that it can be pinned. */
+void or_hash64(or_col keys, uint64_t n, uint64_t* out) {
+  for (uint64_t i = 0; i < n; ++i) out[i] = fmix64((uint64_t)at(keys, i));
+}
+
 /* Radix partition by a hash of the key, for skewed keys (the paper leaves a
  * better hash for skew out of its scope; this reading takes the MurmurHash3
  * 64-bit finalizer and keeps its top log2p bits). */
 void or_part_ids_hash(or_col keys, uint64_t n, uint32_t log2p, uint32_t* ids) {
   for (uint64_t i = 0; i < n; ++i) {
-    uint64_t h = (uint64_t)at(keys, i);
-    h ^= h >> 33;
-    h *= 0xff51afd7ed558ccdULL;
-    h ^= h >> 33;
-    h *= 0xc4ceb9fe1a85ec53ULL;
-    h ^= h >> 33;
+    uint64_t h = fmix64((uint64_t)at(keys, i));
     ids[i] = log2p == 0 ? 0u : (uint32_t)(h >> (64 - log2p));
   }
 }
@@ -356,17 +367,26 @@ double or_late_mat_threshold(double elem_bytes, double line_bytes, double n_exch
  * started from state `seed` is below frac * 2^64.  Keys of kept rows are written in row
  * order; returns their count.
  */
+static uint64_t splitmix64_next(uint64_t* state) {
+  *state += 0x9E3779B97F4A7C15ULL;
+  uint64_t z = *state;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+/* The first n outputs of the SplitMix64 generator started from state `seed`,
+ * so that the stream the sampler draws from can be pinned. */
+void or_splitmix64(uint64_t seed, uint64_t n, uint64_t* out) {
+  uint64_t state = seed;
+  for (uint64_t i = 0; i < n; ++i) out[i] = splitmix64_next(&state);
+}
+
 uint64_t or_sample_bernoulli(or_col keys, uint64_t n, uint64_t seed, double frac, int64_t* out) {
   uint64_t thr = frac >= 1.0 ? ~0ULL : (uint64_t)(frac * 18446744073709551616.0);
   uint64_t state = seed, m = 0;
-  for (uint64_t i = 0; i < n; ++i) {
-    state += 0x9E3779B97F4A7C15ULL;
-    uint64_t z = state;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-    z ^= z >> 31;
-    if (z < thr) out[m++] = at(keys, i);
-  }
+  for (uint64_t i = 0; i < n; ++i)
+    if (splitmix64_next(&state) < thr) out[m++] = at(keys, i);
   return m;
 }
 

@@ -16,6 +16,31 @@ import oracle
 H = 64
 
 
+def test_splitmix64_published_outputs():
+    """SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) from state 0: its first outputs are the
+    published sequence (the same stream as Java's SplittableRandom(0).nextLong(), whose first
+    value is -2152535657050944081)."""
+    got = [int(v) for v in oracle.splitmix64(0, 4)]
+    assert got == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F, 0xF88BB8A8724C81EC]
+    assert got[0] == (1 << 64) - 2152535657050944081
+
+
+def test_sample_bernoulli_uses_stream_and_kept_fraction():
+    """Row i is kept iff the (i+1)-th output of the pinned stream is below frac * 2^64, and the
+    kept count lies in a 5-sigma binomial band."""
+    n, seed = 400_000, 987654321
+    keys = np.arange(n, dtype=np.int64) * 5 - 7
+    z = oracle.splitmix64(seed, n)
+    for frac in (0.01, 0.25):
+        s = oracle.sample_bernoulli(keys, seed, frac)
+        thr = np.uint64(int(frac * 2**64))
+        assert np.array_equal(s, keys[z < thr])
+        sd = math.sqrt(n * frac * (1 - frac))
+        assert abs(len(s) - n * frac) < 5 * sd
+    assert np.array_equal(oracle.sample_bernoulli(keys[:1000], seed, 1.0), keys[:1000])
+    assert len(oracle.sample_bernoulli(keys[:1000], seed, 0.0)) == 0
+
+
 def test_feature_exact_values():
     L = 40
     scale = np.float32(1.0 / (L * 2**23))

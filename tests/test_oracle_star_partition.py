@@ -161,6 +161,36 @@ def test_part_ids_hash_properties():
     assert oracle.part_ids_hash(keys, 0).max() == 0
 
 
+# The published inverse of the MurmurHash3 64-bit finalizer (the "unmix" used to invert it):
+# the xor-shift by 33 undoes itself, and these are the inverses of its two multipliers mod 2^64.
+_UNMIX = (0x9CB4B2F8129337DB, 0x4F74430C22A54005)
+
+
+def _unmix64(h):
+    m = (1 << 64) - 1
+    h ^= h >> 33
+    h = (h * _UNMIX[0]) & m
+    h ^= h >> 33
+    h = (h * _UNMIX[1]) & m
+    h ^= h >> 33
+    return h
+
+
+def test_hash64_inverted_by_published_unmix():
+    """The finalizer's output, run through its published inverse, gives the key back.  A wrong
+    multiplier, shift or step order in the oracle's finalizer breaks this for almost every key."""
+    rng = np.random.default_rng(11)
+    keys = np.concatenate([rng.integers(-2**63, 2**63 - 1, 2000, dtype=np.int64),
+                           np.array([0, 1, -1, 2**63 - 1, -2**63, 2**40, 12345], np.int64)])
+    h = oracle.hash64(keys)
+    assert h[len(keys) - 7] == 0                     # fmix64(0) = 0
+    back = [_unmix64(int(v)) for v in h]
+    assert back == [int(k) & ((1 << 64) - 1) for k in keys]
+    # the radix-hash id is the finalizer's top log2p bits
+    for log2p in (1, 7, 12):
+        assert np.array_equal(oracle.part_ids_hash(keys, log2p), (h >> np.uint64(64 - log2p)).astype(np.uint32))
+
+
 def test_part_ids_range_is_upper_bound():
     rng = np.random.default_rng(4)
     keys = rng.integers(-1000, 1000, 5000).astype(np.int64)
