@@ -22,17 +22,17 @@ sys.path.insert(0, ROOT)
 
 METRIC = "probe rows/s + % host-link peak; learned vs hash partitioning, bit-exact"
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E datasheet peak
-# HBM bytes per launch of the dominant kernel, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs
-# scaled by what the same counters read for a plain 1 GiB device read and write (the summaries
-# under profiles/ give the commands).  Valid for the kernel source they were measured on.
-TRAFFIC_BYTES = {"k_probe_stream": 1.5643e9,    # 8,388,608 probe rows per launch
-                 "k_probe_plain": 6.3886e8,     # 16,777,216 probe rows per launch (direct table)
-                 "k_star": 1.9346e9,            # 16,666,667 fact rows per launch (direct dimension tables)
-                 "batch_graph": 1.8282e11,      # one graph launch: build phase, bit count, probe phase, all 256 jobs
-                 "k_pj_stream": 4.976e8,        # 8,388,608 probe rows per launch (mean over the partitioners)
-                 "k_probe_rows": 1.4712e9,      # 8,388,608 probe rows per launch, output rows included
-                 "k_rj_probe": 6.9041e9,        # 33,554,432 B rows per launch (host reads + table lines)
-                 "sort_run": 2.4941e10}         # one 2^26-key run: 8 x (k_part_hist + k_part_scatter)
+# HBM traffic of a kernel comes from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs, which cannot be
+# taken inside this process; each roofline names the profile summary that holds them
+# ("traffic_profile") and reports "traffic": null.
+PROFILE = {"k_probe_stream": "profiles/k_probe_streamed_join.md",
+           "k_probe_plain": "profiles/k_probe_plain_join.md",
+           "k_star": "profiles/k_star_star_join.md",
+           "batch_graph": "profiles/k_batch_phase_batched_joins.md",
+           "k_pj_stream": "profiles/k_pj_stream_skewed_partitioned_join.md",
+           "k_probe_rows": "profiles/k_probe_rows_streamed_join.md",
+           "k_rj_probe": "profiles/k_rj_probe_two_table_radix_join.md",
+           "sort_run": "profiles/k_part_scatter_out_of_core_sort.md"}
 GiB = 1 << 30
 
 
@@ -52,6 +52,10 @@ def parse():
     ap.add_argument("--chunk-rows", type=int, default=0)
     ap.add_argument("--n-buffers", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-skew", action="store_true",
+                    help="stream workload: leave out the skewed partitioned join block")
+    ap.add_argument("--skew-steps", type=int, default=3,
+                    help="stream workload: timed steps per partitioner in the skewed join block")
     ap.add_argument("--workload", default="stream", choices=["stream", "plain", "star", "batch", "skew", "rows", "radix", "sort", "calib"],
                     help="stream (default) is the headline line; the others print their own line")
     ap.add_argument("--method", default="learned", help="skew workload: partitioner to time")
@@ -67,12 +71,35 @@ def parse():
     return ap.parse_args()
 
 
+def host_info():
+    """What the oracle timings ran on: CPU model, logical CPUs (all, and usable by this process), RAM."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    ram = None
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal:"):
+                    ram = round(int(line.split()[1]) / (1 << 20), 1)
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "host_cpus": os.cpu_count(), "host_cpus_usable": len(os.sched_getaffinity(0)),
+            "ram_gib": ram}
+
+
 def cpu_baseline(log2_build, log2_probe):
     """The oracle (single-threaded, as it stands) on the same workload scaled down 8x:
     2^(b-3) build rows and 2^(p-3) probe rows from the same generators, 10% match.  Also the
     same oracle on all host cores (one build, the probe rows cut into one slice per thread,
     read-only lookups; the C calls release the GIL)."""
-    import os
     from concurrent.futures import ThreadPoolExecutor
     import datagen
     import oracle
@@ -94,10 +121,11 @@ def cpu_baseline(log2_build, log2_probe):
     if [sum(x) % (1 << 64) for x in zip(*parts)] != one:
         raise SystemExit("threaded oracle run disagrees with the single-threaded one")
     sample = f"same generators scaled 1/8: {nb} build rows, {np_} probe rows (10% match)"
+    hi = host_info()
     return ({"value": np_ / dt, "unit": "probe rows/s", "cores": 1, "kind": "oracle",
-             "sample": f"{sample}, build + probe in {dt:.1f} s on 1 host thread"},
+             "sample": f"{sample}, build + probe in {dt:.1f} s on 1 host thread", **hi},
             {"value": np_ / dt_all, "unit": "probe rows/s", "cores": n_thr, "kind": "oracle",
-             "sample": f"{sample}, build on 1 thread + probe on {n_thr} threads in {dt_all:.1f} s"})
+             "sample": f"{sample}, build on 1 thread + probe on {n_thr} threads in {dt_all:.1f} s", **hi})
 
 
 def main():
@@ -164,20 +192,27 @@ def main():
     ms = wall * 1e3 / args.steps
     value = np_ / (ms / 1e3)
 
-    # dominant kernel: the probe kernel (HIP events on the library's compute stream)
+    st = stats[0]
+    count = results[0][0]
+    # The pipeline is bound by the host link: every step moves the build columns, the probe keys
+    # (chunk copies) and the matching rows' payloads (zero-copy gathers) over it.
+    # algorithmic bytes: build columns (8 + 4 + 4 B per row), 8 B per probe key, 16 B of payloads
+    # per match; wire bytes: the same build columns, the bytes the copy stream moved, and the
+    # zero-copy granules the probe kernels counted, times the granule
+    alg_bytes = nb * 16 + np_ * 8 + count * 16
+    wire_bytes = nb * 16 + st["sdma_bytes"] + st["zc_bytes"]
+    granule = calib["zc_granule"]
+    # the binomial wire model, for comparison with the count: each of the 2 payload columns of
+    # 8-byte rows has granule/8 rows per granule, each granule moving if any of its rows matches
+    sel = count / np_
+    zc_model = 2 * np_ * 8 * (1.0 - (1.0 - sel) ** (granule // 8)) if st["zc_mask"] == 3 else None
+    # the probe kernel itself against HBM (secondary): per row 8 B of key from the chunk buffer
+    # and one 16 B table slot, over its average launch time (HIP events on the library's stream)
     kms = sum(s["kernel_ms"] for s in stats)
     klaunch = sum(s["kernel_launches"] for s in stats)
     k_avg_ms = kms / klaunch
-    st = stats[0]
     rows_per_launch = np_ / st["kernel_launches"]
-    count = results[0][0]
-    # algorithmic device-memory bytes per probe row: 8 B key from the chunk buffer + one
-    # 16 B hash-table slot
-    hbm_bytes = 24.0 * rows_per_launch
-    hbm_gbs = hbm_bytes / (k_avg_ms * 1e6)
-    # host link: algorithmic = build columns (16 B/row) + probe keys + payloads of matches
-    alg_bytes = nb * 16 + np_ * 8 + count * 16
-    wire_bytes = nb * 16 + st["sdma_bytes"] + st["zc_bytes_est"]
+    hbm_gbs = 24.0 * rows_per_launch / (k_avg_ms * 1e6)
     out = {
         "metric": METRIC,
         "value": value,
@@ -197,25 +232,221 @@ def main():
                    "chunk_rows": st["chunk_rows"], "n_buffers": st["n_buffers"],
                    "late_mat": {-1: "auto", 0: "sdma", 1: "zero-copy", 2: "paper-TH"}[args.late_mat],
                    "zero_copy_columns": bin(st["zc_mask"]).count("1")},
-        "roofline": {"bound": "hbm", "kernel": "k_probe", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": hbm_gbs / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES["k_probe_stream"],
-                     "avg_launch_ms": k_avg_ms, "rows_per_launch": rows_per_launch},
+        "roofline": {"bound": "host_link",
+                     "kernel": "whole step: build columns read in place, probe-key chunk copies, k_probe's "
+                               "zero-copy payload gathers",
+                     "achieved": alg_bytes / (ms * 1e6), "peak": b_peak, "unit": "GB/s",
+                     "frac": alg_bytes / (ms * 1e6) / b_peak,
+                     "traffic": wire_bytes,
+                     "peak_kind": "host-to-device copy rate measured in this run (PCIe 5.0 x16, 63 GB/s "
+                                  "theoretical); the datasheet gives no achievable figure",
+                     "algorithmic_bytes": "per step: 16 B per build row + 8 B per probe key + 16 B of payloads "
+                                          "per match",
+                     "traffic_kind": "host-link bytes per step: build columns + copy-stream bytes + zero-copy "
+                                     "granules counted by k_probe x granule"},
         "host_link": {"peak_measured_gbs": b_peak,
                       "achieved_wire_gbs": wire_bytes / (ms * 1e6),
                       "frac_wire": wire_bytes / (ms * 1e6) / b_peak,
                       "achieved_algorithmic_gbs": alg_bytes / (ms * 1e6),
                       "frac_algorithmic": alg_bytes / (ms * 1e6) / b_peak,
-                      "wire_bytes_per_step": wire_bytes, "algorithmic_bytes_per_step": alg_bytes},
+                      "wire_bytes_per_step": wire_bytes, "algorithmic_bytes_per_step": alg_bytes,
+                      "zero_copy_bytes_counted": st["zc_bytes"], "zero_copy_granule": granule,
+                      "zero_copy_bytes_binomial_model": zc_model,
+                      "sdma_bytes_per_step": st["sdma_bytes"]},
+        "hbm": {"kernel": "k_probe", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": hbm_gbs / HBM_PEAK_GBS, "traffic": None, "traffic_profile": PROFILE["k_probe_stream"],
+                "avg_launch_ms": k_avg_ms, "rows_per_launch": rows_per_launch,
+                "algorithmic_bytes": "24 B per probe row (8 B key from the chunk buffer + one 16 B slot)"},
         "result": {"match_count": count, "sums": results[0][1:]},
         "calibration": calib,
     }
     ctx.close()
     for h in H.values():
         h.free()
+    del H
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"], out["cpu_baseline_all_cores"] = cpu_baseline(args.log2_build, args.log2_probe)
+    if not args.no_skew:
+        out["skew_partitioned_join"] = skew_block(args)
     print(json.dumps(out), flush=True)
+
+
+# --------------------------------------------------------------------------- skewed partitioned join
+
+def _chunks(n, step=1 << 27):
+    return [(r0, min(n, r0 + step)) for r0 in range(0, n, step)]
+
+
+def _skew_inputs(vx, nb, np_, scramble):
+    import numpy as np
+    import datagen
+    bk, bp, pk = vx.HostBuffer(nb, np.int64), vx.HostBuffer(nb, np.int64), vx.HostBuffer(np_, np.int64)
+    t0 = time.perf_counter()
+    for r0, r1 in _chunks(nb):
+        datagen.skew_build(r1 - r0, out=(bk.array[r0:r1], bp.array[r0:r1]), row0=r0)
+        if scramble:
+            datagen.scramble40(bk.array[r0:r1])
+    for r0, r1 in _chunks(np_):
+        datagen.skew_probe(r1 - r0, out=pk.array[r0:r1], row0=r0)
+        if scramble:
+            datagen.scramble40(pk.array[r0:r1])
+    log(f"skew: {nb} + {np_} rows generated in {time.perf_counter() - t0:.1f} s")
+    return bk, bp, pk
+
+
+def _skew_time(ctx, vx, torch, bk, bp, pk, methods, args, steps, warmup):
+    """Each partitioner timed on the same inputs: warm-up steps, then `steps` timed calls; every
+    step's aggregate must be the same for every method."""
+    lines, failed = {}, {}
+    for method in methods:
+        def step():
+            return ctx.join_partitioned(bk, [bp], pk, method=method, n_parts=args.n_parts, seed=7,
+                                        train_steps=args.train_steps)
+        try:
+            for _ in range(warmup):
+                ref = step()
+            torch.cuda.synchronize()
+            res = []
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                res.append(step())
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / steps
+        except vx.VxError as e:
+            if method == methods[0]:
+                raise
+            # a control partitioner that cannot run under this budget is reported, not timed
+            failed[method] = str(e)
+            log(f"skew {method}: {e}")
+            continue
+        if any(r[0] != res[0][0] for r in res) or (warmup and ref[0] != res[0][0]):
+            raise SystemExit(f"skew {method}: non-deterministic results across steps")
+        agg, st, used = res[0]
+        lines[method] = dict(ms=ms, value=len(pk.array) / (ms / 1e3), agg=agg, st=st, used=used)
+        log(f"skew {method}: {ms:.1f} ms/step, partitions {st['n_parts']}, singleton rows {st['singleton_rows']}")
+    first = lines[methods[0]]["agg"]
+    if any(x["agg"] != first for x in lines.values()):
+        raise SystemExit("partitioned join results differ across partitioners")
+    return lines, failed
+
+
+def _skew_line(x):
+    st = x["st"]
+    return {"ms_per_step": x["ms"], "value": x["value"], "imbalance": st["imbalance"],
+            "imbalance_table_partitions": st["imbalance_tables"],
+            "imbalance_distinct_keys": st["imbalance_distinct"], "part_ms": st["part_ms"],
+            "train_ms": st["train_ms"], "join_ms": st["probe_ms"], "n_parts": st["n_parts"],
+            "singleton_rows": st["singleton_rows"],
+            "h2d_bytes_per_step": st["sdma_bytes"] + st["zc_bytes"]}
+
+
+def _skew_checks(ctx, bk, bp, pk, args, with_oracle):
+    """Checks of the full-size result that do not use the GPU's other partitioners:
+    - the three heaviest keys' singleton partitions against mB(k) mP(k) and sumB(k) mP(k), counted
+      from the arrays with numpy;
+    - when with_oracle (the cpu_baseline leg): two table partitions against the oracle on the rows
+      whose keys fall in them, timed; that is the oracle's rate on a bounded sample."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+    M64 = 1 << 64
+    nb, np_ = len(bk.array), len(pk.array)
+    tot, st, used, per = ctx.join_partitioned(bk, [bp], pk, method="learned", n_parts=args.n_parts, seed=7,
+                                              train_steps=args.train_steps, per_partition=True)
+    r = ctx.partition(bk, method="learned", n_parts=args.n_parts, seed=7, train_steps=args.train_steps)
+    spl = r["splitters"]
+    P = len(spl) + 1
+    if st["n_parts"] != P or [sum(x) % M64 for x in zip(*per)] != tot:
+        raise SystemExit("skew check: per-partition aggregates do not add up to the total")
+    single = {int(spl[i - 1]): i for i in range(1, len(spl)) if spl[i] == spl[i - 1] + 1}
+    n_thr = max(1, min(16, len(os.sched_getaffinity(0))))
+    ex = ThreadPoolExecutor(n_thr)
+
+    def heavy(c, col, pay):
+        k = col.array[c[0]:c[1]]
+        res = []
+        for key in (1, 2, 3):
+            m = k == key
+            res.append((int(m.sum()), int(pay.array[c[0]:c[1]][m].view(np.uint64).sum(dtype=np.uint64))
+                        if pay is not None else 0))
+        return res
+
+    hb = list(ex.map(lambda c: heavy(c, bk, bp), _chunks(nb)))
+    hp = list(ex.map(lambda c: heavy(c, pk, None), _chunks(np_)))
+    heavy_ok = []
+    for i, key in enumerate((1, 2, 3)):
+        mB, sB, mP = sum(x[i][0] for x in hb), sum(x[i][1] for x in hb), sum(x[i][0] for x in hp)
+        ok = key in single and per[single[key]] == [mB * mP % M64, sB * mP % M64]
+        if not ok:
+            raise SystemExit(f"skew check: singleton partition of key {key} differs from its closed form")
+        heavy_ok.append({"key": key, "build_rows": mB, "probe_rows": mP})
+    out = {"heavy_key_singletons_closed_form": heavy_ok, "n_parts": P}
+    if with_oracle:
+        import oracle
+        table_parts = [p for p in range(1, P - 1) if p not in single.values()]
+        checked, rows_b, rows_p, secs = [], 0, 0, 0.0
+        for p in (table_parts[len(table_parts) // 2], table_parts[len(table_parts) // 4]):
+            lo, hi = int(spl[p - 1]), int(spl[p])
+
+            def pick(c, col, pay):
+                k = col.array[c[0]:c[1]]
+                m = (k >= lo) & (k < hi)
+                return k[m], (pay.array[c[0]:c[1]][m] if pay is not None else None)
+
+            b = list(ex.map(lambda c: pick(c, bk, bp), _chunks(nb)))
+            q = list(ex.map(lambda c: pick(c, pk, None), _chunks(np_)))
+            kb, vb = np.concatenate([x[0] for x in b]), np.concatenate([x[1] for x in b])
+            kp = np.concatenate([x[0] for x in q])
+            t0 = time.perf_counter()
+            want = oracle.join_agg(kb, [vb], kp, [])
+            secs += time.perf_counter() - t0
+            if per[p] != want:
+                raise SystemExit(f"skew check: partition {p} differs from the oracle")
+            checked.append({"partition": p, "keys": [lo, hi], "build_rows": len(kb), "probe_rows": len(kp)})
+            rows_b += len(kb)
+            rows_p += len(kp)
+        out["oracle_partitions"] = checked
+        out["cpu_baseline"] = {"value": rows_p / secs, "unit": "probe rows/s", "cores": 1, "kind": "oracle",
+                               "sample": f"the rows of table partitions {[c['partition'] for c in checked]} "
+                                         f"of the same workload ({rows_b} build + {rows_p} probe rows), "
+                                         f"joined in {secs:.1f} s on 1 host thread; the GPU's per-partition "
+                                         f"aggregates must equal the oracle's", **host_info()}
+    ex.shutdown()
+    return out
+
+
+def skew_block(args):
+    """The metric's second half on the default line: learned vs radix-hash (and the sample-quantile
+    control) on the skewed partitioned join at full size, 2^30 Zipf(1.1) build keys over [1, 2^40]
+    with an int64 payload and 2^32 Zipf(1.1) probe keys in pinned host memory, 32 GiB budget."""
+    import torch
+    import paper_2502_09541_amd as vx
+    nb, np_ = 1 << 30, 1 << 32
+    bk, bp, pk = _skew_inputs(vx, nb, np_, False)
+    try:
+        with vx.Context(int(args.skew_budget_gib * GiB)) as ctx:
+            b_peak = ctx.calibrate()["h2d_gbs"]
+            lines, failed = _skew_time(ctx, vx, torch, bk, bp, pk, ["learned", "radix_hash", "quantile"], args,
+                                       args.skew_steps, 1)
+            checks = _skew_checks(ctx, bk, bp, pk, args, not args.no_cpu_baseline)
+    finally:
+        for h in (bk, bp, pk):
+            h.free()
+    a = lines["learned"]
+    out = {"workload": "skewed_partitioned_join", "build_rows": nb, "probe_rows": np_, "zipf_s": 1.1,
+           "key_range": "[1, 2^40]", "device_budget_gib": args.skew_budget_gib, "steps": args.skew_steps,
+           "warmup": 1, "unit": "probe rows/s", "value": a["value"], "ms_per_step": a["ms"],
+           "learned": _skew_line(a),
+           "radix_hash": _skew_line(lines["radix_hash"]) if "radix_hash" in lines else {"error": failed["radix_hash"]},
+           "sample_quantile": _skew_line(lines["quantile"]) if "quantile" in lines else {"error": failed["quantile"]},
+           "learned_speedup_vs_radix_hash": lines["radix_hash"]["ms"] / a["ms"] if "radix_hash" in lines else None,
+           "host_link": {"peak_measured_gbs": b_peak,
+                         "frac": (a["st"]["sdma_bytes"] + a["st"]["zc_bytes"]) / (a["ms"] * 1e6) / b_peak},
+           "result": {"match_count": a["agg"][0], "sum": a["agg"][1]},
+           "bit_exact_across_methods": True, "checks": checks}
+    if "cpu_baseline" in checks:
+        out["cpu_baseline"] = checks.pop("cpu_baseline")
+    return out
 
 
 # --------------------------------------------------------------------------- other workloads
@@ -300,10 +531,10 @@ def run_rows(args):
                     "output_rows": n_out, "output_bytes_per_row": 40, "match_frac": 0.1,
                     "device_budget_gib": args.budget_gib},
                    {"bound": "hbm", "kernel": "k_probe_rows", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": ach / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES["k_probe_rows"], "avg_launch_ms": k_avg,
+                    "frac": ach / HBM_PEAK_GBS, "traffic": None, "traffic_profile": PROFILE["k_probe_rows"], "avg_launch_ms": k_avg,
                     "rows_per_launch": np_ / launches},
                    {"host_link": {"peak_measured_gbs": b_peak,
-                                  "h2d_gbs": (nb * 16 + st["sdma_bytes"] + st["zc_bytes_est"]) / (ms * 1e6),
+                                  "h2d_gbs": (nb * 16 + st["sdma_bytes"] + st["zc_bytes"]) / (ms * 1e6),
                                   "d2h_output_gbs": d2h / (ms * 1e6)},
                     "aggregate_only_ms_per_step": ms_agg,
                     "materialization_cost": ms / ms_agg - 1.0,
@@ -364,7 +595,7 @@ def run_plain(args):
                    {"workload": "plain_join_device_resident", "build_rows": nb, "probe_rows": np_,
                     "key": "int32", "build_payloads": "1 x int32"},
                    {"bound": "hbm", "kernel": "k_probe", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES["k_probe_plain"], "avg_launch_ms": k_ms,
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": None, "traffic_profile": PROFILE["k_probe_plain"], "avg_launch_ms": k_ms,
                     "rows_per_launch": np_},
                    {"result": {"match_count": agg[0], "sum": agg[1]}, "checked_against_oracle": True,
                     "build_ms": st["build_ms"], "probe_ms": st["probe_ms"], "host_resident": host_variant,
@@ -403,7 +634,7 @@ def run_star(args):
     ms, res = _timed(step, args, torch)
     st = res[0][1]
     k_ms = sum(r[1]["kernel_ms"] for r in res) / sum(r[1]["kernel_launches"] for r in res)
-    wire = st["sdma_bytes"] + st["zc_bytes_est"]
+    wire = st["sdma_bytes"] + st["zc_bytes"]
     # algorithmic link bytes: each fact column is needed only for rows alive when it is read
     # (dimensions probed in ascending filter selectivity, then the 3 measures of survivors)
     sel = sorted(float(np.mean(x["filt"] == 0)) for x in dims)
@@ -426,7 +657,7 @@ def run_star(args):
                    # per launch: 4 B foreign key from the chunk buffer + one 8 B slot of the first table
                    "achieved": (nf / st["kernel_launches"]) * 12 / (k_ms * 1e6), "peak": HBM_PEAK_GBS,
                    "unit": "GB/s", "frac": (nf / st["kernel_launches"]) * 12 / (k_ms * 1e6) / HBM_PEAK_GBS,
-                   "traffic": TRAFFIC_BYTES["k_star"], "avg_launch_ms": k_ms,
+                   "traffic": None, "traffic_profile": PROFILE["k_star"], "avg_launch_ms": k_ms,
                    "rows_per_launch": nf / st["kernel_launches"]},
                   {"host_link": {"peak_measured_gbs": b_peak, "achieved_wire_gbs": wire / (ms * 1e6),
                                  "frac_wire": wire / (ms * 1e6) / b_peak,
@@ -472,94 +703,55 @@ def run_batch(args):
                     "tile_rows": st["chunk_rows"], "block": st["n_buffers"], "load_factor": st["imbalance"]},
                    {"bound": "hbm", "kernel": "graph(k_batch_phase build, k_batch_dupcount, k_batch_phase probe)", "achieved": alg / (k_ms * 1e6),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg / (k_ms * 1e6) / HBM_PEAK_GBS,
-                    "traffic": TRAFFIC_BYTES["batch_graph"], "avg_launch_ms": k_ms, "rows_per_launch": rows},
+                    "traffic": None, "traffic_profile": PROFILE["batch_graph"], "avg_launch_ms": k_ms, "rows_per_launch": rows},
                    {"baseline_separate_launches": {"ms_per_step": ms1, "value": rows / (ms1 / 1e3),
                                                    "launches": res1[0][1]["kernel_launches"]},
                     "speedup_vs_separate_launches": ms1 / ms})
 
 
 def run_skew(args):
-    """Skewed partitioned join: 2^30 Zipf(1.1) int64 build keys over [1, 2^40] with an int64
-    payload, 2^32 Zipf(1.1) probe keys, pinned host memory, 32 GiB device budget; the build side
-    is partitioned (learned CDF splitters vs radix-hash), every method must give the same result."""
-    import numpy as np
+    """Skewed partitioned join on its own line: 2^30 Zipf(1.1) int64 build keys over [1, 2^40] with
+    an int64 payload, 2^32 Zipf(1.1) probe keys, pinned host memory, device budget
+    --skew-budget-gib (32); --method against the sample-quantile and radix-hash controls (a control
+    the budget cannot run is reported), optionally with scrambled keys; every method must give the
+    same result."""
     import torch
-    import datagen
     import paper_2502_09541_amd as vx
     nb, np_ = 1 << 30, 1 << 32
-    bk, bp, pk = vx.HostBuffer(nb, np.int64), vx.HostBuffer(nb, np.int64), vx.HostBuffer(np_, np.int64)
-    t0 = time.perf_counter()
-    step_rows = 1 << 27
-    for r0 in range(0, nb, step_rows):
-        datagen.skew_build(step_rows, out=(bk.array[r0:r0 + step_rows], bp.array[r0:r0 + step_rows]), row0=r0)
-        if args.skew_scramble:
-            datagen.scramble40(bk.array[r0:r0 + step_rows])
-    for r0 in range(0, np_, step_rows):
-        datagen.skew_probe(step_rows, out=pk.array[r0:r0 + step_rows], row0=r0)
-        if args.skew_scramble:
-            datagen.scramble40(pk.array[r0:r0 + step_rows])
-        log(f"skew: generated probe rows up to {r0 + step_rows}")
-    log(f"skew: inputs generated in {time.perf_counter() - t0:.1f} s")
-    ctx = vx.Context(int(args.skew_budget_gib * GiB))
-    b_peak = ctx.calibrate()["h2d_gbs"]
-    lines, failed = {}, {}
-    for method in (args.method, "quantile", "radix_hash"):
-        try:
-            ms, res = _timed(lambda: ctx.join_partitioned(bk, [bp], pk, method=method, n_parts=args.n_parts, seed=7,
-                                                          train_steps=args.train_steps),
-                             args, torch)
-        except vx.VxError as e:
-            if method == args.method:
-                raise
-            # a control partitioner that cannot run under this budget is reported, not timed
-            failed[method] = str(e)
-            log(f"skew {method}: {e}")
-            continue
-        agg, st, used = res[0]
-        lines[method] = dict(ms=ms, value=np_ / (ms / 1e3), agg=agg, st=st, used=used)
-        log(f"skew {method}: {ms:.1f} ms/step, partitions {st['n_parts']}, singleton rows {st['singleton_rows']}")
+    bk, bp, pk = _skew_inputs(vx, nb, np_, args.skew_scramble)
+    methods = [args.method] + [m for m in ("quantile", "radix_hash") if m != args.method]
+    try:
+        with vx.Context(int(args.skew_budget_gib * GiB)) as ctx:
+            b_peak = ctx.calibrate()["h2d_gbs"]
+            lines, failed = _skew_time(ctx, vx, torch, bk, bp, pk, methods, args, args.steps, args.warmup)
+    finally:
+        for h in (bk, bp, pk):
+            h.free()
     a = lines[args.method]
-    if any(x["agg"] != a["agg"] for x in lines.values()):
-        raise SystemExit("partitioned join results differ across partitioners")
-
-    def control(name):
-        if name in failed:
-            return {"error": failed[name]}
-        x = lines[name]
-        return {"ms_per_step": x["ms"], "value": x["value"], "imbalance": x["st"]["imbalance"],
-                "imbalance_table_partitions": x["st"]["imbalance_tables"],
-                "imbalance_distinct_keys": x["st"]["imbalance_distinct"], "part_ms": x["st"]["part_ms"],
-                "join_ms": x["st"]["probe_ms"], "singleton_rows": x["st"]["singleton_rows"]}
     st = a["st"]
-    h2d = st["sdma_bytes"] + st["zc_bytes_est"]
+    h2d = st["sdma_bytes"] + st["zc_bytes"]
     # dominant kernel: the probe stream (one launch per probe chunk, HIP events on its stream)
     k_avg = st["kernel_ms"] / max(1, st["chunks"])
     ach = (8.0 * np_ + 32.0 * st["survivors"]) / st["chunks"] / (k_avg * 1e6)
-    ctx.close()
-    for h in (bk, bp, pk):
-        h.free()
     return _common("probe rows/s", a["value"], a["ms"], args, "int64",
                    {"workload": "skewed_partitioned_join", "build_rows": nb, "probe_rows": np_, "zipf_s": 1.1,
                     "key_range": "[1, 2^40]", "device_budget_gib": args.skew_budget_gib,
                     "keys": "scrambled by a bijection of [0, 2^40)" if args.skew_scramble else "Zipf ranks",
-                    "method": args.method,
-                    "n_parts": st["n_parts"]},
+                    "method": args.method, "n_parts": st["n_parts"]},
                    {"bound": "hbm", "kernel": "k_pj_stream", "achieved": ach, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES["k_pj_stream"],
-                    "avg_launch_ms": k_avg,
+                    "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                    "traffic_profile": PROFILE["k_pj_stream"], "avg_launch_ms": k_avg,
                     "rows_per_launch": np_ / st["chunks"],
                     "algorithmic_bytes": "8 B per probe key + 32 B table slot per probe row routed to a table"},
                    {"host_link": {"peak_measured_gbs": b_peak, "h2d_bytes_per_step": h2d,
                                   "achieved_gbs": h2d / (a["ms"] * 1e6), "frac": h2d / (a["ms"] * 1e6) / b_peak},
                     "result": {"match_count": a["agg"][0], "sum": a["agg"][1]},
-                    "learned": {"ms_per_step": a["ms"], "value": a["value"], "imbalance": st["imbalance"],
-                                "imbalance_table_partitions": st["imbalance_tables"],
-                                "imbalance_distinct_keys": st["imbalance_distinct"],
-                                "singleton_rows": st["singleton_rows"], "part_ms": st["part_ms"],
-                                "train_ms": st["train_ms"], "join_ms": st["probe_ms"]},
-                    "radix_hash": control("radix_hash"),
-                    "sample_quantile": control("quantile"),
-                    "learned_speedup_vs_radix_hash": (lines["radix_hash"]["ms"] / a["ms"]) if "radix_hash" in lines
+                    args.method: _skew_line(a),
+                    "radix_hash": _skew_line(lines["radix_hash"]) if "radix_hash" in lines
+                    else {"error": failed.get("radix_hash")},
+                    "sample_quantile": _skew_line(lines["quantile"]) if "quantile" in lines
+                    else {"error": failed.get("quantile")},
+                    "speedup_vs_radix_hash": (lines["radix_hash"]["ms"] / a["ms"]) if "radix_hash" in lines
                     else None,
                     "bit_exact_across_methods": True})
 
@@ -631,8 +823,8 @@ def run_radix(args):
     for h in (ak, av, bk, bv):
         h.free()
     tuples = 2 * n
-    h2d = st["sdma_bytes"] + st["zc_bytes_est"]
-    d2h = st["sdma_bytes"] if st["n_parts"] > 1 and st["zc_bytes_est"] > 0 else 0   # clustered copies written back
+    h2d = st["sdma_bytes"] + st["zc_bytes"]
+    d2h = st["sdma_bytes"] if st["n_parts"] > 1 and st["zc_bytes"] > 0 else 0   # clustered copies written back
     # dominant kernel: the pass-2 probe (B's rows of a partition read in place from host memory)
     k_avg = st["kernel_ms"] / max(1, st["chunks"])
     rows_per_launch = n / max(1, st["chunks"])
@@ -646,7 +838,7 @@ def run_radix(args):
                     "device_budget_gib": args.radix_budget_gib, "n_parts": st["n_parts"],
                     "partition_fn": "raw key bits [0, log2 n_parts)"},
                    {"bound": "host_link", "kernel": "k_rj_probe", "achieved": ach, "peak": b_peak, "unit": "GB/s",
-                    "frac": ach / b_peak, "traffic": TRAFFIC_BYTES["k_rj_probe"] if st["n_parts"] == 16 else None,
+                    "frac": ach / b_peak, "traffic": None, "traffic_profile": PROFILE["k_rj_probe"],
                     "avg_launch_ms": k_avg,
                     "rows_per_launch": rows_per_launch,
                     "algorithmic_bytes": "16 B per B row read in place from pinned host memory"},
@@ -746,7 +938,7 @@ def run_sort(args):
                     "device_budget_gib": args.sort_budget_gib, "runs": runs, "run_keys": rows},
                    {"bound": "hbm", "kernel": "radix sort of one run (8 multisplit passes)", "achieved": ach,
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                    "traffic": TRAFFIC_BYTES["sort_run"] if rows == 1 << 26 else None,
+                    "traffic": None, "traffic_profile": PROFILE["sort_run"],
                     "avg_launch_ms": k_avg, "rows_per_launch": rows,
                     "algorithmic_bytes": "24 B per key per digit pass (8 B histogram read, 8 B read + 8 B written by the scatter), 8 passes"},
                    {"cpu_baseline": cpu,

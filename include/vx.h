@@ -128,7 +128,10 @@ typedef struct {
   uint64_t chunks;          /* chunks streamed (0: device-resident input) */
   uint64_t chunk_rows;      /* rows per chunk used */
   uint64_t sdma_bytes;      /* bytes copied host-to-device by the copy stream */
-  uint64_t zc_bytes_est;    /* zero-copy bytes read, estimated as touched lines of the granule */
+  uint64_t zc_bytes;        /* bytes read from host memory in place (zero-copy).  Gathers (probe
+                               payloads, star fact columns): granules touched x granule size, with
+                               the granules counted by the kernels, each wave counting the distinct
+                               granules holding the rows it reads; in-place scans: bytes read */
   uint32_t zc_mask;         /* bit c set: probe payload / fact column c read by zero-copy */
   uint32_t n_buffers;       /* chunk buffers used by the pipeline */
   double build_ms;          /* wall time of the build phase */
@@ -217,10 +220,23 @@ typedef struct {
 } vx_probe_desc;
 
 /*
- * Probe `table` with every probe row and aggregate the matches.  Device-
- * resident keys are probed in place; host-resident keys are streamed through
- * n_buffers chunk buffers carved from the arena (VX_EBUDGET if two chunks of
- * one row do not fit).  `stats` may be NULL.
+ * Probe `table` with every probe row and aggregate the matches: the probe side
+ * of the paper's hash join (Sec. 7.1) run by its pipelined executor (Sec. 5.3).
+ * Device-resident keys are probed in place.  Host-resident keys are streamed
+ * through n_buffers chunk buffers carved from the arena (the executor's mem A /
+ * mem B; VX_EBUDGET if two chunks of one row do not fit): the copy of chunk
+ * c + 1 runs while the kernel works on chunk c, and each copy is submitted only
+ * once its buffer is free, so it never waits in a hardware queue (Sec. 4.3,
+ * the immediate-execution principle).  Probe payload columns in host memory are
+ * read only for matching rows, by zero-copy loads, or streamed with the keys,
+ * as late_mat chooses (Sec. 6.3).
+ * Arguments: `table` from vx_build on the same context; desc->key of the
+ * table's key type; desc->pay[c] of n rows each, int32 or int64.  Results:
+ * *out = count and sums (build payloads, then probe payloads), mod 2^64; per
+ * chunk in desc->chunk_aggs when given (VX_ECAPACITY if there are more chunks
+ * than chunk_aggs_cap).  `stats` may be NULL.
+ * Errors: VX_EINVAL (type mismatch, more than 4 payloads or 8 sums, n_buffers
+ * outside 2..4, a table of another context), VX_ENOTPINNED, VX_EBUDGET.
  */
 vx_status vx_probe_stream(vx_ctx* ctx, const vx_table* table, const vx_probe_desc* desc,
                           vx_agg* out, vx_stats* stats);
@@ -297,7 +313,11 @@ typedef struct {
 typedef struct {
   uint32_t n_jobs;
   int32_t mode;                /* 0: one HIP graph launch: a build-phase and a probe-phase kernel that
-                                  each drain the tiles of every job; 1: two launches per job */
+                                  each drain the tiles of every job; 1: two launches per job.
+                                  Mode 0 keeps its graph, tables and descriptors in the arena after
+                                  the call, for the next mode-0 call with the same jobs
+                                  (vx_ctx_arena_used counts them); every other call on the context
+                                  gives them back before it allocates */
   const vx_col* build_key;     /* per job, device-resident, unique keys */
   const vx_col* build_pay;     /* per job one payload column (data may be NULL) */
   const uint64_t* n_build;
@@ -351,7 +371,7 @@ typedef struct {
  * probe.chunk_aggs is set it receives one vx_agg per partition (chunk_aggs_cap >= n_parts).
  * stats: n_parts, imbalance (max/mean build + probe rows per partition), singleton_rows,
  * survivors (probe rows routed to a table), part_ms (pass 1), train_ms (splitters),
- * probe_ms (pass 2), sdma_bytes and zc_bytes_est (host-link bytes).
+ * probe_ms (pass 2), sdma_bytes and zc_bytes (host-link bytes).
  * Errors: VX_EBUDGET when the largest partition's transient table or the partition scratch
  * does not fit; VX_ENOMEM when pinned host scratch cannot be had; VX_EUNSUPPORTED for more than
  * one build payload or any probe payload.
@@ -383,7 +403,7 @@ typedef struct {
  * maps to p.
  * stats: n_parts, imbalance (max/mean A + B rows per partition), part_ms (pass 1), probe_ms
  * (pass 2), build_ms and kernel_ms (pass 2's build and probe kernels, summed from HIP events
- * around each launch), sdma_bytes (pass 1 copies), zc_bytes_est (bytes read in place from host
+ * around each launch), sdma_bytes (pass 1 copies), zc_bytes (bytes read in place from host
  * memory), table_bytes (the pass-2 table), chunks (pass-2 build slices: one build and one probe
  * launch each), rows = b.n.
  * Errors: VX_EINVAL for a bad argument (n_parts not a power of two or above 1024, shift > 63,
@@ -421,7 +441,16 @@ typedef struct {
   vx_stats stats;
 } vx_join_out;
 
-/* One-shot join of any kind; `out` must not be NULL. */
+/*
+ * One-shot join of any kind.  PLAIN is the paper's join query SUM(A.val + B.val) over
+ * A.key == B.key, reduced to the match count and per-column sums (Sec. 7.1): vx_build of the
+ * build side, then vx_probe_stream of the probe side, then the table is freed.  STAR is the
+ * Star Schema Benchmark plan of Sec. 7.1 (filter the dimensions, build their tables on the GPU,
+ * stream the fact table, aggregate per group).  PARTITIONED and RADIX are the partitioned joins
+ * of Sec. 6.2 for build sides that do not fit the budget; BATCH runs many small joins in one
+ * graph.  Each kind's descriptor above states its layout, ownership and errors.  `out` must not
+ * be NULL; out->stats is filled on success.
+ */
 vx_status vx_join_agg(vx_ctx* ctx, const vx_join_desc* desc, vx_join_out* out);
 
 /* ------------------------------------------------------------------------ partitioning */

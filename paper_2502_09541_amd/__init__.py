@@ -48,7 +48,7 @@ class Col(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("rows", C.c_uint64), ("chunks", C.c_uint64), ("chunk_rows", C.c_uint64),
-                ("sdma_bytes", C.c_uint64), ("zc_bytes_est", C.c_uint64), ("zc_mask", C.c_uint32),
+                ("sdma_bytes", C.c_uint64), ("zc_bytes", C.c_uint64), ("zc_mask", C.c_uint32),
                 ("n_buffers", C.c_uint32), ("build_ms", C.c_double), ("probe_ms", C.c_double),
                 ("total_ms", C.c_double), ("kernel_ms", C.c_double), ("kernel_launches", C.c_uint64),
                 ("table_bytes", C.c_uint64), ("n_parts", C.c_uint64), ("imbalance", C.c_double),
@@ -611,3 +611,4 @@ def merge_cuts(runs, rank):
     cut = (C.c_uint64 * max(1, len(runs)))()
     _check(lib().vx_merge_cuts(ptrs, lens, len(runs), int(rank), cut))
     return np.array([cut[i] for i in range(len(runs))], np.uint64)
+

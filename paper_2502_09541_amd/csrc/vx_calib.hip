@@ -54,6 +54,7 @@ using namespace vx;
 extern "C" vx_status vx_calibrate(vx_ctx* ctx, void* pinned, uint64_t bytes, vx_link_calib* out) {
   VX_CHECK(ctx && pinned && out, VX_EINVAL, "vx_calibrate: null argument");
   VX_CHECK(bytes >= (64u << 20), VX_EINVAL, "vx_calibrate: at least 64 MiB of pinned memory");
+  vx::release_cached(ctx);
   VX_HIP(hipSetDevice(ctx->device));
   std::memset(out, 0, sizeof *out);
   vx_col c{pinned, VX_I64, 0};

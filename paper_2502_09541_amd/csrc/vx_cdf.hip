@@ -751,6 +751,7 @@ extern "C" {
 vx_status vx_cdf_loss_grad(vx_ctx* ctx, const float* x, const float* t, uint64_t n,
                            const float* params, float* grad, double* loss) {
   VX_CHECK(ctx && x && t && params && grad && n, VX_EINVAL, "vx_cdf_loss_grad: bad argument");
+  release_cached(ctx);
   VX_HIP(hipSetDevice(ctx->device));
   ColInfo xi, ti;
   VX_TRY(cdf_inputs(ctx, x, t, n, &xi, &ti));
@@ -768,6 +769,7 @@ vx_status vx_cdf_loss_grad(vx_ctx* ctx, const float* x, const float* t, uint64_t
 
 vx_status vx_cdf_forward(vx_ctx* ctx, const float* x, uint64_t n, const float* params, float* y) {
   VX_CHECK(ctx && x && params && y, VX_EINVAL, "vx_cdf_forward: bad argument");
+  release_cached(ctx);
   VX_HIP(hipSetDevice(ctx->device));
   if (n == 0) return VX_OK;
   ColInfo xi, ti;
@@ -789,6 +791,7 @@ vx_status vx_cdf_forward(vx_ctx* ctx, const float* x, uint64_t n, const float* p
 vx_status vx_cdf_train(vx_ctx* ctx, const float* x, const float* t, uint64_t n, float* params,
                        uint32_t steps, float lr, double* final_loss) {
   VX_CHECK(ctx && x && t && params && n, VX_EINVAL, "vx_cdf_train: bad argument");
+  release_cached(ctx);
   VX_HIP(hipSetDevice(ctx->device));
   ColInfo xi, ti;
   VX_TRY(cdf_inputs(ctx, x, t, n, &xi, &ti));

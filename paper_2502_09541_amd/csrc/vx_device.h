@@ -44,6 +44,28 @@ __device__ __forceinline__ long long slot_signed(const uint8_t* slot, uint32_t o
   return *(const long long*)(slot + off);
 }
 
+// Zero-copy traffic, counted: the number of distinct granules of 2^shift bytes that hold the
+// elements this wave reads, where lane l reads the element at device address a0 + l * es
+// (consecutive rows in consecutive lanes) when `active`.  A granule is the unit a zero-copy
+// read moves over the host link, so this is what the wave's gather costs on the wire.  Every
+// lane must call it; every lane gets the same count.
+__device__ __forceinline__ uint32_t wave_granules(bool active, uint64_t a0, uint32_t es, uint32_t shift) {
+  const unsigned long long m = __ballot(active);
+  if (m == 0) return 0;
+  const uint32_t lane = threadIdx.x & 63;
+  const unsigned long long below = m & ((1ull << lane) - 1ull);
+  bool first = false;
+  if (active) {
+    if (below == 0) {
+      first = true;
+    } else {   // the granule differs from that of the nearest active lane below
+      const uint32_t prev = 63u - (uint32_t)__clzll(below);
+      first = ((a0 + (uint64_t)prev * es) >> shift) != ((a0 + (uint64_t)lane * es) >> shift);
+    }
+  }
+  return (uint32_t)__popcll(__ballot(first));
+}
+
 template <int NACC>
 __device__ __forceinline__ void block_flush(unsigned long long (&acc)[NACC], int nacc,
                                             unsigned long long* out) {

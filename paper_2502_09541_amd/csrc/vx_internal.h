@@ -120,6 +120,10 @@ namespace vx {
 
 // Drop the batch join's cached graph and tables held for this context.
 void batch_release_ctx(const vx_ctx* ctx);
+// Give back arena memory that a call keeps for reuse by the next call of its kind (the batch
+// join's graph and tables): every entry point that does not reuse it calls this first, so its
+// working set sees the whole arena.
+inline void release_cached(vx_ctx* ctx) { batch_release_ctx(ctx); }
 
 // Pinned host scratch of at least `bytes` (grows by reallocation; contents not kept).
 vx_status host_scratch(vx_ctx* ctx, uint64_t bytes, uint8_t** out);
@@ -139,6 +143,6 @@ void fill_zero(uint64_t* p, uint64_t words, hipStream_t s);
 // spread over `n` rows: the touched lines of `line` bytes under independent selection.
 double zc_wire_bytes(uint64_t n, uint64_t count, int elsize, uint32_t line);
 constexpr uint32_t kScanTilesMax = 1024;
-constexpr int kAccWords = 9;            // count + 8 sums per aggregate row
+constexpr int kAccWords = 10;           // count + 8 sums + zero-copy granules per aggregate row
 
 }  // namespace vx

@@ -309,7 +309,13 @@ struct ProbeCols {
   uint32_t pay_global;        // bit c: pay[c] is indexed by global row (resident / zero-copy)
   const void* pay[kMaxPay];
   uint32_t pay_size[kMaxPay];
+  uint32_t zc_count;          // bit c: pay[c] is host memory read by zero-copy; count its granules
+  uint32_t zc_shift;          // log2 of the zero-copy granule in bytes
 };
+
+// Accumulator row of one probe launch: match count, 8 sums, zero-copy granules read.
+constexpr int kGranuleWord = 9;
+static_assert(kGranuleWord < kAccWords, "the granule count needs its own accumulator word");
 
 // DIRECT: the table's layout (t.direct), fixed at compile time so that the hash loop carries no
 // test of it.
@@ -317,12 +323,13 @@ template <typename K, bool PREAGG, int ITEMS, bool DIRECT>
 __global__ void __launch_bounds__(256) k_probe(TableView t, ProbeCols q, unsigned long long* acc_out) {
   using U = typename KeyTraits<K>::U;
   const U kEmpty = KeyTraits<K>::kEmpty;
-  constexpr int NACC = 9;
+  constexpr int NACC = kAccWords;
   unsigned long long acc[NACC];
 #pragma unroll
   for (int a = 0; a < NACC; ++a) acc[a] = 0;
   const uint32_t nb = t.n_pay;
   const uint64_t tile = (uint64_t)blockDim.x * ITEMS;
+  const uint64_t wave_row = threadIdx.x & ~63u;   // row of lane 0 of this wave, within a tile step
   for (uint64_t base = blockIdx.x * tile; base < q.n; base += (uint64_t)gridDim.x * tile) {
     unsigned long long mb[ITEMS];
     K keys[ITEMS];
@@ -387,9 +394,18 @@ __global__ void __launch_bounds__(256) k_probe(TableView t, ProbeCols q, unsigne
       }
 #pragma unroll
       for (int j = 0; j < ITEMS; ++j) acc[1 + nb + p] += mb[j] * (unsigned long long)v[j];
+      if ((q.zc_count >> p) & 1u) {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+          const uint64_t r0 = (glob ? q.row0 : 0) + base + (uint64_t)j * blockDim.x + wave_row;
+          const uint32_t g = wave_granules(mb[j] != 0, (uint64_t)(uintptr_t)q.pay[p] + r0 * q.pay_size[p],
+                                           q.pay_size[p], q.zc_shift);
+          if ((threadIdx.x & 63) == 0) acc[kGranuleWord] += g;
+        }
+      }
     }
   }
-  block_flush<NACC>(acc, 1 + (int)nb + (int)q.n_pay, acc_out);
+  block_flush<NACC>(acc, NACC, acc_out);
 }
 
 // Where k_probe_rows writes the join's rows (device-visible addresses: device memory or mapped
@@ -411,7 +427,7 @@ __global__ void __launch_bounds__(256) k_probe_rows(TableView t, ProbeCols q, un
                                                     RowsOut o) {
   using U = typename KeyTraits<K>::U;
   const U kEmpty = KeyTraits<K>::kEmpty;
-  constexpr int NACC = 9;
+  constexpr int NACC = kAccWords;
   __shared__ unsigned long long wsum[4];
   __shared__ unsigned long long tile_base;
   unsigned long long acc[NACC];
@@ -474,6 +490,18 @@ __global__ void __launch_bounds__(256) k_probe_rows(TableView t, ProbeCols q, un
         acc[1 + nb + p] += (unsigned long long)pv[j][p];
       }
     }
+    // zero-copy granules of the payloads just gathered (every lane takes part)
+    for (uint32_t p = 0; p < q.n_pay; ++p) {
+      if (!((q.zc_count >> p) & 1u)) continue;
+      const bool glob = (q.pay_global >> p) & 1u;
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) {
+        const uint64_t w0 = (glob ? q.row0 : 0) + base + (uint64_t)j * blockDim.x + (threadIdx.x & ~63u);
+        const uint32_t g = wave_granules(hit[j], (uint64_t)(uintptr_t)q.pay[p] + w0 * q.pay_size[p],
+                                         q.pay_size[p], q.zc_shift);
+        if (lane == 0) acc[kGranuleWord] += g;
+      }
+    }
     // reserve the tile's rows: per-wave counts, one atomic per workgroup
     unsigned long long mine = 0;
 #pragma unroll
@@ -505,7 +533,7 @@ __global__ void __launch_bounds__(256) k_probe_rows(TableView t, ProbeCols q, un
     }
     __syncthreads();   // wsum and tile_base are reused by the next tile
   }
-  block_flush<NACC>(acc, 1 + (int)nb + (int)q.n_pay, acc_out);
+  block_flush<NACC>(acc, NACC, acc_out);
 }
 
 // ---------------------------------------------------------------- key range
@@ -564,10 +592,12 @@ static int ilog2(uint64_t v) {
   return r;
 }
 
-vx_status make_table(vx_ctx* ctx, int32_t key_type, uint32_t flags, const int32_t* pay_types,
-                     uint32_t n_pay, uint64_t expected_rows, float load_factor, vx_table** out,
-                     const KeyRange* kr) {
-  *out = nullptr;
+// The table's layout for `expected_rows` rows: capacity (a power of two), slot size and the view's
+// fields other than its memory.  Direct when `kr` holds a measured range no wider than the hash
+// capacity.
+static vx_status plan_table(int32_t key_type, uint32_t flags, const int32_t* pay_types, uint32_t n_pay,
+                            uint64_t expected_rows, float load_factor, const KeyRange* kr, TableView* out,
+                            uint64_t* cap_out, uint32_t* slot_bytes_out) {
   VX_CHECK(n_pay <= kMaxPay, VX_EINVAL, "build: at most %u payload columns", kMaxPay);
   int ks = elsize_of(key_type);
   VX_CHECK(ks != 0, VX_EINVAL, "build: bad key type %d", key_type);
@@ -614,6 +644,21 @@ vx_status make_table(vx_ctx* ctx, int32_t key_type, uint32_t flags, const int32_
   v.slot_shift = (uint32_t)ilog2(slot_bytes);
   v.log2cap = (uint32_t)ilog2(cap);
   v.mask = cap - 1;
+  *out = v;
+  *cap_out = cap;
+  *slot_bytes_out = slot_bytes;
+  return VX_OK;
+}
+
+vx_status make_table(vx_ctx* ctx, int32_t key_type, uint32_t flags, const int32_t* pay_types,
+                     uint32_t n_pay, uint64_t expected_rows, float load_factor, vx_table** out,
+                     const KeyRange* kr) {
+  *out = nullptr;
+  TableView v{};
+  uint64_t cap = 0;
+  uint32_t slot_bytes = 0;
+  VX_TRY(plan_table(key_type, flags, pay_types, n_pay, expected_rows, load_factor, kr, &v, &cap, &slot_bytes));
+  const int ks = (int)v.key_size;
   uint64_t bytes = cap * slot_bytes + 256;
   uint8_t* mem = ctx->arena.alloc(bytes);
   VX_CHECK(mem != nullptr, VX_EBUDGET,
@@ -864,6 +909,8 @@ vx_status probe_impl(vx_ctx* ctx, const vx_table* t, const vx_probe_desc* d, vx_
     rows->n_out = 0;
   }
 
+  uint32_t zc_shift = 0;
+  while ((2u << zc_shift) <= ctx->zc_line) ++zc_shift;   // log2 of the measured granule
   auto kernel = [&](const ChunkView& v) -> vx_status {
     ProbeCols q{};
     q.key = v.ptr[0];
@@ -874,8 +921,12 @@ vx_status probe_impl(vx_ctx* ctx, const vx_table* t, const vx_probe_desc* d, vx_
     for (uint32_t p = 0; p < d->n_pay; ++p) {
       q.pay[p] = v.ptr[1 + p];
       q.pay_size[p] = (uint32_t)cols[1 + p].info.elsize;
-      if ((v.global_mask >> (1 + p)) & 1u) q.pay_global |= 1u << p;
+      if ((v.global_mask >> (1 + p)) & 1u) {
+        q.pay_global |= 1u << p;
+        if (cols[1 + p].info.where == Where::Host) q.zc_count |= 1u << p;   // read in place: count
+      }
     }
+    q.zc_shift = zc_shift;
     return launch_probe(ctx, t, q, (unsigned long long*)ctx->dev_acc + (v.index % acc_rows) * kAccWords,
                         ctx->compute, rows ? &ro : nullptr);
   };
@@ -920,15 +971,10 @@ vx_status probe_impl(vx_ctx* ctx, const vx_table* t, const vx_probe_desc* d, vx_
   uint32_t zc_mask = 0;
   for (uint32_t p = 0; p < d->n_pay; ++p) {
     const PipeCol& c = pipe.cols()[1 + p];
-    if (c.info.where != Where::Host || c.copy) continue;
-    zc_mask |= 1u << p;
-    // zero-copy wire estimate from per-chunk match counts (unique keys: matches = rows)
-    for (uint64_t k = 0; k < n_chunks; ++k) {
-      uint64_t crows = std::min(pipe.chunk_rows(), n - k * pipe.chunk_rows());
-      uint64_t m = k < acc_rows ? ctx->host_acc[k * kAccWords] : 0;
-      s.zc_bytes_est += (uint64_t)zc_wire_bytes(crows, std::min(m, crows), c.info.elsize, ctx->zc_line);
-    }
+    if (c.info.where == Where::Host && !c.copy) zc_mask |= 1u << p;
   }
+  // zero-copy bytes: the granules the probe kernels counted, times the granule
+  s.zc_bytes = total[kGranuleWord] << zc_shift;
   s.zc_mask = zc_mask;
   s.chunk_rows = pipe.chunk_rows();
   s.chunks = pipe.streamed() ? n_chunks : 0;
@@ -996,6 +1042,7 @@ extern "C" {
 
 vx_status vx_build(vx_ctx* ctx, const vx_build_desc* d, vx_table** out) {
   VX_CHECK(ctx != nullptr, VX_EINVAL, "vx_build: ctx is NULL");
+  release_cached(ctx);
   return build_impl(ctx, d, out, nullptr);
 }
 
@@ -1011,6 +1058,7 @@ vx_status vx_probe_stream(vx_ctx* ctx, const vx_table* t, const vx_probe_desc* d
                           vx_stats* st) {
   VX_CHECK(ctx && t && d && out, VX_EINVAL, "vx_probe_stream: null argument");
   VX_CHECK(t->ctx == ctx, VX_EINVAL, "vx_probe_stream: table belongs to another context");
+  release_cached(ctx);
   return probe_impl(ctx, t, d, out, st, nullptr);
 }
 
@@ -1018,12 +1066,15 @@ vx_status vx_probe_rows(vx_ctx* ctx, const vx_table* t, const vx_probe_desc* d, 
                         vx_agg* out, vx_stats* st) {
   VX_CHECK(ctx && t && d && rows && out, VX_EINVAL, "vx_probe_rows: null argument");
   VX_CHECK(t->ctx == ctx, VX_EINVAL, "vx_probe_rows: table belongs to another context");
+  release_cached(ctx);
   return probe_impl(ctx, t, d, out, st, rows);
 }
 
 vx_status vx_join_agg(vx_ctx* ctx, const vx_join_desc* d, vx_join_out* out) {
   VX_CHECK(ctx && d && out, VX_EINVAL, "vx_join_agg: null argument");
   std::memset(out, 0, sizeof *out);
+  // only the graph-mode batch reuses what an earlier batch call left in the arena
+  if (!(d->kind == VX_JOIN_BATCH && d->u.batch.mode == 0)) release_cached(ctx);
   switch (d->kind) {
     case VX_JOIN_PLAIN: {
       double t0 = now_ms(), bms = 0;
@@ -1046,3 +1097,4 @@ vx_status vx_join_agg(vx_ctx* ctx, const vx_join_desc* d, vx_join_out* out) {
 }
 
 }  // extern "C"
+

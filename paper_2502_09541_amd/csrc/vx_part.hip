@@ -481,5 +481,6 @@ static vx_status partition_impl(vx_ctx* ctx, const vx_partition_desc* d, vx_part
 
 extern "C" vx_status vx_partition(vx_ctx* ctx, const vx_partition_desc* d, vx_partition_out* out) {
   VX_CHECK(ctx && d && out, VX_EINVAL, "vx_partition: null argument");
+  vx::release_cached(ctx);
   return vx::partition_impl(ctx, d, out);
 }

@@ -948,7 +948,7 @@ vx_status join_partitioned(vx_ctx* ctx, const vx_partitioned_join* d, vx_join_ou
   uint64_t pass2_bytes = 0;
   for (uint32_t p = 0; p < P; ++p)
     if (slot[p] < 0 && !bs.on_device) pass2_bytes += brows[p] * (ks + (B.n_pay ? bs.pay[0].elsize : 0));
-  s.zc_bytes_est = pass2_bytes;
+  s.zc_bytes = pass2_bytes;
   s.build_ms = 0;
   s.probe_ms = join_ms;
   s.kernel_ms = pipe.kernel_ms();
@@ -1278,7 +1278,7 @@ vx_status join_radix(vx_ctx* ctx, const vx_radix_join* d, vx_join_out* out) {
   s.part_ms = part_ms;
   s.probe_ms = join_ms;
   s.sdma_bytes = as.sdma + bs.sdma;
-  s.zc_bytes_est = zc_bytes;
+  s.zc_bytes = zc_bytes;
   s.table_bytes = n_jobs ? tcap_max << kSlotShift : 0;
   s.chunks = n_jobs;
   s.chunk_rows = as.chunk_rows;

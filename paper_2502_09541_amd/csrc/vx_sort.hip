@@ -480,6 +480,7 @@ vx_status sort_impl(vx_ctx* ctx, const vx_sort_desc* d, vx_stats* stats) {
 
 extern "C" vx_status vx_sort(vx_ctx* ctx, const vx_sort_desc* d, vx_stats* stats) {
   VX_CHECK(ctx && d, VX_EINVAL, "vx_sort: null argument");
+  vx::release_cached(ctx);
   return vx::sort_impl(ctx, d, stats);
 }
 

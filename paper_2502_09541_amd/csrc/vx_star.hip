@@ -130,15 +130,18 @@ struct StarArgs {
   uint64_t n, row0;
   GroupTable groups;
   unsigned int* flags;
-  unsigned long long* survivors;
+  unsigned long long* survivors;   // [0] fact rows that pass every dimension, [1] zero-copy granules
+  uint32_t fk_zc, meas_zc;         // bit set: the column is host memory read in place (count granules)
+  uint32_t zc_shift;               // log2 of the zero-copy granule in bytes
 };
 
 template <typename K, int kStarItems>
 __global__ void __launch_bounds__(256) k_star(StarArgs a) {
   using U = typename KeyTraits<K>::U;
   const U kEmpty = KeyTraits<K>::kEmpty;
-  unsigned long long alive_count = 0;
+  unsigned long long alive_count = 0, granules = 0;
   const uint64_t tile = (uint64_t)blockDim.x * kStarItems;
+  const uint64_t wave_row = threadIdx.x & ~63u;
   for (uint64_t base = blockIdx.x * tile; base < a.n; base += (uint64_t)gridDim.x * tile) {
     bool alive[kStarItems];
     int g[kStarItems][2];
@@ -159,6 +162,13 @@ __global__ void __launch_bounds__(256) k_star(StarArgs a) {
           else fk[j] = load_key<K>(a.fk[d], glob ? a.row0 + i : i);
         }
       }
+      if ((a.fk_zc >> d) & 1u) {
+#pragma unroll
+        for (int j = 0; j < kStarItems; ++j) {
+          const uint64_t r0 = a.row0 + base + (uint64_t)j * blockDim.x + wave_row;
+          granules += wave_granules(alive[j], (uint64_t)(uintptr_t)a.fk[d] + r0 * sizeof(K), sizeof(K), a.zc_shift);
+        }
+      }
 #pragma unroll
       for (int j = 0; j < kStarItems; ++j) {
         if (!alive[j]) continue;
@@ -177,6 +187,15 @@ __global__ void __launch_bounds__(256) k_star(StarArgs a) {
         if (found && a.gsel[d] >= 0) g[j][a.gsel[d]] = grp;
       }
     }
+    for (uint32_t c = 0; c < a.n_meas; ++c) {
+      if (!((a.meas_zc >> c) & 1u)) continue;
+#pragma unroll
+      for (int j = 0; j < kStarItems; ++j) {
+        const uint64_t r0 = a.row0 + base + (uint64_t)j * blockDim.x + wave_row;
+        granules += wave_granules(alive[j], (uint64_t)(uintptr_t)a.meas[c] + r0 * a.meas_size[c], a.meas_size[c],
+                                  a.zc_shift);
+      }
+    }
 #pragma unroll
     for (int j = 0; j < kStarItems; ++j) {
       if (!alive[j]) continue;
@@ -192,6 +211,8 @@ __global__ void __launch_bounds__(256) k_star(StarArgs a) {
   }
   for (int o = 32; o > 0; o >>= 1) alive_count += __shfl_xor(alive_count, o, 64);
   if ((threadIdx.x & 63) == 0 && alive_count) atomicAdd(a.survivors, alive_count);
+  // every lane holds its wave's granule count
+  if ((threadIdx.x & 63) == 0 && granules) atomicAdd(a.survivors + 1, granules);
 }
 
 // ---------------------------------------------------------------- host side
@@ -368,7 +389,7 @@ vx_status join_star(vx_ctx* ctx, const vx_star_join* d, vx_join_out* out) {
     hipLaunchKernelGGL(k_init_groups, dim3(g), dim3(256), 0, ctx->compute, gt.slots, gwords);
   }
   unsigned long long* survivors = (unsigned long long*)ctx->dev_acc;
-  fill_zero((uint64_t*)survivors, 1, ctx->compute);
+  fill_zero((uint64_t*)survivors, 2, ctx->compute);
   fill_zero((uint64_t*)ctx->dev_flags, 1, ctx->compute);
 
   StarArgs base{};
@@ -382,6 +403,7 @@ vx_status join_star(vx_ctx* ctx, const vx_star_join* d, vx_join_out* out) {
   base.groups = gt;
   base.flags = ctx->dev_flags;
   base.survivors = survivors;
+  while ((2u << base.zc_shift) <= ctx->zc_line) ++base.zc_shift;
 
   vx_status status;
   double tp0 = now_ms();
@@ -399,11 +421,17 @@ vx_status join_star(vx_ctx* ctx, const vx_star_join* d, vx_join_out* out) {
         a.row0 = v.row0;
         for (uint32_t k = 0; k < nd; ++k) {
           a.fk[k] = v.ptr[k];
-          if ((v.global_mask >> k) & 1u) a.fk_global |= 1u << k;
+          if ((v.global_mask >> k) & 1u) {
+            a.fk_global |= 1u << k;
+            if (cols[k].info.where == Where::Host) a.fk_zc |= 1u << k;
+          }
         }
         for (uint32_t c = 0; c < d->n_measures; ++c) {
           a.meas[c] = v.ptr[nd + c];
-          if ((v.global_mask >> (nd + c)) & 1u) a.meas_global |= 1u << c;
+          if ((v.global_mask >> (nd + c)) & 1u) {
+            a.meas_global |= 1u << c;
+            if (cols[nd + c].info.where == Where::Host) a.meas_zc |= 1u << c;
+          }
         }
         if (a.n == 0) return VX_OK;
         const int items = star_items();
@@ -439,9 +467,9 @@ vx_status join_star(vx_ctx* ctx, const vx_star_join* d, vx_join_out* out) {
   }
   // groups back to the host, compacted and sorted by (g0, g1)
   std::vector<unsigned long long> host(gwords);
-  unsigned long long nsurv = 0;
+  unsigned long long nsurv[2] = {0, 0};
   if (hipMemcpy(host.data(), gt.slots, gwords * 8, hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(&nsurv, survivors, 8, hipMemcpyDeviceToHost) != hipSuccess) {
+      hipMemcpy(nsurv, survivors, 16, hipMemcpyDeviceToHost) != hipSuccess) {
     free_dims();
     set_error("star: reading the group table failed");
     return VX_EHIP;
@@ -470,15 +498,12 @@ vx_status join_star(vx_ctx* ctx, const vx_star_join* d, vx_join_out* out) {
   s.sdma_bytes = sdma;
   s.kernel_ms = kms;
   s.kernel_launches = kl;
-  for (size_t c = 0; c < cols.size(); ++c) {
-    if (cols[c].info.where != Where::Host || cols[c].copy) continue;
-    s.zc_mask |= 1u << c;
-    s.zc_bytes_est += (uint64_t)zc_wire_bytes(d->n_fact, (uint64_t)(col_sel[c] * d->n_fact),
-                                              cols[c].info.elsize, ctx->zc_line);
-  }
+  for (size_t c = 0; c < cols.size(); ++c)
+    if (cols[c].info.where == Where::Host && !cols[c].copy) s.zc_mask |= 1u << c;
+  s.zc_bytes = nsurv[1] << base.zc_shift;   // counted granules x granule
   s.probe_ms = now_ms() - tp0;
   s.total_ms = now_ms() - t0;
-  s.survivors = nsurv;
+  s.survivors = nsurv[0];
   out->stats = s;
   VX_CHECK(rows.size() <= d->groups_cap, VX_ECAPACITY, "star: %zu groups exceed groups_cap %llu",
            rows.size(), (unsigned long long)d->groups_cap);

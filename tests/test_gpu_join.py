@@ -196,3 +196,30 @@ def test_calibration_properties(gpu, ctx):
     assert c["hbm_read_gbs"] > 4 * c["h2d_gbs"]
     assert 5 < c["d2h_gbs"] < 64 and 0 < c["zc_write_gbs"] < 64
     assert 5 < c["duplex_sdma_gbs"] < 128 and 5 < c["duplex_zcw_gbs"] < 128 and 5 < c["duplex_zcr_gbs"] < 128
+
+
+@pytest.mark.parametrize("pdt", [np.int64, np.int32])
+def test_zero_copy_granules_counted(gpu, pdt):
+    """zc_bytes of a zero-copy probe is 128 B (the granule before any calibration) times the
+    granules that hold a matching row, counted in each payload column.  The columns are
+    page-aligned and the chunks a multiple of 64 rows, so no granule is split between two waves
+    and the count equals the distinct granules of the matching rows, computed here from the keys."""
+    nb, np_ = 1 << 12, (1 << 18) + 77
+    bk, b0, b1 = datagen.stream_build(nb, seed=5)
+    pk, p0, p1 = datagen.stream_probe(nb, np_, seed=5)
+    p0, p1 = p0.astype(pdt), p1.astype(pdt)
+    hosts = [pinned(gpu, a) for a in (pk, p0, p1)]
+    _say("zero-copy granule count", np.dtype(pdt).name)
+    try:
+        with gpu.Context(1 << 30) as c:
+            got, st = c.join_plain(dev(bk), [dev(b0), dev(b1)], hosts[0], hosts[1:], late_mat=gpu.VX_LATE_ZC,
+                                   chunk_rows=1 << 15)
+        assert got == oracle.join_agg(bk, [b0, b1], pk, [p0, p1])
+        assert st["zc_mask"] == 3
+        rows = np.nonzero(np.isin(pk, bk))[0]          # unique build keys: a row matches iff its key is built
+        granules = len(np.unique(rows * np.dtype(pdt).itemsize // 128))
+        assert 0.05 < len(rows) / np_ < 0.15
+        assert st["zc_bytes"] == 2 * 128 * granules
+    finally:
+        for h in hosts:
+            h.free()

@@ -379,7 +379,7 @@ def test_partitioned_join_clustered_copy_placement(gpu, ctx, placement, monkeypa
                                               per_partition=True)
     assert got == oracle.join_agg(bk, [bp], pk, [])
     assert [sum(x) % (1 << 64) for x in zip(*per)] == got
-    assert (st["zc_bytes_est"] == 0) == (placement == "1")
+    assert (st["zc_bytes"] == 0) == (placement == "1")
 
 
 @pytest.mark.parametrize("placement", ["0", "1"])

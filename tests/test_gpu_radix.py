@@ -58,7 +58,7 @@ def test_radix_join_recipe_one_partition(gpu, ctx):
     assert got == oracle.join_agg(ak, [av], bk, [bv])
     assert got[0] == nb
     assert st["n_parts"] == 1 and st["chunks"] == 1
-    assert st["zc_bytes_est"] == na * 16 + nb * 16
+    assert st["zc_bytes"] == na * 16 + nb * 16
 
 
 @pytest.mark.parametrize("placement", [1, 2])
@@ -79,7 +79,7 @@ def test_radix_join_clustered(gpu, ctx, placement, monkeypatch):
     assert st["n_parts"] == 16 and st["chunks"] == 16
     # pass 1 copies every tuple in; pass 2 reads the clustered copies from host memory again (in
     # place or copied in) only when they live there
-    pass2_host = st["zc_bytes_est"] + st["sdma_bytes"] - (na + nb) * 16
+    pass2_host = st["zc_bytes"] + st["sdma_bytes"] - (na + nb) * 16
     assert (pass2_host == (na + nb) * 16) == (placement == 1)
     assert (pass2_host == 0) == (placement == 2)
 

@@ -78,7 +78,7 @@ def test_skew_scaled_methods_exact(gpu, ctx4, skew, method, placement, monkeypat
         assert st["n_parts"] >= 128
         assert st["singleton_rows"] > 0.15 * (NB + NP)      # the heaviest keys need no table
     if placement in ("0", "1"):
-        assert (st["zc_bytes_est"] == 0) == (placement == "1")
+        assert (st["zc_bytes"] == 0) == (placement == "1")
 
 
 def test_skew_scaled_learned_per_partition(gpu, ctx4, skew, monkeypatch):
@@ -111,7 +111,7 @@ def test_skew_small_budget_table_groups(gpu, skew, monkeypatch):
                                            train_steps=300)
     print("probe-side host-to-device bytes:", st["sdma_bytes"], "for", NP * 8, "bytes of keys", flush=True)
     assert got == exp
-    assert st["zc_bytes_est"] > 0                          # clustered copy read back from host memory
+    assert st["zc_bytes"] > 0                          # clustered copy read back from host memory
     assert st["sdma_bytes"] >= 2 * NP * 8                   # at least two passes over the probe keys
 
 

@@ -78,6 +78,22 @@ def test_star_host_streamed_modes(gpu, ctx, late_mat):
         assert st["zc_mask"] == 0
     if late_mat == 1:
         assert st["zc_mask"] == (1 << 7) - 2      # every column but the first probed key
+        # counted zero-copy traffic: dimensions are probed in ascending filter selectivity (stable);
+        # each later foreign key is read for the rows alive before it, the measures for the
+        # survivors, each in 128-byte granules of 32 int32 rows (page-aligned columns, chunks of
+        # 40,000 rows = 625 waves, so no granule is split between two waves)
+        passing = [d["key"][(d["filt"] >= d["lo"]) & (d["filt"] <= d["hi"])] for d in dims]
+        sel = [len(p) / len(d["key"]) for p, d in zip(passing, dims)]
+        order = sorted(range(len(dims)), key=lambda k: sel[k])
+        alive = np.ones(len(fks[0]), bool)
+        granules = 0
+        for pos, k in enumerate(order):
+            if pos:
+                granules += len(np.unique(np.nonzero(alive)[0] * 4 // 128))
+            alive &= np.isin(fks[k], passing[k])
+        granules += len(meas) * len(np.unique(np.nonzero(alive)[0] * 4 // 128))
+        assert st["survivors"] == int(alive.sum())
+        assert st["zc_bytes"] == 128 * granules
 
 
 def test_star_ssb_shape_medium(gpu, ctx):
