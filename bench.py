@@ -194,18 +194,21 @@ def main():
 
     st = stats[0]
     count = results[0][0]
+    # one more step, untimed, with the probe kernels counting the zero-copy granules they move (the
+    # count slows the gathers, so the timed steps run without it); same result required
+    r_c, st_c = ctx.join_plain(H["bk"], [H["b0"], H["b1"]], H["pk"], [H["p0"], H["p1"]],
+                               late_mat=args.late_mat, chunk_rows=args.chunk_rows, n_buffers=args.n_buffers,
+                               count_zc=True)
+    if r_c != results[0] or (st_c["zc_mask"] and not st_c["zc_counted"]):
+        raise SystemExit("the counted step differs from the timed ones")
     # The pipeline is bound by the host link: every step moves the build columns, the probe keys
     # (chunk copies) and the matching rows' payloads (zero-copy gathers) over it.
     # algorithmic bytes: build columns (8 + 4 + 4 B per row), 8 B per probe key, 16 B of payloads
     # per match; wire bytes: the same build columns, the bytes the copy stream moved, and the
     # zero-copy granules the probe kernels counted, times the granule
     alg_bytes = nb * 16 + np_ * 8 + count * 16
-    wire_bytes = nb * 16 + st["sdma_bytes"] + st["zc_bytes"]
+    wire_bytes = nb * 16 + st["sdma_bytes"] + st_c["zc_bytes"]
     granule = calib["zc_granule"]
-    # the binomial wire model, for comparison with the count: each of the 2 payload columns of
-    # 8-byte rows has granule/8 rows per granule, each granule moving if any of its rows matches
-    sel = count / np_
-    zc_model = 2 * np_ * 8 * (1.0 - (1.0 - sel) ** (granule // 8)) if st["zc_mask"] == 3 else None
     # the probe kernel itself against HBM (secondary): per row 8 B of key from the chunk buffer
     # and one 16 B table slot, over its average launch time (HIP events on the library's stream)
     kms = sum(s["kernel_ms"] for s in stats)
@@ -242,16 +245,16 @@ def main():
                                   "theoretical); the datasheet gives no achievable figure",
                      "algorithmic_bytes": "per step: 16 B per build row + 8 B per probe key + 16 B of payloads "
                                           "per match",
-                     "traffic_kind": "host-link bytes per step: build columns + copy-stream bytes + zero-copy "
-                                     "granules counted by k_probe x granule"},
+                     "traffic_kind": "host-link bytes per step: build columns + copy-stream bytes + the zero-copy "
+                                     "granules k_probe counts (in one more, untimed step with the count on) x granule"},
         "host_link": {"peak_measured_gbs": b_peak,
                       "achieved_wire_gbs": wire_bytes / (ms * 1e6),
                       "frac_wire": wire_bytes / (ms * 1e6) / b_peak,
                       "achieved_algorithmic_gbs": alg_bytes / (ms * 1e6),
                       "frac_algorithmic": alg_bytes / (ms * 1e6) / b_peak,
                       "wire_bytes_per_step": wire_bytes, "algorithmic_bytes_per_step": alg_bytes,
-                      "zero_copy_bytes_counted": st["zc_bytes"], "zero_copy_granule": granule,
-                      "zero_copy_bytes_binomial_model": zc_model,
+                      "zero_copy_bytes_counted": st_c["zc_bytes"], "zero_copy_granule": granule,
+                      "zero_copy_bytes_binomial_model": st["zc_bytes"],
                       "sdma_bytes_per_step": st["sdma_bytes"]},
         "hbm": {"kernel": "k_probe", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": hbm_gbs / HBM_PEAK_GBS, "traffic": None, "traffic_profile": PROFILE["k_probe_stream"],

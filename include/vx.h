@@ -129,9 +129,10 @@ typedef struct {
   uint64_t chunk_rows;      /* rows per chunk used */
   uint64_t sdma_bytes;      /* bytes copied host-to-device by the copy stream */
   uint64_t zc_bytes;        /* bytes read from host memory in place (zero-copy).  Gathers (probe
-                               payloads, star fact columns): granules touched x granule size, with
-                               the granules counted by the kernels, each wave counting the distinct
-                               granules holding the rows it reads; in-place scans: bytes read */
+                               payloads, star fact columns): granules touched x granule size,
+                               counted by the kernels under VX_PROBE_COUNT_ZC (each wave counts the
+                               distinct granules holding the rows it reads), else estimated by
+                               the wire model; in-place scans: bytes read */
   uint32_t zc_mask;         /* bit c set: probe payload / fact column c read by zero-copy */
   uint32_t n_buffers;       /* chunk buffers used by the pipeline */
   double build_ms;          /* wall time of the build phase */
@@ -151,6 +152,8 @@ typedef struct {
                                joined through a table (singletons excluded) */
   double imbalance_distinct; /* partitioned join: max/mean distinct build keys over the same
                                 partitions (their pre-aggregating tables grow with it) */
+  uint32_t zc_counted;      /* 1: zc_bytes of the gathers was counted by the kernels */
+  uint32_t reserved;
 } vx_stats;
 
 /* ------------------------------------------------------------------------ build / probe */
@@ -184,9 +187,12 @@ typedef struct vx_table vx_table;
  * the table's empty marker, INT32_MIN or INT64_MIN, which has a record of its
  * own).  If the range is no wider than the hash table's capacity at the load
  * factor, key k is stored in slot k - min instead of a hashed slot, with a
- * power-of-two capacity no smaller than the range.  Results are the same
- * either way; a probe then reads one slot, or none for keys outside the range.
- * Host-resident keys always get a hash table.
+ * power-of-two capacity no smaller than the range.  A VX_UNIQUE build whose n
+ * keys are exactly the n values of their range (no empty-marker key) is dense:
+ * every key of the range is present, so its slots hold only the payloads (none
+ * without payloads) and a bitmap of the keys seen catches a repeated key.
+ * Results are the same for every layout; a probe then reads one slot, or none
+ * for keys outside the range.  Host-resident keys always get a hash table.
  */
 vx_status vx_build(vx_ctx* ctx, const vx_build_desc* desc, vx_table** out);
 vx_status vx_table_destroy(vx_table* table);
@@ -214,10 +220,19 @@ typedef struct {
   uint64_t n;
   uint64_t chunk_rows; /* 0 = auto */
   uint32_t n_buffers;  /* chunk buffers in the pipeline, 2..4; 0 = 2 (the paper's mem A / mem B) */
-  uint32_t reserved;
+  uint32_t flags;      /* 0 or VX_PROBE_COUNT_ZC */
   vx_agg* chunk_aggs;  /* optional host array: per-chunk aggregates (cap chunk_aggs_cap) */
   uint64_t chunk_aggs_cap;
 } vx_probe_desc;
+
+enum {
+  /* The probe kernels count the zero-copy traffic of their gathers exactly: per wave, the
+     distinct granules that hold a matching row, per zero-copied column; vx_stats.zc_bytes is
+     then that count times the granule (zc_counted = 1).  Without it zc_bytes is the wire model's
+     estimate from the per-chunk match counts.  The count makes the gather loop about 4% slower,
+     so it is asked for, not always on. */
+  VX_PROBE_COUNT_ZC = 1
+};
 
 /*
  * Probe `table` with every probe row and aggregate the matches: the probe side
@@ -298,7 +313,7 @@ typedef struct {
   uint64_t n_fact;
   uint64_t chunk_rows;         /* 0 = auto */
   int32_t late_mat;            /* VX_LATE_*: fact columns after the first probed one */
-  uint32_t reserved;
+  uint32_t flags;              /* 0 or VX_PROBE_COUNT_ZC (counts the fact columns' gathers) */
   vx_group_row* groups;        /* host output, ascending (g0, g1), count > 0 only */
   uint64_t groups_cap;
 } vx_star_join;

@@ -27,6 +27,7 @@ STATUS_NAMES = ["VX_OK", "VX_EINVAL", "VX_EBUDGET", "VX_ENOMEM", "VX_EHIP", "VX_
 VX_I32, VX_I64 = 1, 2
 VX_UNIQUE, VX_PREAGG, VX_HASHED = 1, 2, 4
 VX_LATE_AUTO, VX_LATE_SDMA, VX_LATE_ZC, VX_LATE_PAPER = -1, 0, 1, 2
+VX_PROBE_COUNT_ZC = 1
 VX_JOIN_PLAIN, VX_JOIN_STAR, VX_JOIN_BATCH, VX_JOIN_PARTITIONED, VX_JOIN_RADIX = 1, 2, 3, 4, 5
 (VX_PART_AUTO, VX_PART_RADIX_HASH, VX_PART_RADIX_BITS, VX_PART_LEARNED, VX_PART_QUANTILE,
  VX_PART_UNTRAINED, VX_PART_RANGE) = range(7)
@@ -54,7 +55,7 @@ class Stats(C.Structure):
                 ("table_bytes", C.c_uint64), ("n_parts", C.c_uint64), ("imbalance", C.c_double),
                 ("part_ms", C.c_double), ("train_ms", C.c_double), ("singleton_rows", C.c_uint64),
                 ("survivors", C.c_uint64), ("imbalance_tables", C.c_double),
-                ("imbalance_distinct", C.c_double)]
+                ("imbalance_distinct", C.c_double), ("zc_counted", C.c_uint32), ("reserved", C.c_uint32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -87,7 +88,7 @@ class Agg(C.Structure):
 class ProbeDesc(C.Structure):
     _fields_ = [("key", Col), ("pay", C.POINTER(Col)), ("n_pay", C.c_uint32), ("late_mat", C.c_int32),
                 ("n", C.c_uint64), ("chunk_rows", C.c_uint64), ("n_buffers", C.c_uint32),
-                ("reserved", C.c_uint32), ("chunk_aggs", C.POINTER(Agg)), ("chunk_aggs_cap", C.c_uint64)]
+                ("flags", C.c_uint32), ("chunk_aggs", C.POINTER(Agg)), ("chunk_aggs_cap", C.c_uint64)]
 
 
 class StarDim(C.Structure):
@@ -102,7 +103,7 @@ class GroupRow(C.Structure):
 class StarJoin(C.Structure):
     _fields_ = [("n_dims", C.c_uint32), ("n_measures", C.c_uint32), ("dims", StarDim * 4),
                 ("fact_fk", Col * 4), ("measure", Col * 4), ("n_fact", C.c_uint64),
-                ("chunk_rows", C.c_uint64), ("late_mat", C.c_int32), ("reserved", C.c_uint32),
+                ("chunk_rows", C.c_uint64), ("late_mat", C.c_int32), ("flags", C.c_uint32),
                 ("groups", C.POINTER(GroupRow)), ("groups_cap", C.c_uint64)]
 
 
@@ -334,7 +335,7 @@ class Context:
         return Table(self, h, npay, (pa, key, pays))
 
     def join_plain(self, bkey, bpays, pkey, ppays=(), unique=True, late_mat=VX_LATE_AUTO,
-                   chunk_rows=0, n_buffers=0, load_factor=0.0, hashed=False):
+                   chunk_rows=0, n_buffers=0, load_factor=0.0, hashed=False, count_zc=False):
         """One-shot build + probe. Returns ([count, sums...], stats dict)."""
         bp, nbp = _cols(bpays)
         pp, npp = _cols(ppays)
@@ -344,7 +345,7 @@ class Context:
                                     (VX_UNIQUE if unique else VX_PREAGG) | (VX_HASHED if hashed else 0),
                                     _len(bkey), float(load_factor), 0)
         d.u.plain.probe = ProbeDesc(col(pkey), pp, npp, late_mat, _len(pkey), int(chunk_rows),
-                                    int(n_buffers), 0, None, 0)
+                                    int(n_buffers), VX_PROBE_COUNT_ZC if count_zc else 0, None, 0)
         out = JoinOut()
         _check(lib().vx_join_agg(self.h, C.byref(d), C.byref(out)))
         return out.agg.to_list(nbp + npp), out.stats.as_dict()
@@ -483,13 +484,13 @@ class Context:
         _check(lib().vx_join_agg(self.h, C.byref(d), C.byref(out)))
         return [outs[j].to_list(1) for j in range(J)], out.stats.as_dict()
 
-    def join_star(self, dims, fks, meas, groups_cap=4096, late_mat=VX_LATE_AUTO, chunk_rows=0):
+    def join_star(self, dims, fks, meas, groups_cap=4096, late_mat=VX_LATE_AUTO, chunk_rows=0, count_zc=False):
         """Star join + GROUP BY. dims: list of {key, filt, lo, hi, group (or None)}.
         Returns (g [n,2] int64, count [n] uint64, sums [n, nmeas] uint64, stats), sorted by (g0, g1)."""
-        return _star_call(self, dims, fks, meas, groups_cap, late_mat, chunk_rows)
+        return _star_call(self, dims, fks, meas, groups_cap, late_mat, chunk_rows, count_zc)
 
 
-def _star_call(ctx, dims, fks, meas, groups_cap, late_mat, chunk_rows):
+def _star_call(ctx, dims, fks, meas, groups_cap, late_mat, chunk_rows, count_zc=False):
     d = JoinDesc()
     d.kind = VX_JOIN_STAR
     sj = d.u.star
@@ -505,6 +506,7 @@ def _star_call(ctx, dims, fks, meas, groups_cap, late_mat, chunk_rows):
     sj.n_fact = _len(fks[0])
     sj.chunk_rows = int(chunk_rows)
     sj.late_mat = int(late_mat)
+    sj.flags = VX_PROBE_COUNT_ZC if count_zc else 0
     rows = (GroupRow * max(1, groups_cap))()
     sj.groups = rows
     sj.groups_cap = groups_cap
@@ -538,7 +540,7 @@ class Table:
     def __init__(self, ctx, h, n_pay, keep):
         self.ctx, self.h, self.n_pay, self._keep = ctx, h, n_pay, keep
 
-    def probe(self, key, pays=(), late_mat=VX_LATE_AUTO, chunk_rows=0, n_buffers=0, chunk_aggs=False):
+    def probe(self, key, pays=(), late_mat=VX_LATE_AUTO, chunk_rows=0, n_buffers=0, chunk_aggs=False, count_zc=False):
         """Probe and aggregate. Returns ([count, sums...], stats dict[, per-chunk lists])."""
         pa, npay = _cols(pays)
         n = _len(key)
@@ -547,8 +549,8 @@ class Table:
             cr = chunk_rows or n or 1
             cap = max(1, (n + cr - 1) // cr)
             ca = (Agg * cap)()
-        d = ProbeDesc(col(key), pa, npay, late_mat, n, int(chunk_rows), int(n_buffers), 0,
-                      ca, cap)
+        d = ProbeDesc(col(key), pa, npay, late_mat, n, int(chunk_rows), int(n_buffers),
+                      VX_PROBE_COUNT_ZC if count_zc else 0, ca, cap)
         out, st = Agg(), Stats()
         _check(lib().vx_probe_stream(self.ctx.h, self.h, C.byref(d), C.byref(out), C.byref(st)))
         res = out.to_list(self.n_pay + npay)
@@ -556,7 +558,8 @@ class Table:
             return res, st.as_dict(), [ca[i].to_list(self.n_pay + npay) for i in range(cap)]
         return res, st.as_dict()
 
-    def probe_rows(self, key, pays=(), cap=None, out=None, late_mat=VX_LATE_AUTO, chunk_rows=0, n_buffers=0):
+    def probe_rows(self, key, pays=(), cap=None, out=None, late_mat=VX_LATE_AUTO, chunk_rows=0, n_buffers=0,
+                   count_zc=False):
         """Probe, aggregate and write the join's rows.  `out` = (row, [build pay cols], [probe pay cols])
         of uint64 / int64 arrays (pinned host: HostBuffer.array, or CUDA tensors), each of `cap` rows;
         allocated as pinned HostBuffers of `cap` (default: probe rows) when None.  Returns
@@ -582,7 +585,8 @@ class Table:
         for c, a in enumerate(pcols):
             r.probe_pay[c] = ptr(a)
         r.cap = int(cap)
-        d = ProbeDesc(col(key), pa, npay, late_mat, n, int(chunk_rows), int(n_buffers), 0, None, 0)
+        d = ProbeDesc(col(key), pa, npay, late_mat, n, int(chunk_rows), int(n_buffers),
+                      VX_PROBE_COUNT_ZC if count_zc else 0, None, 0)
         agg, st = Agg(), Stats()
         status = lib().vx_probe_rows(self.ctx.h, self.h, C.byref(d), C.byref(r), C.byref(agg), C.byref(st))
         self._keep_rows = keep

@@ -48,22 +48,53 @@ __device__ __forceinline__ long long slot_signed(const uint8_t* slot, uint32_t o
 // elements this wave reads, where lane l reads the element at device address a0 + l * es
 // (consecutive rows in consecutive lanes) when `active`.  A granule is the unit a zero-copy
 // read moves over the host link, so this is what the wave's gather costs on the wire.  Every
-// lane must call it; every lane gets the same count.
-__device__ __forceinline__ uint32_t wave_granules(bool active, uint64_t a0, uint32_t es, uint32_t shift) {
-  const unsigned long long m = __ballot(active);
+// lane must call it; every lane gets the same count.  es is a power of two no larger than the
+// granule, a0 a multiple of es.  The work is on the wave's ballot mask (scalar operations): with
+// L = lanes per granule and r = the lanes of the first granule that lie before lane 0, the mask
+// shifted up by r splits into whole L-bit groups, one per granule, and the count is the number
+// of nonzero groups.
+__device__ __forceinline__ uint32_t mask_groups(unsigned long long x, uint32_t log2_l) {
+  for (uint32_t s = (1u << log2_l) >> 1; s; s >>= 1) x |= x >> s;   // bit g*L: group g nonzero
+  unsigned long long pick = 1;
+  for (uint32_t s = 1u << log2_l; s < 64; s <<= 1) pick |= pick << s;
+  return (uint32_t)__popcll(x & pick);
+}
+
+// The same count from the wave's ballot mask m of active lanes.
+__device__ __forceinline__ uint32_t mask_granules(unsigned long long m, uint64_t a0, uint32_t es, uint32_t shift) {
   if (m == 0) return 0;
-  const uint32_t lane = threadIdx.x & 63;
-  const unsigned long long below = m & ((1ull << lane) - 1ull);
-  bool first = false;
-  if (active) {
-    if (below == 0) {
-      first = true;
-    } else {   // the granule differs from that of the nearest active lane below
-      const uint32_t prev = 63u - (uint32_t)__clzll(below);
-      first = ((a0 + (uint64_t)prev * es) >> shift) != ((a0 + (uint64_t)lane * es) >> shift);
+  const uint64_t a = __builtin_amdgcn_readfirstlane((uint32_t)a0) |
+                     ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(a0 >> 32)) << 32);
+  const uint32_t log2_es = 31u - (uint32_t)__clz(es);
+  const uint32_t log2_l = shift - log2_es;                  // lanes per granule, log2
+  if (log2_l > 6) {   // a granule wider than the wave: it spans at most two
+    const uint32_t first = (uint32_t)__builtin_ctzll(m), last = 63u - (uint32_t)__clzll(m);
+    return ((a + (uint64_t)first * es) >> shift) == ((a + (uint64_t)last * es) >> shift) ? 1u : 2u;
+  }
+  const uint32_t r = (uint32_t)((a >> log2_es) & ((1u << log2_l) - 1u));
+  if (r == 0) {   // the wave starts on a granule: 8-byte or 4-byte rows in 128-byte granules
+    if (log2_l == 4) {
+      unsigned long long x = m | (m >> 1);
+      x |= x >> 2;
+      x |= x >> 4;
+      x |= x >> 8;
+      return (uint32_t)__popcll(x & 0x0001000100010001ull);
+    }
+    if (log2_l == 5) {
+      unsigned long long x = m | (m >> 1);
+      x |= x >> 2;
+      x |= x >> 4;
+      x |= x >> 8;
+      x |= x >> 16;
+      return (uint32_t)__popcll(x & 0x0000000100000001ull);
     }
   }
-  return (uint32_t)__popcll(__ballot(first));
+  const unsigned long long lo = m << r, hi = r ? m >> (64u - r) : 0ull;
+  return mask_groups(lo, log2_l) + mask_groups(hi, log2_l);
+}
+
+__device__ __forceinline__ uint32_t wave_granules(bool active, uint64_t a0, uint32_t es, uint32_t shift) {
+  return mask_granules(__ballot(active), a0, es, shift);
 }
 
 template <int NACC>

@@ -105,8 +105,10 @@ struct vx_ctx {
   uint64_t* dev_scan = nullptr;        // kScanTilesMax + 1 words: tile sums of the partition scan
   int cu_count = 256;
   uint64_t l2_bytes = 4u << 20;
-  // pinned host mirror of results
+  // pinned host mirror of results (dev_acc_words words), then kHostSmallWords words for small
+  // readbacks (error flags) that are read beside it
   uint64_t* host_acc = nullptr;
+  uint64_t* host_small = nullptr;
   // device-to-host copies of intermediate results (partition pass write-back)
   hipStream_t d2h = nullptr;
   // pinned host memory for intermediates that live in CPU memory (grow-only, kept until destroy)
@@ -143,6 +145,7 @@ void fill_zero(uint64_t* p, uint64_t words, hipStream_t s);
 // spread over `n` rows: the touched lines of `line` bytes under independent selection.
 double zc_wire_bytes(uint64_t n, uint64_t count, int elsize, uint32_t line);
 constexpr uint32_t kScanTilesMax = 1024;
+constexpr uint64_t kHostSmallWords = 32;
 constexpr int kAccWords = 10;           // count + 8 sums + zero-copy granules per aggregate row
 
 }  // namespace vx

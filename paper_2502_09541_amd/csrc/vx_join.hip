@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "vx_device.h"
 #include "vx_pipeline.h"
@@ -151,6 +152,52 @@ __global__ void __launch_bounds__(256) k_direct_count(TableView t, unsigned long
     if (atomicAdd(cnt + 1, 1ull) == gridDim.x - 1) {
       const unsigned long long total = atomicAdd(cnt, 0ull);
       if (total + atomicAdd(t.side, 0ull) != n_rows) atomicOr(flags, kFlagDup);
+    }
+  }
+}
+
+// Dense table: row i's payloads go to slot key - min and its key's presence byte is set, both
+// with plain stores.  Every key lies in the measured range and none is the empty marker (the
+// layout requires both); k_dense_count then checks that every byte of the range was set.
+template <typename K>
+__global__ void k_build_dense(TableView t, BuildCols c, uint64_t n, unsigned int* flags) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t h = key_ord(((const K*)c.key)[i]) - t.kmin_ord;
+    if (h >= t.direct_range) {    // cannot happen: the range was measured over these keys
+      atomicOr(flags, kFlagFull);
+      continue;
+    }
+    if (t.n_pay) write_unique_payloads<K>(t, t.slots + (h << t.slot_shift), c, i);
+    t.present[h] = 1;
+  }
+}
+
+// Set presence bytes of a dense table (four bytes per lane per step), one atomic per workgroup
+// into cnt[0], then a ticket in cnt[1]: the last workgroup compares the total with the rows
+// inserted.  n rows over a range n wide set every byte exactly when no two rows share a key.
+// cnt[0..1] start at zero.
+__global__ void __launch_bounds__(256) k_dense_count(const uint8_t* present, uint64_t range, unsigned long long* cnt,
+                                                     uint64_t n_rows, unsigned int* flags) {
+  __shared__ unsigned long long part[4];
+  unsigned long long c = 0;
+  const uint64_t words = range / 4;
+  for (uint64_t w = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; w < words; w += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t v = ((const uint32_t*)present)[w];   // the bytes are 0 or 1
+    c += (v & 0xffu) + ((v >> 8) & 0xffu) + ((v >> 16) & 0xffu) + (v >> 24);
+  }
+  for (uint64_t b = words * 4 + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; b < range;
+       b += (uint64_t)gridDim.x * blockDim.x)
+    c += present[b];
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) c += part[w];
+    atomicAdd(cnt, c);
+    __threadfence();
+    if (atomicAdd(cnt + 1, 1ull) == gridDim.x - 1) {
+      if (atomicAdd(cnt, 0ull) != n_rows) atomicOr(flags, kFlagDup);
     }
   }
 }
@@ -311,15 +358,19 @@ struct ProbeCols {
   uint32_t pay_size[kMaxPay];
   uint32_t zc_count;          // bit c: pay[c] is host memory read by zero-copy; count its granules
   uint32_t zc_shift;          // log2 of the zero-copy granule in bytes
+  uint32_t zc_mult[kMaxPay];  // columns whose granules pay[c]'s count stands for (same width and
+                              // same offset within a granule: the same granules touched)
 };
 
 // Accumulator row of one probe launch: match count, 8 sums, zero-copy granules read.
 constexpr int kGranuleWord = 9;
 static_assert(kGranuleWord < kAccWords, "the granule count needs its own accumulator word");
 
-// DIRECT: the table's layout (t.direct), fixed at compile time so that the hash loop carries no
-// test of it.
-template <typename K, bool PREAGG, int ITEMS, bool DIRECT>
+// LAYOUT: the table's layout (t.direct: hash, direct or dense), fixed at compile time so that the
+// hash loop carries no test of it.
+// COUNT: count the zero-copy granules of the gathers (compiled in only when asked for: the count
+// slows the gather loop by about 4%).
+template <typename K, bool PREAGG, int ITEMS, int LAYOUT, bool COUNT>
 __global__ void __launch_bounds__(256) k_probe(TableView t, ProbeCols q, unsigned long long* acc_out) {
   using U = typename KeyTraits<K>::U;
   const U kEmpty = KeyTraits<K>::kEmpty;
@@ -330,6 +381,7 @@ __global__ void __launch_bounds__(256) k_probe(TableView t, ProbeCols q, unsigne
   const uint32_t nb = t.n_pay;
   const uint64_t tile = (uint64_t)blockDim.x * ITEMS;
   const uint64_t wave_row = threadIdx.x & ~63u;   // row of lane 0 of this wave, within a tile step
+  unsigned long long granules = 0;                  // the same in every lane of a wave
   for (uint64_t base = blockIdx.x * tile; base < q.n; base += (uint64_t)gridDim.x * tile) {
     unsigned long long mb[ITEMS];
     K keys[ITEMS];
@@ -356,7 +408,18 @@ __global__ void __launch_bounds__(256) k_probe(TableView t, ProbeCols q, unsigne
       // the layout is chosen at compile time: the hash instantiation holds no trace of the direct
       // test (a skip that only folds away after inlining still changes the loop's code)
       uint64_t h;
-      if constexpr (DIRECT) {
+      if constexpr (LAYOUT == kLayoutDense) {
+        // every key of the range is in the table: a key in range is a match, its slot holds
+        // only the payloads
+        h = key_ord(keys[j]) - t.kmin_ord;
+        if (h >= t.direct_range) continue;
+        const uint8_t* slot = t.slots + (h << t.slot_shift);
+        mb[j] = 1;
+        acc[0] += 1;
+        for (uint32_t p = 0; p < nb; ++p)
+          acc[1 + p] += (unsigned long long)slot_signed(slot, t.pay_off[p], t.pay_size[p]);
+        continue;
+      } else if constexpr (LAYOUT == kLayoutDirect) {
         h = key_ord(keys[j]) - t.kmin_ord;
         if (h >= t.direct_range) continue;   // outside the key range: no slot to read
       } else {
@@ -386,25 +449,28 @@ __global__ void __launch_bounds__(256) k_probe(TableView t, ProbeCols q, unsigne
     // late materialization: probe payloads of matching rows only
     for (uint32_t p = 0; p < q.n_pay; ++p) {
       const bool glob = (q.pay_global >> p) & 1u;
+      // the column's base and width, read once per column (the loads below reuse them)
+      const void* const col = q.pay[p];
+      const uint32_t es = q.pay_size[p];
       long long v[ITEMS];
 #pragma unroll
       for (int j = 0; j < ITEMS; ++j) {
         uint64_t i = base + (uint64_t)j * blockDim.x + threadIdx.x;
-        v[j] = mb[j] ? load_signed(q.pay[p], glob ? q.row0 + i : i, q.pay_size[p]) : 0;
+        v[j] = mb[j] ? load_signed(col, glob ? q.row0 + i : i, es) : 0;
+      }
+      // the granules these loads move, counted while they are in flight
+      if (COUNT && ((q.zc_count >> p) & 1u)) {
+        const uint64_t a0 = (uint64_t)(uintptr_t)col + ((glob ? q.row0 : 0) + base + wave_row) * es;
+        uint32_t g = 0;
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) g += wave_granules(mb[j] != 0, a0 + (uint64_t)j * blockDim.x * es, es, q.zc_shift);
+        granules += (unsigned long long)g * q.zc_mult[p];
       }
 #pragma unroll
       for (int j = 0; j < ITEMS; ++j) acc[1 + nb + p] += mb[j] * (unsigned long long)v[j];
-      if ((q.zc_count >> p) & 1u) {
-#pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-          const uint64_t r0 = (glob ? q.row0 : 0) + base + (uint64_t)j * blockDim.x + wave_row;
-          const uint32_t g = wave_granules(mb[j] != 0, (uint64_t)(uintptr_t)q.pay[p] + r0 * q.pay_size[p],
-                                           q.pay_size[p], q.zc_shift);
-          if ((threadIdx.x & 63) == 0) acc[kGranuleWord] += g;
-        }
-      }
     }
   }
+  acc[kGranuleWord] = (threadIdx.x & 63) == 0 ? granules : 0;   // once per wave
   block_flush<NACC>(acc, NACC, acc_out);
 }
 
@@ -422,7 +488,7 @@ struct RowsOut {
 // (global probe row, build payloads, probe payloads), payloads sign-extended.  A workgroup
 // counts its tile's matches, reserves that many rows with one atomic, and its waves write them
 // at consecutive positions (coalesced stores, to host memory beside the host-to-device copies).
-template <typename K, int ITEMS, bool DIRECT>
+template <typename K, int ITEMS, int LAYOUT>
 __global__ void __launch_bounds__(256) k_probe_rows(TableView t, ProbeCols q, unsigned long long* acc_out,
                                                     RowsOut o) {
   using U = typename KeyTraits<K>::U;
@@ -460,7 +526,15 @@ __global__ void __launch_bounds__(256) k_probe_rows(TableView t, ProbeCols q, un
       } else {
         uint64_t h;
         bool in_range = true;
-        if constexpr (DIRECT) {   // compile-time layout, as in k_probe
+        if constexpr (LAYOUT == kLayoutDense) {   // compile-time layout, as in k_probe
+          h = key_ord(keys[j]) - t.kmin_ord;
+          if (h < t.direct_range) {
+            hit[j] = true;
+            const uint8_t* slot = t.slots + (h << t.slot_shift);
+            for (uint32_t p = 0; p < nb; ++p) bv[j][p] = slot_signed(slot, t.pay_off[p], t.pay_size[p]);
+          }
+          in_range = false;   // no probe loop
+        } else if constexpr (LAYOUT == kLayoutDirect) {
           h = key_ord(keys[j]) - t.kmin_ord;
           in_range = h < t.direct_range;
         } else {
@@ -539,15 +613,19 @@ __global__ void __launch_bounds__(256) k_probe_rows(TableView t, ProbeCols q, un
 // ---------------------------------------------------------------- key range
 
 // Min and max of the keys' order-preserving forms, the empty-marker key left out (it lives in
-// the side record, not in a slot).  Workgroup b writes its own pair to mm[2b], mm[2b + 1]
-// (~0 and 0 when it saw no key); the host reduces the pairs.
+// the side record, not in a slot), and the number of rows with that key.  Workgroup b writes its
+// own triple to mm[3b], mm[3b + 1], mm[3b + 2] (~0, 0 and 0 when it saw no key); the host
+// reduces the triples.
 template <typename K>
 __global__ void __launch_bounds__(256) k_key_range(const K* key, uint64_t n, unsigned long long* mm) {
   using U = typename KeyTraits<K>::U;
-  __shared__ unsigned long long rmin[4], rmax[4];
-  unsigned long long mn = ~0ull, mx = 0;
+  __shared__ unsigned long long rmin[4], rmax[4], rempty[4];
+  unsigned long long mn = ~0ull, mx = 0, empties = 0;
   auto take = [&](K k) {
-    if ((U)k == KeyTraits<K>::kEmpty) return;
+    if ((U)k == KeyTraits<K>::kEmpty) {
+      ++empties;
+      return;
+    }
     const unsigned long long o = key_ord(k);
     mn = o < mn ? o : mn;
     mx = o > mx ? o : mx;
@@ -567,20 +645,24 @@ __global__ void __launch_bounds__(256) k_key_range(const K* key, uint64_t n, uns
     const unsigned long long a = __shfl_xor(mn, o, 64), b = __shfl_xor(mx, o, 64);
     mn = a < mn ? a : mn;
     mx = b > mx ? b : mx;
+    empties += __shfl_xor(empties, o, 64);
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) {
     rmin[wave] = mn;
     rmax[wave] = mx;
+    rempty[wave] = empties;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
       mn = rmin[w] < mn ? rmin[w] : mn;
       mx = rmax[w] > mx ? rmax[w] : mx;
+      empties += rempty[w];
     }
-    mm[2 * blockIdx.x] = mn;
-    mm[2 * blockIdx.x + 1] = mx;
+    mm[3 * blockIdx.x] = mn;
+    mm[3 * blockIdx.x + 1] = mx;
+    mm[3 * blockIdx.x + 2] = empties;
   }
 }
 
@@ -594,7 +676,8 @@ static int ilog2(uint64_t v) {
 
 // The table's layout for `expected_rows` rows: capacity (a power of two), slot size and the view's
 // fields other than its memory.  Direct when `kr` holds a measured range no wider than the hash
-// capacity.
+// capacity; dense when, besides, the build is unique, allows it, has no empty-marker key and its
+// rows number exactly the range's width (the capacity is then the width itself).
 static vx_status plan_table(int32_t key_type, uint32_t flags, const int32_t* pay_types, uint32_t n_pay,
                             uint64_t expected_rows, float load_factor, const KeyRange* kr, TableView* out,
                             uint64_t* cap_out, uint32_t* slot_bytes_out) {
@@ -613,14 +696,38 @@ static vx_status plan_table(int32_t key_type, uint32_t flags, const int32_t* pay
     uint64_t dcap = 64;
     while (dcap < range) dcap <<= 1;
     cap = dcap;
-    v.direct = 1;
+    v.direct = kLayoutDirect;
     v.kmin_ord = kr->min_ord;
     v.direct_range = range;
+    if (kr->allow_dense && !preagg && kr->empty_rows == 0 && range == expected_rows) {
+      v.direct = kLayoutDense;
+      cap = range;
+    }
   }
   v.n_pay = n_pay;
   v.preagg = preagg ? 1 : 0;
   v.key_size = (uint32_t)ks;
   uint32_t off;
+  if (v.direct == kLayoutDense) {   // payloads only
+    off = 0;
+    for (uint32_t p = 0; p < n_pay; ++p) {
+      int ps = elsize_of(pay_types[p]);
+      VX_CHECK(ps != 0, VX_EINVAL, "build: bad payload type %d", pay_types[p]);
+      off = (off + ps - 1) / ps * ps;
+      v.pay_off[p] = off;
+      v.pay_size[p] = (uint32_t)ps;
+      off += ps;
+    }
+    uint32_t slot_bytes = off ? 4 : 0;
+    while (slot_bytes && slot_bytes < off) slot_bytes <<= 1;
+    v.slot_shift = slot_bytes ? (uint32_t)ilog2(slot_bytes) : 0;
+    v.log2cap = (uint32_t)ilog2(cap);
+    v.mask = 0;
+    *out = v;
+    *cap_out = cap;
+    *slot_bytes_out = slot_bytes;
+    return VX_OK;
+  }
   if (preagg) {
     off = 16;   // key (8), count (8)
     for (uint32_t p = 0; p < n_pay; ++p) {
@@ -659,7 +766,11 @@ vx_status make_table(vx_ctx* ctx, int32_t key_type, uint32_t flags, const int32_
   uint32_t slot_bytes = 0;
   VX_TRY(plan_table(key_type, flags, pay_types, n_pay, expected_rows, load_factor, kr, &v, &cap, &slot_bytes));
   const int ks = (int)v.key_size;
-  uint64_t bytes = cap * slot_bytes + 256;
+  const bool dense = v.direct == kLayoutDense;
+  // dense: the payload slots, the bitmap of keys seen, the side record; else slots and side record
+  const uint64_t slots_bytes = dense ? (cap * slot_bytes + 255) / 256 * 256 : cap * slot_bytes;
+  const uint64_t bits_bytes = dense ? (cap + 255) / 256 * 256 : 0;   // presence bytes
+  uint64_t bytes = slots_bytes + bits_bytes + 256;
   uint8_t* mem = ctx->arena.alloc(bytes);
   VX_CHECK(mem != nullptr, VX_EBUDGET,
            "build: hash table of %llu slots x %u B = %llu B does not fit the arena (%llu B free, "
@@ -668,7 +779,8 @@ vx_status make_table(vx_ctx* ctx, int32_t key_type, uint32_t flags, const int32_
            (unsigned long long)(ctx->arena.capacity() - ctx->arena.used()),
            (unsigned long long)ctx->arena.largest_free());
   v.slots = mem;
-  v.side = (unsigned long long*)(mem + cap * slot_bytes);
+  v.present = dense ? mem + slots_bytes : nullptr;
+  v.side = (unsigned long long*)(mem + slots_bytes + bits_bytes);
   vx_table* t = new vx_table;
   t->ctx = ctx;
   t->mem = mem;
@@ -678,11 +790,16 @@ vx_status make_table(vx_ctx* ctx, int32_t key_type, uint32_t flags, const int32_
   t->flags = flags;
   for (uint32_t p = 0; p < n_pay; ++p) t->pay_type[p] = (uint32_t)pay_types[p];
   t->view = v;
-  const uint64_t quads = cap * slot_bytes / 16;   // 16-byte stores of k_init_slots
-  uint64_t blocks = std::min<uint64_t>((quads + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_init_slots, dim3((unsigned)blocks), dim3(256), 0, ctx->compute,
-                     (uint32_t*)mem, cap, slot_bytes / 4, (uint32_t)ks);
-  fill_zero((uint64_t*)v.side, 32, ctx->compute);
+  if (dense) {
+    // every payload slot is written by the build; the bitmap and the side record start at zero
+    fill_zero((uint64_t*)v.present, (bits_bytes + 256) / 8, ctx->compute);
+  } else {
+    const uint64_t quads = cap * slot_bytes / 16;   // 16-byte stores of k_init_slots
+    uint64_t blocks = std::min<uint64_t>((quads + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_init_slots, dim3((unsigned)blocks), dim3(256), 0, ctx->compute,
+                       (uint32_t*)mem, cap, slot_bytes / 4, (uint32_t)ks);
+    fill_zero((uint64_t*)v.side, 32, ctx->compute);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     ctx->arena.release(mem);
@@ -696,8 +813,9 @@ vx_status make_table(vx_ctx* ctx, int32_t key_type, uint32_t flags, const int32_
 
 vx_status check_flags(vx_ctx* ctx, const char* what) {
   unsigned int f = 0;
-  VX_HIP(hipMemcpyAsync(&f, ctx->dev_flags, sizeof f, hipMemcpyDeviceToHost, ctx->compute));
+  VX_HIP(hipMemcpyAsync(ctx->host_small, ctx->dev_flags, sizeof f, hipMemcpyDeviceToHost, ctx->compute));
   VX_HIP(hipStreamSynchronize(ctx->compute));
+  std::memcpy(&f, ctx->host_small, sizeof f);
   if (f & kFlagDup) {
     set_error("%s: duplicate key in a build declared unique", what);
     return VX_EDUPKEY;
@@ -726,20 +844,22 @@ vx_status key_range(vx_ctx* ctx, int32_t key_type, const void* dev_keys, uint64_
   if (n == 0) return VX_OK;
   unsigned long long* mm = (unsigned long long*)ctx->dev_acc;   // free between executor steps
   const unsigned g = grid_for(ctx, n, 256 * 16, 2);
-  VX_CHECK(2ull * g <= ctx->dev_acc_words, VX_EINVAL, "key range: %u workgroups exceed the scratch", g);
+  VX_CHECK(3ull * g <= ctx->dev_acc_words, VX_EINVAL, "key range: %u workgroups exceed the scratch", g);
   if (key_type == VX_I64)
     hipLaunchKernelGGL(k_key_range<int64_t>, dim3(g), dim3(256), 0, ctx->compute, (const int64_t*)dev_keys, n, mm);
   else
     hipLaunchKernelGGL(k_key_range<int32_t>, dim3(g), dim3(256), 0, ctx->compute, (const int32_t*)dev_keys, n, mm);
   VX_HIP(hipGetLastError());
-  std::vector<unsigned long long> h(2 * (size_t)g);
-  VX_HIP(hipMemcpyAsync(h.data(), mm, h.size() * 8, hipMemcpyDeviceToHost, ctx->compute));
+  const unsigned long long* h = (const unsigned long long*)ctx->host_acc;   // pinned: a direct copy
+  VX_HIP(hipMemcpyAsync(ctx->host_acc, mm, 3 * (uint64_t)g * 8, hipMemcpyDeviceToHost, ctx->compute));
   VX_HIP(hipStreamSynchronize(ctx->compute));
-  unsigned long long mn = ~0ull, mx = 0;
+  unsigned long long mn = ~0ull, mx = 0, empties = 0;
   for (unsigned b = 0; b < g; ++b) {
-    mn = std::min(mn, h[2 * b]);
-    mx = std::max(mx, h[2 * b + 1]);
+    mn = std::min(mn, h[3 * b]);
+    mx = std::max(mx, h[3 * b + 1]);
+    empties += h[3 * b + 2];
   }
+  out->empty_rows = empties;
   if (mn <= mx) {      // at least one key besides the empty marker
     out->known = true;
     out->min_ord = mn;
@@ -762,6 +882,16 @@ vx_status table_insert(vx_ctx* ctx, vx_table* t, const ColInfo& key, const ColIn
     unsigned g = grid_for(ctx, n, kPreaggTile, 3);
     if (k64) hipLaunchKernelGGL(k_build_preagg<int64_t>, dim3(g), dim3(256), 0, s, t->view, c, n, ctx->dev_flags);
     else hipLaunchKernelGGL(k_build_preagg<int32_t>, dim3(g), dim3(256), 0, s, t->view, c, n, ctx->dev_flags);
+  } else if (t->view.direct == kLayoutDense) {
+    VX_CHECK(t->n_rows == 0, VX_EINVAL, "build: a dense table takes its rows in one insert");
+    unsigned long long* cnt = (unsigned long long*)ctx->dev_acc;
+    fill_zero((uint64_t*)cnt, 2, s);
+    const unsigned g = grid_for(ctx, n, 256, 8);
+    const unsigned gc = grid_for(ctx, t->view.direct_range, 256 * 16, 2);
+    if (k64) hipLaunchKernelGGL(k_build_dense<int64_t>, dim3(g), dim3(256), 0, s, t->view, c, n, ctx->dev_flags);
+    else hipLaunchKernelGGL(k_build_dense<int32_t>, dim3(g), dim3(256), 0, s, t->view, c, n, ctx->dev_flags);
+    hipLaunchKernelGGL(k_dense_count, dim3(gc), dim3(256), 0, s, (const uint8_t*)t->view.present, t->view.direct_range,
+                       cnt, n, ctx->dev_flags);
   } else if (t->view.direct) {
     // one insert per direct table: the duplicate check counts every slot against every row
     VX_CHECK(t->n_rows == 0, VX_EINVAL, "build: a direct table takes its rows in one insert");
@@ -798,30 +928,48 @@ vx_status table_insert(vx_ctx* ctx, vx_table* t, const ColInfo& key, const ColIn
   return VX_OK;
 }
 
-// Launch one probe kernel over q.n rows, accumulating into acc (9 words).
-template <typename K, bool DIRECT>
+// Launch one probe kernel over q.n rows, accumulating into acc (kAccWords words).
+template <typename K, int LAYOUT, bool COUNT>
+static void launch_probe_count(const vx_table* t, const ProbeCols& q, unsigned long long* acc, hipStream_t s,
+                               unsigned g) {
+  constexpr int ITEMS = 4;
+  if constexpr (LAYOUT == kLayoutDense)   // dense tables hold unique keys
+    hipLaunchKernelGGL((k_probe<K, false, ITEMS, LAYOUT, COUNT>), dim3(g), dim3(256), 0, s, t->view, q, acc);
+  else if (t->view.preagg)
+    hipLaunchKernelGGL((k_probe<K, true, ITEMS, LAYOUT, COUNT>), dim3(g), dim3(256), 0, s, t->view, q, acc);
+  else
+    hipLaunchKernelGGL((k_probe<K, false, ITEMS, LAYOUT, COUNT>), dim3(g), dim3(256), 0, s, t->view, q, acc);
+}
+
+template <typename K, int LAYOUT>
 static void launch_probe_as(const vx_table* t, const ProbeCols& q, unsigned long long* acc, hipStream_t s,
                             const RowsOut* ro, unsigned g) {
-  constexpr int ITEMS = 4;
   if (ro)
-    hipLaunchKernelGGL((k_probe_rows<K, ITEMS, DIRECT>), dim3(g), dim3(256), 0, s, t->view, q, acc, *ro);
-  else if (t->view.preagg)
-    hipLaunchKernelGGL((k_probe<K, true, ITEMS, DIRECT>), dim3(g), dim3(256), 0, s, t->view, q, acc);
+    hipLaunchKernelGGL((k_probe_rows<K, 4, LAYOUT>), dim3(g), dim3(256), 0, s, t->view, q, acc, *ro);
+  else if (q.zc_count)
+    launch_probe_count<K, LAYOUT, true>(t, q, acc, s, g);
   else
-    hipLaunchKernelGGL((k_probe<K, false, ITEMS, DIRECT>), dim3(g), dim3(256), 0, s, t->view, q, acc);
+    launch_probe_count<K, LAYOUT, false>(t, q, acc, s, g);
 }
 
 static vx_status launch_probe(vx_ctx* ctx, const vx_table* t, const ProbeCols& q,
                               unsigned long long* acc, hipStream_t s, const RowsOut* ro = nullptr) {
   if (q.n == 0) return VX_OK;
   const unsigned g = grid_for(ctx, q.n, 256 * 4, 8);
-  const bool k64 = t->key_type == VX_I64, direct = t->view.direct != 0;
-  if (k64) {
-    if (direct) launch_probe_as<int64_t, true>(t, q, acc, s, ro, g);
-    else launch_probe_as<int64_t, false>(t, q, acc, s, ro, g);
-  } else {
-    if (direct) launch_probe_as<int32_t, true>(t, q, acc, s, ro, g);
-    else launch_probe_as<int32_t, false>(t, q, acc, s, ro, g);
+  const bool k64 = t->key_type == VX_I64;
+  switch (t->view.direct) {
+    case kLayoutDense:
+      if (k64) launch_probe_as<int64_t, kLayoutDense>(t, q, acc, s, ro, g);
+      else launch_probe_as<int32_t, kLayoutDense>(t, q, acc, s, ro, g);
+      break;
+    case kLayoutDirect:
+      if (k64) launch_probe_as<int64_t, kLayoutDirect>(t, q, acc, s, ro, g);
+      else launch_probe_as<int32_t, kLayoutDirect>(t, q, acc, s, ro, g);
+      break;
+    default:
+      if (k64) launch_probe_as<int64_t, kLayoutHash>(t, q, acc, s, ro, g);
+      else launch_probe_as<int32_t, kLayoutHash>(t, q, acc, s, ro, g);
+      break;
   }
   VX_HIP(hipGetLastError());
   return VX_OK;
@@ -844,8 +992,10 @@ static bool choose_zero_copy(int32_t late_mat, double sel, uint64_t rows, uint64
   return wire < 0.95 * es;
 }
 
+// check_build: the table's build left its error flags unread (build_impl's defer_check); they
+// are read back with the results and turned into the build's error.
 vx_status probe_impl(vx_ctx* ctx, const vx_table* t, const vx_probe_desc* d, vx_agg* out,
-                     vx_stats* st, vx_join_rows* rows) {
+                     vx_stats* st, vx_join_rows* rows, bool check_build = false) {
   double t0 = now_ms();
   VX_CHECK(d->key.type == t->key_type, VX_EINVAL, "probe: key type %d differs from the table's %d",
            d->key.type, t->key_type);
@@ -853,6 +1003,7 @@ vx_status probe_impl(vx_ctx* ctx, const vx_table* t, const vx_probe_desc* d, vx_
   VX_CHECK(d->n_pay == 0 || d->pay != nullptr, VX_EINVAL, "probe: pay is NULL");
   VX_CHECK(t->view.n_pay + d->n_pay <= 8, VX_EINVAL, "probe: more than 8 aggregate sums");
   VX_CHECK(d->late_mat >= -1 && d->late_mat <= 2, VX_EINVAL, "probe: late_mat %d", d->late_mat);
+  VX_CHECK((d->flags & ~(uint32_t)VX_PROBE_COUNT_ZC) == 0, VX_EINVAL, "probe: unknown flags %u", d->flags);
   std::vector<PipeCol> cols(1 + d->n_pay);
   VX_TRY(classify(ctx, d->key, d->n, &cols[0].info, "probe key"));
   cols[0].may_copy = cols[0].copy = true;
@@ -911,6 +1062,7 @@ vx_status probe_impl(vx_ctx* ctx, const vx_table* t, const vx_probe_desc* d, vx_
 
   uint32_t zc_shift = 0;
   while ((2u << zc_shift) <= ctx->zc_line) ++zc_shift;   // log2 of the measured granule
+  const bool count_zc = (d->flags & VX_PROBE_COUNT_ZC) != 0;
   auto kernel = [&](const ChunkView& v) -> vx_status {
     ProbeCols q{};
     q.key = v.ptr[0];
@@ -923,7 +1075,17 @@ vx_status probe_impl(vx_ctx* ctx, const vx_table* t, const vx_probe_desc* d, vx_
       q.pay_size[p] = (uint32_t)cols[1 + p].info.elsize;
       if ((v.global_mask >> (1 + p)) & 1u) {
         q.pay_global |= 1u << p;
-        if (cols[1 + p].info.where == Where::Host) q.zc_count |= 1u << p;   // read in place: count
+        if (count_zc && cols[1 + p].info.where == Where::Host) {   // read in place: count its granules, once
+          // per group of columns with one width and one offset within a granule
+          const uint64_t off = (uint64_t)(uintptr_t)q.pay[p] & (((uint64_t)1 << zc_shift) - 1);
+          uint32_t rep = p;
+          for (uint32_t o = 0; o < p; ++o)
+            if (((q.zc_count >> o) & 1u) && q.pay_size[o] == q.pay_size[p] &&
+                ((uint64_t)(uintptr_t)q.pay[o] & (((uint64_t)1 << zc_shift) - 1)) == off)
+              rep = o;
+          if (rep == p) q.zc_count |= 1u << p;
+          q.zc_mult[rep] += 1;
+        }
       }
     }
     q.zc_shift = zc_shift;
@@ -952,7 +1114,13 @@ vx_status probe_impl(vx_ctx* ctx, const vx_table* t, const vx_probe_desc* d, vx_
   VX_HIP(hipMemcpyAsync(ctx->host_acc, ctx->dev_acc, acc_rows * kAccWords * 8, hipMemcpyDeviceToHost,
                         ctx->compute));
   if (rows) VX_HIP(hipMemcpyAsync(&rows->n_out, ro.count, 8, hipMemcpyDeviceToHost, ctx->compute));
+  if (check_build)
+    VX_HIP(hipMemcpyAsync(ctx->host_small, ctx->dev_flags, 4, hipMemcpyDeviceToHost, ctx->compute));
   VX_HIP(hipStreamSynchronize(ctx->compute));
+  unsigned int build_flags = 0;
+  if (check_build) std::memcpy(&build_flags, ctx->host_small, 4);
+  VX_CHECK(!(build_flags & kFlagDup), VX_EDUPKEY, "vx_join_agg: duplicate key in a build declared unique");
+  VX_CHECK(!(build_flags & kFlagFull), VX_ECAPACITY, "vx_join_agg: hash table full (internal sizing error)");
   double tk1 = now_ms();
   std::vector<unsigned long long> total(kAccWords, 0);
   for (uint64_t r = 0; r < acc_rows; ++r)
@@ -971,10 +1139,19 @@ vx_status probe_impl(vx_ctx* ctx, const vx_table* t, const vx_probe_desc* d, vx_
   uint32_t zc_mask = 0;
   for (uint32_t p = 0; p < d->n_pay; ++p) {
     const PipeCol& c = pipe.cols()[1 + p];
-    if (c.info.where == Where::Host && !c.copy) zc_mask |= 1u << p;
+    if (c.info.where != Where::Host || c.copy) continue;
+    zc_mask |= 1u << p;
+    if (count_zc) continue;
+    // not counted: the wire model's estimate from the per-chunk match counts
+    for (uint64_t k = 0; k < n_chunks; ++k) {
+      const uint64_t crows = std::min(pipe.chunk_rows(), n - k * pipe.chunk_rows());
+      const uint64_t m = k < acc_rows ? ctx->host_acc[k * kAccWords] : 0;
+      s.zc_bytes += (uint64_t)zc_wire_bytes(crows, std::min(m, crows), c.info.elsize, ctx->zc_line);
+    }
   }
-  // zero-copy bytes: the granules the probe kernels counted, times the granule
-  s.zc_bytes = total[kGranuleWord] << zc_shift;
+  // counted: the granules the probe kernels counted, times the granule
+  if (count_zc) s.zc_bytes = total[kGranuleWord] << zc_shift;
+  s.zc_counted = count_zc && zc_mask ? 1u : 0u;
   s.zc_mask = zc_mask;
   s.chunk_rows = pipe.chunk_rows();
   s.chunks = pipe.streamed() ? n_chunks : 0;
@@ -991,7 +1168,9 @@ vx_status probe_impl(vx_ctx* ctx, const vx_table* t, const vx_probe_desc* d, vx_
   return VX_OK;
 }
 
-vx_status build_impl(vx_ctx* ctx, const vx_build_desc* d, vx_table** out, double* ms) {
+// defer_check: leave the build's error flags for the caller to read with its own results (one
+// host round trip less); the table is returned even if they will show a repeated key.
+vx_status build_impl(vx_ctx* ctx, const vx_build_desc* d, vx_table** out, double* ms, bool defer_check) {
   double t0 = now_ms();
   VX_CHECK(d != nullptr && out != nullptr, VX_EINVAL, "vx_build: null argument");
   *out = nullptr;
@@ -1014,11 +1193,12 @@ vx_status build_impl(vx_ctx* ctx, const vx_build_desc* d, vx_table** out, double
   KeyRange kr;
   if (!(d->flags & VX_HASHED) && kc.where == Where::Device)
     VX_TRY(key_range(ctx, d->key.type, kc.dev, d->n, &kr));
+  kr.allow_dense = kind == VX_UNIQUE;
   vx_table* t = nullptr;
   VX_TRY(make_table(ctx, d->key.type, kind, pt, d->n_pay, d->n, d->load_factor, &t, &kr));
   fill_zero((uint64_t*)ctx->dev_flags, 1, ctx->compute);
   vx_status st = table_insert(ctx, t, kc, pc, d->n, ctx->compute, build_group_lanes());
-  if (st == VX_OK) st = check_flags(ctx, "vx_build");
+  if (st == VX_OK && !defer_check) st = check_flags(ctx, "vx_build");
   if (st != VX_OK) {
     ctx->arena.release(t->mem);
     delete t;
@@ -1043,7 +1223,7 @@ extern "C" {
 vx_status vx_build(vx_ctx* ctx, const vx_build_desc* d, vx_table** out) {
   VX_CHECK(ctx != nullptr, VX_EINVAL, "vx_build: ctx is NULL");
   release_cached(ctx);
-  return build_impl(ctx, d, out, nullptr);
+  return build_impl(ctx, d, out, nullptr, false);
 }
 
 vx_status vx_table_destroy(vx_table* t) {
@@ -1079,8 +1259,9 @@ vx_status vx_join_agg(vx_ctx* ctx, const vx_join_desc* d, vx_join_out* out) {
     case VX_JOIN_PLAIN: {
       double t0 = now_ms(), bms = 0;
       vx_table* t = nullptr;
-      VX_TRY(build_impl(ctx, &d->u.plain.build, &t, &bms));
-      vx_status st = probe_impl(ctx, t, &d->u.plain.probe, &out->agg, &out->stats, nullptr);
+      // the build's flags are read with the probe's results: one host round trip for both
+      VX_TRY(build_impl(ctx, &d->u.plain.build, &t, &bms, true));
+      vx_status st = probe_impl(ctx, t, &d->u.plain.probe, &out->agg, &out->stats, nullptr, true);
       vx_table_destroy(t);
       out->stats.build_ms = bms;
       out->stats.total_ms = now_ms() - t0;

@@ -259,7 +259,8 @@ vx_status vx_ctx_create(int device, void* arena, uint64_t arena_bytes, void* str
   }
   if (hipStreamCreateWithFlags(&c->copy, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&c->d2h, hipStreamNonBlocking) != hipSuccess ||
-      hipHostMalloc((void**)&c->host_acc, c->dev_acc_words * 8, hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void**)&c->host_acc, (c->dev_acc_words + kHostSmallWords) * 8, hipHostMallocDefault) !=
+          hipSuccess) {
     if (c->own_compute) (void)hipStreamDestroy(c->compute);
     if (c->copy) (void)hipStreamDestroy(c->copy);
     if (c->d2h) (void)hipStreamDestroy(c->d2h);
@@ -267,6 +268,7 @@ vx_status vx_ctx_create(int device, void* arena, uint64_t arena_bytes, void* str
     set_error("vx_ctx_create: stream or pinned scratch creation failed");
     return VX_EHIP;
   }
+  c->host_small = c->host_acc + c->dev_acc_words;
   *out = c;
   return VX_OK;
 }

@@ -135,7 +135,8 @@ struct StarArgs {
   uint32_t zc_shift;               // log2 of the zero-copy granule in bytes
 };
 
-template <typename K, int kStarItems>
+// COUNT: count the zero-copy granules of the gathers (compiled in only when asked for).
+template <typename K, int kStarItems, bool COUNT>
 __global__ void __launch_bounds__(256) k_star(StarArgs a) {
   using U = typename KeyTraits<K>::U;
   const U kEmpty = KeyTraits<K>::kEmpty;
@@ -162,7 +163,7 @@ __global__ void __launch_bounds__(256) k_star(StarArgs a) {
           else fk[j] = load_key<K>(a.fk[d], glob ? a.row0 + i : i);
         }
       }
-      if ((a.fk_zc >> d) & 1u) {
+      if (COUNT && ((a.fk_zc >> d) & 1u)) {
 #pragma unroll
         for (int j = 0; j < kStarItems; ++j) {
           const uint64_t r0 = a.row0 + base + (uint64_t)j * blockDim.x + wave_row;
@@ -187,7 +188,7 @@ __global__ void __launch_bounds__(256) k_star(StarArgs a) {
         if (found && a.gsel[d] >= 0) g[j][a.gsel[d]] = grp;
       }
     }
-    for (uint32_t c = 0; c < a.n_meas; ++c) {
+    for (uint32_t c = 0; COUNT && c < a.n_meas; ++c) {
       if (!((a.meas_zc >> c) & 1u)) continue;
 #pragma unroll
       for (int j = 0; j < kStarItems; ++j) {
@@ -212,10 +213,21 @@ __global__ void __launch_bounds__(256) k_star(StarArgs a) {
   for (int o = 32; o > 0; o >>= 1) alive_count += __shfl_xor(alive_count, o, 64);
   if ((threadIdx.x & 63) == 0 && alive_count) atomicAdd(a.survivors, alive_count);
   // every lane holds its wave's granule count
-  if ((threadIdx.x & 63) == 0 && granules) atomicAdd(a.survivors + 1, granules);
+  if (COUNT && (threadIdx.x & 63) == 0 && granules) atomicAdd(a.survivors + 1, granules);
 }
 
 // ---------------------------------------------------------------- host side
+
+template <int ITEMS>
+static void launch_star(bool k64, bool count, unsigned g, const StarArgs& a, hipStream_t s) {
+  if (k64) {
+    if (count) hipLaunchKernelGGL((k_star<int64_t, ITEMS, true>), dim3(g), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_star<int64_t, ITEMS, false>), dim3(g), dim3(256), 0, s, a);
+  } else {
+    if (count) hipLaunchKernelGGL((k_star<int32_t, ITEMS, true>), dim3(g), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_star<int32_t, ITEMS, false>), dim3(g), dim3(256), 0, s, a);
+  }
+}
 
 // rows per lane in flight in the fact scan (VX_STAR_ITEMS = 4 or 8; default 8)
 static int star_items() {
@@ -229,6 +241,8 @@ vx_status join_star(vx_ctx* ctx, const vx_star_join* d, vx_join_out* out) {
   VX_CHECK(d->n_measures <= 4, VX_EINVAL, "star: n_measures %u > 4", d->n_measures);
   VX_CHECK(d->late_mat >= -1 && d->late_mat <= 2, VX_EINVAL, "star: late_mat %d", d->late_mat);
   VX_CHECK(d->groups != nullptr || d->groups_cap == 0, VX_EINVAL, "star: groups is NULL");
+  VX_CHECK((d->flags & ~(uint32_t)VX_PROBE_COUNT_ZC) == 0, VX_EINVAL, "star: unknown flags %u", d->flags);
+  const bool count_zc = (d->flags & VX_PROBE_COUNT_ZC) != 0;
   const int32_t ktype = d->dims[0].key.type;
   const uint32_t nd = d->n_dims;
   VX_HIP(hipSetDevice(ctx->device));
@@ -437,13 +451,8 @@ vx_status join_star(vx_ctx* ctx, const vx_star_join* d, vx_join_out* out) {
         const int items = star_items();
         unsigned g = (unsigned)std::min<uint64_t>((a.n + 256 * items - 1) / (256 * items),
                                                   (uint64_t)ctx->cu_count * 8);
-        if (items == 8) {
-          if (ktype == VX_I64) hipLaunchKernelGGL((k_star<int64_t, 8>), dim3(g), dim3(256), 0, ctx->compute, a);
-          else hipLaunchKernelGGL((k_star<int32_t, 8>), dim3(g), dim3(256), 0, ctx->compute, a);
-        } else {
-          if (ktype == VX_I64) hipLaunchKernelGGL((k_star<int64_t, 4>), dim3(g), dim3(256), 0, ctx->compute, a);
-          else hipLaunchKernelGGL((k_star<int32_t, 4>), dim3(g), dim3(256), 0, ctx->compute, a);
-        }
+        if (items == 8) launch_star<8>(ktype == VX_I64, count_zc, g, a, ctx->compute);
+        else launch_star<4>(ktype == VX_I64, count_zc, g, a, ctx->compute);
         VX_HIP(hipGetLastError());
         return VX_OK;
       };
@@ -498,9 +507,17 @@ vx_status join_star(vx_ctx* ctx, const vx_star_join* d, vx_join_out* out) {
   s.sdma_bytes = sdma;
   s.kernel_ms = kms;
   s.kernel_launches = kl;
-  for (size_t c = 0; c < cols.size(); ++c)
-    if (cols[c].info.where == Where::Host && !cols[c].copy) s.zc_mask |= 1u << c;
-  s.zc_bytes = nsurv[1] << base.zc_shift;   // counted granules x granule
+  for (size_t c = 0; c < cols.size(); ++c) {
+    if (cols[c].info.where != Where::Host || cols[c].copy) continue;
+    s.zc_mask |= 1u << c;
+    if (!count_zc)   // not counted: the wire model's estimate from the estimated selectivities
+      s.zc_bytes += (uint64_t)zc_wire_bytes(d->n_fact, (uint64_t)(col_sel[c] * d->n_fact), cols[c].info.elsize,
+                                            ctx->zc_line);
+  }
+  if (count_zc) {
+    s.zc_bytes = nsurv[1] << base.zc_shift;   // counted granules x granule
+    s.zc_counted = s.zc_mask ? 1u : 0u;
+  }
   s.probe_ms = now_ms() - tp0;
   s.total_ms = now_ms() - t0;
   s.survivors = nsurv[0];

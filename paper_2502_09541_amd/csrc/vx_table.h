@@ -43,13 +43,22 @@ struct TableView {
   uint32_t pay_size[kMaxPay]; // 4 or 8 (unique); 8 (pre-aggregated sums)
   uint32_t preagg;
   uint32_t key_size;
-  // Direct layout: key k lives in slot ord(k) - kmin_ord, where ord is the order-preserving
-  // unsigned form of the key, and keys outside [kmin, kmin + direct_range) are absent.  A slot
-  // then holds k or the empty marker, never another key, so every probe ends at its first slot.
+  // Direct layout (direct == 1): key k lives in slot ord(k) - kmin_ord, where ord is the
+  // order-preserving unsigned form of the key, and keys outside [kmin, kmin + direct_range) are
+  // absent.  A slot then holds k or the empty marker, never another key, so every probe ends at
+  // its first slot.
+  // Dense layout (direct == 2): a unique build whose n keys are exactly the n values of their
+  // range.  Every key of the range is present, so a slot holds only the payloads (at pay_off,
+  // from offset 0; no slots at all without payloads) and a probe in range is a match.  `present`
+  // holds one byte per key of the range, set by plain stores while building: a repeated key
+  // leaves another key's byte unset, so fewer set bytes than rows catches it.
   uint32_t direct;
   unsigned long long kmin_ord;
   uint64_t direct_range;
+  uint8_t* present;
 };
+
+enum : uint32_t { kLayoutHash = 0, kLayoutDirect = 1, kLayoutDense = 2 };
 
 }  // namespace vx
 
@@ -71,6 +80,8 @@ namespace vx {
 struct KeyRange {
   bool known = false;
   unsigned long long min_ord = 0, max_ord = 0;
+  uint64_t empty_rows = 0;    // rows whose key is the empty marker
+  bool allow_dense = false;   // the caller's build is unique and may take the dense layout
 };
 
 // Launch helpers implemented in vx_join.hip and used by the other executors.

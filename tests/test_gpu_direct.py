@@ -2,11 +2,14 @@
 hash layout of the same build (VX_HASHED), through the C ABI.
 
 A build over device-resident keys whose range is no wider than the hash table's capacity is laid
-out directly.  Results must not depend on the layout: every aggregate and every materialized row
-is compared exactly.  Covered: dense and gapped ranges, the empty-marker key beside a range,
-ranges at the ends of int32 and int64, probes below, inside and above the range, duplicates
-(rejected for unique builds, aggregated for pre-aggregating ones), streamed host probes, and the
-materialized rows.
+out directly.  When the build is unique and its n keys are exactly the n values of their range
+(no empty-marker key), the table is dense: payloads only, every key of the range present.
+Results must not depend on the layout: every aggregate and every materialized row is compared
+exactly.  Covered: dense and gapped ranges, the empty-marker key beside a range, ranges at the
+ends of int32 and int64, probes below, inside and above the range, duplicates (rejected for
+unique builds, also when they leave the row count equal to the range's width; aggregated for
+pre-aggregating ones), dense tables without payloads and with mixed-width payloads, streamed
+host probes, and the materialized rows.
 """
 import numpy as np
 import pytest
@@ -51,6 +54,20 @@ def _slot_bytes(key_dtype, pay_dtypes):
     return b
 
 
+def _dense_bytes(n, pay_dtypes):
+    """Dense table: n payload slots (the payloads packed, a power of two >= 4 bytes; none without
+    payloads), n presence bytes, each 256-byte aligned, and the 256-byte side record."""
+    off = 0
+    for p in pay_dtypes:
+        s = np.dtype(p).itemsize
+        off = (off + s - 1) // s * s + s
+    b = 4 if off else 0
+    while b and b < off:
+        b *= 2
+    a256 = lambda v: (v + 255) // 256 * 256
+    return a256(n * b) + a256(n) + 256
+
+
 def _probes(rng, lo, n, m, dtype):
     """m probe keys: most inside [lo, lo + n), the rest just below or above it, clipped to the type."""
     info = np.iinfo(dtype)
@@ -76,7 +93,7 @@ def test_direct_dense_matches_hashed_and_oracle(gpu, ctx, lanes, dtype, monkeypa
     got_h, st_h = ctx.join_plain(dev(bkey), [dev(bpay)], dev(pkey), [dev(ppay)], hashed=True)
     assert got_d == exp and got_h == exp
     sb = _slot_bytes(dtype, [np.int32])
-    assert st_d["table_bytes"] == n * sb + 256
+    assert st_d["table_bytes"] == _dense_bytes(n, [np.int32])
     assert st_h["table_bytes"] == 2 * n * sb + 256
 
 
@@ -115,7 +132,7 @@ def test_direct_at_type_extremes(gpu, ctx, dtype, end):
     _say("direct extremes", np.dtype(dtype).name, end)
     got, st = ctx.join_plain(dev(bkey), [dev(bpay)], dev(pkey))
     assert got == oracle.join_agg(bkey, [bpay], pkey, [])
-    assert st["table_bytes"] == n * _slot_bytes(dtype, [np.int64]) + 256
+    assert st["table_bytes"] == _dense_bytes(n, [np.int64])
 
 
 @pytest.mark.parametrize("dup", [0, 500, 999])
@@ -126,6 +143,47 @@ def test_direct_duplicate_rejected(gpu, ctx, dup):
     with pytest.raises(gpu.VxError) as ei:
         ctx.join_plain(dev(bkey), [], dev(bkey))
     assert ei.value.status == gpu.VX_EDUPKEY
+
+
+@pytest.mark.parametrize("swap", [(500, 0), (0, 999), (999, 0)])
+def test_dense_duplicate_rejected(gpu, ctx, swap):
+    """n keys spanning a range n wide but with one key repeated (so another is missing): the row
+    count matches the range, and the build must still fail."""
+    bkey = np.arange(1000, dtype=np.int64)
+    bkey[swap[0]] = swap[1]
+    _say("dense duplicate", swap)
+    with pytest.raises(gpu.VxError) as ei:
+        ctx.join_plain(dev(bkey), [dev(bkey)], dev(np.arange(-5, 1005, dtype=np.int64)))
+    assert ei.value.status == gpu.VX_EDUPKEY
+    with pytest.raises(gpu.VxError) as ei:
+        ctx.build(dev(bkey), [dev(bkey)])
+    assert ei.value.status == gpu.VX_EDUPKEY
+
+
+@pytest.mark.parametrize("pays", [(), (np.int32, np.int64), (np.int64, np.int32, np.int32)])
+def test_dense_payload_layouts(gpu, ctx, pays):
+    """Dense tables without payloads and with mixed-width payloads, against the hash layout and the
+    oracle; a key range one short of the rows (the empty-marker key added) is not dense."""
+    rng = np.random.default_rng(61 + len(pays))
+    n, base = 40_000, 3_000_000_000
+    bkey = (rng.permutation(n) + base).astype(np.int64)
+    bp = [rng.integers(np.iinfo(p).min, np.iinfo(p).max, n, dtype=np.int64, endpoint=True).astype(p) for p in pays]
+    pkey = _probes(rng, base, n, 250_007, np.int64)
+    ppay = rng.integers(-2**62, 2**62, len(pkey)).astype(np.int64)
+    exp = oracle.join_agg(bkey, bp, pkey, [ppay])
+    _say("dense payloads", [np.dtype(p).name for p in pays])
+    got_d, st_d = ctx.join_plain(dev(bkey), [dev(x) for x in bp], dev(pkey), [dev(ppay)])
+    got_h, _ = ctx.join_plain(dev(bkey), [dev(x) for x in bp], dev(pkey), [dev(ppay)], hashed=True)
+    assert got_d == exp and got_h == exp
+    assert st_d["table_bytes"] == _dense_bytes(n, pays)
+    # the empty-marker key makes n + 1 rows over an n-wide range: a keyed direct table
+    mk = np.concatenate([bkey, [np.iinfo(np.int64).min]])
+    mp = [np.concatenate([x, x[:1]]) for x in bp]
+    pk2 = np.concatenate([pkey, np.full(9, np.iinfo(np.int64).min)])
+    pp2 = np.concatenate([ppay, ppay[:9]])
+    got, st = ctx.join_plain(dev(mk), [dev(x) for x in mp], dev(pk2), [dev(pp2)])
+    assert got == oracle.join_agg(mk, mp, pk2, [pp2])
+    assert st["table_bytes"] != _dense_bytes(n, pays)
 
 
 def test_direct_preagg(gpu, ctx):

@@ -213,13 +213,44 @@ def test_zero_copy_granules_counted(gpu, pdt):
     try:
         with gpu.Context(1 << 30) as c:
             got, st = c.join_plain(dev(bk), [dev(b0), dev(b1)], hosts[0], hosts[1:], late_mat=gpu.VX_LATE_ZC,
-                                   chunk_rows=1 << 15)
-        assert got == oracle.join_agg(bk, [b0, b1], pk, [p0, p1])
-        assert st["zc_mask"] == 3
+                                   chunk_rows=1 << 15, count_zc=True)
+            got2, st2 = c.join_plain(dev(bk), [dev(b0), dev(b1)], hosts[0], hosts[1:], late_mat=gpu.VX_LATE_ZC,
+                                     chunk_rows=1 << 15)
+        assert got == oracle.join_agg(bk, [b0, b1], pk, [p0, p1]) and got2 == got
+        assert st["zc_mask"] == 3 and st["zc_counted"] == 1 and st2["zc_counted"] == 0
         rows = np.nonzero(np.isin(pk, bk))[0]          # unique build keys: a row matches iff its key is built
         granules = len(np.unique(rows * np.dtype(pdt).itemsize // 128))
         assert 0.05 < len(rows) / np_ < 0.15
         assert st["zc_bytes"] == 2 * 128 * granules
+        # without the count, the wire model's estimate: within 2% of the count at this size
+        assert abs(st2["zc_bytes"] - st["zc_bytes"]) < 0.02 * st["zc_bytes"]
     finally:
         for h in hosts:
             h.free()
+
+
+def test_zero_copy_granules_unaligned_column(gpu):
+    """A payload column that starts 3 elements into its allocation: a granule can then straddle two
+    waves' rows, and each wave counts the granules of its own 64 rows (each wave's gather moves
+    them).  Expected: per block of 64 rows (the waves' rows: chunks are a multiple of 64 rows),
+    the distinct 128-byte granules of its matching rows, at their byte addresses."""
+    nb, np_ = 1 << 12, (1 << 17) + 5
+    bk, b0, b1 = datagen.stream_build(nb, seed=6)
+    pk, p0, _ = datagen.stream_probe(nb, np_, seed=6)
+    kh = pinned(gpu, pk)
+    ph = gpu.HostBuffer(np_ + 3, np.int64)
+    ph.array[3:] = p0
+    _say("zero-copy granules, unaligned column")
+    try:
+        with gpu.Context(1 << 30) as c:
+            got, st = c.join_plain(dev(bk), [dev(b0)], kh, [ph.array[3:]], late_mat=gpu.VX_LATE_ZC,
+                                   chunk_rows=1 << 14, count_zc=True)
+        assert got == oracle.join_agg(bk, [b0], pk, [p0])
+        rows = np.nonzero(np.isin(pk, bk))[0]
+        addr = (3 + rows) * 8                       # byte offset from the allocation (page-aligned)
+        per_wave = np.unique(np.stack([rows // 64, addr // 128]), axis=1).shape[1]
+        assert per_wave > len(np.unique(addr // 128))     # some granules straddle two waves
+        assert st["zc_bytes"] == 128 * per_wave
+    finally:
+        kh.free()
+        ph.free()

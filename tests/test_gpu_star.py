@@ -70,7 +70,7 @@ def test_star_host_streamed_modes(gpu, ctx, late_mat):
     _say("star streamed late_mat", late_mat)
     exp = oracle.star_groupby(dims, fks, meas)
     got = ctx.join_star(_dev_dims(dims), [pinned(gpu, f) for f in fks], [pinned(gpu, m) for m in meas],
-                        late_mat=late_mat, chunk_rows=40_000)
+                        late_mat=late_mat, chunk_rows=40_000, count_zc=late_mat == 1)
     _check(got, exp)
     st = got[3]
     assert st["chunks"] == (500_003 + 39_999) // 40_000
@@ -93,7 +93,7 @@ def test_star_host_streamed_modes(gpu, ctx, late_mat):
             alive &= np.isin(fks[k], passing[k])
         granules += len(meas) * len(np.unique(np.nonzero(alive)[0] * 4 // 128))
         assert st["survivors"] == int(alive.sum())
-        assert st["zc_bytes"] == 128 * granules
+        assert st["zc_counted"] == 1 and st["zc_bytes"] == 128 * granules
 
 
 def test_star_ssb_shape_medium(gpu, ctx):
