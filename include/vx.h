@@ -567,6 +567,35 @@ vx_status vx_cdf_forward(vx_ctx* ctx, const float* x, uint64_t n, const float* p
 vx_status vx_cdf_train(vx_ctx* ctx, const float* x, const float* t, uint64_t n, float* params,
                        uint32_t steps, float lr, double* final_loss);
 
+/* ------------------------------------------------------------------------ no device allocation */
+
+/* Bytes of the fixed device array behind vx_join_plain_noalloc, per GPU. */
+#define VX_NOALLOC_SCRATCH_BYTES (32ull << 20)
+
+/*
+ * For callers that cannot allocate device memory at all, not even a context's arena: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.  The PLAIN join of
+ * vx_join_agg (build a table over the build side, probe it with every probe row, count and sum
+ * the matches) on device-resident columns, with the hash table in a fixed array of the library
+ * (VX_NOALLOC_SCRATCH_BYTES on each GPU the library runs on, held until the process ends)
+ * instead of in an arena.  It needs no context, allocates nothing (no device or host memory, no
+ * stream, no event), and does not synchronize: the work is enqueued on `stream` (a hipStream_t;
+ * NULL for the null stream) on the calling thread's current device, and the call returns.
+ *   b, p: as for VX_JOIN_PLAIN; every column device memory of the current device; the table is
+ *         always hashed (VX_HASHED implied), VX_UNIQUE or VX_PREAGG, load_factor as for vx_build.
+ *   out:  caller-owned device memory of 10 uint64 words, written in stream order:
+ *         out[0] match count, out[1 .. 8] the sums (build payloads, then probe payloads,
+ *         mod 2^64, unused words 0), out[9] error flags: bit 0 a duplicate key in a VX_UNIQUE
+ *         build, bit 1 a full table (neither leaves the aggregates meaningful).
+ * Errors (returned before anything is enqueued): VX_EINVAL for a bad argument or a column that is
+ * not device memory of the current device; VX_EBUDGET when the build side's table (capacity the
+ * next power of two >= n / load_factor, 8-64 B slots) exceeds the array, e.g. more than 2^20
+ * unique int32 rows with one int32 payload at the default load factor; VX_EHIP.
+ * Every call on a GPU shares that GPU's array and keeps the last call's table in it: calls that
+ * overlap on one GPU (other streams, other threads) race and must be ordered by the caller.
+ */
+vx_status vx_join_plain_noalloc(const vx_build_desc* b, const vx_probe_desc* p, void* stream, uint64_t* out);
+
 #ifdef __cplusplus
 }
 #endif

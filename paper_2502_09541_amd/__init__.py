@@ -171,7 +171,7 @@ class PartitionOut(C.Structure):
 EXPORTS = ["vx_ctx_create", "vx_ctx_destroy", "vx_last_error", "vx_ctx_arena_used", "vx_host_alloc",
            "vx_host_free", "vx_build", "vx_table_destroy", "vx_probe_stream", "vx_join_agg",
            "vx_partition", "vx_cdf_loss_grad", "vx_cdf_forward", "vx_cdf_train", "vx_calibrate",
-           "vx_probe_rows", "vx_sort", "vx_merge_cuts"]
+           "vx_probe_rows", "vx_sort", "vx_merge_cuts", "vx_join_plain_noalloc"]
 N_MODEL_PARAMS = 193
 
 
@@ -205,7 +205,8 @@ def lib():
     L.vx_sort.argtypes = [vp, C.POINTER(SortDesc), C.POINTER(Stats)]
     L.vx_merge_cuts.argtypes = [C.POINTER(C.POINTER(C.c_int64)), C.POINTER(C.c_uint64), C.c_uint32, C.c_uint64,
                                 C.POINTER(C.c_uint64)]
-    for name in ("vx_ctx_create", "vx_ctx_destroy", "vx_host_alloc", "vx_host_free", "vx_build",
+    L.vx_join_plain_noalloc.argtypes = [C.POINTER(BuildDesc), C.POINTER(ProbeDesc), vp, vp]
+    for name in ("vx_join_plain_noalloc", "vx_ctx_create", "vx_ctx_destroy", "vx_host_alloc", "vx_host_free", "vx_build",
                  "vx_table_destroy", "vx_probe_stream", "vx_join_agg", "vx_partition",
                  "vx_cdf_loss_grad", "vx_cdf_forward", "vx_cdf_train", "vx_calibrate", "vx_sort",
                  "vx_merge_cuts", "vx_probe_rows"):
@@ -616,3 +617,19 @@ def merge_cuts(runs, rank):
     _check(lib().vx_merge_cuts(ptrs, lens, len(runs), int(rank), cut))
     return np.array([cut[i] for i in range(len(runs))], np.uint64)
 
+
+def join_plain_noalloc(bkey, bpays, pkey, ppays, out, unique=True, load_factor=0.0, stream=None):
+    """vx_join_plain_noalloc: the plain join of device-resident columns with its table in the
+    library's fixed device array; nothing is allocated.  `out` is a caller-owned CUDA tensor of at
+    least 10 int64 (count, 8 sums, error flags), written in the order of `stream` (default: torch's
+    current stream); the call does not wait."""
+    import torch
+    if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.int64 and out.numel() >= 10
+            and out.is_contiguous()):
+        raise ValueError("out must be a contiguous CUDA int64 tensor of at least 10 elements")
+    bp, nbp = _cols(bpays)
+    pp, npp = _cols(ppays)
+    b = BuildDesc(col(bkey), bp, nbp, VX_UNIQUE if unique else VX_PREAGG, _len(bkey), float(load_factor), 0)
+    p = ProbeDesc(col(pkey), pp, npp, VX_LATE_AUTO, _len(pkey), 0, 0, 0, None, 0)
+    s = torch.cuda.current_stream().cuda_stream if stream is None else int(stream)
+    _check(lib().vx_join_plain_noalloc(C.byref(b), C.byref(p), C.c_void_p(s), C.c_void_p(out.data_ptr())))

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 
 #include "vx_device.h"
@@ -1279,3 +1280,151 @@ vx_status vx_join_agg(vx_ctx* ctx, const vx_join_desc* d, vx_join_out* out) {
 
 }  // extern "C"
 
+// ================================================================ no-allocation entry point
+
+namespace vx {
+
+// The device memory of vx_join_plain_noalloc: a fixed array of the library.  Every GPU the library
+// runs on holds its own copy until the process ends.  Host code reaches it only through the address
+// hipGetSymbolAddress returns with that device current: on the host the array's name is a stand-in,
+// not a device address.  Layout: [0, 256) the table's side record, [256, end) its slots.
+static __device__ __align__(256) uint8_t scratch[VX_NOALLOC_SCRATCH_BYTES];
+constexpr uint64_t kNaSlotsOff = 256;
+constexpr int kNaMaxDevices = 64;
+
+struct NoAllocDevice {
+  std::once_flag once;
+  uint8_t* ptr = nullptr;   // device address of `scratch` on this GPU
+  int cu_count = 0;
+  hipError_t err = hipSuccess;
+};
+static NoAllocDevice g_noalloc[kNaMaxDevices];
+
+// Once per device, with that device current: the array's address there, and the CU count.
+static vx_status noalloc_setup(int dev, NoAllocDevice** out) {
+  VX_CHECK(dev >= 0 && dev < kNaMaxDevices, VX_EINVAL, "vx_join_plain_noalloc: device %d", dev);
+  NoAllocDevice& d = g_noalloc[dev];
+  std::call_once(d.once, [&d, dev]() {
+    void* p = nullptr;
+    d.err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (d.err == hipSuccess) d.err = hipDeviceGetAttribute(&d.cu_count, hipDeviceAttributeMultiprocessorCount, dev);
+    d.ptr = (uint8_t*)p;
+  });
+  if (d.err != hipSuccess || d.ptr == nullptr || d.cu_count <= 0) {
+    set_error("vx_join_plain_noalloc: no address for the scratch array on device %d (%s)", dev,
+              hipGetErrorString(d.err));
+    return VX_EHIP;
+  }
+  *out = &d;
+  return VX_OK;
+}
+
+// `p` points to device memory of device `dev` (any pointer when bytes == 0).
+static vx_status noalloc_device_ptr(const void* p, uint64_t bytes, int dev, const char* what) {
+  if (bytes == 0) return VX_OK;
+  VX_CHECK(p != nullptr, VX_EINVAL, "vx_join_plain_noalloc: %s is NULL", what);
+  hipPointerAttribute_t a;
+  std::memset(&a, 0, sizeof a);
+  const hipError_t e = hipPointerGetAttributes(&a, p);
+  if (e != hipSuccess || a.type != hipMemoryTypeDevice || a.device != dev) {
+    (void)hipGetLastError();
+    set_error("vx_join_plain_noalloc: %s must be device memory of device %d", what, dev);
+    return VX_EINVAL;
+  }
+  return VX_OK;
+}
+
+static unsigned grid_cu(int cu, uint64_t work_items, uint64_t per_block, unsigned per_cu) {
+  uint64_t blocks = (work_items + per_block - 1) / per_block;
+  blocks = std::min<uint64_t>(blocks, (uint64_t)cu * per_cu);
+  return (unsigned)std::max<uint64_t>(blocks, 1);
+}
+
+template <typename K>
+static void noalloc_launch(const TableView& v, uint64_t cap, uint32_t slot_bytes, const BuildCols& bc, uint64_t nb,
+                           const ProbeCols& q, int cu, unsigned long long* out, hipStream_t s) {
+  unsigned int* flags = (unsigned int*)(out + 9);
+  const uint64_t quads = cap * slot_bytes / 16;
+  hipLaunchKernelGGL(k_init_slots, dim3(grid_cu(cu, quads, 256, 32)), dim3(256), 0, s, (uint32_t*)v.slots, cap,
+                     slot_bytes / 4, (uint32_t)sizeof(K));
+  if (nb) {
+    if (v.preagg)
+      hipLaunchKernelGGL(k_build_preagg<K>, dim3(grid_cu(cu, nb, kPreaggTile, 3)), dim3(256), 0, s, v, bc, nb, flags);
+    else
+      hipLaunchKernelGGL((k_build_unique_group<K, 8>), dim3(grid_cu(cu, nb, 256, 8)), dim3(256), 0, s, v, bc, nb,
+                         flags);
+  }
+  if (q.n) {
+    if (v.preagg)
+      hipLaunchKernelGGL((k_probe<K, true, 4, kLayoutHash, false>), dim3(grid_cu(cu, q.n, 1024, 8)), dim3(256), 0, s, v, q, out);
+    else
+      hipLaunchKernelGGL((k_probe<K, false, 4, kLayoutHash, false>), dim3(grid_cu(cu, q.n, 1024, 8)), dim3(256), 0, s, v, q, out);
+  }
+}
+
+}  // namespace vx
+
+extern "C" vx_status vx_join_plain_noalloc(const vx_build_desc* b, const vx_probe_desc* p, void* stream,
+                                           uint64_t* out) {
+  using namespace vx;
+  VX_CHECK(b && p && out, VX_EINVAL, "vx_join_plain_noalloc: null argument");
+  const uint32_t kind = b->flags & ~(uint32_t)VX_HASHED;
+  VX_CHECK(kind == VX_UNIQUE || kind == VX_PREAGG, VX_EINVAL,
+           "vx_join_plain_noalloc: flags must be VX_UNIQUE or VX_PREAGG, optionally with VX_HASHED");
+  VX_CHECK(b->n_pay <= kMaxPay && p->n_pay <= kMaxPay && b->n_pay + p->n_pay <= 8, VX_EINVAL,
+           "vx_join_plain_noalloc: at most 4 payloads per side and 8 sums");
+  VX_CHECK((b->n_pay == 0 || b->pay) && (p->n_pay == 0 || p->pay), VX_EINVAL, "vx_join_plain_noalloc: pay is NULL");
+  VX_CHECK(b->key.type == p->key.type, VX_EINVAL, "vx_join_plain_noalloc: key types differ");
+  const int ks = elsize_of(b->key.type);
+  VX_CHECK(ks != 0, VX_EINVAL, "vx_join_plain_noalloc: key type %d is not VX_I32/VX_I64", b->key.type);
+  int dev = 0;
+  VX_HIP(hipGetDevice(&dev));
+  NoAllocDevice* nd = nullptr;
+  VX_TRY(noalloc_setup(dev, &nd));
+  VX_TRY(noalloc_device_ptr(out, 1, dev, "out"));
+  VX_TRY(noalloc_device_ptr(b->key.data, b->n, dev, "build key"));
+  VX_TRY(noalloc_device_ptr(p->key.data, p->n, dev, "probe key"));
+  BuildCols bc{};
+  bc.key = b->key.data;
+  int32_t pt[kMaxPay] = {0, 0, 0, 0};
+  for (uint32_t c = 0; c < b->n_pay; ++c) {
+    const int es = elsize_of(b->pay[c].type);
+    VX_CHECK(es != 0, VX_EINVAL, "vx_join_plain_noalloc: build payload %u type %d", c, b->pay[c].type);
+    VX_TRY(noalloc_device_ptr(b->pay[c].data, b->n, dev, "build payload"));
+    pt[c] = b->pay[c].type;
+    bc.pay[c] = b->pay[c].data;
+    bc.pay_size[c] = (uint32_t)es;
+  }
+  ProbeCols q{};
+  q.key = p->key.data;
+  q.n = p->n;
+  q.n_pay = p->n_pay;
+  for (uint32_t c = 0; c < p->n_pay; ++c) {
+    const int es = elsize_of(p->pay[c].type);
+    VX_CHECK(es != 0, VX_EINVAL, "vx_join_plain_noalloc: probe payload %u type %d", c, p->pay[c].type);
+    VX_TRY(noalloc_device_ptr(p->pay[c].data, p->n, dev, "probe payload"));
+    q.pay[c] = p->pay[c].data;
+    q.pay_size[c] = (uint32_t)es;
+  }
+  // a hash table (the direct layout would need the keys' range read back first)
+  TableView v{};
+  uint64_t cap = 0;
+  uint32_t slot_bytes = 0;
+  VX_TRY(plan_table(b->key.type, kind, pt, b->n_pay, b->n, b->load_factor, nullptr, &v, &cap, &slot_bytes));
+  const uint64_t limit = VX_NOALLOC_SCRATCH_BYTES - kNaSlotsOff;
+  VX_CHECK(cap * slot_bytes <= limit, VX_EBUDGET,
+           "vx_join_plain_noalloc: %llu build rows need a table of %llu slots x %u B = %llu B; the fixed scratch "
+           "array holds %llu B of slots",
+           (unsigned long long)b->n, (unsigned long long)cap, slot_bytes, (unsigned long long)(cap * slot_bytes),
+           (unsigned long long)limit);
+  v.side = (unsigned long long*)nd->ptr;
+  v.slots = nd->ptr + kNaSlotsOff;
+  const hipStream_t s = (hipStream_t)stream;
+  // the aggregate row, the error word and the side record start at zero (fill kernels, no memset)
+  fill_zero(out, 10, s);
+  fill_zero((uint64_t*)nd->ptr, kNaSlotsOff / 8, s);
+  if (ks == 8) noalloc_launch<int64_t>(v, cap, slot_bytes, bc, b->n, q, nd->cu_count, (unsigned long long*)out, s);
+  else noalloc_launch<int32_t>(v, cap, slot_bytes, bc, b->n, q, nd->cu_count, (unsigned long long*)out, s);
+  VX_HIP(hipGetLastError());
+  return VX_OK;
+}
