@@ -585,6 +585,14 @@ def run_plain(args):
     ms_h, res_h = _timed(lambda: ctx.join_plain(hb[0], [hb[1]], hb[2]), args, torch)
     if res_h[0][0] != agg:
         raise SystemExit("host-resident plain join differs from the device-resident one")
+    # the same device-resident join through a hash table (the general layout; the dense table above
+    # is what this recipe's keys allow)
+    ms_x, res_x = _timed(lambda: ctx.join_plain(d[0], [d[1]], d[2], hashed=True), args, torch)
+    if res_x[0][0] != agg:
+        raise SystemExit("hashed plain join differs from the dense one")
+    kx = sum(r[1]["kernel_ms"] for r in res_x) / sum(r[1]["kernel_launches"] for r in res_x)
+    hashed_variant = {"ms_per_step": ms_x, "value": np_ / (ms_x / 1e3), "unit": "probe rows/s",
+                      "probe_kernel_ms": kx, "table_bytes": res_x[0][1]["table_bytes"]}
     link_bytes = nb * 8 + np_ * 4
     host_variant = {"ms_per_step": ms_h, "value": np_ / (ms_h / 1e3), "unit": "probe rows/s",
                     "link_bytes_per_step": link_bytes, "h2d_peak_measured_gbs": cal["h2d_gbs"],
@@ -599,7 +607,8 @@ def run_plain(args):
                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "traffic_profile": PROFILE["k_probe_plain"], "avg_launch_ms": k_ms,
                     "rows_per_launch": np_},
                    {"result": {"match_count": agg[0], "sum": agg[1]}, "checked_against_oracle": True,
-                    "build_ms": st["build_ms"], "probe_ms": st["probe_ms"], "host_resident": host_variant,
+                    "build_ms": st["build_ms"], "probe_ms": st["probe_ms"], "table_bytes": st["table_bytes"],
+                    "hash_table": hashed_variant, "host_resident": host_variant,
                     "cpu_baseline": {"value": np_ / cpu, "unit": "probe rows/s", "cores": 1, "kind": "oracle",
                                      "sample": f"the full workload, build + probe in {cpu:.1f} s on 1 host thread"}})
 
@@ -691,6 +700,13 @@ def run_batch(args):
     ms1, res1 = _timed(lambda: ctx.join_batch(*args3, mode=1), args, torch)
     if res[0][0] != res1[0][0]:
         raise SystemExit("batched and per-job results differ")
+    # the same batch through hash tables (the general layout; these jobs' dense keys allow direct
+    # tables), graph and per-job baseline
+    log("batch: hash tables for every job")
+    ms_h, res_h = _timed(lambda: ctx.join_batch(*args3, mode=0, hashed=True), args, torch)
+    ms_h1, res_h1 = _timed(lambda: ctx.join_batch(*args3, mode=1, hashed=True), args, torch)
+    if res_h[0][0] != res[0][0] or res_h1[0][0] != res[0][0]:
+        raise SystemExit("hashed batch results differ from the direct ones")
     st = res[0][1]
     k_ms = sum(r[1]["kernel_ms"] for r in res) / len(res)
     # algorithmic bytes with the direct tables these dense-key jobs take: a probe reads its 4 B key
@@ -707,7 +723,14 @@ def run_batch(args):
                     "traffic": None, "traffic_profile": PROFILE["batch_graph"], "avg_launch_ms": k_ms, "rows_per_launch": rows},
                    {"baseline_separate_launches": {"ms_per_step": ms1, "value": rows / (ms1 / 1e3),
                                                    "launches": res1[0][1]["kernel_launches"]},
-                    "speedup_vs_separate_launches": ms1 / ms})
+                    "speedup_vs_separate_launches": ms1 / ms,
+                    "hash_tables": {"ms_per_step": ms_h, "value": rows / (ms_h / 1e3),
+                                    "graph_ms": sum(r[1]["kernel_ms"] for r in res_h) / len(res_h),
+                                    "tile_rows": res_h[0][1]["chunk_rows"], "block": res_h[0][1]["n_buffers"],
+                                    "load_factor": res_h[0][1]["imbalance"],
+                                    "baseline_separate_launches_ms": ms_h1,
+                                    "speedup_vs_separate_launches": ms_h1 / ms_h,
+                                    "vs_direct_tables": ms_h / ms}})
 
 
 def run_skew(args):

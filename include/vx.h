@@ -342,7 +342,7 @@ typedef struct {
   uint32_t tile_rows;          /* 0 = autotuned */
   uint32_t block;              /* workgroup size, 0 = autotuned */
   float load_factor;           /* 0 = autotuned */
-  uint32_t reserved;
+  uint32_t flags;              /* 0, or VX_HASHED: hash tables for every job (no direct tables) */
 } vx_batch_join;
 
 typedef enum {

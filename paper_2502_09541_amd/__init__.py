@@ -112,7 +112,7 @@ class BatchJoin(C.Structure):
                 ("build_pay", C.POINTER(Col)), ("n_build", C.POINTER(C.c_uint64)),
                 ("probe_key", C.POINTER(Col)), ("n_probe", C.POINTER(C.c_uint64)),
                 ("out", C.POINTER(Agg)), ("tile_rows", C.c_uint32), ("block", C.c_uint32),
-                ("load_factor", C.c_float), ("reserved", C.c_uint32)]
+                ("load_factor", C.c_float), ("flags", C.c_uint32)]
 
 
 class PartOpts(C.Structure):
@@ -466,7 +466,7 @@ class Context:
         _check(lib().vx_sort(self.h, C.byref(d), C.byref(st)))
         return st.as_dict()
 
-    def join_batch(self, bkeys, bpays, pkeys, mode=0, tile_rows=0, block=0, load_factor=0.0):
+    def join_batch(self, bkeys, bpays, pkeys, mode=0, tile_rows=0, block=0, load_factor=0.0, hashed=False):
         """Batched joins (device-resident). bpays entries may be None. Returns
         ([[count, sum] per job], stats)."""
         J = len(bkeys)
@@ -479,7 +479,7 @@ class Context:
         d = JoinDesc()
         d.kind = VX_JOIN_BATCH
         d.u.batch = BatchJoin(J, int(mode), bk, bp, nb, pk, npr, outs, int(tile_rows), int(block),
-                              float(load_factor), 0)
+                              float(load_factor), VX_HASHED if hashed else 0)
         out = JoinOut()
         self._keep_batch = (bk, bp, pk, nb, npr, outs, list(bkeys), list(bpays), list(pkeys))
         _check(lib().vx_join_agg(self.h, C.byref(d), C.byref(out)))

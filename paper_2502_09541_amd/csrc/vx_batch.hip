@@ -774,7 +774,13 @@ vx_status join_batch(vx_ctx* ctx, const vx_batch_join* d, vx_join_out* out) {
   const uint32_t J = d->n_jobs;
   // which jobs take a direct table depends on the keys' values: measured on every call
   DirectInfo di;
-  VX_TRY(find_direct(ctx, d, ks, &di));
+  VX_CHECK((d->flags & ~(uint32_t)VX_HASHED) == 0, VX_EINVAL, "batch: unknown flags %u", d->flags);
+  if (d->flags & VX_HASHED) {   // every job hashed: no key-range pass
+    di.direct.assign(J, 0);
+    di.kmin.assign(J, 0);
+  } else {
+    VX_TRY(find_direct(ctx, d, ks, &di));
+  }
   const double t_checked = now_ms();
   BatchConfig cfg;
   bool tuned = d->tile_rows == 0 || d->block == 0 || d->load_factor == 0.0f;

@@ -216,3 +216,17 @@ def test_batch_cache_gives_the_arena_back(gpu):
         assert c.arena_used() == base
         got, _ = c.join_batch(*args, tile_rows=4096, block=256, load_factor=0.5)   # graph built again
         assert got == exp
+
+
+def test_batch_hashed_flag(gpu, ctx):
+    """VX_HASHED puts every job in a hash table even when its keys fill their range; graph and
+    per-job baseline agree with the oracle either way."""
+    jobs = _jobs(12, 45)
+    exp = [oracle.join_agg(bk, [bp], pk, []) for bk, bp, pk in jobs]
+    args = ([dev(j[0]) for j in jobs], [dev(j[1]) for j in jobs], [dev(j[2]) for j in jobs])
+    _say("batch hashed flag")
+    for mode in (0, 1):
+        got_h, st_h = ctx.join_batch(*args, mode=mode, hashed=True, tile_rows=2048, block=256, load_factor=0.5)
+        got_d, st_d = ctx.join_batch(*args, mode=mode, tile_rows=2048, block=256, load_factor=0.5)
+        assert got_h == exp and got_d == exp
+        assert st_h["table_bytes"] > st_d["table_bytes"]   # hash slots of 8 B at load 0.5 against 4 B payloads
