@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0       # MI355X HBM3E datasheet peak
 PROFILE = {"k_probe_stream": "profiles/k_probe_streamed_join.md",
            "k_probe_plain": "profiles/k_probe_plain_join.md",
            "k_star": "profiles/k_star_star_join.md",
-           "batch_graph": "profiles/k_batch_phase_batched_joins.md",
+           "batch_graph": "profiles/batch_graph_batched_joins.md",
            "k_pj_stream": "profiles/k_pj_stream_skewed_partitioned_join.md",
            "k_probe_rows": "profiles/k_probe_rows_streamed_join.md",
            "k_rj_probe": "profiles/k_rj_probe_two_table_radix_join.md",
@@ -717,8 +717,9 @@ def run_batch(args):
     ctx.close()
     return _common("probe rows/s", rows / (ms / 1e3), ms, args, "int32",
                    {"workload": "batched_joins_256", "jobs": 256, "probe_rows": rows, "build_rows": int(b.sum()),
-                    "tile_rows": st["chunk_rows"], "block": st["n_buffers"], "load_factor": st["imbalance"]},
-                   {"bound": "hbm", "kernel": "graph(k_batch_phase build, k_batch_dupcount, k_batch_phase probe)", "achieved": alg / (k_ms * 1e6),
+                    "tile_rows": st["chunk_rows"], "block": st["n_buffers"], "load_factor": st["imbalance"],
+                    "partitioned_jobs": st["n_parts"], "jobs_probed_from_lds": st["survivors"]},
+                   {"bound": "hbm", "kernel": "graph(k_batch_phase build, k_batch_dupcount; k_batch_count, k_batch_scan, k_batch_scatter; k_batch_region)", "achieved": alg / (k_ms * 1e6),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg / (k_ms * 1e6) / HBM_PEAK_GBS,
                     "traffic": None, "traffic_profile": PROFILE["batch_graph"], "avg_launch_ms": k_ms, "rows_per_launch": rows},
                    {"baseline_separate_launches": {"ms_per_step": ms1, "value": rows / (ms1 / 1e3),
@@ -728,6 +729,8 @@ def run_batch(args):
                                     "graph_ms": sum(r[1]["kernel_ms"] for r in res_h) / len(res_h),
                                     "tile_rows": res_h[0][1]["chunk_rows"], "block": res_h[0][1]["n_buffers"],
                                     "load_factor": res_h[0][1]["imbalance"],
+                                    "partitioned_jobs": res_h[0][1]["n_parts"],
+                                    "jobs_probed_from_lds": res_h[0][1]["survivors"],
                                     "baseline_separate_launches_ms": ms_h1,
                                     "speedup_vs_separate_launches": ms_h1 / ms_h,
                                     "vs_direct_tables": ms_h / ms}})

@@ -321,14 +321,20 @@ typedef struct {
 /*
  * Batched join: many independent device-resident joins in one call.  A job whose build keys fill
  * their value range exactly (n unique keys from min to min + n - 1, measured on every call) is
- * joined through a direct table indexed by key - min; other jobs through hash tables.  Results
- * do not depend on which.  Errors: VX_EDUPKEY when a job's build keys repeat; VX_EINVAL for
- * host-resident columns, mixed key types or more than 4096 jobs.
+ * joined through a direct table indexed by key - min; other jobs through hash tables, which drop
+ * probe keys outside the build keys' range.  Mode 0 probes tables from LDS: a table of at most
+ * 64 KiB whole, a larger one by regions of 64 KiB, for which the job's probe keys are first
+ * partitioned by region into arena memory (about 4 or 8 bytes per probe row; a job whose buffers
+ * do not fit the arena is probed from device memory instead).  Results do not depend on any of
+ * this.  Mode-0 stats: n_parts = jobs whose probe side was partitioned, survivors = jobs probed
+ * by regions, kernel_launches = kernels in the graph.  Errors: VX_EDUPKEY when a job's build keys
+ * repeat; VX_EINVAL for host-resident columns, mixed key types or more than 4096 jobs.
  */
 typedef struct {
   uint32_t n_jobs;
-  int32_t mode;                /* 0: one HIP graph launch: a build-phase and a probe-phase kernel that
-                                  each drain the tiles of every job; 1: two launches per job.
+  int32_t mode;                /* 0: one HIP graph launch of queue-draining kernels (build phase,
+                                  probe-side partitioning beside it, probe phase); 1: two launches
+                                  per job.
                                   Mode 0 keeps its graph, tables and descriptors in the arena after
                                   the call, for the next mode-0 call with the same jobs
                                   (vx_ctx_arena_used counts them); every other call on the context

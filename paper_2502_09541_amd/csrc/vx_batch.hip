@@ -19,6 +19,18 @@
 // reading them back; a small kernel between the two phases counts each job's bits, and the host
 // compares the count with the job's rows.  A probe key outside the range then costs no memory
 // access, and one inside reads one payload.
+//
+// Random table reads are what bounds the probe: served by the L2 they reach about half of its
+// request rate, and a table larger than one L2 is read from the MALL or HBM.  So the probe phase
+// reads every table from LDS instead.  A table of at most 64 KiB is staged whole by each probe
+// work item.  A larger one is cut into regions of 64 KiB (key - min for a direct table, the top
+// bits of the first slot for a hash table), and the job's probe keys are first partitioned by
+// region into one contiguous array per region: a count pass tallies each super-tile's keys per
+// region, a per-job scan turns the tallies into positions, and a scatter pass moves the keys.  A
+// probe work item then stages its region in LDS and streams its share of the region's keys.
+// Count, scan and scatter run on a second stream beside the build phase.  Keys that cannot match
+// are dropped: outside the range of a direct table, or outside the smallest and largest build
+// key of a hash table (measured with the ranges, on every call).
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -50,9 +62,37 @@ struct BatchJob {
   uint64_t ctile0;        // first bitmap-count tile of the job (direct tables)
   uint32_t build_tiles, probe_tiles, count_tiles;
   unsigned long long* side;   // sentinel-key record: count, payload sum
+  unsigned long long kmax_ord;   // hash: the largest build key (with kmin_ord, the zone a match needs)
+  // probe by regions (n_parts 0: the probe tiles read the job's own keys, tables from memory)
+  uint32_t n_parts;         // table regions: a key's region is (key - min, or first slot) >> part_shift
+  uint32_t part_shift;
+  uint32_t in_place;        // 1: one region, probed from the job's own keys (no partitioning)
+  uint32_t staged;          // 1: a probe work item holds its region of the table in LDS
+  uint32_t ptiles;          // partition tiles of kPartRows probe rows
+  uint32_t stiles;          // super-tiles of kSuperTiles partition tiles
+  uint32_t items_per_region;   // probe work items per region
+  uint64_t cbase;           // the job's tallies: entry cbase + super-tile * n_parts + region
+  uint8_t* pbuf;            // partitioned keys: the regions' arrays, in region order, then 64 sink slots
+  unsigned long long* kept; // keys kept by the partitioning (written by the scan)
 };
 
 constexpr uint32_t kMaxBatchJobs = 4096;
+
+// Device-memory accesses through pointers read from descriptors, as global (not flat) accesses:
+// flat loads also count against the LDS counter, so every LDS wait would wait for them too.
+#define VX_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ T gload(const void* base, uint64_t i) {
+  return ((const VX_GLOBAL T*)base)[i];
+}
+template <typename T>
+__device__ __forceinline__ T gload_nt(const void* base, uint64_t i) {
+  return __builtin_nontemporal_load((const VX_GLOBAL T*)base + i);
+}
+template <typename T>
+__device__ __forceinline__ void gstore(void* base, uint64_t i, T v) {
+  ((VX_GLOBAL T*)base)[i] = v;
+}
 
 template <typename K>
 __device__ __forceinline__ void batch_build_rows(const BatchJob& jb, uint64_t r0, uint64_t r1,
@@ -102,43 +142,49 @@ __device__ __forceinline__ void batch_build_rows(const BatchJob& jb, uint64_t r0
 }
 
 template <typename K>
+__device__ __forceinline__ void probe_key(const BatchJob& jb, K k, uint32_t slot_shift, unsigned long long& cnt,
+                                          unsigned long long& sum) {
+  using U = typename KeyTraits<K>::U;
+  const U kEmpty = KeyTraits<K>::kEmpty;
+  const U kb = (U)k;
+  if (jb.direct) {
+    const uint64_t idx = key_ord(k) - jb.kmin_ord;
+    if (idx < jb.nb) {   // every key of the range is in the table (no duplicates: checked)
+      cnt += 1;
+      if (jb.pay_size == 4) sum += (unsigned long long)(long long)gload<int>(jb.dpay, idx);
+      else if (jb.pay_size == 8) sum += (unsigned long long)gload<long long>(jb.dpay, idx);
+    }
+    return;
+  }
+  const unsigned long long ko = key_ord(k);
+  if (ko < jb.kmin_ord || ko > jb.kmax_ord) return;   // outside the build keys' range: no match
+  if (kb == kEmpty) {
+    const unsigned long long c = gload<unsigned long long>(jb.side, 0);
+    cnt += c;
+    if (c) sum += gload<unsigned long long>(jb.side, 1);
+    return;
+  }
+  uint64_t h = slot_of(key_bits(k), jb.log2cap);
+  for (uint64_t step = 0; step <= jb.mask; ++step) {
+    const uint8_t* slot = jb.slots + (h << slot_shift);
+    const U sk = gload<U>(slot, 0);
+    if (sk == kb) {
+      cnt += 1;
+      if (jb.pay_size == 4) sum += (unsigned long long)(long long)gload<int>(slot + sizeof(K), 0);
+      else if (jb.pay_size == 8) sum += (unsigned long long)gload<long long>(slot + 8, 0);
+      return;
+    }
+    if (sk == kEmpty) return;
+    h = (h + 1) & jb.mask;
+  }
+}
+
+template <typename K>
 __device__ __forceinline__ void batch_probe_rows(const BatchJob& jb, uint64_t r0, uint64_t r1,
                                                  uint32_t slot_shift, unsigned long long& cnt,
                                                  unsigned long long& sum) {
-  using U = typename KeyTraits<K>::U;
-  const U kEmpty = KeyTraits<K>::kEmpty;
-  for (uint64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-    K k = __builtin_nontemporal_load(((const K*)jb.pkey) + i);
-    U kb = (U)k;
-    if (jb.direct) {
-      const uint64_t idx = key_ord(k) - jb.kmin_ord;
-      if (idx < jb.nb) {   // every key of the range is in the table (no duplicates: checked)
-        cnt += 1;
-        if (jb.pay_size == 4) sum += (unsigned long long)(long long)((const int*)jb.dpay)[idx];
-        else if (jb.pay_size == 8) sum += (unsigned long long)((const long long*)jb.dpay)[idx];
-      }
-      continue;
-    }
-    if (kb == kEmpty) {
-      unsigned long long c = jb.side[0];
-      cnt += c;
-      if (c) sum += jb.side[1];
-      continue;
-    }
-    uint64_t h = slot_of(key_bits(k), jb.log2cap);
-    for (uint64_t step = 0; step <= jb.mask; ++step) {
-      const uint8_t* slot = jb.slots + (h << slot_shift);
-      U sk = *(const U*)slot;
-      if (sk == kb) {
-        cnt += 1;
-        if (jb.pay_size == 4) sum += (unsigned long long)(long long)*(const int*)(slot + sizeof(K));
-        else if (jb.pay_size == 8) sum += (unsigned long long)*(const long long*)(slot + 8);
-        break;
-      }
-      if (sk == kEmpty) break;
-      h = (h + 1) & jb.mask;
-    }
-  }
+  for (uint64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x)
+    probe_key<K>(jb, gload_nt<K>(jb.pkey, i), slot_shift, cnt, sum);
 }
 
 __device__ __forceinline__ void block_add2(unsigned long long cnt, unsigned long long sum,
@@ -159,6 +205,362 @@ __device__ __forceinline__ void block_add2(unsigned long long cnt, unsigned long
     unsigned long long s = 0;
     for (int w = 0; w < nw; ++w) s += red[threadIdx.x][w];
     if (s) atomicAdd(out + threadIdx.x, s);
+  }
+}
+
+// ---------------------------------------------------------------- probe-side partitioning
+
+// A work-list entry read by the whole workgroup, made provably uniform, so that the descriptor
+// it names is read with scalar loads and the code that depends on it does not branch per lane.
+__device__ __forceinline__ unsigned long long uniform_entry(const unsigned long long* __restrict__ map, uint64_t i) {
+  const unsigned long long e = map[i];
+  return (unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)e) |
+         ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(e >> 32)) << 32);
+}
+
+// A workgroup barrier that orders LDS only: global stores still in flight are not waited for.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+constexpr uint32_t kPartThreads = 256, kPartItems = 16, kPartRows = kPartThreads * kPartItems;
+constexpr uint32_t kSuperTiles = 16;                 // partition tiles per super-tile (65536 rows)
+constexpr uint32_t kMaxTableParts = 1024;
+constexpr uint32_t kScanBlock = 1024;
+constexpr uint32_t kRegionThreads = 512;
+constexpr uint32_t kStageBytes = 64 << 10;           // LDS for one table region
+constexpr uint32_t kRunUnroll = 4;
+
+// How a job maps probe keys to table regions, read from its descriptor once (scalar registers).
+struct RegionFn {
+  unsigned long long kmin, kmax;
+  uint64_t nb;
+  uint32_t direct, shift, parts, log2cap;
+  __device__ __forceinline__ explicit RegionFn(const BatchJob& jb)
+      : kmin(jb.kmin_ord), kmax(jb.kmax_ord), nb(jb.nb), direct(jb.direct), shift(jb.part_shift),
+        parts(jb.n_parts), log2cap(jb.log2cap) {}
+  // the region of probe key k; `parts` for a key that cannot match
+  template <typename K>
+  __device__ __forceinline__ uint32_t operator()(K k) const {
+    const unsigned long long ko = key_ord(k);
+    if (direct) {
+      const uint64_t idx = ko - kmin;
+      return idx < nb ? (uint32_t)(idx >> shift) : parts;
+    }
+    if (ko < kmin || ko > kmax) return parts;
+    return (uint32_t)(slot_of(key_bits(k), log2cap) >> shift);
+  }
+};
+
+// Tile t's keys, kPartItems per thread: every load is issued (rows past the end reread the last
+// row), so that no load sits behind a branch and waits stay exact.
+template <typename K>
+__device__ __forceinline__ void load_tile(const void* pkey, uint64_t np, uint64_t t, K (&k)[kPartItems]) {
+  const uint64_t r0 = t * kPartRows;
+  const uint32_t last = (uint32_t)(np - r0 < kPartRows ? np - r0 : kPartRows) - 1;
+#pragma unroll
+  for (uint32_t it = 0; it < kPartItems; ++it) {
+    const uint32_t row = it * kPartThreads + threadIdx.x;
+    k[it] = gload_nt<K>(pkey, r0 + (row < last ? row : last));
+  }
+}
+
+// The regions of this thread's keys of tile t (`parts` for a key that cannot match or a row past
+// the end).
+template <typename K>
+__device__ __forceinline__ void tile_regions(const RegionFn& region, uint64_t np, uint64_t t, const K (&k)[kPartItems],
+                                             uint32_t (&r)[kPartItems]) {
+  const uint64_t r0 = t * kPartRows;
+  const uint32_t n = (uint32_t)(np - r0 < kPartRows ? np - r0 : kPartRows);
+#pragma unroll
+  for (uint32_t it = 0; it < kPartItems; ++it) {
+    const uint32_t row = it * kPartThreads + threadIdx.x;
+    r[it] = row < n ? region(k[it]) : region.parts;
+  }
+}
+
+// Count pass (part_map[g] = job << 32 | super-tile): tally[cbase + st n_parts + r] = the
+// super-tile's keys in region r.
+template <typename K>
+__global__ void __launch_bounds__(kPartThreads) k_batch_count(const BatchJob* __restrict__ jobs,
+                                                              const unsigned long long* __restrict__ part_map,
+                                                              uint64_t n_super, uint32_t* __restrict__ tally) {
+  __shared__ uint32_t cnt[kMaxTableParts + 1];   // entry n_parts takes the keys that cannot match
+  for (uint64_t g = blockIdx.x; g < n_super; g += gridDim.x) {
+    const unsigned long long e = uniform_entry(part_map, g);
+    const BatchJob& jb = jobs[e >> 32];
+    const uint64_t st = e & 0xffffffffull;
+    const RegionFn region(jb);
+    const uint32_t P = region.parts;
+    const void* pkey = jb.pkey;
+    const uint64_t np = jb.np, t0 = st * kSuperTiles;
+    const uint64_t t1 = t0 + kSuperTiles < jb.ptiles ? t0 + kSuperTiles : jb.ptiles;
+    for (uint32_t j = threadIdx.x; j <= P; j += kPartThreads) cnt[j] = 0;   // each thread rereads its own entries below
+    lds_barrier();
+    // the waves of the workgroup go through the tiles independently, each reading the next tile
+    // while it counts the current one (the loads land in kn, always one tile ahead)
+    K k[kPartItems], kn[kPartItems];
+    load_tile(pkey, np, t0, kn);
+    for (uint64_t t = t0; t < t1; ++t) {
+#pragma unroll
+      for (uint32_t it = 0; it < kPartItems; ++it) k[it] = kn[it];
+      if (t + 1 < t1) load_tile(pkey, np, t + 1, kn);
+      uint32_t r[kPartItems];
+      tile_regions(region, np, t, k, r);
+#pragma unroll
+      for (uint32_t it = 0; it < kPartItems; ++it) atomicAdd(&cnt[r[it]], 1u);
+    }
+    lds_barrier();
+    for (uint32_t j = threadIdx.x; j < P; j += kPartThreads) tally[jb.cbase + st * P + j] = cnt[j];
+  }
+}
+
+// One workgroup per partitioned job: its tallies become exclusive positions in region-major
+// order (region r's array starts at the position of (super-tile 0, r)), in place, and *kept the
+// job's total.  Thread (g, r) of G = kScanBlock / n_parts groups covers region r over an even
+// share of the super-tiles.
+__global__ void __launch_bounds__(kScanBlock) k_batch_scan(const BatchJob* __restrict__ jobs, uint32_t* __restrict__ tally) {
+  __shared__ uint32_t part[kScanBlock];
+  const BatchJob& jb = jobs[blockIdx.x];
+  if (!jb.n_parts || jb.in_place) return;
+  const uint32_t P = jb.n_parts, G = kScanBlock / P;
+  const uint32_t g = threadIdx.x / P, r = threadIdx.x % P;
+  const bool active = g < G;
+  const uint64_t S = jb.stiles;
+  const uint64_t s0 = S * g / G, s1 = S * (g + 1) / G;
+  uint32_t* c = tally + jb.cbase;
+  uint32_t sum = 0;
+  if (active)
+    for (uint64_t st = s0; st < s1; ++st) sum += c[st * P + r];
+  part[threadIdx.x] = active ? sum : 0u;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (uint32_t rr = 0; rr < P; ++rr)
+      for (uint32_t gg = 0; gg < G; ++gg) {
+        const uint32_t v = part[gg * P + rr];
+        part[gg * P + rr] = run;
+        run += v;
+      }
+    *jb.kept = run;
+  }
+  __syncthreads();
+  if (active) {
+    uint32_t run = part[threadIdx.x];
+    for (uint64_t st = s0; st < s1; ++st) {
+      const uint32_t v = c[st * P + r];
+      c[st * P + r] = run;
+      run += v;
+    }
+  }
+}
+
+// Scatter pass: each kept key of super-tile st to its region's array, at the super-tile's
+// position for the region plus its rank.  Each tile is first sorted by region in LDS (the rank of
+// a key among the tile's keys of its region comes from an LDS counter), then written out in runs,
+// so that neighbouring lanes store neighbouring keys; the order within a region is arbitrary and
+// the aggregates do not depend on it.  Every thread issues kPartItems stores per tile (slots past
+// the tile's kept keys go to a sink past the partitioned keys), and the next tile's loads are
+// issued before them, so that waiting for those loads never waits for the stores.
+template <typename K>
+__global__ void __launch_bounds__(kPartThreads) k_batch_scatter(const BatchJob* __restrict__ jobs,
+                                                                const unsigned long long* __restrict__ part_map,
+                                                                uint64_t n_super, const uint32_t* __restrict__ pos) {
+  __shared__ uint32_t next[kMaxTableParts + 1], cnt[kMaxTableParts + 1], off[kMaxTableParts + 1];
+  __shared__ K stage[kPartRows];
+  __shared__ uint16_t sreg[kPartRows];
+  const uint32_t lane = threadIdx.x & 63;
+  for (uint64_t g = blockIdx.x; g < n_super; g += gridDim.x) {
+    const unsigned long long e = uniform_entry(part_map, g);
+    const BatchJob& jb = jobs[e >> 32];
+    const uint64_t st = e & 0xffffffffull;
+    const RegionFn region(jb);
+    const uint32_t P = region.parts;
+    const void* pkey = jb.pkey;
+    void* const dst = jb.pbuf;
+    const uint64_t np = jb.np, t0 = st * kSuperTiles, sink = np + lane;
+    const uint64_t t1 = t0 + kSuperTiles < jb.ptiles ? t0 + kSuperTiles : jb.ptiles;
+    for (uint32_t j = threadIdx.x; j <= P; j += kPartThreads) {
+      next[j] = j < P ? pos[jb.cbase + st * P + j] : 0u;
+      cnt[j] = 0;
+    }
+    K k[kPartItems], kn[kPartItems];
+    load_tile(pkey, np, t0, kn);
+    lds_barrier();
+    for (uint64_t t = t0; t < t1; ++t) {
+#pragma unroll
+      for (uint32_t it = 0; it < kPartItems; ++it) k[it] = kn[it];
+      uint32_t r[kPartItems], rank[kPartItems];
+      tile_regions(region, np, t, k, r);
+#pragma unroll
+      for (uint32_t it = 0; it < kPartItems; ++it) rank[it] = atomicAdd(&cnt[r[it]], 1u);
+      lds_barrier();
+      if (threadIdx.x < 64) {   // exclusive scan of cnt[0 .. P) into off; off[P] = the tile's kept keys
+        constexpr uint32_t per = (kMaxTableParts + 63) / 64;
+        uint32_t v[per], own = 0;
+#pragma unroll
+        for (uint32_t u = 0; u < per; ++u) {
+          const uint32_t j = per * lane + u;
+          v[u] = j < P ? cnt[j] : 0u;
+          own += v[u];
+        }
+        uint32_t incl = own;
+#pragma unroll
+        for (uint32_t o = 1; o < 64; o <<= 1) {
+          const uint32_t y = __shfl_up(incl, o, 64);
+          if (lane >= o) incl += y;
+        }
+        uint32_t run = incl - own;
+#pragma unroll
+        for (uint32_t u = 0; u < per; ++u) {
+          const uint32_t j = per * lane + u;
+          if (j < P) off[j] = run;
+          run += v[u];
+        }
+        if (lane == 63) off[P] = incl;
+      }
+      lds_barrier();
+#pragma unroll
+      for (uint32_t it = 0; it < kPartItems; ++it)
+        if (r[it] < P) {
+          const uint32_t slot = off[r[it]] + rank[it];
+          stage[slot] = k[it];
+          sreg[slot] = (uint16_t)r[it];
+        }
+      if (t + 1 < t1) load_tile(pkey, np, t + 1, kn);
+      lds_barrier();
+      const uint32_t total = off[P];
+#pragma unroll
+      for (uint32_t it = 0; it < kPartItems; ++it) {
+        const uint32_t i = it * kPartThreads + threadIdx.x;
+        const uint32_t rr = i < total ? (uint32_t)sreg[i] : 0u;
+        const uint64_t at = i < total ? (uint64_t)(next[rr] + (i - off[rr])) : sink;
+        gstore<K>(dst, at, stage[i]);
+      }
+      lds_barrier();
+#pragma unroll
+      for (uint32_t u = 0; u < (kMaxTableParts + kPartThreads) / kPartThreads; ++u) {   // straight-line: keeps waits exact
+        const uint32_t j = u * kPartThreads + threadIdx.x;
+        if (j < P) next[j] += cnt[j];
+        if (j <= P) cnt[j] = 0;
+      }
+      lds_barrier();
+    }
+  }
+}
+
+// Probe of one key against a table region staged in LDS (stage: region p of the job's table;
+// hash chains that leave the region continue in device memory).
+template <typename K>
+__device__ __forceinline__ void probe_staged(const BatchJob& jb, K k, uint32_t p, const uint8_t* stage,
+                                             uint32_t slot_shift, unsigned long long& cnt, unsigned long long& sum) {
+  using U = typename KeyTraits<K>::U;
+  const U kEmpty = KeyTraits<K>::kEmpty;
+  const U kb = (U)k;
+  const unsigned long long ko = key_ord(k);
+  if (jb.direct) {
+    const uint64_t idx = ko - jb.kmin_ord;
+    if (idx < jb.nb) {
+      cnt += 1;
+      const uint32_t o = (uint32_t)(idx - ((uint64_t)p << jb.part_shift));
+      if (jb.pay_size == 4) sum += (unsigned long long)(long long)((const int*)stage)[o];
+      else if (jb.pay_size == 8) sum += (unsigned long long)((const long long*)stage)[o];
+    }
+    return;
+  }
+  if (ko < jb.kmin_ord || ko > jb.kmax_ord) return;
+  if (kb == kEmpty) {
+    const unsigned long long c = gload<unsigned long long>(jb.side, 0);
+    cnt += c;
+    if (c) sum += gload<unsigned long long>(jb.side, 1);
+    return;
+  }
+  const uint64_t base = (uint64_t)p << jb.part_shift, window = 1ull << jb.part_shift;
+  uint64_t h = slot_of(key_bits(k), jb.log2cap);
+  for (uint64_t step = 0; step <= jb.mask; ++step) {
+    const uint64_t off = (h - base) & jb.mask;
+    U sk;
+    long long v = 0;
+    if (off < window) {   // the staged region
+      const uint8_t* slot = stage + (off << slot_shift);
+      sk = *(const U*)slot;
+      if (sk == kb) v = jb.pay_size == 4 ? (long long)*(const int*)(slot + sizeof(K))
+                                         : jb.pay_size == 8 ? *(const long long*)(slot + 8) : 0;
+    } else {              // a chain that left the region
+      const uint8_t* slot = jb.slots + (h << slot_shift);
+      sk = gload<U>(slot, 0);
+      if (sk == kb) v = jb.pay_size == 4 ? (long long)gload<int>(slot + sizeof(K), 0)
+                                         : jb.pay_size == 8 ? gload<long long>(slot + 8, 0) : 0;
+    }
+    if (sk == kb) {
+      cnt += 1;
+      sum += (unsigned long long)v;
+      return;
+    }
+    if (sk == kEmpty) return;
+    h = (h + 1) & jb.mask;
+  }
+}
+
+// Region probe (region_map[t] = job << 44 | region << 32 | item, ~0 for none): item `item` of
+// region p takes an even share of the region's keys; with its region staged in LDS when the job's
+// regions fit kStageBytes.
+template <typename K>
+__global__ void __launch_bounds__(kRegionThreads) k_batch_region(const BatchJob* __restrict__ jobs,
+                                                                 const unsigned long long* __restrict__ region_map,
+                                                                 uint64_t n_items, uint32_t slot_shift,
+                                                                 const uint32_t* __restrict__ pos,
+                                                                 unsigned long long* __restrict__ acc) {
+  __shared__ __attribute__((aligned(16))) uint8_t stage[kStageBytes];
+  for (uint64_t t = blockIdx.x; t < n_items; t += gridDim.x) {
+    const unsigned long long e = uniform_entry(region_map, t);
+    if (e == ~0ull) continue;   // uniform over the workgroup
+    const uint32_t lo = (uint32_t)(e >> 44) & 0xfffu, p = (uint32_t)(e >> 32) & 0xfffu, item = (uint32_t)e;
+    const BatchJob& jb = jobs[lo];
+    uint64_t start = 0, end = jb.np;
+    const void* keys = jb.pkey;
+    if (!jb.in_place) {
+      start = pos[jb.cbase + p];
+      end = p + 1 < jb.n_parts ? pos[jb.cbase + p + 1] : gload<unsigned long long>(jb.kept, 0);
+      keys = jb.pbuf;
+    }
+    const uint64_t size = end - start, n = jb.items_per_region;
+    const uint64_t q0 = start + size * item / n, q1 = start + size * (item + 1) / n;
+    unsigned long long cnt = 0, sum = 0;
+    if (jb.staged) {
+      // region p of the table: direct payloads of keys min + [p 2^s, (p + 1) 2^s), or hash slots
+      // [p 2^s, (p + 1) 2^s), cut at the table's end
+      const uint64_t entry = jb.direct ? jb.pay_size : (1ull << slot_shift);
+      const uint64_t entries = jb.direct ? jb.nb : jb.mask + 1;
+      const uint64_t first = (uint64_t)p << jb.part_shift;
+      const uint64_t count = (first + (1ull << jb.part_shift) < entries ? (1ull << jb.part_shift) : entries - first);
+      const uint8_t* src = (jb.direct ? jb.dpay : jb.slots) + first * entry;
+      const uint32_t words = (uint32_t)(count * entry / 4);
+      for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) ((uint32_t*)stage)[w] = gload<uint32_t>(src, w);
+      __syncthreads();
+      for (uint64_t q = q0 + threadIdx.x; q < q1; q += (uint64_t)blockDim.x * kRunUnroll) {
+        K k[kRunUnroll];
+#pragma unroll
+        for (uint32_t u = 0; u < kRunUnroll; ++u)
+          k[u] = q + u * blockDim.x < q1 ? gload_nt<K>(keys, q + u * blockDim.x) : K(0);
+#pragma unroll
+        for (uint32_t u = 0; u < kRunUnroll; ++u)
+          if (q + u * blockDim.x < q1) probe_staged<K>(jb, k[u], p, stage, slot_shift, cnt, sum);
+      }
+    } else {
+      for (uint64_t q = q0 + threadIdx.x; q < q1; q += (uint64_t)blockDim.x * kRunUnroll) {
+        K k[kRunUnroll];
+#pragma unroll
+        for (uint32_t u = 0; u < kRunUnroll; ++u)
+          k[u] = q + u * blockDim.x < q1 ? gload_nt<K>(keys, q + u * blockDim.x) : K(0);
+#pragma unroll
+        for (uint32_t u = 0; u < kRunUnroll; ++u)
+          if (q + u * blockDim.x < q1) probe_key<K>(jb, k[u], slot_shift, cnt, sum);
+      }
+    }
+    block_add2(cnt, sum, acc + 2 * lo);   // its barriers also keep the next item's staging behind these reads
   }
 }
 
@@ -334,14 +736,21 @@ struct BatchPlan {
   std::vector<unsigned long long> build_map, probe_map;
   uint64_t direct_bytes = 0;       // bitmaps and payloads of the direct-table jobs (after them)
   uint32_t slot_shift = 3;
+  // probe by regions: the region kernel's work items (kXcds interleaved lists, like the tile
+  // maps), the partitioning passes' super-tiles (job << 32 | super-tile), and the bytes of the
+  // partitioned keys, tallies and kept totals (a block of their own)
+  std::vector<unsigned long long> region_map, part_map;
+  uint64_t part_bytes = 0;
+  uint64_t pkey_bytes = 0, tally_entries = 0;
+  uint32_t part_jobs = 0, region_jobs = 0;
 };
 
 // Which jobs get a direct table: per caller's job, direct[j] and the smallest key kmin[j]
 // (order-preserving unsigned form).
 struct DirectInfo {
   std::vector<uint8_t> direct;
-  std::vector<unsigned long long> kmin;
-  bool operator==(const DirectInfo& o) const { return direct == o.direct && kmin == o.kmin; }
+  std::vector<unsigned long long> kmin, kmax;
+  bool operator==(const DirectInfo& o) const { return direct == o.direct && kmin == o.kmin && kmax == o.kmax; }
 };
 
 uint64_t align256(uint64_t v) { return (v + 255) / 256 * 256; }
@@ -351,7 +760,8 @@ uint64_t direct_region_bytes(uint64_t nb, uint32_t ps) {
 }
 
 // Min and max build key of every job in one launch; a job is direct when its nb keys could be
-// exactly the nb values from its min to its max.
+// exactly the nb values from its min to its max.  Hash-table jobs use the range to drop probe
+// keys that cannot match.
 static vx_status find_direct(vx_ctx* ctx, const vx_batch_join* d, int ks, DirectInfo* di) {
   const uint32_t J = d->n_jobs;
   const uint32_t tile_rows = 65536;
@@ -364,7 +774,8 @@ static vx_status find_direct(vx_ctx* ctx, const vx_batch_join* d, int ks, Direct
     tiles += (d->n_build[j] + tile_rows - 1) / tile_rows;
   }
   di->direct.assign(J, 0);
-  di->kmin.assign(J, 0);
+  di->kmin.assign(J, ~0ull);   // no build keys: an empty range
+  di->kmax.assign(J, 0);
   if (!tiles) return VX_OK;
   ArenaBlock blk;
   blk.a = &ctx->arena;
@@ -390,42 +801,70 @@ static vx_status find_direct(vx_ctx* ctx, const vx_batch_join* d, int ks, Direct
     const unsigned long long mn = h[2 * j], mx = h[2 * j + 1];
     di->direct[j] = nb >= 1 && mx >= mn && mx - mn == nb - 1;
     di->kmin[j] = mn;
+    di->kmax[j] = mx;
   }
   return VX_OK;
 }
 
 constexpr uint32_t kXcds = 8;   // accelerator complex dies of the MI355X, each with its own L2
 
-// The XCD-aware tile maps.  A job whose table fits in 3/4 of one XCD's L2 gets all of its tiles
-// on one XCD (jobs spread over the XCDs longest probe side first, balancing probe tiles), so its
-// table is built and read in that L2 only.  Larger jobs spread their tiles over every XCD in
-// turn and come first in every list.
+// The XCD-aware maps.  Work on one table stays on one XCD where the table can stay in that XCD's
+// L2: a job probed through the tile map whose table fits in 3/4 of an L2 gets all of its tiles
+// there, and each table region of a job probed by regions gets all of its work items on one XCD
+// (with the job's build tiles, when the whole table fits).  Such units spread over the XCDs
+// largest first, balancing entries; the build tiles of larger tables, and all tiles of a larger
+// job probed through the tile map, spread over every XCD in turn and come first in every list.
+static uint64_t table_bytes_of(const BatchJob& b, uint32_t slot_bytes) {
+  return b.direct ? b.nb * (uint64_t)b.pay_size : (b.mask + 1) * (uint64_t)slot_bytes;
+}
+
 static void map_tiles(BatchPlan* pl, uint32_t slot_bytes, uint64_t l2_bytes) {
   const uint32_t J = (uint32_t)pl->jobs.size();
-  std::vector<std::vector<unsigned long long>> bl(kXcds), pr(kXcds);
-  std::vector<uint32_t> small;
-  uint32_t rb = 0, rp = 0;
-  auto tiles = [](std::vector<unsigned long long>& l, uint32_t i, uint32_t n) {
-    for (uint32_t k = 0; k < n; ++k) l.push_back(((unsigned long long)i << 32) | k);
+  std::vector<std::vector<unsigned long long>> bl(kXcds), pr(kXcds), rl(kXcds);
+  struct Unit {
+    uint32_t job, region;   // region ~0: a whole job through the tile map
+    uint64_t entries;
   };
+  std::vector<Unit> units, regions;
+  uint32_t rb = 0, rp = 0;
   for (uint32_t i = 0; i < J; ++i) {
     const BatchJob& b = pl->jobs[i];
-    const uint64_t table = b.direct ? b.nb * (uint64_t)b.pay_size : (b.mask + 1) * (uint64_t)slot_bytes;
-    if (table <= l2_bytes / 4 * 3) {
-      small.push_back(i);
+    const bool local = table_bytes_of(b, slot_bytes) <= l2_bytes / 4 * 3;
+    if (b.n_parts) {
+      for (uint32_t p = 0; p < b.n_parts; ++p) regions.push_back({i, p, b.items_per_region});
+      if (!local)
+        for (uint32_t k = 0; k < b.build_tiles; ++k) bl[rb++ % kXcds].push_back(((unsigned long long)i << 32) | k);
+      continue;
+    }
+    if (local) {
+      units.push_back({i, ~0u, b.probe_tiles});
       continue;
     }
     for (uint32_t k = 0; k < b.build_tiles; ++k) bl[rb++ % kXcds].push_back(((unsigned long long)i << 32) | k);
     for (uint32_t k = 0; k < b.probe_tiles; ++k) pr[rp++ % kXcds].push_back(((unsigned long long)i << 32) | k);
   }
-  std::stable_sort(small.begin(), small.end(),
-                   [&](uint32_t a, uint32_t b) { return pl->jobs[a].probe_tiles > pl->jobs[b].probe_tiles; });
-  for (uint32_t i : small) {
+  auto by_size = [](const Unit& a, const Unit& b) { return a.entries > b.entries; };
+  auto least = [](const std::vector<std::vector<unsigned long long>>& l) {
     uint32_t x = 0;
     for (uint32_t y = 1; y < kXcds; ++y)
-      if (pr[y].size() < pr[x].size()) x = y;
-    tiles(bl[x], i, pl->jobs[i].build_tiles);
-    tiles(pr[x], i, pl->jobs[i].probe_tiles);
+      if (l[y].size() < l[x].size()) x = y;
+    return x;
+  };
+  std::stable_sort(units.begin(), units.end(), by_size);
+  for (const Unit& u : units) {
+    const uint32_t x = least(pr);
+    const BatchJob& b = pl->jobs[u.job];
+    for (uint32_t k = 0; k < b.build_tiles; ++k) bl[x].push_back(((unsigned long long)u.job << 32) | k);
+    for (uint32_t k = 0; k < b.probe_tiles; ++k) pr[x].push_back(((unsigned long long)u.job << 32) | k);
+  }
+  std::stable_sort(regions.begin(), regions.end(), by_size);
+  for (const Unit& u : regions) {
+    const uint32_t x = least(rl);
+    const BatchJob& b = pl->jobs[u.job];
+    if (u.region == 0 && table_bytes_of(b, slot_bytes) <= l2_bytes / 4 * 3)
+      for (uint32_t k = 0; k < b.build_tiles; ++k) bl[x].push_back(((unsigned long long)u.job << 32) | k);
+    for (uint64_t k = 0; k < u.entries; ++k)
+      rl[x].push_back(((unsigned long long)u.job << 44) | ((unsigned long long)u.region << 32) | k);
   }
   auto flatten = [](const std::vector<std::vector<unsigned long long>>& lists, std::vector<unsigned long long>* out) {
     size_t len = 0;
@@ -436,10 +875,82 @@ static void map_tiles(BatchPlan* pl, uint32_t slot_bytes, uint64_t l2_bytes) {
   };
   flatten(bl, &pl->build_map);
   flatten(pr, &pl->probe_map);
+  flatten(rl, &pl->region_map);
+}
+
+// Which jobs are probed by regions, and how.  A table of at most `stage` bytes is one region probed
+// from the job's own keys.  A larger one is cut into regions of `stage` bytes (at most
+// kMaxTableParts; beyond that the regions grow and are read from device memory) and its probe
+// side partitioned, largest probe sides first while the buffers fit part_budget bytes; a job left
+// over, or one of 2^32 probe rows or more, goes through the tile map.  Offsets in the jobs are
+// relative to the partition block until setup_run relocates them.
+static void plan_regions(BatchPlan* pl, int ks, uint32_t slot_bytes, uint64_t part_budget, uint64_t stage) {
+  pl->part_map.clear();
+  pl->part_bytes = pl->pkey_bytes = pl->tally_entries = 0;
+  pl->part_jobs = pl->region_jobs = 0;
+  const uint32_t J = (uint32_t)pl->jobs.size();
+  const uint64_t item_keys = 65536;
+  for (uint32_t i = 0; i < J; ++i) {
+    BatchJob& b = pl->jobs[i];
+    const uint64_t table = table_bytes_of(b, slot_bytes);
+    if (table <= stage) {
+      b.n_parts = 1;
+      b.in_place = 1;
+      b.staged = 1;
+      uint32_t sh = 0;
+      if (b.direct)
+        while ((1ull << sh) < b.nb) ++sh;
+      else
+        sh = b.log2cap;
+      b.part_shift = sh;
+      b.items_per_region = (uint32_t)std::max<uint64_t>(1, (b.np + item_keys - 1) / item_keys);
+      ++pl->region_jobs;
+      continue;
+    }
+    if (b.np == 0 || b.np >= (1ull << 32)) continue;
+    uint32_t parts, shift;
+    bool staged;
+    if (b.direct) {
+      shift = 0;
+      while ((2ull << shift) * b.pay_size <= stage) ++shift;
+      while (((b.nb - 1) >> shift) + 1 > kMaxTableParts) ++shift;
+      parts = (uint32_t)(((b.nb - 1) >> shift) + 1);
+      staged = (1ull << shift) * b.pay_size <= stage;
+    } else {
+      uint32_t bits = 0;
+      const uint32_t max_bits = 10;   // kMaxTableParts regions
+      while ((table >> bits) > stage && bits < max_bits && bits < b.log2cap) ++bits;
+      parts = 1u << bits;
+      shift = b.log2cap - bits;
+      staged = (table >> bits) <= stage;
+    }
+    const uint64_t ptiles = (b.np + kPartRows - 1) / kPartRows;
+    const uint64_t stiles = (ptiles + kSuperTiles - 1) / kSuperTiles;
+    const uint64_t keys = align256((b.np + 64) * (uint64_t)ks), tallies = stiles * parts;   // + the sink slots
+    const uint64_t need = keys + tallies * 4 + 256 + 8;
+    if (pl->part_bytes + need > part_budget) continue;
+    b.n_parts = parts;
+    b.part_shift = shift;
+    b.staged = staged;
+    b.ptiles = (uint32_t)ptiles;
+    b.stiles = (uint32_t)stiles;
+    b.items_per_region = (uint32_t)std::max<uint64_t>(1, (b.np / parts + item_keys - 1) / item_keys);
+    b.pbuf = (uint8_t*)(uintptr_t)pl->pkey_bytes;
+    b.cbase = pl->tally_entries;
+    b.kept = (unsigned long long*)(uintptr_t)(8ull * pl->part_jobs);   // index into the kept totals
+    pl->pkey_bytes += keys;
+    pl->tally_entries += tallies;
+    pl->part_bytes += need;
+    ++pl->part_jobs;
+    ++pl->region_jobs;
+    for (uint64_t t = 0; t < stiles; ++t) pl->part_map.push_back(((unsigned long long)i << 32) | t);
+  }
+  pl->part_bytes = pl->pkey_bytes + align256(pl->tally_entries * 4) + align256(8ull * pl->part_jobs);
 }
 
 static vx_status plan_batch(const vx_batch_join* d, const BatchConfig& cfg, int ks, uint32_t ps,
-                            const DirectInfo& di, uint64_t l2_bytes, BatchPlan* pl) {
+                            const DirectInfo& di, uint64_t l2_bytes, bool regions, uint64_t part_budget,
+                            uint64_t stage, BatchPlan* pl) {
   const uint32_t J = d->n_jobs;
   pl->jobs.resize(J);
   pl->job_of.resize(J);
@@ -462,10 +973,11 @@ static vx_status plan_batch(const vx_batch_join* d, const BatchConfig& cfg, int 
     b.nb = d->n_build[j];
     b.np = d->n_probe[j];
     b.pay_size = b.bpay ? (uint32_t)ps : 0;
+    b.kmin_ord = di.kmin[j];
+    b.kmax_ord = di.kmax[j];
     if (di.direct[j]) {
       // offsets are relocated once memory is carved: direct regions follow the hash slots
       b.direct = 1;
-      b.kmin_ord = di.kmin[j];
       b.slots = (uint8_t*)(uintptr_t)dbytes;
       dbytes += direct_region_bytes(b.nb, b.pay_size);
     } else {
@@ -492,6 +1004,7 @@ static vx_status plan_batch(const vx_batch_join* d, const BatchConfig& cfg, int 
   pl->total_tiles = bt + pt;
   pl->slots = slots;
   pl->direct_bytes = dbytes;
+  if (regions) plan_regions(pl, ks, slot_bytes, part_budget, stage);
   map_tiles(pl, slot_bytes, l2_bytes);
   return VX_OK;
 }
@@ -505,53 +1018,104 @@ struct BatchRun {
   unsigned long long* bits = nullptr;        // per job (tile order): bits set in its direct bitmap
   unsigned long long* probe_map = nullptr;   // the plan's tile maps, in device memory
   unsigned long long* build_map = nullptr;
+  unsigned long long* region_map = nullptr;  // the region probe's work items
+  unsigned long long* part_map = nullptr;    // the partitioning passes' super-tiles
+  uint32_t* tally = nullptr;                 // per partitioned job and super-tile: keys per region, then positions
   uint8_t* slots = nullptr;
   uint64_t counter_words = 0;
 };
 
+// Probe by regions unless VX_BATCH_REGIONS=0; VX_BATCH_STAGE_KB (at most 64) lowers the size of a
+// region staged in LDS, so that small inputs exercise every path.
+static bool regions_enabled() {
+  const char* e = getenv("VX_BATCH_REGIONS");
+  return !(e && e[0] == '0');
+}
+
+static uint64_t stage_bytes() {
+  const char* e = getenv("VX_BATCH_STAGE_KB");
+  const uint64_t v = e ? strtoull(e, nullptr, 10) << 10 : kStageBytes;
+  return std::max<uint64_t>(256, std::min<uint64_t>(v, kStageBytes));
+}
+
+// Device bytes of a run's one arena block: tables, descriptors, counters, maps, then the
+// partition block.
+static uint64_t run_bytes(const BatchPlan& pl, uint32_t J, uint64_t counter_words) {
+  return align256(pl.slots << pl.slot_shift) + align256(pl.direct_bytes) + align256((uint64_t)J * sizeof(BatchJob)) +
+         align256(counter_words * 8) + align256(pl.probe_map.size() * 8) + align256(pl.build_map.size() * 8) +
+         align256(pl.region_map.size() * 8) + align256(pl.part_map.size() * 8) + pl.part_bytes;
+}
+
 static vx_status setup_run(vx_ctx* ctx, const vx_batch_join* d, const BatchConfig& cfg, int ks,
-                           uint32_t ps, const DirectInfo& di, BatchRun* r) {
-  VX_TRY(plan_batch(d, cfg, ks, ps, di, ctx->l2_bytes, &r->plan));
+                           uint32_t ps, const DirectInfo& di, BatchRun* r, bool regions = true) {
   const uint32_t J = d->n_jobs;
-  const uint64_t hash_bytes = align256(r->plan.slots << r->plan.slot_shift);
-  uint64_t slot_bytes = hash_bytes + r->plan.direct_bytes;
-  uint64_t side_bytes = (uint64_t)J * 16;
-  uint64_t desc_bytes = (uint64_t)J * sizeof(BatchJob);
   // side records and accumulators are contiguous so one fill kernel clears them
   r->counter_words = 2 * (uint64_t)J + 2 * (uint64_t)J + (uint64_t)J;
-  const uint64_t bmap_bytes = r->plan.build_map.size() * 8, map_bytes = r->plan.probe_map.size() * 8;
-  uint64_t bytes = slot_bytes + 256 + desc_bytes + 256 + r->counter_words * 8 + 256 + map_bytes + 256 + bmap_bytes + 256;
+  regions = regions && regions_enabled();
+  const uint64_t stage = stage_bytes();
+  VX_TRY(plan_batch(d, cfg, ks, ps, di, ctx->l2_bytes, regions, 0, stage, &r->plan));
+  const uint64_t base = run_bytes(r->plan, J, r->counter_words), room = ctx->arena.largest_free();
+  const char* part_env = getenv("VX_BATCH_PARTITION");   // 0: no probe side is partitioned
+  if (regions && !(part_env && part_env[0] == '0') && room > base + (64ull << 20)) {
+    // a plan that partitions large probe sides; the margin covers its maps
+    BatchPlan pp;
+    VX_TRY(plan_batch(d, cfg, ks, ps, di, ctx->l2_bytes, true, room - base - (64ull << 20), stage, &pp));
+    if (pp.part_jobs && run_bytes(pp, J, r->counter_words) <= room) r->plan = std::move(pp);
+  }
+  const BatchPlan& pl = r->plan;
+  const uint64_t hash_bytes = align256(pl.slots << pl.slot_shift);
+  const uint64_t slot_bytes = hash_bytes + align256(pl.direct_bytes);
+  const uint64_t desc_bytes = (uint64_t)J * sizeof(BatchJob);
+  const uint64_t map_bytes = pl.probe_map.size() * 8, bmap_bytes = pl.build_map.size() * 8;
+  const uint64_t rmap_bytes = pl.region_map.size() * 8, pmap_bytes = pl.part_map.size() * 8;
+  const uint64_t bytes = run_bytes(pl, J, r->counter_words);
   r->mem.a = &ctx->arena;
   r->mem.p = ctx->arena.alloc(bytes);
   VX_CHECK(r->mem.p, VX_EBUDGET, "batch: %llu bytes of tables and descriptors do not fit the arena",
            (unsigned long long)bytes);
   r->slots = r->mem.p;
-  uint8_t* q = r->mem.p + ((slot_bytes + 255) / 256) * 256;
+  uint8_t* q = r->mem.p + slot_bytes;
   r->jobs_dev = (BatchJob*)q;
-  q += ((desc_bytes + 255) / 256) * 256;
+  q += align256(desc_bytes);
   r->counters = (unsigned long long*)q;
   unsigned long long* sides = r->counters;
   r->acc = sides + 2 * (uint64_t)J;
   r->bits = r->acc + 2 * (uint64_t)J;
-  r->probe_map = (unsigned long long*)(q + align256(r->counter_words * 8));
-  r->build_map = (unsigned long long*)((uint8_t*)r->probe_map + align256(map_bytes));
-  (void)side_bytes;
+  q += align256(r->counter_words * 8);
+  r->probe_map = (unsigned long long*)q;
+  q += align256(map_bytes);
+  r->build_map = (unsigned long long*)q;
+  q += align256(bmap_bytes);
+  r->region_map = (unsigned long long*)q;
+  q += align256(rmap_bytes);
+  r->part_map = (unsigned long long*)q;
+  q += align256(pmap_bytes);
+  uint8_t* part_block = q;
+  r->tally = (uint32_t*)(part_block + pl.pkey_bytes);
   for (uint32_t j = 0; j < J; ++j) {
     BatchJob& b = r->plan.jobs[j];
     if (b.direct) {
       b.slots = r->slots + hash_bytes + (uint64_t)(uintptr_t)b.slots;
       b.dpay = b.slots + align256((b.nb + 63) / 64 * 8);
     } else {
-      b.slots = r->slots + (((uint64_t)(uintptr_t)b.slots) << r->plan.slot_shift);
+      b.slots = r->slots + (((uint64_t)(uintptr_t)b.slots) << pl.slot_shift);
     }
     b.side = sides + 2 * (uint64_t)j;
+    if (b.n_parts && !b.in_place) {
+      b.pbuf = part_block + (uint64_t)(uintptr_t)b.pbuf;
+      b.kept = (unsigned long long*)(part_block + pl.pkey_bytes + align256(pl.tally_entries * 4) +
+                                     (uint64_t)(uintptr_t)b.kept);
+    }
   }
-  (void)side_bytes;
-  VX_HIP(hipMemcpyAsync(r->jobs_dev, r->plan.jobs.data(), desc_bytes, hipMemcpyHostToDevice, ctx->compute));
+  VX_HIP(hipMemcpyAsync(r->jobs_dev, pl.jobs.data(), desc_bytes, hipMemcpyHostToDevice, ctx->compute));
   if (map_bytes)
-    VX_HIP(hipMemcpyAsync(r->probe_map, r->plan.probe_map.data(), map_bytes, hipMemcpyHostToDevice, ctx->compute));
+    VX_HIP(hipMemcpyAsync(r->probe_map, pl.probe_map.data(), map_bytes, hipMemcpyHostToDevice, ctx->compute));
   if (bmap_bytes)
-    VX_HIP(hipMemcpyAsync(r->build_map, r->plan.build_map.data(), bmap_bytes, hipMemcpyHostToDevice, ctx->compute));
+    VX_HIP(hipMemcpyAsync(r->build_map, pl.build_map.data(), bmap_bytes, hipMemcpyHostToDevice, ctx->compute));
+  if (rmap_bytes)
+    VX_HIP(hipMemcpyAsync(r->region_map, pl.region_map.data(), rmap_bytes, hipMemcpyHostToDevice, ctx->compute));
+  if (pmap_bytes)
+    VX_HIP(hipMemcpyAsync(r->part_map, pl.part_map.data(), pmap_bytes, hipMemcpyHostToDevice, ctx->compute));
   return VX_OK;
 }
 
@@ -588,6 +1152,37 @@ static vx_status enqueue_batch(vx_ctx* ctx, const BatchRun& r, const BatchConfig
   gb = std::max(kXcds, gb / kXcds * kXcds);
   unsigned gp = (unsigned)std::min<uint64_t>(std::max<uint64_t>(mapped, 1), ctx->cu_count * per_cu);
   gp = std::max(kXcds, gp / kXcds * kXcds);
+  // Streams: the copy stream takes the partitioning (count, scan, scatter) beside the build
+  // phase, then, once the tables are built, the region probe beside the tile-map probe.
+  const char* fork_env = getenv("VX_BATCH_FORK");   // 0: everything on one stream, in order
+  hipStream_t s2 = fork_env && fork_env[0] == '0' ? s : ctx->copy;
+  const bool part = !r.plan.part_map.empty(), reg = !r.plan.region_map.empty();
+  hipEvent_t ev_built = nullptr, ev_done = nullptr;
+  if (reg) {
+    hipEvent_t fork = get_event(ctx);
+    ev_built = get_event(ctx);
+    ev_done = get_event(ctx);
+    VX_CHECK(fork && ev_built && ev_done, VX_EHIP, "batch: no events");
+    VX_HIP(hipEventRecord(fork, s));
+    VX_HIP(hipStreamWaitEvent(s2, fork, 0));
+    put_event(ctx, fork);
+  }
+  if (part) {
+    const uint64_t ns = r.plan.part_map.size();
+    const unsigned g = (unsigned)std::min<uint64_t>(ns, (uint64_t)ctx->cu_count * 8);
+    if (ks == 8) {
+      hipLaunchKernelGGL(k_batch_count<int64_t>, dim3(g), dim3(kPartThreads), 0, s2, r.jobs_dev, r.part_map, ns, r.tally);
+      hipLaunchKernelGGL(k_batch_scan, dim3(J), dim3(kScanBlock), 0, s2, r.jobs_dev, r.tally);
+      hipLaunchKernelGGL(k_batch_scatter<int64_t>, dim3(g), dim3(kPartThreads), 0, s2, r.jobs_dev, r.part_map, ns,
+                         (const uint32_t*)r.tally);
+    } else {
+      hipLaunchKernelGGL(k_batch_count<int32_t>, dim3(g), dim3(kPartThreads), 0, s2, r.jobs_dev, r.part_map, ns, r.tally);
+      hipLaunchKernelGGL(k_batch_scan, dim3(J), dim3(kScanBlock), 0, s2, r.jobs_dev, r.tally);
+      hipLaunchKernelGGL(k_batch_scatter<int32_t>, dim3(g), dim3(kPartThreads), 0, s2, r.jobs_dev, r.part_map, ns,
+                         (const uint32_t*)r.tally);
+    }
+    VX_HIP(hipGetLastError());
+  }
   const unsigned long long* bmap = r.build_map;
   if (ks == 8)
     hipLaunchKernelGGL((k_batch_phase<int64_t, true>), dim3(gb), dim3(cfg.block), 0, s, r.jobs_dev, J,
@@ -596,13 +1191,35 @@ static vx_status enqueue_batch(vx_ctx* ctx, const BatchRun& r, const BatchConfig
     hipLaunchKernelGGL((k_batch_phase<int32_t, true>), dim3(gb), dim3(cfg.block), 0, s, r.jobs_dev, J,
                        (uint64_t)bmapped, cfg.tile_rows, r.plan.slot_shift, r.acc, ctx->dev_flags, bmap);
   launch_dupcount(ctx, r, J, s);
+  if (reg) {
+    VX_HIP(hipEventRecord(ev_built, s));
+    VX_HIP(hipStreamWaitEvent(s2, ev_built, 0));
+    put_event(ctx, ev_built);
+    const uint64_t items = r.plan.region_map.size();
+    unsigned g = (unsigned)std::min<uint64_t>(items, (uint64_t)ctx->cu_count * 2);   // two 64 KiB stages per CU
+    g = std::max(kXcds, g / kXcds * kXcds);
+    if (ks == 8)
+      hipLaunchKernelGGL(k_batch_region<int64_t>, dim3(g), dim3(kRegionThreads), 0, s2, r.jobs_dev, r.region_map, items,
+                         r.plan.slot_shift, (const uint32_t*)r.tally, r.acc);
+    else
+      hipLaunchKernelGGL(k_batch_region<int32_t>, dim3(g), dim3(kRegionThreads), 0, s2, r.jobs_dev, r.region_map, items,
+                         r.plan.slot_shift, (const uint32_t*)r.tally, r.acc);
+    VX_HIP(hipGetLastError());
+    VX_HIP(hipEventRecord(ev_done, s2));
+  }
   const unsigned long long* pmap = r.probe_map;
-  if (ks == 8)
-    hipLaunchKernelGGL((k_batch_phase<int64_t, false>), dim3(gp), dim3(cfg.block), 0, s, r.jobs_dev, J,
-                       (uint64_t)mapped, cfg.tile_rows, r.plan.slot_shift, r.acc, ctx->dev_flags, pmap);
-  else
-    hipLaunchKernelGGL((k_batch_phase<int32_t, false>), dim3(gp), dim3(cfg.block), 0, s, r.jobs_dev, J,
-                       (uint64_t)mapped, cfg.tile_rows, r.plan.slot_shift, r.acc, ctx->dev_flags, pmap);
+  if (mapped) {
+    if (ks == 8)
+      hipLaunchKernelGGL((k_batch_phase<int64_t, false>), dim3(gp), dim3(cfg.block), 0, s, r.jobs_dev, J,
+                         (uint64_t)mapped, cfg.tile_rows, r.plan.slot_shift, r.acc, ctx->dev_flags, pmap);
+    else
+      hipLaunchKernelGGL((k_batch_phase<int32_t, false>), dim3(gp), dim3(cfg.block), 0, s, r.jobs_dev, J,
+                         (uint64_t)mapped, cfg.tile_rows, r.plan.slot_shift, r.acc, ctx->dev_flags, pmap);
+  }
+  if (reg) {
+    VX_HIP(hipStreamWaitEvent(s, ev_done, 0));
+    put_event(ctx, ev_done);
+  }
   VX_HIP(hipGetLastError());
   if (host_out) {   // accumulators and bit counts are contiguous: 3 J words, then the flags
     VX_HIP(hipMemcpyAsync(host_out, r.acc, 3 * (uint64_t)J * 8, hipMemcpyDeviceToHost, s));
@@ -775,13 +1392,16 @@ vx_status join_batch(vx_ctx* ctx, const vx_batch_join* d, vx_join_out* out) {
   // which jobs take a direct table depends on the keys' values: measured on every call
   DirectInfo di;
   VX_CHECK((d->flags & ~(uint32_t)VX_HASHED) == 0, VX_EINVAL, "batch: unknown flags %u", d->flags);
-  if (d->flags & VX_HASHED) {   // every job hashed: no key-range pass
-    di.direct.assign(J, 0);
-    di.kmin.assign(J, 0);
-  } else {
-    VX_TRY(find_direct(ctx, d, ks, &di));
-  }
+  VX_TRY(find_direct(ctx, d, ks, &di));
+  if (d->flags & VX_HASHED) di.direct.assign(J, 0);   // every job hashed; the ranges still filter probes
   const double t_checked = now_ms();
+  if (d->mode == 0) {   // a graph kept for other jobs gives its arena memory back before tuning
+    auto it = g_graphs.find(ctx);
+    if (it != g_graphs.end() && it->second && !(it->second->key == job_keys(d) && it->second->di == di)) {
+      drop_graph(it->second);
+      it->second = nullptr;
+    }
+  }
   BatchConfig cfg;
   bool tuned = d->tile_rows == 0 || d->block == 0 || d->load_factor == 0.0f;
   if (tuned && d->mode == 0) VX_TRY(autotune(ctx, d, ks, ps, di, &cfg));
@@ -845,14 +1465,19 @@ vx_status join_batch(vx_ctx* ctx, const vx_batch_join* d, vx_join_out* out) {
              VX_EDUPKEY, "batch: duplicate build key");
     VX_CHECK(!(f & kFlagFull), VX_ECAPACITY, "batch: table full (internal sizing error)");
     s.kernel_ms = ms;
-    s.kernel_launches = gc->run->plan.count_tiles ? 3 : 2;   // build phase, bit count, probe phase
+    // build phase, bit count, tile-map probe, count, scan, scatter, region probe
+    const BatchPlan& gp = gc->run->plan;
+    s.kernel_launches = 1 + (gp.count_tiles ? 1 : 0) + (gp.probe_map.empty() ? 0 : 1) + (gp.part_jobs ? 3 : 0) +
+                        (gp.region_map.empty() ? 0 : 1);
+    s.n_parts = gp.part_jobs;
+    s.survivors = gp.region_jobs;
     s.table_bytes = (gc->run->plan.slots << gc->run->plan.slot_shift) + gc->run->plan.direct_bytes;
     s.chunk_rows = cfg.tile_rows;
     s.n_buffers = cfg.block;
     s.imbalance = cfg.load_factor;
   } else {
     BatchRun r;
-    VX_TRY(setup_run(ctx, d, cfg, ks, ps, di, &r));
+    VX_TRY(setup_run(ctx, d, cfg, ks, ps, di, &r, false));   // the baseline reads every job's own keys
     uint32_t sw = (1u << r.plan.slot_shift) / 4;
     fill_zero((uint64_t*)r.counters, r.counter_words, ctx->compute);
     fill_zero((uint64_t*)ctx->dev_flags, 1, ctx->compute);

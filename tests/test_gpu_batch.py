@@ -59,8 +59,10 @@ def test_batch_explicit_configs_and_graph_replay(gpu, ctx):
         assert got == exp
         torch.cuda.synchronize()
         _ = (args[2][0] + 1).sum().item()
-    # one graph: build phase, bit count of the direct tables (these jobs' keys fill their ranges), probe phase
-    assert st["kernel_launches"] == 3
+    # one graph: build phase, bit count of the direct tables (these jobs' keys fill their ranges), and
+    # the probe by regions: count, scan and scatter of the probe sides whose tables exceed 64 KiB,
+    # then the region probe
+    assert st["kernel_launches"] == 6 and st["n_parts"] > 0
 
 
 def test_batch_edges(gpu, ctx):
@@ -230,3 +232,67 @@ def test_batch_hashed_flag(gpu, ctx):
         got_d, st_d = ctx.join_batch(*args, mode=mode, tile_rows=2048, block=256, load_factor=0.5)
         assert got_h == exp and got_d == exp
         assert st_h["table_bytes"] > st_d["table_bytes"]   # hash slots of 8 B at load 0.5 against 4 B payloads
+
+
+def _part_jobs(rng, kt):
+    """Jobs for the partitioned probe path: direct-table jobs (ranges at 0, at the type's minimum and
+    maximum, negative) and hash-table jobs (one holding the empty-marker key), probe sides from empty
+    to ragged multiples of the partition tile."""
+    info = np.iinfo(kt)
+    bk, bp, pk = [], [], []
+    specs = [(5000, 0, 4097), (20000, int(info.min), 50000), (70001, int(info.max) - 70000, 123457),
+             (300000, -12345, 200003), (16384, 7, 0), (9000, None, 4096), (40000, None, 99999),
+             (123456, None, 4095), (60000, "min", 70000)]
+    for n, base, m in specs:
+        if base is None or base == "min":
+            k = np.unique(rng.integers(-10**6 if kt == np.int32 else -2**62, 10**6 if kt == np.int32 else 2**62,
+                                       n + n // 8)).astype(kt)[:n]
+            rng.shuffle(k)
+            if base == "min":
+                k[0] = info.min
+        else:
+            k = (rng.permutation(n).astype(np.int64) + base).astype(kt)
+        bk.append(k)
+        bp.append(rng.integers(-2**31, 2**31, n).astype(np.int32))
+        lo, hi = int(k.min()), int(k.max())
+        span_lo = max(int(info.min), lo - n // 2)
+        span_hi = min(int(info.max), hi + n) if base is not None and base != "min" else hi
+        rand = rng.integers(span_lo, span_hi, m // 2, dtype=np.int64, endpoint=True).astype(kt)
+        hits = k[rng.integers(0, n, m - m // 2)]
+        q = np.concatenate([rand, hits])
+        rng.shuffle(q)
+        if base == "min" and m:
+            q[:50] = info.min
+        pk.append(q)
+    return bk, bp, pk
+
+
+@pytest.mark.parametrize("kt", [np.int32, np.int64])
+def test_batch_partitioned_probe(gpu, kt, monkeypatch):
+    """The probe by regions: tables of at most the LDS stage probed whole from the jobs' own keys,
+    larger ones cut into regions with the probe side partitioned into one array per region, regions
+    staged in LDS or (past the region-count cap) read from device memory; direct and hash tables
+    (whose probe keys outside the build keys' range are dropped).  Stages of 1 KiB and 64 KiB, and
+    the probe through the tile map alone, against the oracle, with graph replays."""
+    rng = np.random.default_rng(19 if kt == np.int32 else 23)
+    bk, bp, pk = _part_jobs(rng, kt)
+    exp = [oracle.join_agg(a, [b], c, []) for a, b, c in zip(bk, bp, pk)]
+    args = ([dev(x) for x in bk], [dev(x) for x in bp], [dev(x) for x in pk])
+    for stage_kb in ("1", "64"):
+        monkeypatch.setenv("VX_BATCH_STAGE_KB", stage_kb)
+        for hashed in (False, True):
+            for tile, block, lf in ((1024, 256, 0.5), (65536, 512, 0.7)):
+                _say("batch by regions", kt.__name__, "stage KiB", stage_kb, "hashed", hashed, "config", tile, block, lf)
+                with gpu.Context(2 * GiB) as c:
+                    for rep in range(2):
+                        got, st = c.join_batch(*args, hashed=hashed, tile_rows=tile, block=block, load_factor=lf)
+                        assert got == exp, f"replay {rep}"
+                assert st["n_parts"] >= 4                       # jobs whose probe side was partitioned
+                # jobs probed by regions: all but the one with no probe rows, unless its table fits the stage
+                assert st["survivors"] == len(bk) - (1 if stage_kb == "1" or hashed else 0)
+                # build phase, count, scan, scatter, region probe, and the direct tables' bit count
+                assert st["kernel_launches"] == 5 + (0 if hashed else 1)
+    monkeypatch.setenv("VX_BATCH_REGIONS", "0")
+    with gpu.Context(2 * GiB) as c:
+        got, st = c.join_batch(*args, tile_rows=1024, block=256, load_factor=0.5)
+    assert got == exp and st["n_parts"] == 0 and st["kernel_launches"] == 3
