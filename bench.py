@@ -518,6 +518,10 @@ def run_rows(args):
     agg, st, n_out, _ = res[0]
     if agg != res_agg[0][0] or any(r[0] != agg or r[2] != n_out for r in res):
         raise SystemExit("materialized join disagrees with the aggregate-only join")
+    # one more, untimed step with the kernels counting the zero-copy granules they touch
+    agg_c, st_c, n_c, _ = t.probe_rows(H["pk"], [H["p0"], H["p1"]], out=out, cap=cap, count_zc=True)
+    if agg_c != agg or n_c != n_out or not st_c["zc_counted"]:
+        raise SystemExit("counted step disagrees")
     t.destroy()
     ctx.close()
     for h in list(H.values()) + O:
@@ -535,7 +539,9 @@ def run_rows(args):
                     "frac": ach / HBM_PEAK_GBS, "traffic": None, "traffic_profile": PROFILE["k_probe_rows"], "avg_launch_ms": k_avg,
                     "rows_per_launch": np_ / launches},
                    {"host_link": {"peak_measured_gbs": b_peak,
-                                  "h2d_gbs": (nb * 16 + st["sdma_bytes"] + st["zc_bytes"]) / (ms * 1e6),
+                                  "h2d_gbs": (nb * 16 + st["sdma_bytes"] + st_c["zc_bytes"]) / (ms * 1e6),
+                                  "zero_copy_bytes_counted": st_c["zc_bytes"],
+                                  "zero_copy_bytes_binomial_model": st["zc_bytes"],
                                   "d2h_output_gbs": d2h / (ms * 1e6)},
                     "aggregate_only_ms_per_step": ms_agg,
                     "materialization_cost": ms / ms_agg - 1.0,
@@ -644,7 +650,11 @@ def run_star(args):
     ms, res = _timed(step, args, torch)
     st = res[0][1]
     k_ms = sum(r[1]["kernel_ms"] for r in res) / sum(r[1]["kernel_launches"] for r in res)
-    wire = st["sdma_bytes"] + st["zc_bytes"]
+    # one more, untimed step with the kernels counting the zero-copy granules they touch
+    g_c, c_c, s_c, st_c = ctx.join_star(ddims, fk, ms_, groups_cap=4096, count_zc=True)
+    if (g_c.tolist(), c_c.tolist(), s_c.tolist()) != res[0][0] or not st_c["zc_counted"]:
+        raise SystemExit("counted star step disagrees")
+    wire = st["sdma_bytes"] + st_c["zc_bytes"]
     # algorithmic link bytes: each fact column is needed only for rows alive when it is read
     # (dimensions probed in ascending filter selectivity, then the 3 measures of survivors)
     sel = sorted(float(np.mean(x["filt"] == 0)) for x in dims)
@@ -671,6 +681,8 @@ def run_star(args):
                    "rows_per_launch": nf / st["kernel_launches"]},
                   {"host_link": {"peak_measured_gbs": b_peak, "achieved_wire_gbs": wire / (ms * 1e6),
                                  "frac_wire": wire / (ms * 1e6) / b_peak,
+                                 "zero_copy_bytes_counted": st_c["zc_bytes"],
+                                 "zero_copy_bytes_binomial_model": st["zc_bytes"],
                                  "achieved_algorithmic_gbs": alg / (ms * 1e6),
                                  "frac_algorithmic": alg / (ms * 1e6) / b_peak},
                    "survivors": st["survivors"], "build_ms": st["build_ms"],

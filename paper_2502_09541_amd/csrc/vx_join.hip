@@ -574,7 +574,7 @@ __global__ void __launch_bounds__(256) k_probe_rows(TableView t, ProbeCols q, un
         const uint64_t w0 = (glob ? q.row0 : 0) + base + (uint64_t)j * blockDim.x + (threadIdx.x & ~63u);
         const uint32_t g = wave_granules(hit[j], (uint64_t)(uintptr_t)q.pay[p] + w0 * q.pay_size[p],
                                          q.pay_size[p], q.zc_shift);
-        if (lane == 0) acc[kGranuleWord] += g;
+        if (lane == 0) acc[kGranuleWord] += (unsigned long long)g * q.zc_mult[p];   // for each column it stands for
       }
     }
     // reserve the tile's rows: per-wave counts, one atomic per workgroup

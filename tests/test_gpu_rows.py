@@ -113,3 +113,29 @@ def test_rows_edges(gpu, ctx):
         tp.probe_rows(dev(pk), [])
     assert ei.value.status == gpu.VX_EUNSUPPORTED
     tp.destroy()
+
+
+def test_rows_zero_copy_granules_counted(gpu):
+    """zc_bytes of a zero-copy rows probe, counted by the kernels: 128 B (the granule before any
+    calibration) times the granules that hold a matching row, in each of the two payload columns
+    (one count stands for both, as they share width and offset), as in the aggregate-only probe.
+    Page-aligned columns and chunks of a multiple of 64 rows keep each granule in one wave."""
+    nb, np_ = 1 << 12, (1 << 18) + 77
+    bk, b0, b1 = datagen.stream_build(nb, seed=5)
+    pk, p0, p1 = datagen.stream_probe(nb, np_, seed=5)
+    hosts = [pinned(gpu, a) for a in (pk, p0, p1)]
+    _say("rows zero-copy granule count")
+    try:
+        with gpu.Context(1 << 30) as c:
+            t = c.build(dev(bk), [dev(b0), dev(b1)])
+            agg, st, n_out, (row, bc, pc) = t.probe_rows(hosts[0], hosts[1:], late_mat=gpu.VX_LATE_ZC,
+                                                         chunk_rows=1 << 15, count_zc=True)
+            _check(row, bc, pc, n_out, bk, [b0, b1], pk, [p0, p1])
+            t.destroy()
+        assert st["zc_mask"] == 3 and st["zc_counted"] == 1
+        rows = np.nonzero(np.isin(pk, bk))[0]
+        granules = len(np.unique(rows * 8 // 128))
+        assert st["zc_bytes"] == 2 * 128 * granules
+    finally:
+        for h in hosts:
+            h.free()
