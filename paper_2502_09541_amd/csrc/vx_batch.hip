@@ -72,7 +72,7 @@ struct BatchJob {
   uint32_t stiles;          // super-tiles of kSuperTiles partition tiles
   uint32_t items_per_region;   // probe work items per region
   uint64_t cbase;           // the job's tallies: entry cbase + super-tile * n_parts + region
-  uint8_t* pbuf;            // partitioned keys: the regions' arrays, in region order, then 64 sink slots
+  uint8_t* pbuf;            // partitioned keys: the regions' arrays, in region order, then the sink slots
   unsigned long long* kept; // keys kept by the partitioning (written by the scan)
 };
 
@@ -92,6 +92,11 @@ __device__ __forceinline__ T gload_nt(const void* base, uint64_t i) {
 template <typename T>
 __device__ __forceinline__ void gstore(void* base, uint64_t i, T v) {
   ((VX_GLOBAL T*)base)[i] = v;
+}
+// the same, at a byte offset below 2^32 from a base common to the wave (one address register)
+template <typename T>
+__device__ __forceinline__ void gstore_at(void* base, uint32_t byte_off, T v) {
+  *(VX_GLOBAL T*)((VX_GLOBAL uint8_t*)base + byte_off) = v;
 }
 
 template <typename K>
@@ -232,6 +237,7 @@ constexpr uint32_t kScanBlock = 1024;
 constexpr uint32_t kRegionThreads = 512;
 constexpr uint32_t kStageBytes = 64 << 10;           // LDS for one table region
 constexpr uint32_t kRunUnroll = 4;
+constexpr uint32_t kSinkGroups = 256;                // scatter sink slots: 64 per group of workgroups
 
 // How a job maps probe keys to table regions, read from its descriptor once (scalar registers).
 struct RegionFn {
@@ -287,7 +293,7 @@ template <typename K>
 __global__ void __launch_bounds__(kPartThreads) k_batch_count(const BatchJob* __restrict__ jobs,
                                                               const unsigned long long* __restrict__ part_map,
                                                               uint64_t n_super, uint32_t* __restrict__ tally) {
-  __shared__ uint32_t cnt[kMaxTableParts + 1];   // entry n_parts takes the keys that cannot match
+  __shared__ uint32_t cnt[kMaxTableParts];
   for (uint64_t g = blockIdx.x; g < n_super; g += gridDim.x) {
     const unsigned long long e = uniform_entry(part_map, g);
     const BatchJob& jb = jobs[e >> 32];
@@ -297,7 +303,7 @@ __global__ void __launch_bounds__(kPartThreads) k_batch_count(const BatchJob* __
     const void* pkey = jb.pkey;
     const uint64_t np = jb.np, t0 = st * kSuperTiles;
     const uint64_t t1 = t0 + kSuperTiles < jb.ptiles ? t0 + kSuperTiles : jb.ptiles;
-    for (uint32_t j = threadIdx.x; j <= P; j += kPartThreads) cnt[j] = 0;   // each thread rereads its own entries below
+    for (uint32_t j = threadIdx.x; j < P; j += kPartThreads) cnt[j] = 0;   // each thread rereads its own entries below
     lds_barrier();
     // the waves of the workgroup go through the tiles independently, each reading the next tile
     // while it counts the current one (the loads land in kn, always one tile ahead)
@@ -310,7 +316,8 @@ __global__ void __launch_bounds__(kPartThreads) k_batch_count(const BatchJob* __
       uint32_t r[kPartItems];
       tile_regions(region, np, t, k, r);
 #pragma unroll
-      for (uint32_t it = 0; it < kPartItems; ++it) atomicAdd(&cnt[r[it]], 1u);
+      for (uint32_t it = 0; it < kPartItems; ++it)   // keys that cannot match are not counted: on one
+        if (r[it] < P) atomicAdd(&cnt[r[it]], 1u);   // shared counter they would serialize the lanes
     }
     lds_barrier();
     for (uint32_t j = threadIdx.x; j < P; j += kPartThreads) tally[jb.cbase + st * P + j] = cnt[j];
@@ -332,8 +339,17 @@ __global__ void __launch_bounds__(kScanBlock) k_batch_scan(const BatchJob* __res
   const uint64_t s0 = S * g / G, s1 = S * (g + 1) / G;
   uint32_t* c = tally + jb.cbase;
   uint32_t sum = 0;
-  if (active)
-    for (uint64_t st = s0; st < s1; ++st) sum += c[st * P + r];
+  if (active) {
+    uint64_t st = s0;
+    for (; st + 8 <= s1; st += 8) {   // eight independent loads in flight
+      uint32_t v[8];
+#pragma unroll
+      for (uint32_t u = 0; u < 8; ++u) v[u] = c[(st + u) * P + r];
+#pragma unroll
+      for (uint32_t u = 0; u < 8; ++u) sum += v[u];
+    }
+    for (; st < s1; ++st) sum += c[st * P + r];
+  }
   part[threadIdx.x] = active ? sum : 0u;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -349,7 +365,18 @@ __global__ void __launch_bounds__(kScanBlock) k_batch_scan(const BatchJob* __res
   __syncthreads();
   if (active) {
     uint32_t run = part[threadIdx.x];
-    for (uint64_t st = s0; st < s1; ++st) {
+    uint64_t st = s0;
+    for (; st + 8 <= s1; st += 8) {
+      uint32_t v[8];
+#pragma unroll
+      for (uint32_t u = 0; u < 8; ++u) v[u] = c[(st + u) * P + r];
+#pragma unroll
+      for (uint32_t u = 0; u < 8; ++u) {
+        c[(st + u) * P + r] = run;
+        run += v[u];
+      }
+    }
+    for (; st < s1; ++st) {
       const uint32_t v = c[st * P + r];
       c[st * P + r] = run;
       run += v;
@@ -362,7 +389,7 @@ __global__ void __launch_bounds__(kScanBlock) k_batch_scan(const BatchJob* __res
 // a key among the tile's keys of its region comes from an LDS counter), then written out in runs,
 // so that neighbouring lanes store neighbouring keys; the order within a region is arbitrary and
 // the aggregates do not depend on it.  Every thread issues kPartItems stores per tile (slots past
-// the tile's kept keys go to a sink past the partitioned keys), and the next tile's loads are
+// the tile's kept keys go to sink slots past the partitioned keys), and the next tile's loads are
 // issued before them, so that waiting for those loads never waits for the stores.
 template <typename K>
 __global__ void __launch_bounds__(kPartThreads) k_batch_scatter(const BatchJob* __restrict__ jobs,
@@ -380,7 +407,10 @@ __global__ void __launch_bounds__(kPartThreads) k_batch_scatter(const BatchJob* 
     const uint32_t P = region.parts;
     const void* pkey = jb.pkey;
     void* const dst = jb.pbuf;
-    const uint64_t np = jb.np, t0 = st * kSuperTiles, sink = np + lane;
+    // slots past a tile's kept keys store to this workgroup's own 64 sink slots, so that no line
+    // is written by many workgroups at once
+    const uint64_t np = jb.np, t0 = st * kSuperTiles;
+    const uint32_t sink = (uint32_t)np + 64u * (blockIdx.x % kSinkGroups) + lane;   // the planner keeps it below 2^32 / key size
     const uint64_t t1 = t0 + kSuperTiles < jb.ptiles ? t0 + kSuperTiles : jb.ptiles;
     for (uint32_t j = threadIdx.x; j <= P; j += kPartThreads) {
       next[j] = j < P ? pos[jb.cbase + st * P + j] : 0u;
@@ -392,20 +422,19 @@ __global__ void __launch_bounds__(kPartThreads) k_batch_scatter(const BatchJob* 
     for (uint64_t t = t0; t < t1; ++t) {
 #pragma unroll
       for (uint32_t it = 0; it < kPartItems; ++it) k[it] = kn[it];
-      uint32_t r[kPartItems], rank[kPartItems];
-      tile_regions(region, np, t, k, r);
+      // per key: region << 16 | rank among the tile's keys of its region (no rank for a key that
+      // cannot match: see the count)
+      uint32_t rr[kPartItems];
+      tile_regions(region, np, t, k, rr);
 #pragma unroll
-      for (uint32_t it = 0; it < kPartItems; ++it) rank[it] = atomicAdd(&cnt[r[it]], 1u);
+      for (uint32_t it = 0; it < kPartItems; ++it)
+        rr[it] = rr[it] < P ? rr[it] << 16 | atomicAdd(&cnt[rr[it]], 1u) : P << 16;
       lds_barrier();
       if (threadIdx.x < 64) {   // exclusive scan of cnt[0 .. P) into off; off[P] = the tile's kept keys
-        constexpr uint32_t per = (kMaxTableParts + 63) / 64;
-        uint32_t v[per], own = 0;
-#pragma unroll
-        for (uint32_t u = 0; u < per; ++u) {
-          const uint32_t j = per * lane + u;
-          v[u] = j < P ? cnt[j] : 0u;
-          own += v[u];
-        }
+        const uint32_t per = (P + 63) / 64, j0 = per * lane;
+        uint32_t own = 0;
+        for (uint32_t u = 0; u < per; ++u)
+          if (j0 + u < P) own += cnt[j0 + u];
         uint32_t incl = own;
 #pragma unroll
         for (uint32_t o = 1; o < 64; o <<= 1) {
@@ -413,31 +442,32 @@ __global__ void __launch_bounds__(kPartThreads) k_batch_scatter(const BatchJob* 
           if (lane >= o) incl += y;
         }
         uint32_t run = incl - own;
-#pragma unroll
-        for (uint32_t u = 0; u < per; ++u) {
-          const uint32_t j = per * lane + u;
-          if (j < P) off[j] = run;
-          run += v[u];
-        }
+        for (uint32_t u = 0; u < per; ++u)
+          if (j0 + u < P) {
+            off[j0 + u] = run;
+            run += cnt[j0 + u];
+          }
         if (lane == 63) off[P] = incl;
       }
       lds_barrier();
 #pragma unroll
-      for (uint32_t it = 0; it < kPartItems; ++it)
-        if (r[it] < P) {
-          const uint32_t slot = off[r[it]] + rank[it];
+      for (uint32_t it = 0; it < kPartItems; ++it) {
+        const uint32_t r = rr[it] >> 16;
+        if (r < P) {
+          const uint32_t slot = off[r] + (rr[it] & 0xffffu);
           stage[slot] = k[it];
-          sreg[slot] = (uint16_t)r[it];
+          sreg[slot] = (uint16_t)r;
         }
+      }
       if (t + 1 < t1) load_tile(pkey, np, t + 1, kn);
       lds_barrier();
       const uint32_t total = off[P];
 #pragma unroll
       for (uint32_t it = 0; it < kPartItems; ++it) {
         const uint32_t i = it * kPartThreads + threadIdx.x;
-        const uint32_t rr = i < total ? (uint32_t)sreg[i] : 0u;
-        const uint64_t at = i < total ? (uint64_t)(next[rr] + (i - off[rr])) : sink;
-        gstore<K>(dst, at, stage[i]);
+        const uint32_t rg = i < total ? (uint32_t)sreg[i] : 0u;
+        const uint32_t at = i < total ? next[rg] + (i - off[rg]) : sink;
+        gstore_at<K>(dst, at * (uint32_t)sizeof(K), stage[i]);
       }
       lds_barrier();
 #pragma unroll
@@ -882,7 +912,7 @@ static void map_tiles(BatchPlan* pl, uint32_t slot_bytes, uint64_t l2_bytes) {
 // from the job's own keys.  A larger one is cut into regions of `stage` bytes (at most
 // kMaxTableParts; beyond that the regions grow and are read from device memory) and its probe
 // side partitioned, largest probe sides first while the buffers fit part_budget bytes; a job left
-// over, or one of 2^32 probe rows or more, goes through the tile map.  Offsets in the jobs are
+// over, or one whose partitioned keys would pass 4 GiB, goes through the tile map.  Offsets in the jobs are
 // relative to the partition block until setup_run relocates them.
 static void plan_regions(BatchPlan* pl, int ks, uint32_t slot_bytes, uint64_t part_budget, uint64_t stage) {
   pl->part_map.clear();
@@ -907,7 +937,8 @@ static void plan_regions(BatchPlan* pl, int ks, uint32_t slot_bytes, uint64_t pa
       ++pl->region_jobs;
       continue;
     }
-    if (b.np == 0 || b.np >= (1ull << 32)) continue;
+    // the scatter addresses a job's partitioned keys (and sink slots) by 32-bit byte offsets
+    if (b.np == 0 || (b.np + 64ull * kSinkGroups) * (uint64_t)ks >= (1ull << 32)) continue;
     uint32_t parts, shift;
     bool staged;
     if (b.direct) {
@@ -926,7 +957,7 @@ static void plan_regions(BatchPlan* pl, int ks, uint32_t slot_bytes, uint64_t pa
     }
     const uint64_t ptiles = (b.np + kPartRows - 1) / kPartRows;
     const uint64_t stiles = (ptiles + kSuperTiles - 1) / kSuperTiles;
-    const uint64_t keys = align256((b.np + 64) * (uint64_t)ks), tallies = stiles * parts;   // + the sink slots
+    const uint64_t keys = align256((b.np + 64ull * kSinkGroups) * (uint64_t)ks), tallies = stiles * parts;   // + the sink slots
     const uint64_t need = keys + tallies * 4 + 256 + 8;
     if (pl->part_bytes + need > part_budget) continue;
     b.n_parts = parts;
