@@ -384,20 +384,52 @@ __global__ void __launch_bounds__(kScanBlock) k_batch_scan(const BatchJob* __res
   }
 }
 
-// Scatter pass: each kept key of super-tile st to its region's array, at the super-tile's
-// position for the region plus its rank.  Each tile is first sorted by region in LDS (the rank of
-// a key among the tile's keys of its region comes from an LDS counter), then written out in runs,
-// so that neighbouring lanes store neighbouring keys; the order within a region is arbitrary and
-// the aggregates do not depend on it.  Every thread issues kPartItems stores per tile (slots past
-// the tile's kept keys go to sink slots past the partitioned keys), and the next tile's loads are
-// issued before them, so that waiting for those loads never waits for the stores.
+// Rows r0 .. r0 + T kPartItems of a job's probe keys, kPartItems per thread of T (rows past the
+// end reread the last row), and their regions (`parts` for a key that cannot match or a row past
+// the end).
+template <typename K, uint32_t T>
+__device__ __forceinline__ void load_rows(const void* pkey, uint64_t np, uint64_t r0, K (&k)[kPartItems]) {
+  const uint32_t last = (uint32_t)(np - r0 < T * kPartItems ? np - r0 : T * kPartItems) - 1;
+#pragma unroll
+  for (uint32_t it = 0; it < kPartItems; ++it) {
+    const uint32_t row = it * T + threadIdx.x;
+    k[it] = gload_nt<K>(pkey, r0 + (row < last ? row : last));
+  }
+}
+
+template <typename K, uint32_t T>
+__device__ __forceinline__ void rows_regions(const RegionFn& region, uint64_t np, uint64_t r0, const K (&k)[kPartItems],
+                                             uint32_t (&r)[kPartItems]) {
+  const uint32_t n = (uint32_t)(np - r0 < T * kPartItems ? np - r0 : T * kPartItems);
+#pragma unroll
+  for (uint32_t it = 0; it < kPartItems; ++it) {
+    const uint32_t row = it * T + threadIdx.x;
+    r[it] = row < n ? region(k[it]) : region.parts;
+  }
+}
+
+// Workgroup size of the scatter: one round sorts T kPartItems keys in LDS (16384 int32 or 8192
+// int64 keys), so that a region's run per round is about a line on the bench's batch.
 template <typename K>
-__global__ void __launch_bounds__(kPartThreads) k_batch_scatter(const BatchJob* __restrict__ jobs,
-                                                                const unsigned long long* __restrict__ part_map,
-                                                                uint64_t n_super, const uint32_t* __restrict__ pos) {
+constexpr uint32_t scatter_threads() { return sizeof(K) == 4 ? 1024 : 512; }
+
+// Scatter pass: each kept key of super-tile st to its region's array, at the super-tile's
+// position for the region plus its rank.  The super-tile goes in rounds of T kPartItems keys; each
+// round is first sorted by region in LDS (the rank of a key among the round's keys of its region
+// comes from an LDS counter), then written out in runs, so that neighbouring lanes store
+// neighbouring keys; the order within a region is arbitrary and the aggregates do not depend on
+// it.  Every thread issues kPartItems stores per round (slots past the round's kept keys go to
+// sink slots past the partitioned keys), and the next round's loads are issued before them, so
+// that waiting for those loads never waits for the stores.
+template <typename K, uint32_t T>
+__global__ void __launch_bounds__(T) k_batch_scatter(const BatchJob* __restrict__ jobs,
+                                                     const unsigned long long* __restrict__ part_map,
+                                                     uint64_t n_super, const uint32_t* __restrict__ pos) {
+  constexpr uint32_t R = T * kPartItems;
+  constexpr uint64_t kSuperRows = (uint64_t)kPartRows * kSuperTiles;
   __shared__ uint32_t next[kMaxTableParts + 1], cnt[kMaxTableParts + 1], off[kMaxTableParts + 1];
-  __shared__ K stage[kPartRows];
-  __shared__ uint16_t sreg[kPartRows];
+  __shared__ K stage[R];
+  __shared__ uint16_t sreg[R];
   const uint32_t lane = threadIdx.x & 63;
   for (uint64_t g = blockIdx.x; g < n_super; g += gridDim.x) {
     const unsigned long long e = uniform_entry(part_map, g);
@@ -407,30 +439,29 @@ __global__ void __launch_bounds__(kPartThreads) k_batch_scatter(const BatchJob* 
     const uint32_t P = region.parts;
     const void* pkey = jb.pkey;
     void* const dst = jb.pbuf;
-    // slots past a tile's kept keys store to this workgroup's own 64 sink slots, so that no line
-    // is written by many workgroups at once
-    const uint64_t np = jb.np, t0 = st * kSuperTiles;
+    // slots past a round's kept keys store to this workgroup's own 64 sink slots, so that no
+    // line is written by many workgroups at once
+    const uint64_t np = jb.np, s0 = st * kSuperRows, s1 = s0 + kSuperRows < np ? s0 + kSuperRows : np;
     const uint32_t sink = (uint32_t)np + 64u * (blockIdx.x % kSinkGroups) + lane;   // the planner keeps it below 2^32 / key size
-    const uint64_t t1 = t0 + kSuperTiles < jb.ptiles ? t0 + kSuperTiles : jb.ptiles;
-    for (uint32_t j = threadIdx.x; j <= P; j += kPartThreads) {
+    for (uint32_t j = threadIdx.x; j <= P; j += T) {
       next[j] = j < P ? pos[jb.cbase + st * P + j] : 0u;
       cnt[j] = 0;
     }
     K k[kPartItems], kn[kPartItems];
-    load_tile(pkey, np, t0, kn);
+    load_rows<K, T>(pkey, np, s0, kn);
     lds_barrier();
-    for (uint64_t t = t0; t < t1; ++t) {
+    for (uint64_t r0 = s0; r0 < s1; r0 += R) {
 #pragma unroll
       for (uint32_t it = 0; it < kPartItems; ++it) k[it] = kn[it];
-      // per key: region << 16 | rank among the tile's keys of its region (no rank for a key that
+      // per key: region << 16 | rank among the round's keys of its region (no rank for a key that
       // cannot match: see the count)
       uint32_t rr[kPartItems];
-      tile_regions(region, np, t, k, rr);
+      rows_regions<K, T>(region, np, r0, k, rr);
 #pragma unroll
       for (uint32_t it = 0; it < kPartItems; ++it)
         rr[it] = rr[it] < P ? rr[it] << 16 | atomicAdd(&cnt[rr[it]], 1u) : P << 16;
       lds_barrier();
-      if (threadIdx.x < 64) {   // exclusive scan of cnt[0 .. P) into off; off[P] = the tile's kept keys
+      if (threadIdx.x < 64) {   // exclusive scan of cnt[0 .. P) into off; off[P] = the round's kept keys
         const uint32_t per = (P + 63) / 64, j0 = per * lane;
         uint32_t own = 0;
         for (uint32_t u = 0; u < per; ++u)
@@ -459,20 +490,20 @@ __global__ void __launch_bounds__(kPartThreads) k_batch_scatter(const BatchJob* 
           sreg[slot] = (uint16_t)r;
         }
       }
-      if (t + 1 < t1) load_tile(pkey, np, t + 1, kn);
+      if (r0 + R < s1) load_rows<K, T>(pkey, np, r0 + R, kn);
       lds_barrier();
       const uint32_t total = off[P];
 #pragma unroll
       for (uint32_t it = 0; it < kPartItems; ++it) {
-        const uint32_t i = it * kPartThreads + threadIdx.x;
+        const uint32_t i = it * T + threadIdx.x;
         const uint32_t rg = i < total ? (uint32_t)sreg[i] : 0u;
         const uint32_t at = i < total ? next[rg] + (i - off[rg]) : sink;
         gstore_at<K>(dst, at * (uint32_t)sizeof(K), stage[i]);
       }
       lds_barrier();
 #pragma unroll
-      for (uint32_t u = 0; u < (kMaxTableParts + kPartThreads) / kPartThreads; ++u) {   // straight-line: keeps waits exact
-        const uint32_t j = u * kPartThreads + threadIdx.x;
+      for (uint32_t u = 0; u < (kMaxTableParts + T) / T; ++u) {   // straight-line: keeps waits exact
+        const uint32_t j = u * T + threadIdx.x;
         if (j < P) next[j] += cnt[j];
         if (j <= P) cnt[j] = 0;
       }
@@ -1201,15 +1232,16 @@ static vx_status enqueue_batch(vx_ctx* ctx, const BatchRun& r, const BatchConfig
   if (part) {
     const uint64_t ns = r.plan.part_map.size();
     const unsigned g = (unsigned)std::min<uint64_t>(ns, (uint64_t)ctx->cu_count * 8);
+    const unsigned gs = (unsigned)std::min<uint64_t>(ns, (uint64_t)ctx->cu_count);   // one scatter workgroup per CU (its LDS)
     if (ks == 8) {
       hipLaunchKernelGGL(k_batch_count<int64_t>, dim3(g), dim3(kPartThreads), 0, s2, r.jobs_dev, r.part_map, ns, r.tally);
       hipLaunchKernelGGL(k_batch_scan, dim3(J), dim3(kScanBlock), 0, s2, r.jobs_dev, r.tally);
-      hipLaunchKernelGGL(k_batch_scatter<int64_t>, dim3(g), dim3(kPartThreads), 0, s2, r.jobs_dev, r.part_map, ns,
+      hipLaunchKernelGGL((k_batch_scatter<int64_t, scatter_threads<int64_t>()>), dim3(gs), dim3(scatter_threads<int64_t>()), 0, s2, r.jobs_dev, r.part_map, ns,
                          (const uint32_t*)r.tally);
     } else {
       hipLaunchKernelGGL(k_batch_count<int32_t>, dim3(g), dim3(kPartThreads), 0, s2, r.jobs_dev, r.part_map, ns, r.tally);
       hipLaunchKernelGGL(k_batch_scan, dim3(J), dim3(kScanBlock), 0, s2, r.jobs_dev, r.tally);
-      hipLaunchKernelGGL(k_batch_scatter<int32_t>, dim3(g), dim3(kPartThreads), 0, s2, r.jobs_dev, r.part_map, ns,
+      hipLaunchKernelGGL((k_batch_scatter<int32_t, scatter_threads<int32_t>()>), dim3(gs), dim3(scatter_threads<int32_t>()), 0, s2, r.jobs_dev, r.part_map, ns,
                          (const uint32_t*)r.tally);
     }
     VX_HIP(hipGetLastError());
