@@ -236,7 +236,7 @@ constexpr uint32_t kMaxTableParts = 1024;
 constexpr uint32_t kScanBlock = 1024;
 constexpr uint32_t kRegionThreads = 512;
 constexpr uint32_t kStageBytes = 64 << 10;           // LDS for one table region
-constexpr uint32_t kRunUnroll = 4;
+constexpr uint32_t kRunUnroll = 16;                  // keys in flight per lane in the region probe
 constexpr uint32_t kSinkGroups = 256;                // scatter sink slots: 64 per group of workgroups
 
 // How a job maps probe keys to table regions, read from its descriptor once (scalar registers).
@@ -950,7 +950,7 @@ static void plan_regions(BatchPlan* pl, int ks, uint32_t slot_bytes, uint64_t pa
   pl->part_bytes = pl->pkey_bytes = pl->tally_entries = 0;
   pl->part_jobs = pl->region_jobs = 0;
   const uint32_t J = (uint32_t)pl->jobs.size();
-  const uint64_t item_keys = 65536;
+  const uint64_t item_keys = 131072;   // probe keys per work item (its region is staged once)
   for (uint32_t i = 0; i < J; ++i) {
     BatchJob& b = pl->jobs[i];
     const uint64_t table = table_bytes_of(b, slot_bytes);
