@@ -28,7 +28,7 @@
 // region into one contiguous array per region: a count pass tallies each super-tile's keys per
 // region, a per-job scan turns the tallies into positions, and a scatter pass moves the keys.  A
 // probe work item then stages its region in LDS and streams its share of the region's keys.
-// Count, scan and scatter run on a second stream beside the build phase.  Keys that cannot match
+// Count, scan and scatter run on a second stream, the build phase beside the scatter.  Keys that cannot match
 // are dropped: outside the range of a direct table, or outside the smallest and largest build
 // key of a hash table (measured with the ranges, on every call).
 #include <algorithm>
@@ -1233,17 +1233,26 @@ static vx_status enqueue_batch(vx_ctx* ctx, const BatchRun& r, const BatchConfig
     const uint64_t ns = r.plan.part_map.size();
     const unsigned g = (unsigned)std::min<uint64_t>(ns, (uint64_t)ctx->cu_count * 8);
     const unsigned gs = (unsigned)std::min<uint64_t>(ns, (uint64_t)ctx->cu_count);   // one scatter workgroup per CU (its LDS)
-    if (ks == 8) {
+    if (ks == 8)
       hipLaunchKernelGGL(k_batch_count<int64_t>, dim3(g), dim3(kPartThreads), 0, s2, r.jobs_dev, r.part_map, ns, r.tally);
-      hipLaunchKernelGGL(k_batch_scan, dim3(J), dim3(kScanBlock), 0, s2, r.jobs_dev, r.tally);
+    else
+      hipLaunchKernelGGL(k_batch_count<int32_t>, dim3(g), dim3(kPartThreads), 0, s2, r.jobs_dev, r.part_map, ns, r.tally);
+    hipLaunchKernelGGL(k_batch_scan, dim3(J), dim3(kScanBlock), 0, s2, r.jobs_dev, r.tally);
+    // the build phase starts after the count, which reads at the memory's rate: beside the
+    // scatter, which does not, the two slow each other less
+    if (s2 != s) {
+      hipEvent_t counted = get_event(ctx);
+      VX_CHECK(counted, VX_EHIP, "batch: no events");
+      VX_HIP(hipEventRecord(counted, s2));
+      VX_HIP(hipStreamWaitEvent(s, counted, 0));
+      put_event(ctx, counted);
+    }
+    if (ks == 8)
       hipLaunchKernelGGL((k_batch_scatter<int64_t, scatter_threads<int64_t>()>), dim3(gs), dim3(scatter_threads<int64_t>()), 0, s2, r.jobs_dev, r.part_map, ns,
                          (const uint32_t*)r.tally);
-    } else {
-      hipLaunchKernelGGL(k_batch_count<int32_t>, dim3(g), dim3(kPartThreads), 0, s2, r.jobs_dev, r.part_map, ns, r.tally);
-      hipLaunchKernelGGL(k_batch_scan, dim3(J), dim3(kScanBlock), 0, s2, r.jobs_dev, r.tally);
+    else
       hipLaunchKernelGGL((k_batch_scatter<int32_t, scatter_threads<int32_t>()>), dim3(gs), dim3(scatter_threads<int32_t>()), 0, s2, r.jobs_dev, r.part_map, ns,
                          (const uint32_t*)r.tally);
-    }
     VX_HIP(hipGetLastError());
   }
   const unsigned long long* bmap = r.build_map;
