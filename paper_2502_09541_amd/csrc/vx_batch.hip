@@ -28,9 +28,9 @@
 // region into one contiguous array per region: a count pass tallies each super-tile's keys per
 // region, a per-job scan turns the tallies into positions, and a scatter pass moves the keys.  A
 // probe work item then stages its region in LDS and streams its share of the region's keys.
-// Count, scan and scatter run on a second stream, the build phase beside the scatter.  Keys that cannot match
-// are dropped: outside the range of a direct table, or outside the smallest and largest build
-// key of a hash table (measured with the ranges, on every call).
+// Count, scan and scatter run on a second stream, the build phase beside the scatter.  Keys that
+// cannot match are dropped: outside the range of a direct table, or outside the smallest and
+// largest build key of a hash table (measured with the ranges, on every call).
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
