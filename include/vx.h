@@ -524,8 +524,9 @@ typedef struct {
  * Out-of-core sort (Sec. 6.1): the n keys (int32 or int64) in ascending signed order, written
  * back in place.
  * Pass 1 (the paper's SortExKernel) streams runs of chunk_rows keys through the chunk pipeline.
- * Each run is sorted on the GPU by an LSD radix sort (stable multisplit passes of 8 bits) and
- * stored to the context's pinned host scratch by a kernel on a second stream.
+ * Each run is sorted on the GPU by an LSD radix sort (stable passes of 8-bit digits over tiles of
+ * 8192 keys sorted in LDS) and stored to the context's pinned host scratch by a kernel on a
+ * second stream.
  * Pass 2 (the paper's MergeExKernel) cuts every run at the ranks 0, chunk_rows, 2 chunk_rows, ...
  * (vx_merge_cuts).  For each output range it copies the runs' segments in, merges them in a
  * tree of merge-path kernels, and stores the result to its place in the key column.  One run is

@@ -1,10 +1,11 @@
 // Out-of-core sort of a key column larger than the device budget (Sec. 6.1).
 //
 // Pass 1 (the paper's SortExKernel): the column streams through the chunk pipeline in runs of
-// chunk_rows keys.  Each run is sorted on the GPU by an LSD radix sort whose digit passes are the
-// library's stable multisplit (8 bits per pass, the sign bit flipped so that signed order comes
-// out), and is stored to pinned host scratch by a kernel on a second stream: kernel stores to
-// mapped host memory run beside the host-to-device copies.
+// chunk_rows keys.  Each run is sorted on the GPU by an LSD radix sort of 8-bit digits (the sign
+// bit flipped so that signed order comes out) whose stable passes sort tiles of 8192 keys in LDS
+// and write each digit's keys of a tile as one run, and is stored to pinned host scratch by a
+// kernel on a second stream: kernel stores to mapped host memory run beside the host-to-device
+// copies.
 // Pass 2 (the paper's MergeExKernel): every run is cut at the same global ranks (multiples of the
 // run length), found by binary search over the runs on the host.  Output range i then holds one
 // sorted segment of every run.  Its segments are copied in, merged in a tree of pairwise
@@ -108,6 +109,164 @@ __global__ void __launch_bounds__(256) k_store4(const uint32_t* src, uint32_t* d
     dst[i] = src[i];
 }
 
+// ---------------------------------------------------------------- LSD radix digit pass
+//
+// One workgroup per tile of 8192 consecutive keys; wave w holds keys [w*1024, (w+1)*1024) of the
+// tile, 16 per lane in steps of 64.  The histogram launch counts each tile's keys per digit into
+// hist[d * tiles + t] (digit-major), so the exclusive scan of that array is where tile t's keys of
+// digit d start in the output.  The scatter launch ranks the tile's keys by digit in input order
+// (ballots give a lane its rank among the step's lanes of the same digit, a per-wave LDS counter
+// carries the count across steps), sorts the tile into LDS by that rank, and writes it out in
+// LDS order: each digit's keys of the tile form one run of consecutive output addresses, about 32
+// keys long, so the stores fill whole lines.  A stable pass, as LSD radix sorting needs.
+constexpr uint32_t kDigitThreads = 512;
+constexpr uint32_t kDigitWaves = kDigitThreads / 64;
+constexpr uint32_t kDigitItems = 16;                            // keys per lane
+constexpr uint32_t kDigitTile = kDigitThreads * kDigitItems;    // keys per workgroup tile
+constexpr uint32_t kWaveKeys = 64 * kDigitItems;                // keys per wave, contiguous
+
+uint64_t digit_tiles(uint64_t rows) { return std::max<uint64_t>(1, (rows + kDigitTile - 1) / kDigitTile); }
+
+// 8 bits at `shift` of the key's order-preserving unsigned image (sign bit flipped)
+__device__ __forceinline__ uint32_t digit_of(int32_t k, uint32_t shift) {
+  return (((uint32_t)k ^ 0x80000000u) >> shift) & 255u;
+}
+__device__ __forceinline__ uint32_t digit_of(int64_t k, uint32_t shift) {
+  return (uint32_t)((((uint64_t)k ^ 0x8000000000000000ull) >> shift) & 255u);
+}
+
+// the valid lanes of the wave whose digit equals this lane's
+__device__ __forceinline__ unsigned long long same_digit(uint32_t d, bool valid) {
+  unsigned long long m = __ballot(valid);
+#pragma unroll
+  for (uint32_t b = 0; b < 8; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const unsigned long long v = __ballot(bit);
+    m &= bit ? v : ~v;
+  }
+  return m;
+}
+
+// this lane's keys of tile t (zero past n); a full tile loads unconditionally
+template <typename K>
+__device__ __forceinline__ void digit_load(const K* in, uint64_t n, uint64_t first, bool full,
+                                           K (&k)[kDigitItems]) {
+  if (full) {
+#pragma unroll
+    for (uint32_t j = 0; j < kDigitItems; ++j) k[j] = __builtin_nontemporal_load(in + first + j * 64);
+  } else {
+#pragma unroll
+    for (uint32_t j = 0; j < kDigitItems; ++j) k[j] = first + j * 64 < n ? in[first + j * 64] : K(0);
+  }
+}
+
+// rank[j] = number of this wave's earlier keys with key j's digit; cnt[d] ends as the wave's
+// count of digit d (cnt is the wave's own row, zeroed by the caller)
+template <typename K>
+__device__ __forceinline__ void digit_rank(const K (&k)[kDigitItems], uint64_t n, uint64_t first,
+                                           uint32_t shift, uint32_t* cnt, uint32_t (&rank)[kDigitItems]) {
+  const uint32_t lane = threadIdx.x & 63;
+  const unsigned long long lower = (1ull << lane) - 1;
+#pragma unroll
+  for (uint32_t j = 0; j < kDigitItems; ++j) {
+    const bool valid = first + j * 64 < n;
+    const uint32_t d = digit_of(k[j], shift);
+    const unsigned long long peers = same_digit(d, valid);
+    const uint32_t below = (uint32_t)__popcll(peers & lower);
+    const uint32_t c = valid ? cnt[d] : 0u;
+    rank[j] = c + below;
+    // every lane has read cnt[] before the group's first lane advances it
+    __builtin_amdgcn_wave_barrier();
+    if (valid && below == 0) cnt[d] = c + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+template <typename K>
+__global__ void __launch_bounds__(kDigitThreads) k_digit_hist(const K* in, uint64_t n, uint32_t shift,
+                                                             uint32_t* hist) {
+  __shared__ uint32_t cnt[kDigitWaves][256];
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t t = blockIdx.x, tiles = gridDim.x;
+  for (uint32_t i = threadIdx.x; i < kDigitWaves * 256; i += kDigitThreads) (&cnt[0][0])[i] = 0;
+  __syncthreads();
+  const uint64_t first = t * kDigitTile + wave * kWaveKeys + lane;
+  K k[kDigitItems];
+  uint32_t rank[kDigitItems];
+  digit_load(in, n, first, (t + 1) * kDigitTile <= n, k);
+  digit_rank(k, n, first, shift, cnt[wave], rank);
+  __syncthreads();
+  if (threadIdx.x < 256) {
+    uint32_t c = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < kDigitWaves; ++w) c += cnt[w][threadIdx.x];
+    hist[(uint64_t)threadIdx.x * tiles + t] = c;
+  }
+}
+
+// offs[d * tiles + t] = output position of tile t's first key of digit d
+template <typename K>
+__global__ void __launch_bounds__(kDigitThreads) k_digit_scatter(const K* in, K* out, uint64_t n, uint32_t shift,
+                                                                const unsigned long long* offs) {
+  __shared__ K stage[kDigitTile];
+  __shared__ uint32_t cnt[kDigitWaves][256];
+  __shared__ uint32_t dstart[256];
+  __shared__ uint32_t wsum[4];
+  __shared__ unsigned long long gbase[256];
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t t = blockIdx.x, tiles = gridDim.x;
+  for (uint32_t i = threadIdx.x; i < kDigitWaves * 256; i += kDigitThreads) (&cnt[0][0])[i] = 0;
+  __syncthreads();
+  const uint64_t first = t * kDigitTile + wave * kWaveKeys + lane;
+  const bool full = (t + 1) * kDigitTile <= n;
+  K k[kDigitItems];
+  uint32_t rank[kDigitItems];
+  digit_load(in, n, first, full, k);
+  digit_rank(k, n, first, shift, cnt[wave], rank);
+  __syncthreads();
+  // per digit: the waves' exclusive offsets, then the digits' exclusive offsets in the tile
+  uint32_t tot = 0;
+  if (threadIdx.x < 256) {
+#pragma unroll
+    for (uint32_t w = 0; w < kDigitWaves; ++w) {
+      const uint32_t c = cnt[w][threadIdx.x];
+      cnt[w][threadIdx.x] = tot;
+      tot += c;
+    }
+  }
+  uint32_t x = tot;
+#pragma unroll
+  for (uint32_t o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (threadIdx.x < 256 && lane == 63) wsum[wave] = x;
+  __syncthreads();
+  if (threadIdx.x < 256) {
+    uint32_t e = x - tot;
+    for (uint32_t w = 0; w < wave; ++w) e += wsum[w];
+    dstart[threadIdx.x] = e;
+    gbase[threadIdx.x] = offs[(uint64_t)threadIdx.x * tiles + t] - e;
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t j = 0; j < kDigitItems; ++j)
+    if (first + j * 64 < n) {
+      const uint32_t d = digit_of(k[j], shift);
+      stage[dstart[d] + cnt[wave][d] + rank[j]] = k[j];
+    }
+  __syncthreads();
+  const uint32_t m = full ? kDigitTile : (uint32_t)(n - t * kDigitTile);
+#pragma unroll
+  for (uint32_t j = 0; j < kDigitItems; ++j) {
+    const uint32_t p = j * kDigitThreads + threadIdx.x;
+    if (p < m) {
+      const K v = stage[p];
+      out[gbase[digit_of(v, shift)] + p] = v;
+    }
+  }
+}
+
 unsigned grid_of(const vx_ctx* ctx, uint64_t items, uint64_t per_block, uint64_t per_cu) {
   return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((items + per_block - 1) / per_block,
                                                             (uint64_t)ctx->cu_count * per_cu));
@@ -167,37 +326,34 @@ void merge_cuts_t(const K* const* runs, const uint64_t* len, uint32_t n_runs, ui
   }
 }
 
-// LSD radix sort of rows keys from src (left unchanged) into dst, through alt: multisplit passes
-// of 8 bits over the key's bits (int64: 8 passes; int32: the 4 low bytes, then the sign, from
-// the sign-extended value), each stable.  Passes alternate between dst and alt so the last one
-// writes dst.
-vx_status radix_sort_run(vx_ctx* ctx, const void* src, void* alt, void* dst, uint64_t rows, uint32_t ks,
-                         uint32_t* hist, unsigned long long* offs, hipStream_t s) {
-  static const uint32_t kShift64[] = {0, 8, 16, 24, 32, 40, 48, 56};
-  static const uint32_t kShift32[] = {0, 8, 16, 24, 56};
-  const uint32_t* shifts = ks == 8 ? kShift64 : kShift32;
-  const uint32_t passes = ks == 8 ? 8 : 5;
-  const PartGeom g = part_geom(ctx, rows);
-  const void* in = src;
+// LSD radix sort of rows keys from src (left unchanged) into dst, through alt: digit passes of 8
+// bits over the key's order-preserving image (int64: 8 passes, int32: 4), each a histogram
+// launch, the three-launch scan and a tile scatter.  Passes alternate between dst and alt so the
+// last one writes dst.  hist and offs hold 256 * digit_tiles(rows) entries.
+template <typename K>
+vx_status radix_sort_keys(const K* src, K* alt, K* dst, uint64_t rows, uint32_t* hist, unsigned long long* offs,
+                          vx_ctx* ctx, hipStream_t s) {
+  const uint32_t passes = sizeof(K);
+  const uint64_t tiles = digit_tiles(rows);
+  VX_CHECK(tiles < (1ull << 31), VX_EINVAL, "sort: run of %llu keys is too long", (unsigned long long)rows);
+  const K* in = src;
   for (uint32_t p = 0; p < passes; ++p) {
-    void* out = ((passes - 1 - p) % 2 == 0) ? dst : alt;
-    PartSpec ps{};
-    ps.fn = kPartBits;
-    ps.n_parts = 256;
-    ps.log2p = 8;
-    ps.shift = shifts[p];
-    ps.flip_sign = 1;
-    PartIO io{};
-    io.key = in;
-    io.key_size = ks;
-    io.n = rows;
-    io.out_key = out;
-    VX_TRY(part_hist(ctx, ps, io, g, hist, nullptr, nullptr, nullptr, s));
-    VX_TRY(part_scan(ctx, hist, 256, g.waves, nullptr, offs, nullptr, s));
-    VX_TRY(part_scatter(ctx, ps, io, g, offs, s));
+    K* out = ((passes - 1 - p) % 2 == 0) ? dst : alt;
+    hipLaunchKernelGGL(k_digit_hist<K>, dim3((unsigned)tiles), dim3(kDigitThreads), 0, s, in, rows, 8 * p, hist);
+    VX_TRY(part_scan(ctx, hist, 256, (uint32_t)tiles, nullptr, offs, nullptr, s));
+    hipLaunchKernelGGL(k_digit_scatter<K>, dim3((unsigned)tiles), dim3(kDigitThreads), 0, s, in, out, rows, 8 * p,
+                       offs);
+    VX_HIP(hipGetLastError());
     in = out;
   }
   return VX_OK;
+}
+
+vx_status radix_sort_run(vx_ctx* ctx, const void* src, void* alt, void* dst, uint64_t rows, uint32_t ks,
+                         uint32_t* hist, unsigned long long* offs, hipStream_t s) {
+  if (ks == 8)
+    return radix_sort_keys((const int64_t*)src, (int64_t*)alt, (int64_t*)dst, rows, hist, offs, ctx, s);
+  return radix_sort_keys((const int32_t*)src, (int32_t*)alt, (int32_t*)dst, rows, hist, offs, ctx, s);
 }
 
 uint64_t align_to(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
@@ -234,7 +390,7 @@ vx_status sort_impl(vx_ctx* ctx, const vx_sort_desc* d, vx_stats* stats) {
   // buffer, two staging runs) and digit histograms fit the free arena; pass 2 needs 4 runs' room
   const uint64_t free0 = ctx->arena.capacity() - ctx->arena.used();
   auto pass1_bytes = [&](uint64_t rows) {
-    return 5 * align_to(rows * ks, 256) + (uint64_t)256 * part_geom(ctx, rows).waves * 12 + (1ull << 20);
+    return 5 * align_to(rows * ks, 256) + (uint64_t)256 * digit_tiles(rows) * 12 + (1ull << 20);
   };
   uint64_t C = d->chunk_rows;
   if (!C) {
@@ -245,7 +401,7 @@ vx_status sort_impl(vx_ctx* ctx, const vx_sort_desc* d, vx_stats* stats) {
   }
   VX_CHECK(C >= 1, VX_EINVAL, "sort: chunk_rows is 0");
   const uint64_t runs = (n + C - 1) / C;
-  const PartGeom gmax = part_geom(ctx, std::min(C, n));
+  const uint64_t tiles_max = digit_tiles(std::min(C, n));
   const uint64_t run_bytes = align_to(std::min(C, n) * ks, 256);
   // host scratch for the sorted runs (several runs only)
   uint8_t* hs = nullptr;
@@ -262,8 +418,8 @@ vx_status sort_impl(vx_ctx* ctx, const vx_sort_desc* d, vx_stats* stats) {
   {
     ArenaBlock blk;
     blk.a = &ctx->arena;
-    const uint64_t hist_bytes = align_to((uint64_t)256 * gmax.waves * 4, 256);
-    blk.p = ctx->arena.alloc(3 * run_bytes + hist_bytes + (uint64_t)256 * gmax.waves * 8 + 256);
+    const uint64_t hist_bytes = align_to((uint64_t)256 * tiles_max * 4, 256);
+    blk.p = ctx->arena.alloc(3 * run_bytes + hist_bytes + (uint64_t)256 * tiles_max * 8 + 256);
     VX_CHECK(blk.p, VX_EBUDGET, "sort: no room for runs of %llu keys (radix and staging buffers)",
              (unsigned long long)C);
     uint8_t* alt = blk.p;
@@ -291,7 +447,7 @@ vx_status sort_impl(vx_ctx* ctx, const vx_sort_desc* d, vx_stats* stats) {
       VX_HIP(hipEventRecord(e0, ctx->compute));
       VX_TRY(radix_sort_run(ctx, src, alt, stage[b], v.rows, ks, hist, offs, ctx->compute));
       VX_HIP(hipEventRecord(e1, ctx->compute));
-      launches += ks == 8 ? 40 : 25;   // per digit pass: histogram, three scan launches, scatter
+      launches += 5 * ks;   // per digit pass: histogram, three scan launches, scatter
       VX_HIP(hipEventRecord(sorted_ev[b], ctx->compute));
       // a single run is the result: store it in place; otherwise to its rows of the scratch
       uint8_t* dst = (runs > 1 ? (uint8_t*)hs_dev : out_dev) + v.row0 * ks;

@@ -69,6 +69,21 @@ def test_sort_int32_heavy_duplicates(gpu, ctx, n, chunk):
     assert np.array_equal(h.array, want)
 
 
+@pytest.mark.parametrize("n,chunk", [(300_001, 65_536), (3 * 8192 + 1, 0), (8192, 0)])
+def test_sort_int32_full_range(gpu, ctx, n, chunk):
+    """int32 keys over the whole range: every digit value in each of the 4 digit passes, the sign
+    digit last; runs of whole 8192-key tiles plus a ragged tile, one key past a tile, and one
+    exact tile."""
+    rng = np.random.default_rng(11)
+    k = rng.integers(np.iinfo(np.int32).min, np.iinfo(np.int32).max, n, dtype=np.int64, endpoint=True)
+    k = k.astype(np.int32)
+    want = oracle.sort(k).astype(np.int32)
+    h = pinned(gpu, k)
+    _say("sort int32 full range", n, chunk)
+    ctx.sort(h, chunk_rows=chunk)
+    assert np.array_equal(h.array, want)
+
+
 def test_sort_device_column_many_runs(gpu, ctx):
     import torch
     k = _keys(400_000, np.int64, 5)
