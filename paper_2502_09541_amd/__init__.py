@@ -247,6 +247,17 @@ class HostBuffer:
             pass
 
 
+_TORCH_TYPES = None
+
+
+def _torch_types():
+    global _TORCH_TYPES
+    if _TORCH_TYPES is None:
+        import torch
+        _TORCH_TYPES = {torch.int32: VX_I32, torch.int64: VX_I64}
+    return _TORCH_TYPES
+
+
 def col(x):
     """A vx_col for a CUDA tensor, a numpy array (pinned host memory) or a HostBuffer."""
     if isinstance(x, HostBuffer):
@@ -262,11 +273,43 @@ def col(x):
     if isinstance(x, torch.Tensor):
         if not x.is_contiguous():
             raise ValueError("columns must be contiguous")
-        t = {torch.int32: VX_I32, torch.int64: VX_I64}.get(x.dtype)
+        t = _torch_types().get(x.dtype)
         if t is None:
             raise TypeError(f"column dtype {x.dtype} is not int32/int64")
         return Col(x.data_ptr() if x.numel() else None, t, 0)
     raise TypeError(f"unsupported column object {type(x)}")
+
+
+_COL_NP = np.dtype([("data", "<u8"), ("type", "<i4"), ("reserved", "<i4")])
+
+
+def _col_array(xs, none_ok=False):
+    """A vx_col array and a uint64 length array for a list of columns (None entries allowed with
+    none_ok: a null int32 column of length 0).  Contiguous int32/int64 tensors take a short path;
+    anything else goes through col()."""
+    J = len(xs)
+    arr = (Col * max(1, J))()
+    lens = (C.c_uint64 * max(1, J))()
+    if not J:
+        return arr, lens
+    import torch
+    types, tensor = _torch_types(), torch.Tensor
+    ptr, typ, ln = [0] * J, [VX_I32] * J, [0] * J
+    for i, x in enumerate(xs):
+        if x is None and none_ok:
+            continue
+        t = types.get(x.dtype) if isinstance(x, tensor) else None
+        if t is not None and x.dim() == 1 and x.is_contiguous():
+            n = x.numel()
+            ptr[i], typ[i], ln[i] = x.data_ptr() if n else 0, t, n
+        else:
+            c = col(x)
+            ptr[i], typ[i], ln[i] = c.data or 0, c.type, _len(x)
+    v = np.frombuffer(arr, dtype=_COL_NP, count=J)
+    v["data"] = ptr
+    v["type"] = typ
+    np.frombuffer(lens, dtype=np.uint64, count=J)[:] = ln
+    return arr, lens
 
 
 def _cols(xs):
@@ -470,11 +513,9 @@ class Context:
         """Batched joins (device-resident). bpays entries may be None. Returns
         ([[count, sum] per job], stats)."""
         J = len(bkeys)
-        bk = (Col * max(1, J))(*[col(x) for x in bkeys])
-        bp = (Col * max(1, J))(*[col(x) if x is not None else Col(None, VX_I32, 0) for x in bpays])
-        pk = (Col * max(1, J))(*[col(x) for x in pkeys])
-        nb = (C.c_uint64 * max(1, J))(*[_len(x) for x in bkeys])
-        npr = (C.c_uint64 * max(1, J))(*[_len(x) for x in pkeys])
+        bk, nb = _col_array(bkeys)
+        bp, _ = _col_array(bpays, none_ok=True)
+        pk, npr = _col_array(pkeys)
         outs = (Agg * max(1, J))()
         d = JoinDesc()
         d.kind = VX_JOIN_BATCH
@@ -483,7 +524,8 @@ class Context:
         out = JoinOut()
         self._keep_batch = (bk, bp, pk, nb, npr, outs, list(bkeys), list(bpays), list(pkeys))
         _check(lib().vx_join_agg(self.h, C.byref(d), C.byref(out)))
-        return [outs[j].to_list(1) for j in range(J)], out.stats.as_dict()
+        res = np.frombuffer(outs, dtype=np.uint64).reshape(-1, 9)[:J, :2].tolist()
+        return res, out.stats.as_dict()
 
     def join_star(self, dims, fks, meas, groups_cap=4096, late_mat=VX_LATE_AUTO, chunk_rows=0, count_zc=False):
         """Star join + GROUP BY. dims: list of {key, filt, lo, hi, group (or None)}.

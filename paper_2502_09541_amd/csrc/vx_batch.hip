@@ -727,11 +727,12 @@ struct MmJob {
 template <typename K>
 __global__ void __launch_bounds__(256) k_batch_minmax(const MmJob* jobs, uint32_t n_jobs, uint64_t tiles,
                                                       uint32_t tile_rows, unsigned long long* mm) {
-  __shared__ unsigned long long t0[kMaxBatchJobs];
+  extern __shared__ unsigned long long t0[];   // n_jobs first-tile indices
   __shared__ unsigned long long rmin[4], rmax[4];
   for (uint32_t j = threadIdx.x; j < n_jobs; j += blockDim.x) t0[j] = jobs[j].tile0;
   __syncthreads();
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr uint32_t kVec = 16 / sizeof(K);   // keys per 16-byte load
   for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
     uint32_t lo = 0, hi = n_jobs;
     while (hi - lo > 1) {
@@ -741,9 +742,44 @@ __global__ void __launch_bounds__(256) k_batch_minmax(const MmJob* jobs, uint32_
     }
     const MmJob jb = jobs[lo];
     const uint64_t r0 = (t - jb.tile0) * tile_rows, r1 = r0 + tile_rows < jb.n ? r0 + tile_rows : jb.n;
+    const K* key = (const K*)jb.key;
     unsigned long long mn = ~0ull, mx = 0;
-    for (uint64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-      const unsigned long long o = key_ord(((const K*)jb.key)[i]);
+    uint64_t i0 = r0;
+    if (((uintptr_t)(key + r0) & 15) == 0) {
+      // 16-byte loads, four in flight per lane; tile_rows is a multiple of 4 * 256 * kVec
+      const uint64_t nv = (r1 - r0) / kVec;
+      typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+      const u32x4* v = (const u32x4*)(key + r0);
+      uint64_t q = threadIdx.x;
+      for (; q + 3 * 256 < nv; q += 4 * 256) {
+        u32x4 w[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) w[u] = __builtin_nontemporal_load(v + q + u * 256);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const K* e = (const K*)&w[u];
+#pragma unroll
+          for (uint32_t c = 0; c < kVec; ++c) {
+            const unsigned long long o = key_ord(e[c]);
+            mn = o < mn ? o : mn;
+            mx = o > mx ? o : mx;
+          }
+        }
+      }
+      for (; q < nv; q += 256) {
+        const u32x4 w = __builtin_nontemporal_load(v + q);
+        const K* e = (const K*)&w;
+#pragma unroll
+        for (uint32_t c = 0; c < kVec; ++c) {
+          const unsigned long long o = key_ord(e[c]);
+          mn = o < mn ? o : mn;
+          mx = o > mx ? o : mx;
+        }
+      }
+      i0 = r0 + nv * kVec;
+    }
+    for (uint64_t i = i0 + threadIdx.x; i < r1; i += blockDim.x) {
+      const unsigned long long o = key_ord(key[i]);
       mn = o < mn ? o : mn;
       mx = o > mx ? o : mx;
     }
@@ -847,11 +883,12 @@ static vx_status find_direct(vx_ctx* ctx, const vx_batch_join* d, int ks, Direct
   VX_HIP(hipMemcpyAsync(mjd, mj.data(), (uint64_t)J * sizeof(MmJob), hipMemcpyHostToDevice, ctx->compute));
   hipLaunchKernelGGL(k_mm_init, dim3((J + 255) / 256), dim3(256), 0, ctx->compute, mm, J);
   const unsigned g = (unsigned)std::min<uint64_t>(tiles, (uint64_t)ctx->cu_count * 8);
+  const size_t lds = (size_t)J * sizeof(unsigned long long);
   if (ks == 8)
-    hipLaunchKernelGGL(k_batch_minmax<int64_t>, dim3(g), dim3(256), 0, ctx->compute, (const MmJob*)mjd, J, tiles,
+    hipLaunchKernelGGL(k_batch_minmax<int64_t>, dim3(g), dim3(256), lds, ctx->compute, (const MmJob*)mjd, J, tiles,
                        tile_rows, mm);
   else
-    hipLaunchKernelGGL(k_batch_minmax<int32_t>, dim3(g), dim3(256), 0, ctx->compute, (const MmJob*)mjd, J, tiles,
+    hipLaunchKernelGGL(k_batch_minmax<int32_t>, dim3(g), dim3(256), lds, ctx->compute, (const MmJob*)mjd, J, tiles,
                        tile_rows, mm);
   VX_HIP(hipGetLastError());
   std::vector<unsigned long long> h(2 * (uint64_t)J);
