@@ -420,16 +420,22 @@ constexpr uint32_t scatter_threads() { return sizeof(K) == 4 ? 1024 : 512; }
 // neighbouring keys; the order within a region is arbitrary and the aggregates do not depend on
 // it.  Every thread issues kPartItems stores per round (slots past the round's kept keys go to
 // sink slots past the partitioned keys), and the next round's loads are issued before them, so
-// that waiting for those loads never waits for the stores.
+// that waiting for those loads never waits for the stores.  A round takes three barriers: after
+// the ranks, after the scan (which also advances the positions for the next round and clears
+// the counts), and after the sort; a sorted key's region is recomputed from the key when it is
+// stored.
 template <typename K, uint32_t T>
 __global__ void __launch_bounds__(T) k_batch_scatter(const BatchJob* __restrict__ jobs,
                                                      const unsigned long long* __restrict__ part_map,
                                                      uint64_t n_super, const uint32_t* __restrict__ pos) {
   constexpr uint32_t R = T * kPartItems;
   constexpr uint64_t kSuperRows = (uint64_t)kPartRows * kSuperTiles;
-  __shared__ uint32_t next[kMaxTableParts + 1], cnt[kMaxTableParts + 1], off[kMaxTableParts + 1];
+  // per region: next = where the region's next key goes, cnt = the round's keys, off = the
+  // round's first sorted slot, delta = next - off (sorted key i of the region goes to delta + i,
+  // modulo 2^32)
+  __shared__ uint32_t next[kMaxTableParts + 1], cnt[kMaxTableParts + 1], off[kMaxTableParts + 1],
+      delta[kMaxTableParts + 1];
   __shared__ K stage[R];
-  __shared__ uint16_t sreg[R];
   const uint32_t lane = threadIdx.x & 63;
   for (uint64_t g = blockIdx.x; g < n_super; g += gridDim.x) {
     const unsigned long long e = uniform_entry(part_map, g);
@@ -443,6 +449,8 @@ __global__ void __launch_bounds__(T) k_batch_scatter(const BatchJob* __restrict_
     // line is written by many workgroups at once
     const uint64_t np = jb.np, s0 = st * kSuperRows, s1 = s0 + kSuperRows < np ? s0 + kSuperRows : np;
     const uint32_t sink = (uint32_t)np + 64u * (blockIdx.x % kSinkGroups) + lane;   // the planner keeps it below 2^32 / key size
+    // the previous super-tile's last stores, which may still be going on, read only stage, delta
+    // and off[P]
     for (uint32_t j = threadIdx.x; j <= P; j += T) {
       next[j] = j < P ? pos[jb.cbase + st * P + j] : 0u;
       cnt[j] = 0;
@@ -454,13 +462,14 @@ __global__ void __launch_bounds__(T) k_batch_scatter(const BatchJob* __restrict_
 #pragma unroll
       for (uint32_t it = 0; it < kPartItems; ++it) k[it] = kn[it];
       // per key: region << 16 | rank among the round's keys of its region (no rank for a key that
-      // cannot match: see the count)
+      // cannot match: see the count).  cnt was cleared by the previous round's scan; the stores
+      // of the previous round, which may still be going on in other waves, do not read it.
       uint32_t rr[kPartItems];
       rows_regions<K, T>(region, np, r0, k, rr);
 #pragma unroll
       for (uint32_t it = 0; it < kPartItems; ++it)
         rr[it] = rr[it] < P ? rr[it] << 16 | atomicAdd(&cnt[rr[it]], 1u) : P << 16;
-      lds_barrier();
+      lds_barrier();   // the ranks are taken, and every store of the previous round has read its LDS
       if (threadIdx.x < 64) {   // exclusive scan of cnt[0 .. P) into off; off[P] = the round's kept keys
         const uint32_t per = (P + 63) / 64, j0 = per * lane;
         uint32_t own = 0;
@@ -475,8 +484,12 @@ __global__ void __launch_bounds__(T) k_batch_scatter(const BatchJob* __restrict_
         uint32_t run = incl - own;
         for (uint32_t u = 0; u < per; ++u)
           if (j0 + u < P) {
-            off[j0 + u] = run;
-            run += cnt[j0 + u];
+            const uint32_t j = j0 + u, c = cnt[j];
+            off[j] = run;
+            delta[j] = next[j] - run;
+            next[j] += c;
+            cnt[j] = 0;
+            run += c;
           }
         if (lane == 63) off[P] = incl;
       }
@@ -484,11 +497,7 @@ __global__ void __launch_bounds__(T) k_batch_scatter(const BatchJob* __restrict_
 #pragma unroll
       for (uint32_t it = 0; it < kPartItems; ++it) {
         const uint32_t r = rr[it] >> 16;
-        if (r < P) {
-          const uint32_t slot = off[r] + (rr[it] & 0xffffu);
-          stage[slot] = k[it];
-          sreg[slot] = (uint16_t)r;
-        }
+        if (r < P) stage[off[r] + (rr[it] & 0xffffu)] = k[it];
       }
       if (r0 + R < s1) load_rows<K, T>(pkey, np, r0 + R, kn);
       lds_barrier();
@@ -496,18 +505,10 @@ __global__ void __launch_bounds__(T) k_batch_scatter(const BatchJob* __restrict_
 #pragma unroll
       for (uint32_t it = 0; it < kPartItems; ++it) {
         const uint32_t i = it * T + threadIdx.x;
-        const uint32_t rg = i < total ? (uint32_t)sreg[i] : 0u;
-        const uint32_t at = i < total ? next[rg] + (i - off[rg]) : sink;
-        gstore_at<K>(dst, at * (uint32_t)sizeof(K), stage[i]);
+        const K v = stage[i];
+        const uint32_t at = i < total ? delta[region(v)] + i : sink;   // a kept key's region is below P
+        gstore_at<K>(dst, at * (uint32_t)sizeof(K), v);
       }
-      lds_barrier();
-#pragma unroll
-      for (uint32_t u = 0; u < (kMaxTableParts + T) / T; ++u) {   // straight-line: keeps waits exact
-        const uint32_t j = u * T + threadIdx.x;
-        if (j < P) next[j] += cnt[j];
-        if (j <= P) cnt[j] = 0;
-      }
-      lds_barrier();
     }
   }
 }
