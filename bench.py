@@ -12,6 +12,8 @@ roofline fractions (peaks measured live on this machine where the datasheet has 
 and the CPU oracle timed on a bounded sample.
 """
 import argparse
+import contextlib
+import gc
 import json
 import os
 import sys
@@ -178,13 +180,14 @@ def main():
         log(f"warmup {w}: {st['total_ms']:.1f} ms, matches {ref[0]}")
     torch.cuda.synchronize()
     results, stats = [], []
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        r, st = step()
-        results.append(r)
-        stats.append(st)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    with gc_paused():
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            r, st = step()
+            results.append(r)
+            stats.append(st)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
     for k, st in enumerate(stats):
         log(f"step {k}: {st['total_ms']:.1f} ms (build {st['build_ms']:.1f}, probe {st['probe_ms']:.1f})")
     if any(r != results[0] for r in results) or (args.warmup and results[0] != ref):
@@ -311,11 +314,12 @@ def _skew_time(ctx, vx, torch, bk, bp, pk, methods, args, steps, warmup):
                 ref = step()
             torch.cuda.synchronize()
             res = []
-            t0 = time.perf_counter()
-            for _ in range(steps):
-                res.append(step())
-            torch.cuda.synchronize()
-            ms = (time.perf_counter() - t0) * 1e3 / steps
+            with gc_paused():
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    res.append(step())
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) * 1e3 / steps
         except vx.VxError as e:
             if method == methods[0]:
                 raise
@@ -463,17 +467,33 @@ def _common(metric_unit, value, ms, args, dtype, config, roofline, extra=None):
     return out
 
 
+@contextlib.contextmanager
+def gc_paused():
+    """Timed steps run with Python's cyclic garbage collector paused, as timeit runs them: a full
+    collection of this process's objects takes tens of milliseconds and would land in whichever
+    step happens to trigger it."""
+    gc.collect()
+    was = gc.isenabled()
+    gc.disable()
+    try:
+        yield
+    finally:
+        if was:
+            gc.enable()
+
+
 def _timed(step, args, torch):
     ref = None
     for _ in range(args.warmup):
         ref = step()
     torch.cuda.synchronize()
     res = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        res.append(step())
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    with gc_paused():
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            res.append(step())
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
     first = res[0][0]
     if any(r[0] != first for r in res) or (ref is not None and ref[0] != first):
         raise SystemExit("non-deterministic results across steps")
@@ -936,10 +956,11 @@ def run_sort(args):
         if i:
             _fill_sort_keys(h, n)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        st = ctx.sort(h)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) * 1e3
+        with gc_paused():
+            t0 = time.perf_counter()
+            st = ctx.sort(h)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) * 1e3
         if i >= args.warmup:
             times.append(dt)
         log(f"sort step {i}: {dt:.1f} ms (pass 1 {st['part_ms']:.1f}, pass 2 {st['probe_ms']:.1f}, "

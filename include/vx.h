@@ -190,7 +190,7 @@ typedef struct vx_table vx_table;
  * power-of-two capacity no smaller than the range.  A VX_UNIQUE build whose n
  * keys are exactly the n values of their range (no empty-marker key) is dense:
  * every key of the range is present, so its slots hold only the payloads (none
- * without payloads) and a bitmap of the keys seen catches a repeated key.
+ * without payloads) and a presence byte per key of the range catches a repeated key.
  * Results are the same for every layout; a probe then reads one slot, or none
  * for keys outside the range.  Host-resident keys always get a hash table.
  */

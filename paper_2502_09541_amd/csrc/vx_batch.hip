@@ -14,11 +14,12 @@
 //
 // A job whose build keys fill their value range exactly (n unique keys from min to min + n - 1,
 // found by a min/max pass over every job before the graph runs) gets a direct table instead of
-// a hash table: the payload of key k sits at k - min, and a bitmap of the keys seen catches a
-// duplicate (which would leave a key of the range missing).  The build sets the bits without
-// reading them back; a small kernel between the two phases counts each job's bits, and the host
-// compares the count with the job's rows.  A probe key outside the range then costs no memory
-// access, and one inside reads one payload.
+// a hash table: the payload of key k sits at k - min, and a presence byte per key of the range
+// catches a duplicate (which would leave a key of the range missing).  The build sets the bytes
+// with plain stores (distinct keys never share a byte, so no atomic is needed); a small kernel
+// between the two phases counts each job's set bytes, and the host compares the count with the
+// job's rows.  A probe key outside the range then costs no memory access, and one inside reads
+// one payload.
 //
 // Random table reads are what bounds the probe: served by the L2 they reach about half of its
 // request rate, and a table larger than one L2 is read from the MALL or HBM.  So the probe phase
@@ -52,14 +53,14 @@ struct BatchJob {
   const void* pkey;
   uint64_t nb, np;
   uint8_t* slots;         // hash: capacity slots of 8 (int32 key + int32 payload) or 16 bytes;
-                          // direct: the key bitmap ((nb + 63) / 64 words), then the payloads
+                          // direct: a presence byte per key of the range, then the payloads
   uint8_t* dpay;          // direct: payload of key kmin + i at index i
   unsigned long long kmin_ord;   // direct: the smallest key, order-preserving unsigned form
   uint32_t direct;        // 1: direct table
   uint64_t mask;
   uint32_t log2cap;
   uint32_t pay_size;      // 0 (no payload), 4 or 8
-  uint64_t ctile0;        // first bitmap-count tile of the job (direct tables)
+  uint64_t ctile0;        // first presence-count tile of the job (direct tables)
   uint32_t build_tiles, probe_tiles, count_tiles;
   unsigned long long* side;   // sentinel-key record: count, payload sum
   unsigned long long kmax_ord;   // hash: the largest build key (with kmin_ord, the zone a match needs)
@@ -77,6 +78,7 @@ struct BatchJob {
 };
 
 constexpr uint32_t kMaxBatchJobs = 4096;
+constexpr uint32_t kXcds = 8;   // accelerator complex dies of the MI355X, each with its own L2
 
 // Device-memory accesses through pointers read from descriptors, as global (not flat) accesses:
 // flat loads also count against the LDS counter, so every LDS wait would wait for them too.
@@ -99,6 +101,7 @@ __device__ __forceinline__ void gstore_at(void* base, uint32_t byte_off, T v) {
   *(VX_GLOBAL T*)((VX_GLOBAL uint8_t*)base + byte_off) = v;
 }
 
+// Rows [r0, r1) of a job's build side into its table.
 template <typename K>
 __device__ __forceinline__ void batch_build_rows(const BatchJob& jb, uint64_t r0, uint64_t r1,
                                                  uint32_t slot_shift, unsigned int* flags) {
@@ -107,17 +110,18 @@ __device__ __forceinline__ void batch_build_rows(const BatchJob& jb, uint64_t r0
   for (uint64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
     K k = ((const K*)jb.bkey)[i];
     U kb = (U)k;
-    long long v = jb.pay_size ? load_signed(jb.bpay, i, jb.pay_size) : 0;
     if (jb.direct) {
       // every build key lies in [kmin, kmin + nb): the range was measured over these keys.  The
-      // bit is set without reading it back; k_batch_dupcount counts the bits afterwards, and a
-      // job with fewer than nb bits had a repeated key.
+      // presence byte is set by a plain store; k_batch_dupcount counts the set bytes afterwards,
+      // and a job with fewer than nb of them had a repeated key.
       const uint64_t idx = key_ord(k) - jb.kmin_ord;
-      atomicOr((unsigned long long*)jb.slots + (idx >> 6), 1ull << (idx & 63));
+      const long long v = jb.pay_size ? load_signed(jb.bpay, i, jb.pay_size) : 0;
+      jb.slots[idx] = 1;
       if (jb.pay_size == 4) ((int*)jb.dpay)[idx] = (int)v;
       else if (jb.pay_size == 8) ((long long*)jb.dpay)[idx] = v;
       continue;
     }
+    const long long v = jb.pay_size ? load_signed(jb.bpay, i, jb.pay_size) : 0;
     if (kb == kEmpty) {
       unsigned long long prev = atomicAdd(jb.side, 1ull);
       if (prev) atomicOr(flags, kFlagDup);
@@ -653,9 +657,9 @@ __global__ void __launch_bounds__(512) k_batch_phase(const BatchJob* jobs, uint3
   }
 }
 
-// Bits set in the direct-table jobs' bitmaps, per job, into cnt[j] (tile order).  Count tile t
-// belongs to the job whose first count tile is the largest one <= t; each covers kCountWords
-// bitmap words.
+// Presence bytes set in the direct-table jobs' tables, per job, into cnt[j] (tile order).  Count
+// tile t belongs to the job whose first count tile is the largest one <= t; each covers
+// kCountWords 8-byte words.  A byte is 0 or 1, so a word's popcount is its set bytes.
 constexpr uint32_t kCountWords = 4096;
 
 __global__ void __launch_bounds__(256) k_batch_dupcount(const BatchJob* jobs, uint32_t n_jobs, uint64_t tiles,
@@ -672,7 +676,7 @@ __global__ void __launch_bounds__(256) k_batch_dupcount(const BatchJob* jobs, ui
       else hi = mid;
     }
     const BatchJob& jb = jobs[lo];
-    const uint64_t words = (jb.nb + 63) / 64;
+    const uint64_t words = (jb.nb + 7) / 8;   // the bytes past nb up to the 256-byte alignment are 0
     const uint64_t w0 = (t - jb.ctile0) * kCountWords;
     const uint64_t w1 = w0 + kCountWords < words ? w0 + kCountWords : words;
     unsigned long long c = 0;
@@ -832,7 +836,7 @@ struct BatchPlan {
   // and a grid of a multiple of 8 workgroups walks tile t on workgroup t mod grid, so list x
   // runs on XCD x.  A job's build and probe tiles go to the same XCD.
   std::vector<unsigned long long> build_map, probe_map;
-  uint64_t direct_bytes = 0;       // bitmaps and payloads of the direct-table jobs (after them)
+  uint64_t direct_bytes = 0;       // presence bytes and payloads of the direct-table jobs (after them)
   uint32_t slot_shift = 3;
   // probe by regions: the region kernel's work items (kXcds interleaved lists, like the tile
   // maps), the partitioning passes' super-tiles (job << 32 | super-tile), and the bytes of the
@@ -854,7 +858,7 @@ struct DirectInfo {
 uint64_t align256(uint64_t v) { return (v + 255) / 256 * 256; }
 
 uint64_t direct_region_bytes(uint64_t nb, uint32_t ps) {
-  return align256((nb + 63) / 64 * 8) + align256(nb * ps);
+  return align256(nb) + align256(nb * ps);
 }
 
 // Min and max build key of every job in one launch; a job is direct when its nb keys could be
@@ -904,8 +908,6 @@ static vx_status find_direct(vx_ctx* ctx, const vx_batch_join* d, int ks, Direct
   }
   return VX_OK;
 }
-
-constexpr uint32_t kXcds = 8;   // accelerator complex dies of the MI355X, each with its own L2
 
 // The XCD-aware maps.  Work on one table stays on one XCD where the table can stay in that XCD's
 // L2: a job probed through the tile map whose table fits in 3/4 of an L2 gets all of its tiles
@@ -1093,7 +1095,7 @@ static vx_status plan_batch(const vx_batch_join* d, const BatchConfig& cfg, int 
     b.ctile0 = ct;
     b.build_tiles = (uint32_t)((b.nb + cfg.tile_rows - 1) / cfg.tile_rows);
     b.probe_tiles = (uint32_t)((b.np + cfg.tile_rows - 1) / cfg.tile_rows);
-    b.count_tiles = b.direct ? (uint32_t)(((b.nb + 63) / 64 + kCountWords - 1) / kCountWords) : 0;
+    b.count_tiles = b.direct ? (uint32_t)(((b.nb + 7) / 8 + kCountWords - 1) / kCountWords) : 0;
     bt += b.build_tiles;
     pt += b.probe_tiles;
     ct += b.count_tiles;
@@ -1115,7 +1117,7 @@ struct BatchRun {
   BatchJob* jobs_dev = nullptr;
   unsigned long long* counters = nullptr;   // sides, accumulators, bit counts (cleared together)
   unsigned long long* acc = nullptr;         // per job (tile order): count, sum
-  unsigned long long* bits = nullptr;        // per job (tile order): bits set in its direct bitmap
+  unsigned long long* bits = nullptr;        // per job (tile order): presence bytes set in its direct table
   unsigned long long* probe_map = nullptr;   // the plan's tile maps, in device memory
   unsigned long long* build_map = nullptr;
   unsigned long long* region_map = nullptr;  // the region probe's work items
@@ -1196,7 +1198,7 @@ static vx_status setup_run(vx_ctx* ctx, const vx_batch_join* d, const BatchConfi
     BatchJob& b = r->plan.jobs[j];
     if (b.direct) {
       b.slots = r->slots + hash_bytes + (uint64_t)(uintptr_t)b.slots;
-      b.dpay = b.slots + align256((b.nb + 63) / 64 * 8);
+      b.dpay = b.slots + align256(b.nb);
     } else {
       b.slots = r->slots + (((uint64_t)(uintptr_t)b.slots) << pl.slot_shift);
     }
@@ -1225,7 +1227,7 @@ static void launch_dupcount(vx_ctx* ctx, const BatchRun& r, uint32_t J, hipStrea
   hipLaunchKernelGGL(k_batch_dupcount, dim3(g), dim3(256), 0, s, r.jobs_dev, J, r.plan.count_tiles, r.bits);
 }
 
-// A direct-table job whose bitmap holds fewer than nb bits had a repeated build key.
+// A direct-table job with fewer than nb presence bytes set had a repeated build key.
 static bool direct_dups(const BatchPlan& pl, const unsigned long long* bits) {
   for (size_t i = 0; i < pl.jobs.size(); ++i)
     if (pl.jobs[i].direct && bits[i] != pl.jobs[i].nb) return true;
@@ -1331,7 +1333,7 @@ static vx_status enqueue_batch(vx_ctx* ctx, const BatchRun& r, const BatchConfig
     put_event(ctx, ev_done);
   }
   VX_HIP(hipGetLastError());
-  if (host_out) {   // accumulators and bit counts are contiguous: 3 J words, then the flags
+  if (host_out) {   // accumulators and presence counts are contiguous: 3 J words, then the flags
     VX_HIP(hipMemcpyAsync(host_out, r.acc, 3 * (uint64_t)J * 8, hipMemcpyDeviceToHost, s));
     VX_HIP(hipMemcpyAsync(host_out + 3 * (uint64_t)J, ctx->dev_flags, 4, hipMemcpyDeviceToHost, s));
   }
@@ -1575,7 +1577,7 @@ vx_status join_batch(vx_ctx* ctx, const vx_batch_join* d, vx_join_out* out) {
              VX_EDUPKEY, "batch: duplicate build key");
     VX_CHECK(!(f & kFlagFull), VX_ECAPACITY, "batch: table full (internal sizing error)");
     s.kernel_ms = ms;
-    // build phase, bit count, tile-map probe, count, scan, scatter, region probe
+    // build phase, presence count, tile-map probe, count, scan, scatter, region probe
     const BatchPlan& gp = gc->run->plan;
     s.kernel_launches = 1 + (gp.count_tiles ? 1 : 0) + (gp.probe_map.empty() ? 0 : 1) + (gp.part_jobs ? 3 : 0) +
                         (gp.region_map.empty() ? 0 : 1);

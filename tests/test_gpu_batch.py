@@ -296,3 +296,53 @@ def test_batch_partitioned_probe(gpu, kt, monkeypatch):
     with gpu.Context(2 * GiB) as c:
         got, st = c.join_batch(*args, tile_rows=1024, block=256, load_factor=0.5)
     assert got == exp and st["n_parts"] == 0 and st["kernel_launches"] == 3
+
+
+@pytest.mark.parametrize("kt,pt", [(np.int32, np.int32), (np.int64, np.int32), (np.int64, np.int64)])
+def test_batch_direct_tables_larger_than_l2(gpu, ctx, kt, pt):
+    """Direct tables of 6 MB and more of payloads (their probe sides partitioned into regions),
+    beside a direct table that fits an L2 and a hash table, int32 and int64 payloads: against the
+    oracle in the graph (two replays, the tuned and an explicit configuration) and in the per-job
+    baseline."""
+    rng = np.random.default_rng(31)
+    info = np.iinfo(kt)
+    specs = [(1_500_001, -700_000), (1_000_003, int(info.max) - 1_000_002), (400_000, 12), (200_000, None)]
+    bk, bp, pk = [], [], []
+    for n, base in specs:
+        if base is None:
+            k = np.unique(rng.integers(-10**9, 10**9, n + n // 8)).astype(kt)[:n]
+            rng.shuffle(k)
+        else:
+            k = (rng.permutation(n).astype(np.int64) + base).astype(kt)
+        bk.append(k)
+        bp.append(rng.integers(np.iinfo(pt).min, np.iinfo(pt).max, n, dtype=np.int64, endpoint=True).astype(pt))
+        lo = max(int(info.min), int(k.min()) - n // 4)
+        hi = min(int(info.max), int(k.max()) + n // 4)
+        q = np.concatenate([rng.integers(lo, hi, n, dtype=np.int64, endpoint=True).astype(kt), k[rng.integers(0, n, n)]])
+        rng.shuffle(q)
+        pk.append(q)
+    exp = [oracle.join_agg(a, [b], c, []) for a, b, c in zip(bk, bp, pk)]
+    args = ([dev(x) for x in bk], [dev(x) for x in bp], [dev(x) for x in pk])
+    for cfg in ({}, {"tile_rows": 8192, "block": 512, "load_factor": 0.7}):
+        _say("batch large direct tables", kt.__name__, pt.__name__, "config", cfg)
+        for rep in range(2):
+            got, _ = ctx.join_batch(*args, **cfg)
+            assert got == exp, f"replay {rep}"
+    got, _ = ctx.join_batch(*args, mode=1)
+    assert got == exp
+
+
+def test_batch_direct_large_duplicate_detected(gpu, ctx):
+    """A repeated key in a direct table of 1.2 M keys (filling their range by count, one value
+    missing) is found by the presence count, in the graph and in the per-job baseline."""
+    rng = np.random.default_rng(5)
+    n = 1_200_000
+    k = rng.permutation(n).astype(np.int32)
+    lo, hi = int(np.argmin(k)), int(np.argmax(k))
+    i, j = [x for x in range(10) if x not in (lo, hi)][:2]
+    k[i] = k[j]
+    for mode in (0, 1):
+        with pytest.raises(gpu.VxError) as ei:
+            ctx.join_batch([dev(k)], [dev(rng.integers(0, 100, n).astype(np.int32))], [dev(k[:1000])], mode=mode,
+                           tile_rows=8192, block=512, load_factor=0.5)
+        assert ei.value.status == gpu.VX_EDUPKEY
