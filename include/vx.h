@@ -323,7 +323,7 @@ typedef struct {
  * their value range exactly (n unique keys from min to min + n - 1, measured on every call) is
  * joined through a direct table indexed by key - min; other jobs through hash tables, which drop
  * probe keys outside the build keys' range.  Mode 0 probes tables from LDS: a table of at most
- * 64 KiB whole, a larger one by regions of 64 KiB, for which the job's probe keys are first
+ * 128 KiB whole, a larger one by regions of 128 KiB, for which the job's probe keys are first
  * partitioned by region into arena memory (about 4 or 8 bytes per probe row; a job whose buffers
  * do not fit the arena is probed from device memory instead).  Results do not depend on any of
  * this.  Mode-0 stats: n_parts = jobs whose probe side was partitioned, survivors = jobs probed

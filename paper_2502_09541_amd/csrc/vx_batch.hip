@@ -23,12 +23,13 @@
 //
 // Random table reads are what bounds the probe: served by the L2 they reach about half of its
 // request rate, and a table larger than one L2 is read from the MALL or HBM.  So the probe phase
-// reads every table from LDS instead.  A table of at most 64 KiB is staged whole by each probe
-// work item.  A larger one is cut into regions of 64 KiB (key - min for a direct table, the top
+// reads every table from LDS instead.  A table of at most 128 KiB is staged whole by each probe
+// work item.  A larger one is cut into regions of 128 KiB (key - min for a direct table, the top
 // bits of the first slot for a hash table), and the job's probe keys are first partitioned by
 // region into one contiguous array per region: a count pass tallies each super-tile's keys per
 // region, a per-job scan turns the tallies into positions, and a scatter pass moves the keys.  A
-// probe work item then stages its region in LDS and streams its share of the region's keys.
+// probe work item (one 1024-thread workgroup per compute unit, its LDS) then stages its region
+// and streams its share of the region's keys, about a million.
 // Count, scan and scatter run on a second stream, the build phase beside the scatter.  Keys that
 // cannot match are dropped: outside the range of a direct table, or outside the smallest and
 // largest build key of a hash table (measured with the ranges, on every call).
@@ -130,6 +131,30 @@ __device__ __forceinline__ void batch_build_rows(const BatchJob& jb, uint64_t r0
     }
     uint64_t h = slot_of(key_bits(k), jb.log2cap);
     bool done = false;
+    if constexpr (sizeof(K) == 4) {
+      if (jb.pay_size != 8) {
+        // an 8-byte slot (int32 key, int32 payload or none): one 64-bit compare-and-swap claims
+        // the slot and writes the payload with it.  An empty slot is exactly (empty marker, 0):
+        // the init zeroes payloads, and the empty-marker key itself goes to the side record.
+        const unsigned long long empty = (unsigned long long)(uint32_t)kEmpty;
+        const unsigned long long want = (unsigned long long)(uint32_t)kb | ((unsigned long long)(uint32_t)(int)v << 32);
+        for (uint64_t step = 0; step <= jb.mask; ++step) {
+          const unsigned long long prev = atomicCAS((unsigned long long*)(jb.slots + (h << slot_shift)), empty, want);
+          if (prev == empty) {
+            done = true;
+            break;
+          }
+          if ((uint32_t)prev == (uint32_t)kb) {
+            atomicOr(flags, kFlagDup);
+            done = true;
+            break;
+          }
+          h = (h + 1) & jb.mask;
+        }
+        if (!done) atomicOr(flags, kFlagFull);
+        continue;
+      }
+    }
     for (uint64_t step = 0; step <= jb.mask; ++step) {
       uint8_t* slot = jb.slots + (h << slot_shift);
       U prev = atomicCAS((U*)slot, kEmpty, kb);
@@ -238,8 +263,9 @@ constexpr uint32_t kPartThreads = 256, kPartItems = 16, kPartRows = kPartThreads
 constexpr uint32_t kSuperTiles = 16;                 // partition tiles per super-tile (65536 rows)
 constexpr uint32_t kMaxTableParts = 1024;
 constexpr uint32_t kScanBlock = 1024;
-constexpr uint32_t kRegionThreads = 512;
-constexpr uint32_t kStageBytes = 64 << 10;           // LDS for one table region
+constexpr uint32_t kLdsBytes = 160 << 10;            // LDS per compute unit
+constexpr uint32_t kRegionThreads = 1024;
+constexpr uint32_t kStageBytes = 128 << 10;          // LDS for one table region
 constexpr uint32_t kRunUnroll = 16;                  // keys in flight per lane in the region probe
 constexpr uint32_t kSinkGroups = 256;                // scatter sink slots: 64 per group of workgroups
 
@@ -990,7 +1016,7 @@ static void plan_regions(BatchPlan* pl, int ks, uint32_t slot_bytes, uint64_t pa
   pl->part_bytes = pl->pkey_bytes = pl->tally_entries = 0;
   pl->part_jobs = pl->region_jobs = 0;
   const uint32_t J = (uint32_t)pl->jobs.size();
-  const uint64_t item_keys = 131072;   // probe keys per work item (its region is staged once)
+  const uint64_t item_keys = 1 << 20;   // probe keys per work item (its region is staged once per item)
   for (uint32_t i = 0; i < J; ++i) {
     BatchJob& b = pl->jobs[i];
     const uint64_t table = table_bytes_of(b, slot_bytes);
@@ -1308,7 +1334,7 @@ static vx_status enqueue_batch(vx_ctx* ctx, const BatchRun& r, const BatchConfig
     VX_HIP(hipStreamWaitEvent(s2, ev_built, 0));
     put_event(ctx, ev_built);
     const uint64_t items = r.plan.region_map.size();
-    unsigned g = (unsigned)std::min<uint64_t>(items, (uint64_t)ctx->cu_count * 2);   // two 64 KiB stages per CU
+    unsigned g = (unsigned)std::min<uint64_t>(items, (uint64_t)ctx->cu_count * (kLdsBytes / kStageBytes));   // stages per CU
     g = std::max(kXcds, g / kXcds * kXcds);
     if (ks == 8)
       hipLaunchKernelGGL(k_batch_region<int64_t>, dim3(g), dim3(kRegionThreads), 0, s2, r.jobs_dev, r.region_map, items,

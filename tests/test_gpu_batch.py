@@ -60,7 +60,7 @@ def test_batch_explicit_configs_and_graph_replay(gpu, ctx):
         torch.cuda.synchronize()
         _ = (args[2][0] + 1).sum().item()
     # one graph: build phase, bit count of the direct tables (these jobs' keys fill their ranges), and
-    # the probe by regions: count, scan and scatter of the probe sides whose tables exceed 64 KiB,
+    # the probe by regions: count, scan and scatter of the probe sides whose tables exceed the stage,
     # then the region probe
     assert st["kernel_launches"] == 6 and st["n_parts"] > 0
 
