@@ -81,6 +81,27 @@ def test_batch_edges(gpu, ctx):
     assert ei.value.status == gpu.VX_EDUPKEY
 
 
+def test_batch_hash_duplicate_detected(gpu, ctx):
+    """A repeated key with a different payload in a hash-table job (the insert that claims key and
+    payload in one 64-bit compare-and-swap finds the key already there), and in a job whose keys
+    would take a direct table but are forced into a hash table; both modes."""
+    rng = np.random.default_rng(8)
+    k = np.unique(rng.integers(-10**9, 10**9, 20_000)).astype(np.int32)
+    rng.shuffle(k)
+    k = np.concatenate([k, k[:1]])
+    pay = rng.integers(-100, 100, len(k)).astype(np.int32)
+    pay[-1] = pay[0] + 1
+    cases = [([dev(k)], [dev(pay)], False),
+             ([dev(np.array([0, 1, 1, 3], np.int32))], [dev(np.array([5, 6, 7, 8], np.int32))], True)]
+    for bks, bps, hashed in cases:
+        for mode in (0, 1):
+            _say("batch hash duplicate", len(bks[0]), "hashed", hashed, "mode", mode)
+            with pytest.raises(gpu.VxError) as ei:
+                ctx.join_batch(bks, bps, [dev(np.array([1, 2], np.int32))], mode=mode, hashed=hashed,
+                               tile_rows=1024, block=256, load_factor=0.5)
+            assert ei.value.status == gpu.VX_EDUPKEY
+
+
 def test_batch_int64_keys(gpu, ctx):
     rng = np.random.default_rng(3)
     bk = [rng.permutation(1 << 40)[:0] if False else np.unique(rng.integers(-2**60, 2**60, n)).astype(np.int64)
