@@ -260,6 +260,7 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 constexpr uint32_t kPartThreads = 256, kPartItems = 16, kPartRows = kPartThreads * kPartItems;
+constexpr uint32_t kScatterItems = 16;               // keys per lane in a scatter round
 constexpr uint32_t kSuperTiles = 16;                 // partition tiles per super-tile (65536 rows)
 constexpr uint32_t kMaxTableParts = 1024;
 constexpr uint32_t kScanBlock = 1024;
@@ -414,41 +415,41 @@ __global__ void __launch_bounds__(kScanBlock) k_batch_scan(const BatchJob* __res
   }
 }
 
-// Rows r0 .. r0 + T kPartItems of a job's probe keys, kPartItems per thread of T (rows past the
+// Rows r0 .. r0 + T kScatterItems of a job's probe keys, kScatterItems per thread of T (rows past the
 // end reread the last row), and their regions (`parts` for a key that cannot match or a row past
 // the end).
 template <typename K, uint32_t T>
-__device__ __forceinline__ void load_rows(const void* pkey, uint64_t np, uint64_t r0, K (&k)[kPartItems]) {
-  const uint32_t last = (uint32_t)(np - r0 < T * kPartItems ? np - r0 : T * kPartItems) - 1;
+__device__ __forceinline__ void load_rows(const void* pkey, uint64_t np, uint64_t r0, K (&k)[kScatterItems]) {
+  const uint32_t last = (uint32_t)(np - r0 < T * kScatterItems ? np - r0 : T * kScatterItems) - 1;
 #pragma unroll
-  for (uint32_t it = 0; it < kPartItems; ++it) {
+  for (uint32_t it = 0; it < kScatterItems; ++it) {
     const uint32_t row = it * T + threadIdx.x;
     k[it] = gload_nt<K>(pkey, r0 + (row < last ? row : last));
   }
 }
 
 template <typename K, uint32_t T>
-__device__ __forceinline__ void rows_regions(const RegionFn& region, uint64_t np, uint64_t r0, const K (&k)[kPartItems],
-                                             uint32_t (&r)[kPartItems]) {
-  const uint32_t n = (uint32_t)(np - r0 < T * kPartItems ? np - r0 : T * kPartItems);
+__device__ __forceinline__ void rows_regions(const RegionFn& region, uint64_t np, uint64_t r0, const K (&k)[kScatterItems],
+                                             uint32_t (&r)[kScatterItems]) {
+  const uint32_t n = (uint32_t)(np - r0 < T * kScatterItems ? np - r0 : T * kScatterItems);
 #pragma unroll
-  for (uint32_t it = 0; it < kPartItems; ++it) {
+  for (uint32_t it = 0; it < kScatterItems; ++it) {
     const uint32_t row = it * T + threadIdx.x;
     r[it] = row < n ? region(k[it]) : region.parts;
   }
 }
 
-// Workgroup size of the scatter: one round sorts T kPartItems keys in LDS (16384 int32 or 8192
+// Workgroup size of the scatter: one round sorts T kScatterItems keys in LDS (16384 int32 or 8192
 // int64 keys), so that a region's run per round is about a line on the bench's batch.
 template <typename K>
 constexpr uint32_t scatter_threads() { return sizeof(K) == 4 ? 1024 : 512; }
 
 // Scatter pass: each kept key of super-tile st to its region's array, at the super-tile's
-// position for the region plus its rank.  The super-tile goes in rounds of T kPartItems keys; each
+// position for the region plus its rank.  The super-tile goes in rounds of T kScatterItems keys; each
 // round is first sorted by region in LDS (the rank of a key among the round's keys of its region
 // comes from an LDS counter), then written out in runs, so that neighbouring lanes store
 // neighbouring keys; the order within a region is arbitrary and the aggregates do not depend on
-// it.  Every thread issues kPartItems stores per round (slots past the round's kept keys go to
+// it.  Every thread issues kScatterItems stores per round (slots past the round's kept keys go to
 // sink slots past the partitioned keys), and the next round's loads are issued before them, so
 // that waiting for those loads never waits for the stores.  A round takes three barriers: after
 // the ranks, after the scan (which also advances the positions for the next round and clears
@@ -458,7 +459,7 @@ template <typename K, uint32_t T>
 __global__ void __launch_bounds__(T) k_batch_scatter(const BatchJob* __restrict__ jobs,
                                                      const unsigned long long* __restrict__ part_map,
                                                      uint64_t n_super, const uint32_t* __restrict__ pos) {
-  constexpr uint32_t R = T * kPartItems;
+  constexpr uint32_t R = T * kScatterItems;
   constexpr uint64_t kSuperRows = (uint64_t)kPartRows * kSuperTiles;
   // per region: next = where the region's next key goes, cnt = the round's keys, off = the
   // round's first sorted slot, delta = next - off (sorted key i of the region goes to delta + i,
@@ -485,19 +486,19 @@ __global__ void __launch_bounds__(T) k_batch_scatter(const BatchJob* __restrict_
       next[j] = j < P ? pos[jb.cbase + st * P + j] : 0u;
       cnt[j] = 0;
     }
-    K k[kPartItems], kn[kPartItems];
+    K k[kScatterItems], kn[kScatterItems];
     load_rows<K, T>(pkey, np, s0, kn);
     lds_barrier();
     for (uint64_t r0 = s0; r0 < s1; r0 += R) {
 #pragma unroll
-      for (uint32_t it = 0; it < kPartItems; ++it) k[it] = kn[it];
+      for (uint32_t it = 0; it < kScatterItems; ++it) k[it] = kn[it];
       // per key: region << 16 | rank among the round's keys of its region (no rank for a key that
       // cannot match: see the count).  cnt was cleared by the previous round's scan; the stores
       // of the previous round, which may still be going on in other waves, do not read it.
-      uint32_t rr[kPartItems];
+      uint32_t rr[kScatterItems];
       rows_regions<K, T>(region, np, r0, k, rr);
 #pragma unroll
-      for (uint32_t it = 0; it < kPartItems; ++it)
+      for (uint32_t it = 0; it < kScatterItems; ++it)
         rr[it] = rr[it] < P ? rr[it] << 16 | atomicAdd(&cnt[rr[it]], 1u) : P << 16;
       lds_barrier();   // the ranks are taken, and every store of the previous round has read its LDS
       if (threadIdx.x < 64) {   // exclusive scan of cnt[0 .. P) into off; off[P] = the round's kept keys
@@ -525,7 +526,7 @@ __global__ void __launch_bounds__(T) k_batch_scatter(const BatchJob* __restrict_
       }
       lds_barrier();
 #pragma unroll
-      for (uint32_t it = 0; it < kPartItems; ++it) {
+      for (uint32_t it = 0; it < kScatterItems; ++it) {
         const uint32_t r = rr[it] >> 16;
         if (r < P) stage[off[r] + (rr[it] & 0xffffu)] = k[it];
       }
@@ -533,7 +534,7 @@ __global__ void __launch_bounds__(T) k_batch_scatter(const BatchJob* __restrict_
       lds_barrier();
       const uint32_t total = off[P];
 #pragma unroll
-      for (uint32_t it = 0; it < kPartItems; ++it) {
+      for (uint32_t it = 0; it < kScatterItems; ++it) {
         const uint32_t i = it * T + threadIdx.x;
         const K v = stage[i];
         const uint32_t at = i < total ? delta[region(v)] + i : sink;   // a kept key's region is below P
