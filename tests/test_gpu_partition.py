@@ -291,6 +291,46 @@ def test_cdf_train_deterministic_and_descends(gpu, ctx):
     assert np.allclose(q[big], qo[big], rtol=0, atol=1e-6)
 
 
+def _oracle_train(p0, x, t, steps, lr=1e-2, flip=None):
+    """The oracle's trajectory: full-batch Adam from p0 with the trainer's cosine learning rate,
+    each step from the oracle's gradient rounded to FP32.  flip (a numpy Generator): every
+    gradient component moved one FP32 ulp up or down at random, to measure how far rounding
+    alone carries the trajectory."""
+    p, m, v = p0.copy(), np.zeros_like(p0), np.zeros_like(p0)
+    for k in range(1, steps + 1):
+        _, g = oracle.mlp_loss_grad(p, x, t)
+        g = g.astype(np.float32)
+        if flip is not None:
+            g = np.nextafter(g, np.where(flip.random(len(g)) < 0.5, -np.inf, np.inf).astype(np.float32))
+        oracle.adam_step(p, m, v, g, k, lr=lr * (1 + np.cos(np.pi * (k - 1) / steps)) / 2)
+    return p, oracle.mlp_loss_grad(p, x, t)[0]
+
+
+def test_cdf_train_trajectory_parity(gpu, ctx):
+    """50 training steps on the GPU against the oracle's 50 steps from the same start (its gradient
+    and its Adam step, both pinned on their own): the final loss and the model's outputs on the
+    training points agree within 100 times what a one-ulp change of every gradient component does
+    to the oracle's own trajectory (about 1e-7 here), and never closer than 1e-5 is required."""
+    import torch
+    rng = np.random.default_rng(3)
+    s = np.sort(rng.zipf(1.2, 100_000)).astype(np.int64)
+    x = oracle.cdf_feature(s, s[0], oracle.feature_scale(s[0], s[-1]))
+    t = oracle.cdf_targets(s)
+    H, steps = 64, 50
+    p0 = np.concatenate([np.ones(H), -np.arange(H) / H, np.full(H, 1 / H), [0]]).astype(np.float32)
+    po, lo = _oracle_train(p0, x, t, steps)
+    pf, lf = _oracle_train(p0, x, t, steps, flip=np.random.default_rng(1))
+    yo, yf = oracle.mlp_forward(po, x), oracle.mlp_forward(pf, x)
+    tol_y = max(1e-5, 100 * float(np.abs(yo - yf).max()))
+    tol_l = max(1e-5, 100 * abs(lo - lf) / lo)
+    _say("cdf train trajectory", steps, "tolerances", tol_y, tol_l)
+    pg, lg = ctx.cdf_train(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda(), p0, steps)
+    assert lo < 0.5 * oracle.mlp_loss_grad(p0, x, t)[0]            # the oracle's run does train
+    assert abs(lg - lo) <= tol_l * lo, (lg, lo)
+    yg = oracle.mlp_forward(pg, x)
+    assert float(np.abs(yg - yo).max()) <= tol_y, float(np.abs(yg - yo).max())
+
+
 def test_auto_method_reports_estimates(gpu, ctx):
     rng = np.random.default_rng(8)
     key = rng.zipf(1.1, 2_000_000).astype(np.int64)
