@@ -112,8 +112,10 @@ typedef struct {
   double zc_stride_gelems[8];   /* elements per ns at each stride */
   double d2h_gbs;               /* device-to-host copy rate (64 MiB copies) */
   double duplex_sdma_gbs;       /* host-to-device and device-to-host copies at once, both directions summed */
-  double zc_write_gbs;          /* kernel stores to mapped pinned host memory */
-  double duplex_zcw_gbs;        /* host-to-device copies beside kernel stores to host, summed */
+  double zc_write_gbs;          /* kernel stores to mapped pinned host memory (16-byte stores,
+                                   one workgroup per 16 compute units) */
+  double duplex_zcw_gbs;        /* host-to-device copies beside such kernel stores to host, summed;
+                                   the best of three runs */
   double duplex_zcr_gbs;        /* kernel reads of host memory beside device-to-host copies, summed */
 } vx_link_calib;
 

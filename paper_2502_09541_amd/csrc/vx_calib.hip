@@ -18,17 +18,19 @@ __global__ void k_calib_read(const unsigned long long* p, uint64_t n_elems, uint
   if (acc == 0x9E3779B97F4A7C15ull) atomicAdd(sink, 1ull);
 }
 
+// Writes n 8-byte words of device memory with vector stores.
 __global__ void k_calib_fill(unsigned long long* p, uint64_t n) {
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * blockDim.x)
     p[i] = i * 0x9E3779B97F4A7C15ull;
 }
 
-// Writes n 8-byte words (device memory or mapped host memory) with vector stores.
-__global__ void k_calib_write(unsigned long long* p, uint64_t n) {
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+// Writes n16 16-byte words of mapped host memory, the form the library's stores to host
+// memory take.
+__global__ void k_calib_write16(uint4* p, uint64_t n16) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n16;
        i += (uint64_t)gridDim.x * blockDim.x)
-    p[i] = i;
+    p[i] = make_uint4((uint32_t)i, (uint32_t)(i >> 32), 0u, 1u);
 }
 
 static vx_status time_read(vx_ctx* ctx, const void* p, uint64_t bytes, uint64_t step, unsigned grid,
@@ -154,25 +156,29 @@ extern "C" vx_status vx_calibrate(vx_ctx* ctx, void* pinned, uint64_t bytes, vx_
   VX_HIP(hipEventRecord(e2, ctx->d2h));
   VX_TRY(span_ms(e0, e1, e2, &ms));
   out->duplex_sdma_gbs = 2.0 * dbytes / (ms * 1e6);
-  // kernel stores to mapped host memory, alone
-  hipLaunchKernelGGL(k_calib_write, dim3(grid), dim3(256), 0, ctx->compute, (unsigned long long*)hs_dev,
-                     chunk / 8);
+  // kernel stores to mapped host memory, alone: 16-byte stores from one workgroup per 16 compute
+  // units, the form the library's stores to host memory take (more workgroups slow the kernels
+  // beside them and gain nothing)
+  const unsigned wgrid = (unsigned)std::max(1, ctx->cu_count / 16);
+  hipLaunchKernelGGL(k_calib_write16, dim3(wgrid), dim3(256), 0, ctx->compute, (uint4*)hs_dev, chunk / 16);
   VX_HIP(hipEventRecord(e0, ctx->compute));
-  hipLaunchKernelGGL(k_calib_write, dim3(grid), dim3(256), 0, ctx->compute, (unsigned long long*)hs_dev,
-                     dbytes / 8);
+  hipLaunchKernelGGL(k_calib_write16, dim3(wgrid), dim3(256), 0, ctx->compute, (uint4*)hs_dev, dbytes / 16);
   VX_HIP(hipEventRecord(e1, ctx->compute));
   VX_TRY(span_ms(e0, e1, e1, &ms));
   out->zc_write_gbs = dbytes / (ms * 1e6);
-  // host-to-device copies beside kernel stores to host
-  VX_HIP(hipEventRecord(e0, ctx->compute));
-  VX_HIP(hipStreamWaitEvent(ctx->copy, e0, 0));
-  VX_TRY(h2d_copies());
-  hipLaunchKernelGGL(k_calib_write, dim3(grid), dim3(256), 0, ctx->compute, (unsigned long long*)hs_dev,
-                     dbytes / 8);
-  VX_HIP(hipEventRecord(e1, ctx->copy));
-  VX_HIP(hipEventRecord(e2, ctx->compute));
-  VX_TRY(span_ms(e0, e1, e2, &ms));
-  out->duplex_zcw_gbs = 2.0 * dbytes / (ms * 1e6);
+  // host-to-device copies beside kernel stores to host: the best of three runs (the rate the
+  // sort and the partition passes move at, so its peak is taken as a maximum)
+  out->duplex_zcw_gbs = 0;
+  for (int trial = 0; trial < 3; ++trial) {
+    VX_HIP(hipEventRecord(e0, ctx->compute));
+    VX_HIP(hipStreamWaitEvent(ctx->copy, e0, 0));
+    VX_TRY(h2d_copies());
+    hipLaunchKernelGGL(k_calib_write16, dim3(wgrid), dim3(256), 0, ctx->compute, (uint4*)hs_dev, dbytes / 16);
+    VX_HIP(hipEventRecord(e1, ctx->copy));
+    VX_HIP(hipEventRecord(e2, ctx->compute));
+    VX_TRY(span_ms(e0, e1, e2, &ms));
+    out->duplex_zcw_gbs = std::max(out->duplex_zcw_gbs, 2.0 * dbytes / (ms * 1e6));
+  }
   // kernel reads of mapped host memory beside device-to-host copies
   VX_HIP(hipEventRecord(e0, ctx->compute));
   VX_HIP(hipStreamWaitEvent(ctx->d2h, e0, 0));

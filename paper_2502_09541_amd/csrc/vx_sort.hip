@@ -113,8 +113,11 @@ __global__ void __launch_bounds__(256) k_store4(const uint32_t* src, uint32_t* d
 //
 // One workgroup per tile of 8192 consecutive keys; wave w holds keys [w*1024, (w+1)*1024) of the
 // tile, 16 per lane in steps of 64.  The histogram launch counts each tile's keys per digit into
-// hist[d * tiles + t] (digit-major), so the exclusive scan of that array is where tile t's keys of
-// digit d start in the output.  The scatter launch ranks the tile's keys by digit in input order
+// hist[t * 256 + d] (tile-major: a workgroup's 256 counts are one contiguous store).  A column
+// scan turns them into offs[t * 256 + d], where tile t's first key of digit d goes: the keys of
+// every lower digit plus those of digit d in earlier tiles.  It walks the tiles in blocks, one
+// thread per digit, so its loads and stores are contiguous across the threads.  The scatter
+// launch ranks the tile's keys by digit in input order
 // (ballots give a lane its rank among the step's lanes of the same digit, a per-wave LDS counter
 // carries the count across steps), sorts the tile into LDS by that rank, and writes it out in
 // LDS order: each digit's keys of the tile form one run of consecutive output addresses, about 32
@@ -187,7 +190,7 @@ __global__ void __launch_bounds__(kDigitThreads) k_digit_hist(const K* in, uint6
                                                              uint32_t* hist) {
   __shared__ uint32_t cnt[kDigitWaves][256];
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint64_t t = blockIdx.x, tiles = gridDim.x;
+  const uint64_t t = blockIdx.x;
   for (uint32_t i = threadIdx.x; i < kDigitWaves * 256; i += kDigitThreads) (&cnt[0][0])[i] = 0;
   __syncthreads();
   const uint64_t first = t * kDigitTile + wave * kWaveKeys + lane;
@@ -200,11 +203,90 @@ __global__ void __launch_bounds__(kDigitThreads) k_digit_hist(const K* in, uint6
     uint32_t c = 0;
 #pragma unroll
     for (uint32_t w = 0; w < kDigitWaves; ++w) c += cnt[w][threadIdx.x];
-    hist[(uint64_t)threadIdx.x * tiles + t] = c;
+    hist[t * 256 + threadIdx.x] = c;
   }
 }
 
-// offs[d * tiles + t] = output position of tile t's first key of digit d
+// Column scan of the tile-major histogram, in blocks of `per` tiles (at most kColBlocks blocks;
+// thread d of every launch handles digit d).  part holds kColBlocks * 256 words.
+constexpr uint32_t kColBlocks = 128;
+
+uint64_t col_per(uint64_t tiles) { return std::max<uint64_t>(1, (tiles + kColBlocks - 1) / kColBlocks); }
+
+// part[b * 256 + d] = block b's keys of digit d
+__global__ void __launch_bounds__(256) k_digit_colsum(const uint32_t* hist, uint64_t tiles, uint64_t per,
+                                                      unsigned long long* part) {
+  const uint64_t t0 = blockIdx.x * per, t1 = t0 + per < tiles ? t0 + per : tiles;
+  unsigned long long s = 0;
+  uint64_t t = t0;
+  for (; t + 8 <= t1; t += 8) {   // eight independent loads in flight
+    uint32_t v[8];
+#pragma unroll
+    for (uint32_t u = 0; u < 8; ++u) v[u] = hist[(t + u) * 256 + threadIdx.x];
+#pragma unroll
+    for (uint32_t u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; t < t1; ++t) s += hist[t * 256 + threadIdx.x];
+  part[(uint64_t)blockIdx.x * 256 + threadIdx.x] = s;
+}
+
+// One workgroup: part[b * 256 + d] becomes the output position of block b's first key of digit d.
+__global__ void __launch_bounds__(256) k_digit_colbase(unsigned long long* part, uint32_t nb) {
+  __shared__ unsigned long long ws[4];
+  const uint32_t d = threadIdx.x, lane = d & 63, wave = d >> 6;
+  unsigned long long total = 0;
+  uint32_t b = 0;
+  for (; b + 8 <= nb; b += 8) {   // eight independent loads in flight
+    unsigned long long v[8];
+#pragma unroll
+    for (uint32_t u = 0; u < 8; ++u) v[u] = part[(uint64_t)(b + u) * 256 + d];
+#pragma unroll
+    for (uint32_t u = 0; u < 8; ++u) {
+      part[(uint64_t)(b + u) * 256 + d] = total;
+      total += v[u];
+    }
+  }
+  for (; b < nb; ++b) {
+    const unsigned long long v = part[(uint64_t)b * 256 + d];
+    part[(uint64_t)b * 256 + d] = total;
+    total += v;
+  }
+  unsigned long long x = total;   // exclusive scan of the digits' totals over the workgroup
+#pragma unroll
+  for (uint32_t o = 1; o < 64; o <<= 1) {
+    const unsigned long long y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) ws[wave] = x;
+  __syncthreads();
+  unsigned long long base = x - total;
+  for (uint32_t w = 0; w < wave; ++w) base += ws[w];
+  for (uint32_t b = 0; b < nb; ++b) part[(uint64_t)b * 256 + d] += base;
+}
+
+// offs[t * 256 + d] = output position of tile t's first key of digit d
+__global__ void __launch_bounds__(256) k_digit_colapply(const uint32_t* hist, uint64_t tiles, uint64_t per,
+                                                        const unsigned long long* part, unsigned long long* offs) {
+  const uint64_t t0 = blockIdx.x * per, t1 = t0 + per < tiles ? t0 + per : tiles;
+  unsigned long long run = part[(uint64_t)blockIdx.x * 256 + threadIdx.x];
+  uint64_t t = t0;
+  for (; t + 8 <= t1; t += 8) {
+    uint32_t v[8];
+#pragma unroll
+    for (uint32_t u = 0; u < 8; ++u) v[u] = hist[(t + u) * 256 + threadIdx.x];
+#pragma unroll
+    for (uint32_t u = 0; u < 8; ++u) {
+      offs[(t + u) * 256 + threadIdx.x] = run;
+      run += v[u];
+    }
+  }
+  for (; t < t1; ++t) {
+    offs[t * 256 + threadIdx.x] = run;
+    run += hist[t * 256 + threadIdx.x];
+  }
+}
+
+// offs[t * 256 + d] = output position of tile t's first key of digit d
 template <typename K>
 __global__ void __launch_bounds__(kDigitThreads) k_digit_scatter(const K* in, K* out, uint64_t n, uint32_t shift,
                                                                 const unsigned long long* offs) {
@@ -214,7 +296,7 @@ __global__ void __launch_bounds__(kDigitThreads) k_digit_scatter(const K* in, K*
   __shared__ uint32_t wsum[4];
   __shared__ unsigned long long gbase[256];
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint64_t t = blockIdx.x, tiles = gridDim.x;
+  const uint64_t t = blockIdx.x;
   for (uint32_t i = threadIdx.x; i < kDigitWaves * 256; i += kDigitThreads) (&cnt[0][0])[i] = 0;
   __syncthreads();
   const uint64_t first = t * kDigitTile + wave * kWaveKeys + lane;
@@ -246,7 +328,7 @@ __global__ void __launch_bounds__(kDigitThreads) k_digit_scatter(const K* in, K*
     uint32_t e = x - tot;
     for (uint32_t w = 0; w < wave; ++w) e += wsum[w];
     dstart[threadIdx.x] = e;
-    gbase[threadIdx.x] = offs[(uint64_t)threadIdx.x * tiles + t] - e;
+    gbase[threadIdx.x] = offs[t * 256 + threadIdx.x] - e;
   }
   __syncthreads();
 #pragma unroll
@@ -328,19 +410,26 @@ void merge_cuts_t(const K* const* runs, const uint64_t* len, uint32_t n_runs, ui
 
 // LSD radix sort of rows keys from src (left unchanged) into dst, through alt: digit passes of 8
 // bits over the key's order-preserving image (int64: 8 passes, int32: 4), each a histogram
-// launch, the three-launch scan and a tile scatter.  Passes alternate between dst and alt so the
-// last one writes dst.  hist and offs hold 256 * digit_tiles(rows) entries.
+// launch, the three-launch column scan and a tile scatter.  Passes alternate between dst and alt
+// so the last one writes dst.  hist holds 256 * digit_tiles(rows) entries, offs that many plus
+// 256 * kColBlocks (the column scan's block sums, after the offsets).
 template <typename K>
 vx_status radix_sort_keys(const K* src, K* alt, K* dst, uint64_t rows, uint32_t* hist, unsigned long long* offs,
                           vx_ctx* ctx, hipStream_t s) {
   const uint32_t passes = sizeof(K);
   const uint64_t tiles = digit_tiles(rows);
   VX_CHECK(tiles < (1ull << 31), VX_EINVAL, "sort: run of %llu keys is too long", (unsigned long long)rows);
+  const uint64_t per = col_per(tiles);
+  const unsigned nb = (unsigned)((tiles + per - 1) / per);   // <= kColBlocks
+  unsigned long long* part = offs + 256 * tiles;
+  (void)ctx;
   const K* in = src;
   for (uint32_t p = 0; p < passes; ++p) {
     K* out = ((passes - 1 - p) % 2 == 0) ? dst : alt;
     hipLaunchKernelGGL(k_digit_hist<K>, dim3((unsigned)tiles), dim3(kDigitThreads), 0, s, in, rows, 8 * p, hist);
-    VX_TRY(part_scan(ctx, hist, 256, (uint32_t)tiles, nullptr, offs, nullptr, s));
+    hipLaunchKernelGGL(k_digit_colsum, dim3(nb), dim3(256), 0, s, hist, tiles, per, part);
+    hipLaunchKernelGGL(k_digit_colbase, dim3(1), dim3(256), 0, s, part, nb);
+    hipLaunchKernelGGL(k_digit_colapply, dim3(nb), dim3(256), 0, s, hist, tiles, per, part, offs);
     hipLaunchKernelGGL(k_digit_scatter<K>, dim3((unsigned)tiles), dim3(kDigitThreads), 0, s, in, out, rows, 8 * p,
                        offs);
     VX_HIP(hipGetLastError());
@@ -390,7 +479,7 @@ vx_status sort_impl(vx_ctx* ctx, const vx_sort_desc* d, vx_stats* stats) {
   // buffer, two staging runs) and digit histograms fit the free arena; pass 2 needs 4 runs' room
   const uint64_t free0 = ctx->arena.capacity() - ctx->arena.used();
   auto pass1_bytes = [&](uint64_t rows) {
-    return 5 * align_to(rows * ks, 256) + (uint64_t)256 * digit_tiles(rows) * 12 + (1ull << 20);
+    return 5 * align_to(rows * ks, 256) + (uint64_t)256 * (digit_tiles(rows) * 12 + kColBlocks * 8) + (1ull << 20);
   };
   uint64_t C = d->chunk_rows;
   if (!C) {
@@ -419,7 +508,7 @@ vx_status sort_impl(vx_ctx* ctx, const vx_sort_desc* d, vx_stats* stats) {
     ArenaBlock blk;
     blk.a = &ctx->arena;
     const uint64_t hist_bytes = align_to((uint64_t)256 * tiles_max * 4, 256);
-    blk.p = ctx->arena.alloc(3 * run_bytes + hist_bytes + (uint64_t)256 * tiles_max * 8 + 256);
+    blk.p = ctx->arena.alloc(3 * run_bytes + hist_bytes + (uint64_t)256 * (tiles_max + kColBlocks) * 8 + 256);
     VX_CHECK(blk.p, VX_EBUDGET, "sort: no room for runs of %llu keys (radix and staging buffers)",
              (unsigned long long)C);
     uint8_t* alt = blk.p;
