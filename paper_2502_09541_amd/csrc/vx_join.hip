@@ -768,7 +768,8 @@ vx_status make_table(vx_ctx* ctx, int32_t key_type, uint32_t flags, const int32_
   VX_TRY(plan_table(key_type, flags, pay_types, n_pay, expected_rows, load_factor, kr, &v, &cap, &slot_bytes));
   const int ks = (int)v.key_size;
   const bool dense = v.direct == kLayoutDense;
-  // dense: the payload slots, the bitmap of keys seen, the side record; else slots and side record
+  // dense: the payload slots, a presence byte per key of the range, the side record; else slots
+  // and side record
   const uint64_t slots_bytes = dense ? (cap * slot_bytes + 255) / 256 * 256 : cap * slot_bytes;
   const uint64_t bits_bytes = dense ? (cap + 255) / 256 * 256 : 0;   // presence bytes
   uint64_t bytes = slots_bytes + bits_bytes + 256;
@@ -792,7 +793,7 @@ vx_status make_table(vx_ctx* ctx, int32_t key_type, uint32_t flags, const int32_
   for (uint32_t p = 0; p < n_pay; ++p) t->pay_type[p] = (uint32_t)pay_types[p];
   t->view = v;
   if (dense) {
-    // every payload slot is written by the build; the bitmap and the side record start at zero
+    // every payload slot is written by the build; the presence bytes and the side record start at zero
     fill_zero((uint64_t*)v.present, (bits_bytes + 256) / 8, ctx->compute);
   } else {
     const uint64_t quads = cap * slot_bytes / 16;   // 16-byte stores of k_init_slots
