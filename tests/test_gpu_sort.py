@@ -43,9 +43,11 @@ def _keys(n, dtype, seed):
     return k
 
 
-@pytest.mark.parametrize("n,chunk", [(100_003, 0), (1_000_003, 65_536), (50_000, 1024), (300_001, 100_000)])
+@pytest.mark.parametrize("n,chunk", [(100_003, 0), (1_000_003, 65_536), (50_000, 1024), (300_001, 100_000),
+                                     (5_000_003, 0)])
 def test_sort_host_int64(gpu, ctx, n, chunk):
-    """One run, 16 runs with a ragged last one, 49 runs (a deep merge tree), 4 runs."""
+    """One run, 16 runs with a ragged last one, 49 runs (a deep merge tree), 4 runs, and one run of
+    611 digit tiles (the column scan's blocks hold 5 tiles each, the last one a single tile)."""
     k = _keys(n, np.int64, n)
     want = oracle.sort(k)
     h = pinned(gpu, k)
