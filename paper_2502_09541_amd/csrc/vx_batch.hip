@@ -383,15 +383,28 @@ __global__ void __launch_bounds__(kScanBlock) k_batch_scan(const BatchJob* __res
   }
   part[threadIdx.x] = active ? sum : 0u;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t run = 0;
-    for (uint32_t rr = 0; rr < P; ++rr)
-      for (uint32_t gg = 0; gg < G; ++gg) {
-        const uint32_t v = part[gg * P + rr];
-        part[gg * P + rr] = run;
-        run += v;
-      }
-    *jb.kept = run;
+  {   // exclusive scan of the P * G partial sums in region-major order (entry k = rr * G + gg)
+    __shared__ uint32_t wtot[kScanBlock / 64];
+    const uint32_t k = threadIdx.x, lane = k & 63, wave = k >> 6;
+    const uint32_t at = (k % G) * P + k / G;   // k < P * G: where entry k sits in part
+    const uint32_t v = k < P * G ? part[at] : 0u;
+    uint32_t incl = v;
+#pragma unroll
+    for (uint32_t o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) wtot[wave] = incl;
+    __syncthreads();
+    uint32_t base = 0, total = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < kScanBlock / 64; ++w) {
+      base += w < wave ? wtot[w] : 0u;
+      total += wtot[w];
+    }
+    __syncthreads();   // every entry is read before any is overwritten
+    if (k < P * G) part[at] = base + incl - v;
+    if (k == 0) *jb.kept = total;
   }
   __syncthreads();
   if (active) {
