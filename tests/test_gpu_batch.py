@@ -102,6 +102,26 @@ def test_batch_hash_duplicate_detected(gpu, ctx):
             assert ei.value.status == gpu.VX_EDUPKEY
 
 
+@pytest.mark.parametrize("kt", [np.int32, np.int64])
+def test_batch_without_payloads(gpu, ctx, kt):
+    """Jobs with no payload column: counts only (the sums stay 0).  Direct tables then hold
+    nothing to read (a probe key in range is a match); hash tables (an insert claims key and a
+    zero payload at once) of 512 KiB and more have their probe sides partitioned, with the
+    forced-hash flag for every job; in the graph and in the per-job baseline."""
+    rng = np.random.default_rng(12)
+    bk = [(rng.permutation(n).astype(np.int64) - 5).astype(kt) for n in (3000, 70_000)]
+    bk.append(np.unique(rng.integers(-10**6, 10**6, 40_000)).astype(kt))
+    pk = [np.concatenate([rng.integers(int(k.min()) - 100, int(k.max()) + 100, 3 * len(k)).astype(kt),
+                          k[rng.integers(0, len(k), len(k))]]) for k in bk]
+    exp = [oracle.join_agg(a, [], c, []) + [0] for a, c in zip(bk, pk)]
+    args = ([dev(x) for x in bk], [None] * len(bk), [dev(x) for x in pk])
+    for hashed in (False, True):
+        for mode in (0, 1):
+            _say("batch without payloads", kt.__name__, "hashed", hashed, "mode", mode)
+            got, _ = ctx.join_batch(*args, mode=mode, hashed=hashed, tile_rows=1024, block=256, load_factor=0.7)
+            assert got == exp
+
+
 def test_batch_int64_keys(gpu, ctx):
     rng = np.random.default_rng(3)
     bk = [rng.permutation(1 << 40)[:0] if False else np.unique(rng.integers(-2**60, 2**60, n)).astype(np.int64)
