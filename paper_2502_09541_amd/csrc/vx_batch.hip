@@ -453,7 +453,7 @@ __device__ __forceinline__ void rows_regions(const RegionFn& region, uint64_t np
 }
 
 // Workgroup size of the scatter: one round sorts T kScatterItems keys in LDS (16384 int32 or 8192
-// int64 keys), so that a region's run per round is about a line on the bench's batch.
+// int64 keys), so that a region's run per round is a line or two on the bench's batch.
 template <typename K>
 constexpr uint32_t scatter_threads() { return sizeof(K) == 4 ? 1024 : 512; }
 
