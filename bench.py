@@ -9,7 +9,9 @@ through the double buffer, gather matching payloads by zero-copy, aggregate, ret
 
 Prints ONE JSON line (rank 0) with the throughput in probe rows/s, the host-link and HBM
 roofline fractions (peaks measured live on this machine where the datasheet has no figure),
-and the CPU oracle timed on a bounded sample.
+and the CPU oracle timed on a bounded sample.  Two blocks ride on the same line: the skewed
+partitioned join (learned splitters against radix-hash, `--no-skew` leaves it out) and the 256
+batched joins in one graph launch (`--no-batch`).
 """
 import argparse
 import contextlib
@@ -58,6 +60,10 @@ def parse():
                     help="stream workload: leave out the skewed partitioned join block")
     ap.add_argument("--skew-steps", type=int, default=3,
                     help="stream workload: timed steps per partitioner in the skewed join block")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="stream workload: leave out the batched joins block")
+    ap.add_argument("--batch-steps", type=int, default=5,
+                    help="stream workload: timed steps per variant in the batched joins block")
     ap.add_argument("--workload", default="stream", choices=["stream", "plain", "star", "batch", "skew", "rows", "radix", "sort", "calib"],
                     help="stream (default) is the headline line; the others print their own line")
     ap.add_argument("--method", default="learned", help="skew workload: partitioner to time")
@@ -275,6 +281,8 @@ def main():
         out["cpu_baseline"], out["cpu_baseline_all_cores"] = cpu_baseline(args.log2_build, args.log2_probe)
     if not args.no_skew:
         out["skew_partitioned_join"] = skew_block(args)
+    if not args.no_batch:
+        out["batched_joins"] = batch_block(args)
     print(json.dumps(out), flush=True)
 
 
@@ -739,6 +747,7 @@ def run_batch(args):
     ms_h1, res_h1 = _timed(lambda: ctx.join_batch(*args3, mode=1, hashed=True), args, torch)
     if res_h[0][0] != res[0][0] or res_h1[0][0] != res[0][0]:
         raise SystemExit("hashed batch results differ from the direct ones")
+    checked = _batch_checks(b, p, res[0][0])
     st = res[0][1]
     k_ms = sum(r[1]["kernel_ms"] for r in res) / len(res)
     # algorithmic bytes with the direct tables these dense-key jobs take: a probe reads its 4 B key
@@ -765,7 +774,43 @@ def run_batch(args):
                                     "jobs_probed_from_lds": res_h[0][1]["survivors"],
                                     "baseline_separate_launches_ms": ms_h1,
                                     "speedup_vs_separate_launches": ms_h1 / ms_h,
-                                    "vs_direct_tables": ms_h / ms}})
+                                    "vs_direct_tables": ms_h / ms},
+                    "result": {"match_count": matches,
+                               "closed_form_checked_jobs": checked}})
+
+
+def _batch_checks(b, p, got):
+    """Sampled jobs of the batch against their closed form: a job's build keys are a permutation of
+    0..n_build-1 and its probe keys fall in 0..2*n_build-1, so its COUNT is the number of probe keys
+    below n_build and its SUM adds the payload that the permutation gives each of them (mod 2^64).
+    Checked: the jobs with the largest build and the largest probe side, the smallest build, and
+    five seeded picks."""
+    import numpy as np
+    import datagen
+    M64 = 1 << 64
+    pick = {int(np.argmax(b)), int(np.argmax(p)), int(np.argmin(b))}
+    pick |= {int(j) for j in np.random.default_rng(0xC4).choice(len(b), 5, replace=False)}
+    for j in sorted(pick):
+        bk, bp, pk = datagen.batch_job(j, int(b[j]), int(p[j]))
+        pay_of_key = np.empty(len(bk), np.int64)
+        pay_of_key[bk] = bp
+        hit = pk < len(bk)
+        exp = [int(hit.sum()), int(pay_of_key[pk[hit]].sum()) % M64]
+        if list(got[j]) != exp:
+            raise SystemExit(f"batched join {j}: {list(got[j])} against the closed form {exp}")
+    return sorted(pick)
+
+
+def batch_block(args):
+    """The batched joins on the default line: 256 int32 joins in one HIP graph launch per step,
+    direct and hash tables, each against the per-job baseline (the batch workload's line, without
+    the fields the headline line already carries)."""
+    sub = argparse.Namespace(**vars(args))
+    sub.steps, sub.warmup = args.batch_steps, 1
+    r = run_batch(sub)
+    keep = ("value", "unit", "ms_per_step", "steps", "warmup", "dtype", "config", "roofline",
+            "baseline_separate_launches", "speedup_vs_separate_launches", "hash_tables", "result")
+    return {k: r[k] for k in keep}
 
 
 def run_skew(args):
