@@ -9,9 +9,10 @@ through the double buffer, gather matching payloads by zero-copy, aggregate, ret
 
 Prints ONE JSON line (rank 0) with the throughput in probe rows/s, the host-link and HBM
 roofline fractions (peaks measured live on this machine where the datasheet has no figure),
-and the CPU oracle timed on a bounded sample.  Two blocks ride on the same line: the skewed
-partitioned join (learned splitters against radix-hash, `--no-skew` leaves it out) and the 256
-batched joins in one graph launch (`--no-batch`).
+and the CPU oracle timed on a bounded sample.  The other workloads of the scope ride on the same
+line as blocks: the skewed partitioned join (learned splitters against radix-hash, `--no-skew`
+leaves it out), the in-memory join (`--no-plain`), the star join with group-by (`--no-star`) and
+the 256 batched joins in one graph launch (`--no-batch`).
 """
 import argparse
 import contextlib
@@ -60,6 +61,10 @@ def parse():
                     help="stream workload: leave out the skewed partitioned join block")
     ap.add_argument("--skew-steps", type=int, default=3,
                     help="stream workload: timed steps per partitioner in the skewed join block")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="stream workload: leave out the in-memory join block")
+    ap.add_argument("--no-star", action="store_true",
+                    help="stream workload: leave out the star join block")
     ap.add_argument("--no-batch", action="store_true",
                     help="stream workload: leave out the batched joins block")
     ap.add_argument("--batch-steps", type=int, default=5,
@@ -281,8 +286,12 @@ def main():
         out["cpu_baseline"], out["cpu_baseline_all_cores"] = cpu_baseline(args.log2_build, args.log2_probe)
     if not args.no_skew:
         out["skew_partitioned_join"] = skew_block(args)
+    if not args.no_plain:
+        out["in_memory_join"] = _sub_block(run_plain, args, 50, 10)
+    if not args.no_star:
+        out["star_join_groupby"] = _sub_block(run_star, args, 5, 1)
     if not args.no_batch:
-        out["batched_joins"] = batch_block(args)
+        out["batched_joins"] = _sub_block(run_batch, args, args.batch_steps, 1)
     print(json.dumps(out), flush=True)
 
 
@@ -801,16 +810,14 @@ def _batch_checks(b, p, got):
     return sorted(pick)
 
 
-def batch_block(args):
-    """The batched joins on the default line: 256 int32 joins in one HIP graph launch per step,
-    direct and hash tables, each against the per-job baseline (the batch workload's line, without
-    the fields the headline line already carries)."""
+def _sub_block(run, args, steps, warmup):
+    """Another workload's line as a block of the default line: the workload runs with its own
+    steps and warmup, and the block keeps its fields except those the headline line carries."""
     sub = argparse.Namespace(**vars(args))
-    sub.steps, sub.warmup = args.batch_steps, 1
-    r = run_batch(sub)
-    keep = ("value", "unit", "ms_per_step", "steps", "warmup", "dtype", "config", "roofline",
-            "baseline_separate_launches", "speedup_vs_separate_launches", "hash_tables", "result")
-    return {k: r[k] for k in keep}
+    sub.steps, sub.warmup = steps, warmup
+    r = run(sub)
+    return {k: v for k, v in r.items()
+            if k not in ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data")}
 
 
 def run_skew(args):
