@@ -568,15 +568,29 @@ def run_rows(args):
     launches = max(1, st["kernel_launches"])
     k_avg = st["kernel_ms"] / launches
     ach = 24.0 * (np_ / launches) / (k_avg * 1e6)
+    # the step waits on the host link, as the aggregate-only join does: algorithmic host-to-device
+    # bytes as there (16 B per build row, 8 B per probe key, 16 B of payloads per match); the
+    # output rows leave in the other direction
+    alg = nb * 16 + np_ * 8 + agg[0] * 16
+    wire = nb * 16 + st["sdma_bytes"] + st_c["zc_bytes"]
     return _common("probe rows/s", np_ / (ms / 1e3), ms, args, "int64",
                    {"workload": "streamed_join_rows_materialized", "build_rows": nb, "probe_rows": np_,
                     "output_rows": n_out, "output_bytes_per_row": 40, "match_frac": 0.1,
                     "device_budget_gib": args.budget_gib},
-                   {"bound": "hbm", "kernel": "k_probe_rows", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": ach / HBM_PEAK_GBS, "traffic": None, "traffic_profile": PROFILE["k_probe_rows"], "avg_launch_ms": k_avg,
-                    "rows_per_launch": np_ / launches},
-                   {"host_link": {"peak_measured_gbs": b_peak,
-                                  "h2d_gbs": (nb * 16 + st["sdma_bytes"] + st_c["zc_bytes"]) / (ms * 1e6),
+                   {"bound": "host_link",
+                    "kernel": "whole step: build columns, probe-key chunk copies, k_probe_rows' zero-copy payload "
+                              "reads and output row stores",
+                    "achieved": alg / (ms * 1e6), "peak": b_peak, "unit": "GB/s", "frac": alg / (ms * 1e6) / b_peak,
+                    "traffic": wire, "peak_kind": "host-to-device copy rate measured in this run",
+                    "algorithmic_bytes": "host-to-device per step: 16 B per build row + 8 B per probe key + 16 B of "
+                                         "payloads per match",
+                    "traffic_kind": "host-to-device bytes per step: build columns + copy-stream bytes + the "
+                                    "zero-copy granules k_probe_rows counts x granule"},
+                   {"hbm": {"kernel": "k_probe_rows", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": ach / HBM_PEAK_GBS, "traffic": None, "traffic_profile": PROFILE["k_probe_rows"],
+                            "avg_launch_ms": k_avg, "rows_per_launch": np_ / launches},
+                    "host_link": {"peak_measured_gbs": b_peak,
+                                  "h2d_gbs": wire / (ms * 1e6),
                                   "zero_copy_bytes_counted": st_c["zc_bytes"],
                                   "zero_copy_bytes_binomial_model": st["zc_bytes"],
                                   "d2h_output_gbs": d2h / (ms * 1e6)},
@@ -653,7 +667,8 @@ def run_plain(args):
                     "build_ms": st["build_ms"], "probe_ms": st["probe_ms"], "table_bytes": st["table_bytes"],
                     "hash_table": hashed_variant, "host_resident": host_variant,
                     "cpu_baseline": {"value": np_ / cpu, "unit": "probe rows/s", "cores": 1, "kind": "oracle",
-                                     "sample": f"the full workload, build + probe in {cpu:.1f} s on 1 host thread"}})
+                                     "sample": f"the full workload, build + probe in {cpu:.1f} s on 1 host thread",
+                                     **host_info()}})
 
 
 def run_star(args):
@@ -710,13 +725,26 @@ def run_star(args):
                   {"workload": "star_join_groupby", "fact_rows": nf, "dims": list(rows),
                    "filter_selectivity": ["1/7", "1/5", "1/25", "1"], "groups": len(res[0][0][0]),
                    "chunk_rows": st["chunk_rows"], "zero_copy_columns": bin(st["zc_mask"]).count("1")},
-                  {"bound": "hbm", "kernel": "k_star",
-                   # per launch: 4 B foreign key from the chunk buffer + one 8 B slot of the first table
-                   "achieved": (nf / st["kernel_launches"]) * 12 / (k_ms * 1e6), "peak": HBM_PEAK_GBS,
-                   "unit": "GB/s", "frac": (nf / st["kernel_launches"]) * 12 / (k_ms * 1e6) / HBM_PEAK_GBS,
-                   "traffic": None, "traffic_profile": PROFILE["k_star"], "avg_launch_ms": k_ms,
-                   "rows_per_launch": nf / st["kernel_launches"]},
-                  {"host_link": {"peak_measured_gbs": b_peak, "achieved_wire_gbs": wire / (ms * 1e6),
+                  # the step waits on the host link: the first foreign key column arrives by chunk
+                  # copies, the other columns of the rows still alive by k_star's zero-copy reads
+                  {"bound": "host_link",
+                   "kernel": "whole step: chunk copies of the first foreign key, k_star's zero-copy reads of the "
+                             "other columns for surviving rows",
+                   "achieved": alg / (ms * 1e6), "peak": b_peak, "unit": "GB/s", "frac": alg / (ms * 1e6) / b_peak,
+                   "traffic": wire,
+                   "peak_kind": "host-to-device copy rate measured in this run",
+                   "algorithmic_bytes": "per fact row: 4 B of each foreign key column while the row is alive "
+                                        "(dimensions in ascending filter selectivity), then 12 B of measures "
+                                        "per surviving row",
+                   "traffic_kind": "host-link bytes per step: copy-stream bytes + the zero-copy granules k_star "
+                                   "counts (in one more, untimed step with the count on) x granule"},
+                  {"hbm": {"kernel": "k_star",
+                           # per launch: 4 B foreign key from the chunk buffer + one 8 B slot of the first table
+                           "achieved": (nf / st["kernel_launches"]) * 12 / (k_ms * 1e6), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": (nf / st["kernel_launches"]) * 12 / (k_ms * 1e6) / HBM_PEAK_GBS,
+                           "traffic": None, "traffic_profile": PROFILE["k_star"], "avg_launch_ms": k_ms,
+                           "rows_per_launch": nf / st["kernel_launches"]},
+                   "host_link": {"peak_measured_gbs": b_peak, "achieved_wire_gbs": wire / (ms * 1e6),
                                  "frac_wire": wire / (ms * 1e6) / b_peak,
                                  "zero_copy_bytes_counted": st_c["zc_bytes"],
                                  "zero_copy_bytes_binomial_model": st["zc_bytes"],
@@ -724,7 +752,8 @@ def run_star(args):
                                  "frac_algorithmic": alg / (ms * 1e6) / b_peak},
                    "survivors": st["survivors"], "build_ms": st["build_ms"],
                    "cpu_baseline": {"value": n_cpu / cpu, "unit": "fact rows/s", "cores": 1, "kind": "oracle",
-                                    "sample": f"first {n_cpu} fact rows in {cpu:.1f} s on 1 host thread"}})
+                                    "sample": f"first {n_cpu} fact rows in {cpu:.1f} s on 1 host thread",
+                                    **host_info()}})
     for h in fk + ms_:
         h.free()
     return out
@@ -844,17 +873,27 @@ def run_skew(args):
     # dominant kernel: the probe stream (one launch per probe chunk, HIP events on its stream)
     k_avg = st["kernel_ms"] / max(1, st["chunks"])
     ach = (8.0 * np_ + 32.0 * st["survivors"]) / st["chunks"] / (k_avg * 1e6)
+    alg = 16 * nb + 8 * np_
     return _common("probe rows/s", a["value"], a["ms"], args, "int64",
                    {"workload": "skewed_partitioned_join", "build_rows": nb, "probe_rows": np_, "zipf_s": 1.1,
                     "key_range": "[1, 2^40]", "device_budget_gib": args.skew_budget_gib,
                     "keys": "scrambled by a bijection of [0, 2^40)" if args.skew_scramble else "Zipf ranks",
                     "method": args.method, "n_parts": st["n_parts"]},
-                   {"bound": "hbm", "kernel": "k_pj_stream", "achieved": ach, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                    "traffic_profile": PROFILE["k_pj_stream"], "avg_launch_ms": k_avg,
-                    "rows_per_launch": np_ / st["chunks"],
-                    "algorithmic_bytes": "8 B per probe key + 32 B table slot per probe row routed to a table"},
-                   {"host_link": {"peak_measured_gbs": b_peak, "h2d_bytes_per_step": h2d,
+                   # the step waits on the host link: each build and probe column crosses it once
+                   {"bound": "host_link",
+                    "kernel": "whole step: splitters, pass-1 clustering of the build side, partition builds, "
+                              "the probe stream",
+                    "achieved": alg / (a["ms"] * 1e6), "peak": b_peak, "unit": "GB/s",
+                    "frac": alg / (a["ms"] * 1e6) / b_peak, "traffic": h2d,
+                    "peak_kind": "host-to-device copy rate measured in this run",
+                    "algorithmic_bytes": "16 B per build row (key, payload) + 8 B per probe key, each read once",
+                    "traffic_kind": "host-to-device bytes per step: copy-stream bytes + zero-copy bytes"},
+                   {"hbm": {"kernel": "k_pj_stream", "achieved": ach, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                            "traffic_profile": PROFILE["k_pj_stream"], "avg_launch_ms": k_avg,
+                            "rows_per_launch": np_ / st["chunks"],
+                            "algorithmic_bytes": "8 B per probe key + 32 B table slot per probe row routed to a table"},
+                    "host_link": {"peak_measured_gbs": b_peak, "h2d_bytes_per_step": h2d,
                                   "achieved_gbs": h2d / (a["ms"] * 1e6), "frac": h2d / (a["ms"] * 1e6) / b_peak},
                     "result": {"match_count": a["agg"][0], "sum": a["agg"][1]},
                     args.method: _skew_line(a),
@@ -914,7 +953,7 @@ def run_radix(args):
             raise SystemExit("oracle sample: unexpected match count")
         cpu = {"value": (len(sak) + len(sbk)) / dt, "unit": "tuples/s", "cores": 1, "kind": "oracle",
                "sample": f"rows of A and B with key < 2^{args.radix_log2 - 4}: {len(sak)} + {len(sbk)} rows, "
-                         f"joined in {dt:.1f} s on 1 host thread"}
+                         f"joined in {dt:.1f} s on 1 host thread", **host_info()}
         # the same oracle on all host cores: the sample's key range cut into one range per thread
         # (each range's join is independent), the C calls run without the GIL
         from concurrent.futures import ThreadPoolExecutor
@@ -930,7 +969,8 @@ def run_radix(args):
         if [sum(x) % (1 << 64) for x in zip(*outs)] != got:
             raise SystemExit("threaded oracle run disagrees with the single-threaded one")
         cpu_all = {"value": (len(sak) + len(sbk)) / dt_all, "unit": "tuples/s", "cores": n_thr, "kind": "oracle",
-                   "sample": f"the same sample cut into {n_thr} key ranges, one per thread, in {dt_all:.1f} s"}
+                   "sample": f"the same sample cut into {n_thr} key ranges, one per thread, in {dt_all:.1f} s",
+                   **host_info()}
     for h in (ak, av, bk, bv):
         h.free()
     tuples = 2 * n
@@ -1034,7 +1074,8 @@ def run_sort(args):
         if not bool(np.all(got[1:] >= got[:-1])):
             raise SystemExit("oracle sample not sorted")
         cpu = {"value": m / dt, "unit": "keys/s", "cores": 1, "kind": "oracle",
-               "sample": f"the first {m} keys of the same generator (1/16), std::sort in {dt:.1f} s on 1 host thread"}
+               "sample": f"the first {m} keys of the same generator (1/16), std::sort in {dt:.1f} s on 1 host thread",
+               **host_info()}
     h.free()
     runs = st["chunks"]
     # Both passes move every key in and back out over the link at the rate measured for copies in
