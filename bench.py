@@ -786,6 +786,7 @@ def run_batch(args):
     if res_h[0][0] != res[0][0] or res_h1[0][0] != res[0][0]:
         raise SystemExit("hashed batch results differ from the direct ones")
     checked = _batch_checks(b, p, res[0][0])
+    cpu = _batch_cpu_baseline(b, p, res[0][0])
     st = res[0][1]
     k_ms = sum(r[1]["kernel_ms"] for r in res) / len(res)
     # algorithmic bytes per graph: the join's per-unit figure, as for the in-memory join (a probe
@@ -824,7 +825,8 @@ def run_batch(args):
                                     "speedup_vs_separate_launches": ms_h1 / ms_h,
                                     "vs_direct_tables": ms_h / ms},
                     "result": {"match_count": matches,
-                               "closed_form_checked_jobs": checked}})
+                               "closed_form_checked_jobs": checked},
+                    "cpu_baseline": cpu})
 
 
 def _batch_checks(b, p, got):
@@ -847,6 +849,28 @@ def _batch_checks(b, p, got):
         if list(got[j]) != exp:
             raise SystemExit(f"batched join {j}: {list(got[j])} against the closed form {exp}")
     return sorted(pick)
+
+
+def _batch_cpu_baseline(b, p, got):
+    """The CPU oracle on a bounded sample of the batch: eight jobs that span its sizes (the middle
+    job of each eighth in order of probe size, about 1.2e8 probe rows), joined one after another
+    on one host thread; their results must equal the GPU's."""
+    import numpy as np
+    import datagen
+    import oracle
+    sample = sorted(int(j) for j in np.argsort(p, kind="stable")[16::32])
+    rows, secs = 0, 0.0
+    for j in sample:
+        bk, bp, pk = datagen.batch_job(j, int(b[j]), int(p[j]))
+        t0 = time.perf_counter()
+        exp = oracle.join_agg(bk, [bp], pk, [])
+        secs += time.perf_counter() - t0
+        rows += len(pk)
+        if list(got[j]) != exp:
+            raise SystemExit(f"batched join {j}: {list(got[j])} against the oracle {exp}")
+    return {"value": rows / secs, "unit": "probe rows/s", "cores": 1, "kind": "oracle",
+            "sample": f"jobs {sample} of the batch ({rows} probe rows), build + probe in {secs:.1f} s on 1 host "
+                      f"thread, results equal to the GPU's", **host_info()}
 
 
 def _sub_block(run, args, steps, warmup):
